@@ -1,0 +1,216 @@
+"""FP64 CPU oracle for the all-sky string ISW map (test infrastructure only).
+
+This package is the independent reference that the HIP library is checked
+against.  It is used by the test-suite, by ``__graft_entry__.smoke()`` and by
+the CPU-baseline leg of ``bench.py``; the product library never imports,
+links or executes it.  The arithmetic lives in ``csmap_oracle.c`` (plain C,
+IEEE double, no floating-point contraction); this module only builds it and
+marshals numpy arrays through ``ctypes``.
+
+Inputs follow the shapes the workload generator produces: per box an origin,
+an extent, a conformal-time slab, a visibility rule, and segment arrays
+``x_rel (n,3)``, ``xdot (n,3)``, ``xprime (n,3)``, ``dsigma (n,)``.  Values
+stored in float32 are widened to float64 exactly before they reach the C code,
+so the oracle sees the very numbers the GPU sees.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "csmap_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+VIS_ALL, VIS_BOX, VIS_CAP = 0, 1, 2
+BOX_STRIDE = 16
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (OpenMP, no contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+               "-fPIC", "-shared", "-Wall", "-Wextra", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        _lib = ctypes.CDLL(_LIB)
+        i64, f64p, i64p, u8p = (ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint8))
+        _lib.oracle_isqrt.argtypes = [i64]
+        _lib.oracle_isqrt.restype = i64
+        _lib.oracle_pix2vec_many.argtypes = [i64, i64, i64p, f64p]
+        _lib.oracle_ring_many.argtypes = [i64, i64, i64p, i64p, i64p]
+        _lib.oracle_theta_dirs.argtypes = [i64, f64p, ctypes.c_double, i64, f64p, i64p,
+                                           f64p, f64p, f64p, f64p, ctypes.c_int, f64p]
+        _lib.oracle_theta_pixels.argtypes = [i64, i64, i64p, ctypes.c_double, i64, f64p, i64p,
+                                             f64p, f64p, f64p, f64p, f64p]
+        _lib.oracle_visible_many.argtypes = [i64, i64, i64p, ctypes.c_double, f64p, u8p]
+        _lib.oracle_kept_many.argtypes = [i64, f64p, ctypes.c_double, f64p, f64p, f64p, f64p,
+                                          u8p]
+        _lib.oracle_grad.argtypes = [i64, i64, i64p, f64p, ctypes.c_double, i64, f64p, i64p,
+                                     f64p, f64p, f64p, f64p, i64, i64p, f64p]
+        _lib.oracle_num_threads.restype = ctypes.c_int
+    return _lib
+
+
+def _p(a: np.ndarray, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _i64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int64))
+
+
+def num_threads() -> int:
+    return int(lib().oracle_num_threads())
+
+
+# ----------------------------------------------------------------------------
+# HEALPix RING geometry (Gorski et al. 2005, the pixelisation of Sec. II.D)
+# ----------------------------------------------------------------------------
+
+def npix(nside: int) -> int:
+    return 12 * nside * nside
+
+
+def isqrt(x: int) -> int:
+    return int(lib().oracle_isqrt(int(x)))
+
+
+def ring_of_pixel(nside: int, pix) -> tuple[np.ndarray, np.ndarray]:
+    """(ring 1..4N-1, 0-based position in the ring) of each RING pixel."""
+    p = _i64(pix).ravel()
+    ring = np.empty_like(p)
+    pos = np.empty_like(p)
+    lib().oracle_ring_many(nside, p.size, _p(p, ctypes.c_int64), _p(ring, ctypes.c_int64),
+                           _p(pos, ctypes.c_int64))
+    return ring, pos
+
+
+def pix2vec(nside: int, pix) -> np.ndarray:
+    """Unit vectors (n,3) of RING pixel centres."""
+    p = _i64(pix).ravel()
+    out = np.empty((p.size, 3), dtype=np.float64)
+    lib().oracle_pix2vec_many(nside, p.size, _p(p, ctypes.c_int64), _p(out, ctypes.c_double))
+    return out
+
+
+# ----------------------------------------------------------------------------
+# Boxes and segments
+# ----------------------------------------------------------------------------
+
+def box_record(box) -> np.ndarray:
+    """Pack one box (an object with origin, ext, eta_lo, eta_hi, vis, cap_dir,
+    cap_cos attributes) into the 16-double record the C code reads."""
+    r = np.zeros(BOX_STRIDE, dtype=np.float64)
+    r[0:3] = np.asarray(box.origin, dtype=np.float64)
+    r[3:6] = np.asarray(box.ext, dtype=np.float64)
+    r[6] = box.eta_lo
+    r[7] = box.eta_hi
+    r[8] = int(box.vis)
+    if box.cap_dir is not None:
+        r[9:12] = np.asarray(box.cap_dir, dtype=np.float64)
+    r[12] = box.cap_cos if box.cap_cos is not None else 0.0
+    return r
+
+
+class _Packed:
+    def __init__(self, boxes: Sequence):
+        self.nbox = len(boxes)
+        self.boxes = np.ascontiguousarray(np.stack([box_record(b) for b in boxes]) if boxes
+                                          else np.zeros((0, BOX_STRIDE)))
+        counts = [len(b.dsigma) for b in boxes]
+        self.seg_off = _i64(np.concatenate([[0], np.cumsum(counts)]))
+        cat = (lambda name, shape: _f64(np.concatenate([getattr(b, name) for b in boxes]))
+               if boxes else np.zeros(shape))
+        self.x = cat("x_rel", (0, 3)).reshape(-1, 3)
+        self.xd = cat("xdot", (0, 3)).reshape(-1, 3)
+        self.xp = cat("xprime", (0, 3)).reshape(-1, 3)
+        self.ds = cat("dsigma", (0,)).ravel()
+
+    def args(self):
+        c = ctypes.c_double
+        return (self.nbox, _p(self.boxes, c), _p(self.seg_off, ctypes.c_int64),
+                _p(self.x, c), _p(self.xd, c), _p(self.xp, c), _p(self.ds, c))
+
+
+def theta_dirs(dirs, eta0: float, boxes: Sequence, use_vis: bool = False) -> np.ndarray:
+    """Theta/GU (Eq. 1) at arbitrary unit directions (n,3)."""
+    d = _f64(dirs).reshape(-1, 3)
+    out = np.empty(d.shape[0], dtype=np.float64)
+    pk = _Packed(boxes)
+    lib().oracle_theta_dirs(d.shape[0], _p(d, ctypes.c_double), float(eta0), *pk.args(),
+                            int(bool(use_vis)), _p(out, ctypes.c_double))
+    return out
+
+
+def theta_pixels(nside: int, pix, eta0: float, boxes: Sequence) -> np.ndarray:
+    """Theta/GU at RING pixel centres, each pixel summing the boxes it sees."""
+    p = _i64(pix).ravel()
+    out = np.empty(p.size, dtype=np.float64)
+    pk = _Packed(boxes)
+    lib().oracle_theta_pixels(nside, p.size, _p(p, ctypes.c_int64), float(eta0), *pk.args(),
+                              _p(out, ctypes.c_double))
+    return out
+
+
+def visible(nside: int, pix, eta0: float, box) -> np.ndarray:
+    p = _i64(pix).ravel()
+    out = np.empty(p.size, dtype=np.uint8)
+    rec = box_record(box)
+    lib().oracle_visible_many(nside, p.size, _p(p, ctypes.c_int64), float(eta0),
+                              _p(rec, ctypes.c_double), _p(out, ctypes.c_uint8))
+    return out.astype(bool)
+
+
+def kept(eta0: float, box) -> np.ndarray:
+    """Light-cone selection flag of every segment of one box."""
+    rec = box_record(box)
+    x, xd, xp, ds = (_f64(box.x_rel).reshape(-1, 3), _f64(box.xdot).reshape(-1, 3),
+                     _f64(box.xprime).reshape(-1, 3), _f64(box.dsigma).ravel())
+    out = np.empty(ds.size, dtype=np.uint8)
+    c = ctypes.c_double
+    lib().oracle_kept_many(ds.size, _p(rec, c), float(eta0), _p(x, c), _p(xd, c), _p(xp, c),
+                           _p(ds, c), _p(out, ctypes.c_uint8))
+    return out.astype(bool)
+
+
+def grad(nside: int, pix, cotangent, eta0: float, boxes: Sequence, sel) -> np.ndarray:
+    """Gradient of sum_p g_p Theta_p/GU over the listed pixels with respect to
+    (x_rel[3], xdot[3], xprime[3], dsigma) of the selected segments.
+
+    ``sel`` holds global segment indices (box-major concatenation order).
+    Returns an array (len(sel), 10)."""
+    p = _i64(pix).ravel()
+    g = _f64(cotangent).ravel()
+    if g.size != p.size:
+        raise ValueError("cotangent must have one value per listed pixel")
+    s = _i64(sel).ravel()
+    pk = _Packed(boxes)
+    if s.size and (s.min() < 0 or s.max() >= pk.seg_off[-1]):
+        raise ValueError("segment index out of range")
+    out = np.empty((s.size, 10), dtype=np.float64)
+    lib().oracle_grad(nside, p.size, _p(p, ctypes.c_int64), _p(g, ctypes.c_double),
+                      float(eta0), *pk.args(), s.size, _p(s, ctypes.c_int64),
+                      _p(out, ctypes.c_double))
+    return out

@@ -1,0 +1,471 @@
+/*
+ * csmap_oracle.c -- plain FP64 CPU oracle for the all-sky string ISW sum.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library calls, links or
+ * loads this file; only the test-suite, the smoke check and the CPU baseline
+ * of the benchmark do.  It shares no source, header or table with the HIP
+ * implementation: the two are written independently from the same physics
+ * (Ringeval & Bouchet, "All sky CMB map from cosmic strings integrated
+ * Sachs-Wolfe effect") and the same published HEALPix definition (Gorski et
+ * al. 2005, cited in the paper's Sec. I and Sec. II.D).
+ *
+ * What it computes (all in IEEE double precision, compiled without
+ * floating-point contraction so every rounding is spelled out):
+ *
+ *   - HEALPix RING pixel centres (Sec. II.D: the map directions are the
+ *     centres of an Nside HEALPix RING pixelisation).
+ *   - The light-cone selection of a simulation box: an event recorded at
+ *     observer-relative position P lies on the past light cone at conformal
+ *     time eta = eta0 - |P| (Sec. II.A, gauge footnote X^0 = eta = tau); a box
+ *     contributes the events with eta_lo <= eta < eta_hi.
+ *   - Eq. (1) with Eq. (2), discretised over segments (Sec. II.A: every
+ *     segment on the light cone enters every pixel, no cut):
+ *         Theta(n)/GU = sum_s -4 u.(R n - P)/|R n - P|^2 * eps * dsigma,
+ *         u = Xdot - (n.X')X'/(1 + n.Xdot),  eps^2 = X'^2/(1 - Xdot^2),
+ *     with R = |P| (the non-bold X of Eq. (1)), each pixel sampled at its
+ *     centre (Sec. III.B: each pixel represents the signal in its centroid
+ *     direction).  A term whose |R n - P|^2 is exactly zero contributes 0.
+ *   - The gradient of a linear functional sum_p g_p Theta_p with respect to
+ *     every segment's (x_rel, Xdot, X', dsigma), by the chain rule applied to
+ *     the same expression (the paper does not differentiate; this is the
+ *     adjoint of its Eq. (1)).
+ *
+ * Sums over segments are Neumaier-compensated.  Pixels are distributed over
+ * OpenMP threads; the order of terms inside one pixel is fixed (box order,
+ * then segment order), so results do not depend on the thread count.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Integer stage of the RING scheme.                                         */
+/* Rings are numbered i = 1 .. 4N-1 from north to south.  North-cap ring     */
+/* i < N holds 4i pixels, the 2N+1 rings N..3N of the equatorial belt hold  */
+/* 4N pixels each, and the south cap mirrors the north.  Pixel indices run  */
+/* ring by ring from the north pole, and by increasing azimuth in a ring.   */
+/* ------------------------------------------------------------------------ */
+
+/* floor(sqrt(x)) for 0 <= x < 2^62, exact. */
+int64_t oracle_isqrt(int64_t x)
+{
+    if (x <= 0) return 0;
+    int64_t r = (int64_t)sqrt((double)x);
+    while (r * r > x) --r;
+    while ((r + 1) * (r + 1) <= x) ++r;
+    return r;
+}
+
+/* Number of pixels in the north polar cap: sum_{i<N} 4i = 2N(N-1). */
+static int64_t cap_pixels(int64_t n) { return 2 * n * (n - 1); }
+
+/* Ring index (1-based, north to south) and 0-based position in the ring. */
+void oracle_ring_of_pixel(int64_t nside, int64_t p, int64_t *ring, int64_t *pos)
+{
+    const int64_t ncap = cap_pixels(nside);
+    const int64_t npix = 12 * nside * nside;
+    if (p < ncap) {
+        /* Largest i with 2i(i-1) <= p. */
+        int64_t i = (1 + oracle_isqrt(1 + 2 * p)) / 2;
+        *ring = i;
+        *pos = p - 2 * i * (i - 1);
+    } else if (p < npix - ncap) {
+        int64_t q = p - ncap;
+        *ring = nside + q / (4 * nside);
+        *pos = q % (4 * nside);
+    } else {
+        /* Mirror image of a north-cap pixel; azimuth order is preserved. */
+        int64_t m = npix - 1 - p;               /* index counted from the end */
+        int64_t i = (1 + oracle_isqrt(1 + 2 * m)) / 2;
+        int64_t back = m - 2 * i * (i - 1);     /* position counted from the ring's end */
+        *ring = 4 * nside - i;
+        *pos = 4 * i - 1 - back;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Float stage.  Every quantity is a correctly rounded IEEE operation on     */
+/* exact integers, or a fixed fma polynomial, so that any implementation     */
+/* that follows the same steps reproduces the same bits.                     */
+/* ------------------------------------------------------------------------ */
+
+/* Taylor coefficients of sin(pi x / 2) = x * S(x^2): the double nearest to
+ * (-1)^k (pi/2)^(2k+1) / (2k+1)!, k = 0..8. */
+static const double SIN_C[9] = {
+     0x1.921fb54442d18p+0, -0x1.4abbce625be53p-1,  0x1.466bc6775aae2p-4,
+    -0x1.32d2cce62bd86p-8,  0x1.50783487ee782p-13, -0x1.e3074fde8871fp-19,
+     0x1.e8f434d018d63p-25, -0x1.6fadb9f155744p-31, 0x1.aaec32af93359p-38,
+};
+/* Taylor coefficients of cos(pi x / 2) = C(x^2): the double nearest to
+ * (-1)^k (pi/2)^(2k) / (2k)!, k = 0..8. */
+static const double COS_C[9] = {
+     0x1.0000000000000p+0, -0x1.3bd3cc9be45dep+0,  0x1.03c1f081b5ac4p-2,
+    -0x1.55d3c7e3cbffap-6,  0x1.e1f506891babbp-11, -0x1.a6d1f2a204a8cp-16,
+     0x1.f9d38a3763cc3p-22, -0x1.b6e24f44b128fp-28, 0x1.20c62c2f2d7f5p-34,
+};
+
+/* sin and cos of (pi/2) x for 0 <= x <= 1/2 (an angle of at most pi/4). */
+static void sincos_quarter(double x, double *s, double *c)
+{
+    const double y = x * x;
+    double ps = SIN_C[8], pc = COS_C[8];
+    for (int k = 7; k >= 0; --k) {
+        ps = fma(ps, y, SIN_C[k]);
+        pc = fma(pc, y, COS_C[k]);
+    }
+    *s = x * ps;
+    *c = pc;
+}
+
+/* Unit vector of an azimuth phi = (pi/2) * num/den, 0 <= num < 4 den.
+ * The quadrant is split off with integers, the remainder is folded into
+ * [0, pi/4] by the complement identity, and only then evaluated. */
+static void azimuth(int64_t num, int64_t den, double *cphi, double *sphi)
+{
+    const int64_t quad = num / den;
+    const int64_t rem = num - quad * den;
+    double s, c, cq, sq;
+    if (2 * rem <= den) {
+        sincos_quarter((double)rem / (double)den, &s, &c);
+        cq = c; sq = s;
+    } else {
+        sincos_quarter((double)(den - rem) / (double)den, &s, &c);
+        cq = s; sq = c;
+    }
+    switch (quad & 3) {
+    case 0: *cphi = cq;  *sphi = sq;  break;
+    case 1: *cphi = -sq; *sphi = cq;  break;
+    case 2: *cphi = -cq; *sphi = -sq; break;
+    default: *cphi = sq; *sphi = -cq; break;
+    }
+}
+
+/* Direction of the centre of RING pixel p (observer at the origin). */
+void oracle_pix2vec(int64_t nside, int64_t p, double v[3])
+{
+    int64_t i, j;
+    oracle_ring_of_pixel(nside, p, &i, &j);
+    const int64_t n = nside;
+    double z, st;
+    int64_t num, den;
+    if (i < n || i > 3 * n) {
+        /* Polar caps.  k is the ring counted from the nearer pole:
+         *   z = +-(3N^2 - k^2)/(3N^2),  sin(theta) = k sqrt(6N^2 - k^2)/(3N^2),
+         *   phi = (pi/2)(2j + 1)/(2k). */
+        const int64_t k = (i < n) ? i : 4 * n - i;
+        const double d = (double)(3 * n * n);
+        z = (double)(3 * n * n - k * k) / d;
+        st = ((double)k * sqrt((double)(6 * n * n - k * k))) / d;
+        if (i > 3 * n) z = -z;
+        num = 2 * j + 1;
+        den = 2 * k;
+    } else {
+        /* Equatorial belt: z = 2(2N - i)/(3N), sin(theta) = sqrt(9N^2 - 4(2N-i)^2)/(3N).
+         * Ring N is shifted by half a pixel like the cap rings, and the shift
+         * alternates ring by ring: phi = (pi/2)(2j + shift)/(2N). */
+        const int64_t m = 2 * n - i;
+        const double d = (double)(3 * n);
+        z = (double)(2 * m) / d;
+        st = sqrt((double)(9 * n * n - 4 * m * m)) / d;
+        const int64_t shift = ((i - n) % 2 == 0) ? 1 : 0;
+        num = 2 * j + shift;
+        den = 2 * n;
+    }
+    double cphi, sphi;
+    azimuth(num, den, &cphi, &sphi);
+    v[0] = st * cphi;
+    v[1] = st * sphi;
+    v[2] = z;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Box description.  One box is 16 doubles:                                   */
+/*   [0..2] origin (observer-relative FP64 position of the box corner that   */
+/*          x_rel is measured from), [3..5] box extent along x, y, z,        */
+/*   [6] eta_lo, [7] eta_hi (conformal-time slab of its light-cone events),  */
+/*   [8] visibility mode (0 all pixels, 1 pixels whose ray crosses the box   */
+/*       within the slab's radii, 2 pixels inside a cap),                    */
+/*   [9..11] cap centre (unit vector), [12] cosine of the cap radius.        */
+/* ------------------------------------------------------------------------ */
+enum { BOX_STRIDE = 16 };
+
+/* Does the ray t n (t >= 0) cross the closed axis-aligned box at some
+ * distance inside the slab's radii (r_lo, r_hi]? */
+static int ray_sees_box(const double n[3], const double *box, double eta0)
+{
+    const double r_lo = eta0 - box[7];
+    const double r_hi = eta0 - box[6];
+    double t_in = 0.0, t_out = INFINITY;
+    for (int k = 0; k < 3; ++k) {
+        const double lo = box[k];
+        const double hi = box[k] + box[3 + k];
+        if (n[k] == 0.0) {
+            if (lo > 0.0 || hi < 0.0) return 0;
+            continue;
+        }
+        const double ta = lo / n[k];
+        const double tb = hi / n[k];
+        const double tmin = (ta < tb) ? ta : tb;
+        const double tmax = (ta < tb) ? tb : ta;
+        if (tmin > t_in) t_in = tmin;
+        if (tmax < t_out) t_out = tmax;
+    }
+    return (t_in <= t_out) && (t_out > r_lo) && (t_in <= r_hi);
+}
+
+int oracle_pixel_sees_box(const double n[3], const double *box, double eta0)
+{
+    const int mode = (int)box[8];
+    if (mode == 0) return 1;
+    if (mode == 1) return ray_sees_box(n, box, eta0);
+    const double dot = (n[0] * box[9] + n[1] * box[10]) + n[2] * box[11];
+    return dot >= box[12];
+}
+
+/* Light-cone selection and per-segment constants of one segment.
+ * Returns 1 if the event is on the part of the past light cone the box
+ * covers (eta_lo <= eta0 - R < eta_hi with R > 0). */
+typedef struct {
+    double P[3];   /* observer-relative position */
+    double R;      /* |P| = eta0 - eta */
+    double V[3];   /* Xdot */
+    double T[3];   /* X' */
+    double eps;    /* sqrt(X'^2 / (1 - Xdot^2)) */
+    double w;      /* dsigma */
+} seg_t;
+
+static int load_segment(const double *box, double eta0, const double *x,
+                        const double *xd, const double *xp, double ds, seg_t *s)
+{
+    for (int k = 0; k < 3; ++k) {
+        s->P[k] = box[k] + x[k];
+        s->V[k] = xd[k];
+        s->T[k] = xp[k];
+    }
+    s->R = sqrt((s->P[0] * s->P[0] + s->P[1] * s->P[1]) + s->P[2] * s->P[2]);
+    const double eta = eta0 - s->R;
+    if (!(s->R > 0.0) || !(eta >= box[6]) || !(eta < box[7])) return 0;
+    const double tt = (s->T[0] * s->T[0] + s->T[1] * s->T[1]) + s->T[2] * s->T[2];
+    const double vv = (s->V[0] * s->V[0] + s->V[1] * s->V[1]) + s->V[2] * s->V[2];
+    s->eps = sqrt(tt / (1.0 - vv));
+    s->w = ds;
+    return 1;
+}
+
+int oracle_segment_kept(const double *box, double eta0, const double *x,
+                        const double *xd, const double *xp, double ds)
+{
+    seg_t s;
+    return load_segment(box, eta0, x, xd, xp, ds, &s);
+}
+
+static double dot3(const double a[3], const double b[3])
+{
+    return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2];
+}
+
+/* One term of the discrete Eq. (1) in units of GU. */
+static double term(const double n[3], const seg_t *s)
+{
+    double d[3];
+    for (int k = 0; k < 3; ++k) d[k] = s->R * n[k] - s->P[k];
+    const double q = dot3(d, d);
+    if (q == 0.0) return 0.0;
+    const double a = dot3(n, s->T);
+    const double b = 1.0 + dot3(n, s->V);
+    double u[3];
+    for (int k = 0; k < 3; ++k) u[k] = s->V[k] - (a / b) * s->T[k];
+    return -4.0 * (dot3(u, d) / q) * s->eps * s->w;
+}
+
+/* Neumaier compensated summation. */
+typedef struct { double sum, comp; } csum_t;
+static void cadd(csum_t *acc, double x)
+{
+    const double t = acc->sum + x;
+    if (fabs(acc->sum) >= fabs(x)) acc->comp += (acc->sum - t) + x;
+    else acc->comp += (x - t) + acc->sum;
+    acc->sum = t;
+}
+
+/*
+ * Theta/GU at ndir arbitrary unit directions dirs[ndir*3].
+ * Segments of box b are x_rel/xdot/xprime[3*s..], dsigma[s] for
+ * s in [seg_off[b], seg_off[b+1]).  When use_vis is non-zero each
+ * direction only receives the boxes it sees.
+ */
+void oracle_theta_dirs(int64_t ndir, const double *dirs, double eta0,
+                       int64_t nbox, const double *boxes, const int64_t *seg_off,
+                       const double *x_rel, const double *xdot, const double *xprime,
+                       const double *dsigma, int use_vis, double *out)
+{
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t p = 0; p < ndir; ++p) {
+        const double *n = dirs + 3 * p;
+        csum_t acc = {0.0, 0.0};
+        for (int64_t b = 0; b < nbox; ++b) {
+            const double *box = boxes + BOX_STRIDE * b;
+            if (use_vis && !oracle_pixel_sees_box(n, box, eta0)) continue;
+            for (int64_t i = seg_off[b]; i < seg_off[b + 1]; ++i) {
+                seg_t s;
+                if (!load_segment(box, eta0, x_rel + 3 * i, xdot + 3 * i, xprime + 3 * i,
+                                  dsigma[i], &s))
+                    continue;
+                cadd(&acc, term(n, &s));
+            }
+        }
+        out[p] = acc.sum + acc.comp;
+    }
+}
+
+/* Theta/GU at the RING pixels pix[npix_list] of an Nside map. */
+void oracle_theta_pixels(int64_t nside, int64_t nlist, const int64_t *pix, double eta0,
+                         int64_t nbox, const double *boxes, const int64_t *seg_off,
+                         const double *x_rel, const double *xdot, const double *xprime,
+                         const double *dsigma, double *out)
+{
+    double *dirs = (double *)malloc(sizeof(double) * 3 * (size_t)(nlist > 0 ? nlist : 1));
+    #pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < nlist; ++p) oracle_pix2vec(nside, pix[p], dirs + 3 * p);
+    oracle_theta_dirs(nlist, dirs, eta0, nbox, boxes, seg_off, x_rel, xdot, xprime, dsigma,
+                      1, out);
+    free(dirs);
+}
+
+void oracle_pix2vec_many(int64_t nside, int64_t nlist, const int64_t *pix, double *out)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < nlist; ++p) oracle_pix2vec(nside, pix[p], out + 3 * p);
+}
+
+void oracle_ring_many(int64_t nside, int64_t nlist, const int64_t *pix, int64_t *ring,
+                      int64_t *pos)
+{
+    for (int64_t p = 0; p < nlist; ++p) oracle_ring_of_pixel(nside, pix[p], ring + p, pos + p);
+}
+
+/* Visibility of box b for each listed pixel (1/0). */
+void oracle_visible_many(int64_t nside, int64_t nlist, const int64_t *pix, double eta0,
+                         const double *box, uint8_t *out)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < nlist; ++p) {
+        double n[3];
+        oracle_pix2vec(nside, pix[p], n);
+        out[p] = (uint8_t)oracle_pixel_sees_box(n, box, eta0);
+    }
+}
+
+/* Light-cone selection flag of each segment of one box (1/0). */
+void oracle_kept_many(int64_t nseg, const double *box, double eta0, const double *x_rel,
+                      const double *xdot, const double *xprime, const double *dsigma,
+                      uint8_t *out)
+{
+    for (int64_t i = 0; i < nseg; ++i)
+        out[i] = (uint8_t)oracle_segment_kept(box, eta0, x_rel + 3 * i, xdot + 3 * i,
+                                              xprime + 3 * i, dsigma[i]);
+}
+
+/*
+ * Gradient of sum_p g_p Theta_p/GU over the pixels pix[nlist] of an Nside map
+ * with respect to (x_rel[3], xdot[3], xprime[3], dsigma) of each listed
+ * segment sel[nsel] (global segment indices; box_of_sel[j] is its box).
+ * out[10*j + (0..9)].  Segments off the light-cone slab get zero gradient.
+ *
+ * With C = -4 eps w, d = R n - P, q = d.d, N = u.d, f = C N / q:
+ *   df/dP  = C [ ((u.n) Phat - u)/q - N (2 (d.n) Phat - 2 d)/q^2 ]
+ *            (d depends on P through R n - P, and dR/dP = Phat)
+ *   df/dV  = (C/q) [ d + (a (T.d)/b^2) n ] + f V/(1 - V^2)
+ *   df/dT  = -(C/(b q)) [ (T.d) n + a d ] + f T/T^2
+ *   df/dw  = f / w
+ * where the last terms come from eps = sqrt(T^2/(1 - V^2)).
+ */
+void oracle_grad(int64_t nside, int64_t nlist, const int64_t *pix, const double *g,
+                 double eta0, int64_t nbox, const double *boxes, const int64_t *seg_off,
+                 const double *x_rel, const double *xdot, const double *xprime,
+                 const double *dsigma, int64_t nsel, const int64_t *sel, double *out)
+{
+    double *dirs = (double *)malloc(sizeof(double) * 3 * (size_t)(nlist > 0 ? nlist : 1));
+    #pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < nlist; ++p) oracle_pix2vec(nside, pix[p], dirs + 3 * p);
+
+    /* Pixels are cut into a fixed number of chunks whose compensated partial
+     * sums are combined in chunk order, so the result is independent of the
+     * number of threads. */
+    enum { NCHUNK = 256 };
+    csum_t *part = (csum_t *)malloc(sizeof(csum_t) * 10 * NCHUNK);
+
+    for (int64_t j = 0; j < nsel; ++j) {
+        const int64_t i = sel[j];
+        int64_t b = 0;
+        while (b < nbox - 1 && seg_off[b + 1] <= i) ++b;
+        const double *box = boxes + BOX_STRIDE * b;
+        double *o = out + 10 * j;
+        for (int c = 0; c < 10; ++c) o[c] = 0.0;
+        seg_t s;
+        if (!load_segment(box, eta0, x_rel + 3 * i, xdot + 3 * i, xprime + 3 * i, dsigma[i], &s))
+            continue;
+        double Ph[3];
+        for (int k = 0; k < 3; ++k) Ph[k] = s.P[k] / s.R;
+        const double vv = dot3(s.V, s.V);
+        const double tt = dot3(s.T, s.T);
+        const double C = -4.0 * s.eps * s.w;
+        memset(part, 0, sizeof(csum_t) * 10 * NCHUNK);
+
+        #pragma omp parallel for schedule(dynamic, 1)
+        for (int ch = 0; ch < NCHUNK; ++ch) {
+            csum_t *loc = part + 10 * ch;
+            const int64_t p0 = nlist * ch / NCHUNK, p1 = nlist * (ch + 1) / NCHUNK;
+            for (int64_t p = p0; p < p1; ++p) {
+                const double *n = dirs + 3 * p;
+                if (!oracle_pixel_sees_box(n, box, eta0)) continue;
+                double d[3];
+                for (int k = 0; k < 3; ++k) d[k] = s.R * n[k] - s.P[k];
+                const double q = dot3(d, d);
+                if (q == 0.0) continue;
+                const double a = dot3(n, s.T);
+                const double bb = 1.0 + dot3(n, s.V);
+                double u[3];
+                for (int k = 0; k < 3; ++k) u[k] = s.V[k] - (a / bb) * s.T[k];
+                const double N = dot3(u, d);
+                const double f = C * N / q;
+                const double un = dot3(u, n), dn = dot3(d, n), td = dot3(s.T, d);
+                const double gp = g[p];
+                for (int k = 0; k < 3; ++k) {
+                    const double dP = C * ((un * Ph[k] - u[k]) / q
+                                           - N * (2.0 * dn * Ph[k] - 2.0 * d[k]) / (q * q));
+                    const double dV = (C / q) * (d[k] + (a * td / (bb * bb)) * n[k])
+                                      + f * s.V[k] / (1.0 - vv);
+                    const double dT = -(C / (bb * q)) * (td * n[k] + a * d[k]) + f * s.T[k] / tt;
+                    cadd(&loc[k], gp * dP);
+                    cadd(&loc[3 + k], gp * dV);
+                    cadd(&loc[6 + k], gp * dT);
+                }
+                cadd(&loc[9], gp * (f / s.w));
+            }
+        }
+        for (int c = 0; c < 10; ++c) {
+            csum_t acc = {0.0, 0.0};
+            for (int ch = 0; ch < NCHUNK; ++ch) {
+                cadd(&acc, part[10 * ch + c].sum);
+                cadd(&acc, part[10 * ch + c].comp);
+            }
+            o[c] = acc.sum + acc.comp;
+        }
+    }
+    free(part);
+    free(dirs);
+}
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

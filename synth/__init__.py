@@ -1,0 +1,217 @@
+"""Seeded synthetic workloads for the string-ISW map maker.
+
+This module only draws inputs: random string segments in boxes, box
+placements, conformal-time slabs and visibility rules.  It contains none of
+the map arithmetic and is shared, as plain input data, by the HIP library's
+tests and benchmark and by the CPU oracle.
+
+The paper's own light-cone data (Nambu-Goto simulations, Sec. II.B-C) is not
+available, so segments are drawn independently in each box, with the gauge
+conditions of Eq. (1) (transverse temporal gauge, Xdot.X' = 0) and the
+conformal normalisation Xdot^2 + X'^2 = 1, i.e. eps = 1:
+
+    x_rel  ~ U[0, side)^3                 (position inside the box)
+    s_hat  ~ uniform on S^2               (string tangent direction)
+    v_hat  ~ uniform in the plane _|_ s   (velocity direction)
+    v      ~ U(0.2, 0.8)                   (speed)
+    dsigma ~ U(0.001, 0.01)               (segment length parameter)
+    Xdot = v v_hat,   X' = sqrt(1 - v^2) s_hat
+
+drawn in that order from ``numpy.random.Generator(PCG64(seed))``.  Values are
+then stored in the precision of the workload (float64 or float32); every
+consumer reads the stored values.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+VIS_ALL, VIS_BOX, VIS_CAP = 0, 1, 2
+
+
+@dataclasses.dataclass
+class Box:
+    origin: np.ndarray            # (3,) float64, observer-relative corner of the box
+    ext: np.ndarray               # (3,) float64, box extent
+    eta_lo: float                 # conformal-time slab [eta_lo, eta_hi)
+    eta_hi: float
+    x_rel: np.ndarray             # (n,3) position relative to origin
+    xdot: np.ndarray              # (n,3)
+    xprime: np.ndarray            # (n,3)
+    dsigma: np.ndarray            # (n,)
+    vis: int = VIS_ALL
+    cap_dir: Optional[np.ndarray] = None   # (3,) unit vector for VIS_CAP
+    cap_cos: Optional[float] = None        # cosine of the cap radius for VIS_CAP
+    seed: Optional[int] = None
+
+    @property
+    def n(self) -> int:
+        return int(self.dsigma.shape[0])
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    nside: int
+    eta0: float
+    boxes: list
+    gu: float = 1e-7
+
+    @property
+    def npix(self) -> int:
+        return 12 * self.nside * self.nside
+
+
+def _unit_rows(a: np.ndarray) -> np.ndarray:
+    return a / np.linalg.norm(a, axis=1, keepdims=True)
+
+
+def segments(n: int, seed: int, dtype=np.float64, side: float = 1.0):
+    """Draw n segments with the recipe in the module docstring."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = rng.random((n, 3)) * side
+    s_hat = _unit_rows(rng.standard_normal((n, 3)))
+    g = rng.standard_normal((n, 3))
+    g = g - np.sum(g * s_hat, axis=1, keepdims=True) * s_hat
+    v_hat = _unit_rows(g)
+    v = rng.uniform(0.2, 0.8, n)
+    ds = rng.uniform(0.001, 0.01, n)
+    xdot = v[:, None] * v_hat
+    xprime = np.sqrt(1.0 - v * v)[:, None] * s_hat
+    cast = lambda a: np.ascontiguousarray(a.astype(dtype))
+    return cast(x), cast(xdot), cast(xprime), cast(ds)
+
+
+def make_box(n: int, seed: int, origin, eta_lo: float, eta_hi: float, dtype=np.float64,
+             side: float = 1.0, vis: int = VIS_ALL, cap_dir=None, cap_cos=None) -> Box:
+    x, xd, xp, ds = segments(n, seed, dtype, side)
+    return Box(origin=np.asarray(origin, dtype=np.float64), ext=np.full(3, float(side)),
+               eta_lo=float(eta_lo), eta_hi=float(eta_hi), x_rel=x, xdot=xd, xprime=xp,
+               dsigma=ds, vis=vis,
+               cap_dir=None if cap_dir is None else np.asarray(cap_dir, dtype=np.float64),
+               cap_cos=None if cap_cos is None else float(cap_cos), seed=seed)
+
+
+def uniform_directions(n: int, seed: int) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return _unit_rows(rng.standard_normal((n, 3)))
+
+
+def sample_pixels(npix: int, count: int, seed: int) -> np.ndarray:
+    """Sorted distinct pixel indices drawn uniformly."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    count = min(count, npix)
+    return np.sort(rng.choice(npix, size=count, replace=False)).astype(np.int64)
+
+
+# ----------------------------------------------------------------------------
+# The five benchmark workloads.  Geometry the task description leaves open is
+# fixed here once (box placement, slabs, eta0) so every consumer agrees.
+# ----------------------------------------------------------------------------
+
+def config0() -> Workload:
+    """Plain FP64: Nside=64, one unit box centred on the observer, 2,000
+    segments (seed 0), eta0 = 1 and slab [0, 1) so every segment is kept."""
+    box = make_box(2000, 0, origin=(-0.5, -0.5, -0.5), eta_lo=0.0, eta_hi=1.0,
+                   dtype=np.float64)
+    return Workload("config0: Nside=64, 1 box x 2,000 segments, FP64", 64, 1.0, [box], 1e-7)
+
+
+def shell24_centres() -> np.ndarray:
+    """The 24 integer points whose coordinates are a permutation of (0, +-1, +-2)."""
+    pts = set()
+    for a in (1, -1):
+        for b in (2, -2):
+            for perm in ((0, a, b), (0, b, a), (a, 0, b), (a, b, 0), (b, 0, a), (b, a, 0)):
+                pts.add(perm)
+    return np.array(sorted(pts), dtype=np.float64)
+
+
+def config1(nseg: int = 100_000, nside: int = 512) -> Workload:
+    """Plain vs FP32: Nside=512, 24 unit boxes tiling a shell at distance
+    sqrt(5) (centres = permutations of (0, +-1, +-2)), 100,000 FP32 segments
+    each (box b uses seed b+1), eta0 = 3 with slab [0.4, 1.1) (radii
+    (1.9, 2.6]); a pixel sees a box when its ray crosses it within the slab."""
+    boxes = []
+    for b, c in enumerate(shell24_centres()):
+        boxes.append(make_box(nseg, b + 1, origin=c - 0.5, eta_lo=0.4, eta_hi=1.1,
+                              dtype=np.float32, vis=VIS_BOX))
+    return Workload(f"config1: Nside={nside}, 24 shell boxes x {nseg:,} segments, FP32",
+                    nside, 3.0, boxes, 1e-7)
+
+
+def config2_geometry(nbox: int = 64):
+    """Box origins for the Nside=2048 throughput workload: box b's nearest
+    distance is r_b = 0.1 * 140^(b/63) Gpc along a direction drawn uniformly
+    (seed 99); its centre sits at (r_b + sqrt(3)/2) d_b."""
+    dirs = uniform_directions(64, 99)
+    out = []
+    for b in range(nbox):
+        r = 0.1 * 140.0 ** (b / 63.0)
+        centre = (r + math.sqrt(3.0) / 2.0) * dirs[b]
+        out.append(centre - 0.5)
+    return out
+
+
+def config2_box(b: int, nseg: int = 400_000) -> Box:
+    origin = config2_geometry()[b]
+    return make_box(nseg, 100 + b, origin=origin, eta_lo=0.0, eta_hi=16.0, dtype=np.float32)
+
+
+def config2(boxes=range(64), nseg: int = 400_000, nside: int = 2048) -> Workload:
+    """FP32 throughput: Nside=2048, 64 boxes of side 1 Gpc at 0.1-14 Gpc,
+    400,000 FP32 segments each (seeds 100-163), eta0 = 16 Gpc, slab [0, 16)
+    (every segment kept), every pixel sees every box."""
+    bl = [config2_box(b, nseg) for b in boxes]
+    return Workload(f"config2: Nside={nside}, boxes {list(boxes)[:4]}... x {nseg:,} segments",
+                    nside, 16.0, bl, 1e-7)
+
+
+def config3_geometry(nbox: int = 256):
+    rng = np.random.Generator(np.random.PCG64(399))
+    g = rng.standard_normal(nbox)
+    counts = np.clip(np.round(50_000 * np.exp(1.0 * g)), 1_000, 2_000_000).astype(np.int64)
+    r = np.exp(rng.uniform(math.log(0.1), math.log(14.0), nbox))
+    dirs = _unit_rows(rng.standard_normal((nbox, 3)))
+    frac = np.exp(rng.uniform(math.log(0.001), math.log(0.05), nbox))
+    return counts, r, dirs, frac
+
+
+def config3(nbox: int = 256, nside: int = 4096, count_scale: float = 1.0) -> Workload:
+    """Batched uneven: 256 boxes, lognormal segment counts (median 50,000,
+    sigma 1, clipped to [1,000, 2,000,000]), distances log-uniform in
+    [0.1, 14] Gpc, each box seen by a cap of sky fraction f_b log-uniform in
+    [0.1%, 5%] around its direction (cos rho = 1 - 2 f_b); FP32 segments
+    (seeds 400-655)."""
+    counts, r, dirs, frac = config3_geometry(256)
+    boxes = []
+    for b in range(nbox):
+        n = max(1, int(round(counts[b] * count_scale)))
+        centre = (r[b] + math.sqrt(3.0) / 2.0) * dirs[b]
+        boxes.append(make_box(n, 400 + b, origin=centre - 0.5, eta_lo=0.0, eta_hi=16.0,
+                              dtype=np.float32, vis=VIS_CAP, cap_dir=dirs[b],
+                              cap_cos=1.0 - 2.0 * frac[b]))
+    return Workload(f"config3: Nside={nside}, {nbox} uneven boxes, FP32", nside, 16.0, boxes,
+                    1e-7)
+
+
+def config4(nseg: int = 50_000, nside: int = 1024, nbox: int = 8) -> Workload:
+    """Differentiation: Nside=1024, 8 boxes x 50,000 FP32 segments (seeds
+    200-207) at 1..8 Gpc along directions drawn with seed 208."""
+    dirs = uniform_directions(8, 208)
+    boxes = []
+    for b in range(nbox):
+        centre = (float(b + 1) + math.sqrt(3.0) / 2.0) * dirs[b]
+        boxes.append(make_box(nseg, 200 + b, origin=centre - 0.5, eta_lo=0.0, eta_hi=16.0,
+                              dtype=np.float32))
+    return Workload(f"config4: Nside={nside}, {nbox} boxes x {nseg:,} segments", nside, 16.0,
+                    boxes, 1e-7)
+
+
+def config4_weights(npix: int) -> np.ndarray:
+    """Gaussian pixel weights w_p of the loss L = sum_p w_p Theta_p^2 (seed 209)."""
+    rng = np.random.Generator(np.random.PCG64(209))
+    return rng.standard_normal(npix)
