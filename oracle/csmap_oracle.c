@@ -25,6 +25,10 @@
  *     with R = |P| (the non-bold X of Eq. (1)), each pixel sampled at its
  *     centre (Sec. III.B: each pixel represents the signal in its centroid
  *     direction).  A term whose |R n - P|^2 is exactly zero contributes 0.
+ *     P is the FP64 sum origin + x_rel and R the FP64 square root of the
+ *     FP64 sum of squares (these are the inputs of the sum); R n - P is
+ *     formed with one rounding, so each term is accurate to a few units in
+ *     the last place even for events a tiny angle off the line of sight.
  *   - The gradient of a linear functional sum_p g_p Theta_p with respect to
  *     every segment's (x_rel, Xdot, X', dsigma), by the chain rule applied to
  *     the same expression (the paper does not differentiate; this is the
@@ -271,8 +275,11 @@ static double dot3(const double a[3], const double b[3])
 /* One term of the discrete Eq. (1) in units of GU. */
 static double term(const double n[3], const seg_t *s)
 {
+    /* R n - P with a single rounding: for an event close to the line of
+     * sight the two terms nearly cancel, and a separately rounded product
+     * would leave an error of order eps R in a vector of length ~R theta. */
     double d[3];
-    for (int k = 0; k < 3; ++k) d[k] = s->R * n[k] - s->P[k];
+    for (int k = 0; k < 3; ++k) d[k] = fma(s->R, n[k], -s->P[k]);
     const double q = dot3(d, d);
     if (q == 0.0) return 0.0;
     const double a = dot3(n, s->T);
@@ -424,7 +431,7 @@ void oracle_grad(int64_t nside, int64_t nlist, const int64_t *pix, const double 
                 const double *n = dirs + 3 * p;
                 if (!oracle_pixel_sees_box(n, box, eta0)) continue;
                 double d[3];
-                for (int k = 0; k < 3; ++k) d[k] = s.R * n[k] - s.P[k];
+                for (int k = 0; k < 3; ++k) d[k] = fma(s.R, n[k], -s.P[k]);
                 const double q = dot3(d, d);
                 if (q == 0.0) continue;
                 const double a = dot3(n, s.T);

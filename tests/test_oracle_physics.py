@@ -355,3 +355,37 @@ def test_gradient_against_finite_differences():
     assert np.all(G[~kept] == 0.0)
     scale = np.max(np.abs(fd[kept]))
     assert np.max(np.abs(G[kept] - fd[kept])) <= 1e-6 * scale, np.max(np.abs(G - fd)) / scale
+
+
+@pytest.mark.parametrize("theta", [1e-2, 1e-4, 1e-6, 1e-8, 1e-9])
+def test_single_term_accuracy_near_line_of_sight(theta):
+    """One term of Eq. (1)-(2) for an event at angle theta from the direction,
+    against 50-digit arithmetic on the same FP64 inputs (P, and R formed as
+    the FP64 root of the FP64 sum of squares): accurate to ~1e-14 for every
+    theta."""
+    import mpmath as mp
+    mp.mp.dps = 50
+    rng = np.random.default_rng(int(-math.log10(theta)))
+    n = rng.standard_normal(3)
+    n /= np.linalg.norm(n)
+    perp = np.cross(n, rng.standard_normal(3))
+    perp /= np.linalg.norm(perp)
+    R0 = 1.7
+    P = R0 * (math.cos(theta) * n + math.sin(theta) * perp)
+    x, xd, xp, ds = synth.segments(1, 3, np.float64)
+    box = _box(P[None, :], xd, xp, ds)
+    got = oracle.theta_dirs(n[None, :], 10.0, [box])[0]
+    R = math.sqrt((P[0] * P[0] + P[1] * P[1]) + P[2] * P[2])
+    mn = [mp.mpf(float(v)) for v in n]
+    mP = [mp.mpf(float(v)) for v in P]
+    mR = mp.mpf(R)
+    V = [mp.mpf(float(v)) for v in xd[0]]
+    T = [mp.mpf(float(v)) for v in xp[0]]
+    d = [mR * mn[k] - mP[k] for k in range(3)]
+    q = sum(v * v for v in d)
+    a = sum(mn[k] * T[k] for k in range(3))
+    b = 1 + sum(mn[k] * V[k] for k in range(3))
+    u = [V[k] - a / b * T[k] for k in range(3)]
+    eps = mp.sqrt(sum(t * t for t in T) / (1 - sum(v * v for v in V)))
+    exact = -4 * sum(u[k] * d[k] for k in range(3)) / q * eps * mp.mpf(float(ds[0]))
+    assert abs(got - float(exact)) <= 1e-14 * abs(float(exact)), (got, float(exact))
