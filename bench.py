@@ -1,0 +1,169 @@
+"""Benchmark of the all-sky string ISW map maker on one MI355X.
+
+Workload (the Nside=2048 throughput case): HEALPix Nside=2048 (50,331,648
+RING pixels), boxes of 400,000 FP32 segments (box b: seed 100+b, side 1 Gpc,
+nearest distance 0.1 * 140^(b/63) Gpc, eta0 = 16 Gpc, every segment kept,
+every pixel sees every box).  One step renders the full sky from one box
+(2.01e13 pixel-segment pairs): the light-cone precompute kernels and the
+pair kernel, FP32C form.  Step k uses box W+k (warm-up steps use boxes
+0..W-1), so every timed step works on fresh data already resident in HBM.
+
+Printed: one JSON line with pairs/s of the FP32C form, the FP64 form's
+pairs/s on one box, the forward kernel's achieved FLOP/s against the FP32
+vector peak (36 algorithmic FLOP per pair), and the FP64 CPU oracle timed on
+a sample of the same workload on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pixel-segment pairs/s (FP32 vs FP64, Nside=2048) + % of VALU peak"
+FLOP_PER_PAIR = 36          # algorithmic count of one Eq. (1) term
+FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector peak
+FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector peak
+NSIDE = 2048
+NSEG = 400_000
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_sky(B, torch, b, form, nseg, nside):
+    import synth
+    box = synth.config2_box(b, nseg)
+    sky = B.Sky(nside, 16.0, form)
+    t = [torch.from_numpy(np.ascontiguousarray(a)).cuda()
+         for a in (box.x_rel, box.xdot, box.xprime, box.dsigma)]
+    sky.add_box(*t, origin=tuple(box.origin), eta_lo=box.eta_lo, eta_hi=box.eta_hi)
+    return sky, box
+
+
+def cpu_baseline(box, nside, npix_sample, seed=98):
+    import oracle
+    import synth
+    pix = synth.sample_pixels(12 * nside * nside, npix_sample, seed=seed)
+    t0 = time.perf_counter()
+    oracle.theta_pixels(nside, pix, 16.0, [box])
+    dt = time.perf_counter() - t0
+    pairs = len(pix) * box.n
+    return {"value": pairs / dt, "unit": "pairs/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{len(pix)} random pixels x box 0 ({box.n:,} segments) at Nside={nside}: "
+                      f"{pairs:.3e} pairs in {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nseg", type=int, default=NSEG)
+    ap.add_argument("--nside", type=int, default=NSIDE)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-pixels", type=int, default=6000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU layout is described, not run).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1204_5041_amd import binding as B
+    assert torch.cuda.is_available(), "no GPU visible"
+
+    W, K = args.warmup, args.steps
+    _log(f"bench: generating {W + K} boxes of {args.nseg:,} segments")
+    skies = [make_sky(B, torch, b, B.CSMAP_FORM_FP32C, args.nseg, args.nside) for b in range(W + K)]
+    npix = 12 * args.nside * args.nside
+    maps = torch.empty(npix, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+
+    for i in range(W):
+        _log(f"bench: warm-up step {i}")
+        skies[i][0].render(maps)
+    torch.cuda.synchronize()
+
+    fwd_ms, pairs = [], 0
+    t0 = time.perf_counter()
+    for k in range(K):
+        sky = skies[W + k][0]
+        sky.render(maps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for k in range(K):
+        st = skies[W + k][0].stats()
+        fwd_ms.append(st["ms_forward"])
+        pairs += st["pairs"]
+        _log(f"bench: step {k} box {W + k}: pairs={st['pairs']} forward {st['ms_forward']:.1f} ms "
+             f"precompute {st['ms_precompute']:.2f} ms near_steps={st['near_steps']}")
+    value = pairs / elapsed
+    kern_s = float(np.mean(fwd_ms)) / 1e3
+    pairs_per_step = pairs / K
+    achieved = FLOP_PER_PAIR * pairs_per_step / kern_s / 1e12
+    cfg = {k: v for k, v in skies[W][0].stats().items()
+           if k in ("pix_per_lane", "waves", "schedule", "graph", "chunk", "near_w")}
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": elapsed * 1e3 / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"Nside={args.nside} full sky, one box of {args.nseg:,} FP32 "
+                               f"segments per step (boxes of the 64-box 0.1-14 Gpc "
+                               f"throughput set), FP32C form",
+                   "nside": args.nside, "segments_per_step": args.nseg,
+                   "pairs_per_step": pairs_per_step, "tile": cfg},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "k_fwd32", "kernel_ms": kern_s * 1e3,
+                     "flop_per_pair": FLOP_PER_PAIR},
+    }
+    del skies
+    torch.cuda.synchronize()
+
+    if not args.no_fp64:
+        _log("bench: FP64 form, one box")
+        sky64, _ = make_sky(B, torch, 0, B.CSMAP_FORM_FP64, args.nseg, args.nside)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sky64.render(maps)
+        torch.cuda.synchronize()
+        e64 = time.perf_counter() - t0
+        st = sky64.stats()
+        v64 = st["pairs"] / e64
+        a64 = FLOP_PER_PAIR * st["pairs"] / (st["ms_forward"] / 1e3) / 1e12
+        out["fp64"] = {"value": v64, "unit": "pairs/s", "ms_per_step": e64 * 1e3,
+                       "kernel_ms": st["ms_forward"], "achieved_tflops": a64,
+                       "frac_fp64_peak": a64 / FP64_PEAK_TFLOPS}
+        out["speedup_fp32_over_fp64"] = value / v64
+        sky64.close()
+
+    if not args.no_cpu:
+        import synth
+        _log("bench: CPU oracle baseline")
+        box0 = synth.config2_box(0, args.nseg)
+        out["cpu_baseline"] = cpu_baseline(box0, args.nside, args.cpu_pixels)
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

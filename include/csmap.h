@@ -1,0 +1,228 @@
+/*
+ * csmap.h -- C ABI of libcsmap, the MI355X (gfx950) implementation of the
+ * all-sky string integrated Sachs-Wolfe map maker of Ringeval & Bouchet.
+ *
+ * The problem (paper Sec. II.A, Eq. (1)-(2), and Sec. III opening
+ * paragraph): simulations record, for every Nambu-Goto string segment on the
+ * observer's past light cone, its position X, velocity Xdot, tangent X' and
+ * length element dsigma.  The map value in direction n is
+ *
+ *   Theta(n) = -4 GU sum_s  u.(R n - X)/|R n - X|^2 * eps * dsigma,
+ *   u = Xdot - (n.X') X' / (1 + n.Xdot),   eps^2 = X'^2 / (1 - Xdot^2),
+ *
+ * summed over every segment of every box (no cut, Sec. II.A), with R = |X|
+ * the observer-relative distance of the event and n the centre of a HEALPix
+ * RING pixel (Sec. II.D).  Maps of disjoint sets of boxes add (Sec. III.A:
+ * the final map is the sum of full-sky maps from subsets of cones).  The
+ * library returns Theta/GU; multiply by GU to obtain Theta = Delta T / T.
+ *
+ * Coordinates: the observer sits at the origin at conformal time eta0.  A
+ * segment of a box at position x_rel (relative to the box's origin) has the
+ * observer-relative position P = origin + x_rel (formed in FP64 on the
+ * device), lies on the past light cone at eta = eta0 - |P| (gauge
+ * X^0 = eta = tau, footnote of Sec. II.A), and enters the map only when
+ * eta_lo <= eta < eta_hi (the conformal-time slab the box covers).
+ *
+ * Conventions of every entry point:
+ *   - Array arguments are device pointers (memory from hipMalloc or a torch
+ *     CUDA tensor) unless stated otherwise, row-major, naturally aligned.
+ *   - Work is enqueued asynchronously on the HIP stream given at sky creation
+ *     (NULL = the default stream); the caller synchronises that stream
+ *     before reading results.  add_box copies the segment arrays on that
+ *     stream, so the caller may free them once the stream has passed the copy.
+ *   - Every call returns a csmap_status; on failure csmap_last_error() gives
+ *     a message (thread-local, valid until the next call on that thread).
+ *     Argument errors are detected on the host before any device work and
+ *     leave the sky unchanged.  A HIP failure returns CSMAP_E_DEVICE and
+ *     marks the sky failed: later calls on it return CSMAP_E_STATE.
+ *   - A sky is not thread-safe: use one sky per thread.
+ *   - Physical preconditions (|Xdot| < 1, |X'| > 0, no straight static string,
+ *     Sec. II.A) are the caller's; they are documented, not checked.
+ */
+#ifndef CSMAP_H
+#define CSMAP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct csmap_sky csmap_sky;
+
+typedef enum {
+    CSMAP_OK = 0,
+    CSMAP_E_INVALID = -1,      /* bad argument; nothing was changed */
+    CSMAP_E_NOMEM = -2,        /* device or host allocation failed */
+    CSMAP_E_DEVICE = -3,       /* a HIP call failed; the sky is now unusable */
+    CSMAP_E_STATE = -4,        /* call not valid in the sky's current state */
+    CSMAP_E_UNSUPPORTED = -5   /* valid request this build does not provide */
+} csmap_status;
+
+/* Arithmetic form of the pair evaluation.
+ *   CSMAP_FORM_FP64  : every step in FP64, directions differenced in FP64.
+ *   CSMAP_FORM_FP32C : light-cone geometry (P = origin + x_rel, |P|, the slab
+ *                      test, unit vectors) in FP64; the pair arithmetic in
+ *                      FP32, with the direction difference R(n - P/R) taken
+ *                      in FP64 for pairs closer than a threshold angle (see
+ *                      CSMAP_OPT_NEAR_W); per-pixel sums in FP32 with Kahan
+ *                      compensation; the map written as FP64. */
+typedef enum { CSMAP_FORM_FP64 = 0, CSMAP_FORM_FP32C = 1 } csmap_form;
+
+/* Element type of segment arrays passed to csmap_add_box. */
+typedef enum { CSMAP_F32 = 0, CSMAP_F64 = 1 } csmap_dtype;
+
+/* Which pixels receive a box's segments.
+ *   CSMAP_VIS_ALL : every pixel (the paper's rule: no cut, Sec. II.A).
+ *   CSMAP_VIS_BOX : pixels whose ray t n (t >= 0) crosses the closed box
+ *                   [origin, origin + ext] at a distance inside the slab's
+ *                   radii (eta0 - eta_hi, eta0 - eta_lo].
+ *   CSMAP_VIS_CAP : pixels with n . cap_dir >= cap_cos.
+ * The last two restrict the sum to a subset of the sky; they exist to shape
+ * workloads (they are not part of the paper's method). */
+typedef enum { CSMAP_VIS_ALL = 0, CSMAP_VIS_BOX = 1, CSMAP_VIS_CAP = 2 } csmap_vis;
+
+/* One simulation box of light-cone events. */
+typedef struct {
+    int64_t n;              /* number of segments, >= 0 */
+    csmap_dtype dtype;      /* type of the four arrays below */
+    const void *x_rel;      /* n x 3: position relative to origin */
+    const void *xdot;       /* n x 3: Xdot, worldsheet velocity dX/dtau */
+    const void *xprime;     /* n x 3: X', worldsheet tangent dX/dsigma */
+    const void *dsigma;     /* n: worldsheet length parameter of the segment */
+    double origin[3];       /* observer-relative position x_rel is measured from */
+    double ext[3];          /* box extent (used by CSMAP_VIS_BOX), each > 0 */
+    double eta_lo, eta_hi;  /* conformal-time slab [eta_lo, eta_hi), eta_lo < eta_hi */
+    csmap_vis vis;          /* pixel visibility rule */
+    double cap_dir[3];      /* CSMAP_VIS_CAP: cap centre, a unit vector, used as given */
+    double cap_cos;         /* CSMAP_VIS_CAP: cosine of the cap radius, in [-1, 1] */
+} csmap_box;
+
+/* Caller-owned FP64 gradient outputs for one box (device pointers, same
+ * shapes as the box's inputs).  Any pointer may be NULL to skip it. */
+typedef struct {
+    double *x_rel;          /* n x 3: dL/dx_rel (equal to dL/dP) */
+    double *xdot;           /* n x 3: dL/dXdot */
+    double *xprime;         /* n x 3: dL/dX' */
+    double *dsigma;         /* n: dL/ddsigma */
+} csmap_grad;
+
+/* Tunables (csmap_set_option).  Values are doubles; integers are rounded. */
+typedef enum {
+    /* Launch schedule of render/backward:
+     *   0 = one launch, one wavefront per pixel tile, tiles in RING order;
+     *   1 = one persistent launch whose wavefronts pull tiles, most expensive
+     *       first, from a device work counter;
+     *   2 = one launch per box (each box accumulates into the map). */
+    CSMAP_OPT_SCHEDULE = 0,
+    /* 1 = capture render's launches in a hipGraph and replay it while the sky
+     * and the output pointer are unchanged; 0 = plain launches. */
+    CSMAP_OPT_GRAPH = 1,
+    /* Pixels per lane of the forward kernels: 1, 2, 4 or 8.  A tile is
+     * 64 x this many consecutive RING pixels, owned by one wavefront. */
+    CSMAP_OPT_PIX_PER_LANE = 2,
+    /* Wavefronts per workgroup: 1, 2, 4 or 8. */
+    CSMAP_OPT_WAVES = 3,
+    /* FP32C form: pairs with 1 - n.P/R below this value (default 5e-3, an
+     * angle of about 0.1 rad) take the FP64 direction difference; the others
+     * use the algebraically equal FP32 form built from 1 - n.P/R.  A value
+     * >= 2 sends every pair through the FP64 difference. */
+    CSMAP_OPT_NEAR_W = 4,
+    /* Segments per FP32 partial sum before the Kahan-compensated update of a
+     * pixel's running sum (FP32C form): 8 .. 4096. */
+    CSMAP_OPT_CHUNK = 5,
+    /* Adjoint: number of pixel chunks each segment's sum is split into
+     * (0 = chosen by the library). */
+    CSMAP_OPT_ADJ_SPLIT = 6
+} csmap_option;
+
+/* Counters of the last render/backward (csmap_get_stats synchronises). */
+typedef struct {
+    int64_t nside, npix, nbox;
+    int64_t segments;          /* segments added */
+    int64_t kept;              /* segments inside their box's light-cone slab */
+    int64_t pairs;             /* (visible pixel, kept segment) pairs evaluated */
+    int64_t near_steps;        /* FP32C: (wavefront, segment) steps that took the FP64 path */
+    double ms_precompute;      /* device time of the light-cone / record kernels */
+    double ms_forward;         /* device time of the pair kernel of the last render */
+    double ms_backward;        /* device time of the adjoint kernels of the last backward */
+    int64_t pix_per_lane, waves, schedule, graph, chunk;
+    double near_w;
+} csmap_stats;
+
+/* Number of pixels of an Nside map, 12 Nside^2 (Sec. II.D); -1 if Nside is
+ * outside [1, 8192]. */
+int64_t csmap_npix(int64_t nside);
+
+/* Create a sky of 12 Nside^2 RING pixels observed at conformal time eta0,
+ * evaluated in the given form, enqueuing work on hip_stream (a hipStream_t,
+ * NULL for the default stream).  Nside in [1, 8192].  *out receives a handle
+ * owned by the caller until csmap_destroy_sky. */
+csmap_status csmap_create_sky(int64_t nside, double eta0, csmap_form form, void *hip_stream,
+                              csmap_sky **out);
+
+/* Add one box of light-cone events (Sec. II.B-C: the events a simulation
+ * recorded; Sec. III: events in, map out).  The arrays are copied into
+ * library-owned device memory; box_id (may be NULL) receives the box's index
+ * (0, 1, ... in call order). */
+csmap_status csmap_add_box(csmap_sky *sky, const csmap_box *box, int64_t *box_id);
+
+/* Evaluate Theta/GU (Eq. (1)) at every RING pixel centre from all boxes
+ * added so far and write it to map (device, 12 Nside^2 doubles, RING order).
+ * Each pixel's value is its own sum; results are deterministic for a given
+ * sky and options. */
+csmap_status csmap_render(csmap_sky *sky, double *map);
+
+/* Adjoint of render: given dmap = dL/d(Theta_p/GU) (device, npix doubles),
+ * write dL/d(x_rel, xdot, xprime, dsigma) of every segment of box b into
+ * grads[b] for b = 0 .. nbox-1 (nbox must equal the number of boxes).
+ * Segments outside their slab get zero gradient.  The paper does not
+ * differentiate Eq. (1); this is its exact derivative. */
+csmap_status csmap_backward(csmap_sky *sky, const double *dmap, const csmap_grad *grads,
+                            int64_t nbox);
+
+/* Drop all boxes (device memory is kept for reuse). */
+csmap_status csmap_reset(csmap_sky *sky);
+
+/* Free the sky and everything it owns.  NULL is accepted. */
+csmap_status csmap_destroy_sky(csmap_sky *sky);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *csmap_last_error(void);
+
+/* Write the unit vectors of RING pixels first .. first+count-1 of an Nside
+ * map (Sec. II.D; HEALPix definition of Gorski et al. 2005, cited in the
+ * paper) to xyz (device, count x 3 doubles), enqueued on hip_stream.  The
+ * same device routine supplies the ray directions of render/backward. */
+csmap_status csmap_pix2vec_ring(int64_t nside, int64_t first, int64_t count, double *xyz,
+                                void *hip_stream);
+
+/* Set a tunable (see csmap_option).  Invalidates any captured graph. */
+csmap_status csmap_set_option(csmap_sky *sky, csmap_option opt, double value);
+
+/* Counters and timings of the last render/backward; synchronises the stream. */
+csmap_status csmap_get_stats(csmap_sky *sky, csmap_stats *out);
+
+/* Time the forward kernel over a grid of tile shapes on this sky's boxes and
+ * keep the fastest (pixels per lane, waves per workgroup, schedule).  If
+ * cache_path is not NULL the choice is read from / appended to that text
+ * file, keyed by device name, form, Nside and workload shape.  Writes to
+ * scratch memory only; synchronises the stream. */
+csmap_status csmap_autotune(csmap_sky *sky, const char *cache_path);
+
+/* Host-side helper, no device work: the RING pixel tiles of `tile` pixels
+ * that may contain pixels within angle rho (radians) of the unit vector
+ * (cx, cy, cz) at Nside.  Writes up to max_ranges [first, last] tile index
+ * pairs (inclusive, ascending, disjoint) to ranges and their number to
+ * *n_ranges; returns CSMAP_E_INVALID if max_ranges is too small (with
+ * *n_ranges set to the number needed).  The result is conservative: it may
+ * include tiles with no such pixel, never omits one. */
+csmap_status csmap_cap_tiles(int64_t nside, int64_t tile, double cx, double cy, double cz,
+                             double rho, int64_t *ranges, int64_t max_ranges,
+                             int64_t *n_ranges);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CSMAP_H */

@@ -1,0 +1,302 @@
+"""ctypes binding of libcsmap (include/csmap.h).
+
+Argument marshalling only: every step of the map computation runs in the HIP
+library.  The functions ``csmap_*`` mirror the C entry points one to one;
+:class:`Sky` is a small convenience wrapper that takes torch CUDA tensors
+(PyTorch supplies device memory and the stream, nothing else).
+
+Importing this module loads ``libcsmap.so`` built in-tree; it raises if the
+library is missing.  There is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcsmap.so")
+
+CSMAP_OK, CSMAP_E_INVALID, CSMAP_E_NOMEM, CSMAP_E_DEVICE, CSMAP_E_STATE, CSMAP_E_UNSUPPORTED = \
+    0, -1, -2, -3, -4, -5
+CSMAP_FORM_FP64, CSMAP_FORM_FP32C = 0, 1
+CSMAP_F32, CSMAP_F64 = 0, 1
+CSMAP_VIS_ALL, CSMAP_VIS_BOX, CSMAP_VIS_CAP = 0, 1, 2
+(CSMAP_OPT_SCHEDULE, CSMAP_OPT_GRAPH, CSMAP_OPT_PIX_PER_LANE, CSMAP_OPT_WAVES, CSMAP_OPT_NEAR_W,
+ CSMAP_OPT_CHUNK, CSMAP_OPT_ADJ_SPLIT) = range(7)
+
+_STATUS_NAMES = {0: "CSMAP_OK", -1: "CSMAP_E_INVALID", -2: "CSMAP_E_NOMEM", -3: "CSMAP_E_DEVICE",
+                 -4: "CSMAP_E_STATE", -5: "CSMAP_E_UNSUPPORTED"}
+
+EXPORTED = ["csmap_npix", "csmap_create_sky", "csmap_add_box", "csmap_render", "csmap_backward",
+            "csmap_reset", "csmap_destroy_sky", "csmap_last_error", "csmap_pix2vec_ring",
+            "csmap_set_option", "csmap_get_stats", "csmap_autotune", "csmap_cap_tiles"]
+
+
+class csmap_box(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("dtype", ctypes.c_int), ("x_rel", ctypes.c_void_p),
+                ("xdot", ctypes.c_void_p), ("xprime", ctypes.c_void_p),
+                ("dsigma", ctypes.c_void_p), ("origin", ctypes.c_double * 3),
+                ("ext", ctypes.c_double * 3), ("eta_lo", ctypes.c_double),
+                ("eta_hi", ctypes.c_double), ("vis", ctypes.c_int),
+                ("cap_dir", ctypes.c_double * 3), ("cap_cos", ctypes.c_double)]
+
+
+class csmap_grad(ctypes.Structure):
+    _fields_ = [("x_rel", ctypes.c_void_p), ("xdot", ctypes.c_void_p),
+                ("xprime", ctypes.c_void_p), ("dsigma", ctypes.c_void_p)]
+
+
+class csmap_stats(ctypes.Structure):
+    _fields_ = [("nside", ctypes.c_int64), ("npix", ctypes.c_int64), ("nbox", ctypes.c_int64),
+                ("segments", ctypes.c_int64), ("kept", ctypes.c_int64), ("pairs", ctypes.c_int64),
+                ("near_steps", ctypes.c_int64), ("ms_precompute", ctypes.c_double),
+                ("ms_forward", ctypes.c_double), ("ms_backward", ctypes.c_double),
+                ("pix_per_lane", ctypes.c_int64), ("waves", ctypes.c_int64),
+                ("schedule", ctypes.c_int64), ("graph", ctypes.c_int64), ("chunk", ctypes.c_int64),
+                ("near_w", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class CsmapError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"libcsmap is not built ({path} missing); run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    vp, i64, dbl, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    lib.csmap_npix.argtypes = [i64]
+    lib.csmap_npix.restype = i64
+    lib.csmap_create_sky.argtypes = [i64, dbl, i32, vp, ctypes.POINTER(vp)]
+    lib.csmap_add_box.argtypes = [vp, ctypes.POINTER(csmap_box), ctypes.POINTER(i64)]
+    lib.csmap_render.argtypes = [vp, vp]
+    lib.csmap_backward.argtypes = [vp, vp, ctypes.POINTER(csmap_grad), i64]
+    lib.csmap_reset.argtypes = [vp]
+    lib.csmap_destroy_sky.argtypes = [vp]
+    lib.csmap_last_error.restype = ctypes.c_char_p
+    lib.csmap_pix2vec_ring.argtypes = [i64, i64, i64, vp, vp]
+    lib.csmap_set_option.argtypes = [vp, i32, dbl]
+    lib.csmap_get_stats.argtypes = [vp, ctypes.POINTER(csmap_stats)]
+    lib.csmap_autotune.argtypes = [vp, ctypes.c_char_p]
+    lib.csmap_cap_tiles.argtypes = [i64, i64, dbl, dbl, dbl, dbl, ctypes.POINTER(i64), i64,
+                                    ctypes.POINTER(i64)]
+    for name in EXPORTED:
+        if name not in ("csmap_npix", "csmap_last_error"):
+            getattr(lib, name).restype = i32
+    return lib
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        _lib = load_library()
+    return _lib
+
+
+def _check(status: int):
+    if status != CSMAP_OK:
+        raise CsmapError(status, lib().csmap_last_error().decode())
+
+
+# ---- one-to-one wrappers of the C entry points -------------------------------
+
+def csmap_npix(nside: int) -> int:
+    return int(lib().csmap_npix(nside))
+
+
+def csmap_create_sky(nside: int, eta0: float, form: int, stream: int | None) -> int:
+    out = ctypes.c_void_p()
+    _check(lib().csmap_create_sky(nside, eta0, form, stream or None, ctypes.byref(out)))
+    return out.value
+
+
+def csmap_add_box(sky: int, box: csmap_box) -> int:
+    bid = ctypes.c_int64()
+    _check(lib().csmap_add_box(sky, ctypes.byref(box), ctypes.byref(bid)))
+    return bid.value
+
+
+def csmap_render(sky: int, map_ptr: int):
+    _check(lib().csmap_render(sky, map_ptr))
+
+
+def csmap_backward(sky: int, dmap_ptr: int, grads: list):
+    arr = (csmap_grad * max(len(grads), 1))(*grads)
+    _check(lib().csmap_backward(sky, dmap_ptr, arr, len(grads)))
+
+
+def csmap_reset(sky: int):
+    _check(lib().csmap_reset(sky))
+
+
+def csmap_destroy_sky(sky: int):
+    _check(lib().csmap_destroy_sky(sky))
+
+
+def csmap_last_error() -> str:
+    return lib().csmap_last_error().decode()
+
+
+def csmap_pix2vec_ring(nside: int, first: int, count: int, xyz_ptr: int, stream: int | None):
+    _check(lib().csmap_pix2vec_ring(nside, first, count, xyz_ptr, stream or None))
+
+
+def csmap_set_option(sky: int, opt: int, value: float):
+    _check(lib().csmap_set_option(sky, opt, float(value)))
+
+
+def csmap_get_stats(sky: int) -> dict:
+    st = csmap_stats()
+    _check(lib().csmap_get_stats(sky, ctypes.byref(st)))
+    return st.as_dict()
+
+
+def csmap_autotune(sky: int, cache_path: str | None):
+    _check(lib().csmap_autotune(sky, cache_path.encode() if cache_path else None))
+
+
+def csmap_cap_tiles(nside: int, tile: int, c, rho: float, max_ranges: int = 1 << 16):
+    buf = (ctypes.c_int64 * (2 * max_ranges))()
+    n = ctypes.c_int64()
+    _check(lib().csmap_cap_tiles(nside, tile, float(c[0]), float(c[1]), float(c[2]), float(rho),
+                                 buf, max_ranges, ctypes.byref(n)))
+    return [(buf[2 * i], buf[2 * i + 1]) for i in range(n.value)]
+
+
+# ---- torch-facing convenience wrapper ---------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_ptr(t) -> int:
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+class Sky:
+    """A HEALPix RING sky of Theta/GU owned by libcsmap.
+
+    Segment tensors must be CUDA tensors of one dtype (float32 or float64):
+    x_rel, xdot, xprime of shape (n, 3) and dsigma of shape (n,)."""
+
+    def __init__(self, nside: int, eta0: float, form: int = CSMAP_FORM_FP32C, stream=None):
+        torch = _torch()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.nside = int(nside)
+        self.npix = csmap_npix(self.nside)
+        self.eta0 = float(eta0)
+        self.form = form
+        self.handle = csmap_create_sky(self.nside, self.eta0, form, self.stream.cuda_stream)
+        self._keep = []           # tensors whose copy may still be in flight
+        self.box_shapes = []
+        self.box_dtypes = []
+
+    def add_box(self, x_rel, xdot, xprime, dsigma, origin, eta_lo, eta_hi,
+                vis=CSMAP_VIS_ALL, ext=(1.0, 1.0, 1.0), cap_dir=(0.0, 0.0, 1.0), cap_cos=-1.0):
+        torch = _torch()
+        dt = x_rel.dtype
+        if dt not in (torch.float32, torch.float64):
+            raise TypeError("segment tensors must be float32 or float64")
+        n = int(dsigma.shape[0])
+        for t, shape in ((x_rel, (n, 3)), (xdot, (n, 3)), (xprime, (n, 3)), (dsigma, (n,))):
+            if tuple(t.shape) != shape or t.dtype != dt:
+                raise ValueError("segment tensors must share a dtype with shapes (n,3)x3 and (n,)")
+        b = csmap_box()
+        b.n = n
+        b.dtype = CSMAP_F32 if dt == torch.float32 else CSMAP_F64
+        if n:
+            b.x_rel, b.xdot, b.xprime, b.dsigma = (_dev_ptr(x_rel), _dev_ptr(xdot),
+                                                   _dev_ptr(xprime), _dev_ptr(dsigma))
+        b.origin = (ctypes.c_double * 3)(*[float(v) for v in origin])
+        b.ext = (ctypes.c_double * 3)(*[float(v) for v in ext])
+        b.eta_lo, b.eta_hi = float(eta_lo), float(eta_hi)
+        b.vis = int(vis)
+        b.cap_dir = (ctypes.c_double * 3)(*[float(v) for v in cap_dir])
+        b.cap_cos = float(cap_cos)
+        bid = csmap_add_box(self.handle, b)
+        self._keep.append((x_rel, xdot, xprime, dsigma))
+        self.box_shapes.append(n)
+        self.box_dtypes.append(dt)
+        return bid
+
+    def render(self, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty(self.npix, dtype=torch.float64, device="cuda")
+        if out.dtype != torch.float64 or out.numel() != self.npix:
+            raise ValueError("map must be a float64 tensor of npix elements")
+        csmap_render(self.handle, _dev_ptr(out))
+        return out
+
+    def backward(self, dmap, grads=None):
+        """dL/d(x_rel, xdot, xprime, dsigma) of every box (float64 tensors)."""
+        torch = _torch()
+        if dmap.dtype != torch.float64 or dmap.numel() != self.npix:
+            raise ValueError("dmap must be a float64 tensor of npix elements")
+        if grads is None:
+            grads = []
+            for n in self.box_shapes:
+                grads.append(tuple(torch.empty(s, dtype=torch.float64, device="cuda")
+                                   for s in ((n, 3), (n, 3), (n, 3), (n,))))
+        gs = []
+        for g in grads:
+            gs.append(csmap_grad(*[(_dev_ptr(t) if t is not None and t.numel() else None)
+                                   for t in g]))
+        csmap_backward(self.handle, _dev_ptr(dmap.contiguous()), gs)
+        return grads
+
+    def set_option(self, opt, value):
+        csmap_set_option(self.handle, opt, value)
+
+    def stats(self) -> dict:
+        return csmap_get_stats(self.handle)
+
+    def autotune(self, cache_path=None):
+        csmap_autotune(self.handle, cache_path)
+
+    def reset(self):
+        csmap_reset(self.handle)
+        self._keep.clear()
+        self.box_shapes.clear()
+        self.box_dtypes.clear()
+
+    def synchronize(self):
+        self.stream.synchronize()
+        self._keep.clear()
+
+    def close(self):
+        if self.handle:
+            csmap_destroy_sky(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pix2vec_ring(nside: int, first: int = 0, count: int | None = None):
+    """Pixel-centre unit vectors from the device routine (float64, (count, 3))."""
+    torch = _torch()
+    npix = csmap_npix(nside)
+    if count is None:
+        count = npix - first
+    out = torch.empty((count, 3), dtype=torch.float64, device="cuda")
+    csmap_pix2vec_ring(nside, first, count, _dev_ptr(out), torch.cuda.current_stream().cuda_stream)
+    return out

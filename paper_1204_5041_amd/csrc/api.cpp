@@ -1,0 +1,822 @@
+// api.cpp -- the C ABI of libcsmap (include/csmap.h): sky state, argument
+// validation, device memory, launch planning, graph capture and tuning.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <fstream>
+#include <numeric>
+#include <sstream>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/csmap.h"
+#include "internal.h"
+#include "sched.h"
+
+namespace csmap {
+hipError_t launch_precompute(const PreArgs& A, int64_t nbox, hipStream_t st);
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
+hipError_t launch_zero_counters(unsigned long long* c, int n, uint32_t* work, hipStream_t st);
+hipError_t launch_pix2vec(int64_t nside, int64_t first, int64_t count, double* xyz,
+                          hipStream_t st);
+hipError_t launch_forward(bool fp64, int K, bool persistent, const FwdArgs& A, unsigned grid,
+                          unsigned block, hipStream_t st);
+hipError_t launch_pixtab(int64_t nside, int64_t npix, const double* dmap, float* tab32,
+                         double* tab64, hipStream_t st);
+hipError_t launch_adjoint(const AdjArgs& A, hipStream_t st);
+hipError_t launch_adj_finalize(const DevBox* boxes, const DevBoxCount* counts, int32_t b,
+                               int64_t nseg, const char* raw, const int32_t* orig_index,
+                               const double* phat64, const double* partial, int32_t nsplit,
+                               double* gx, double* gxd, double* gxp, double* gds,
+                               hipStream_t st);
+}  // namespace csmap
+
+using namespace csmap;
+
+namespace {
+
+thread_local std::string g_err;
+
+csmap_status fail(csmap_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+// Device allocation that only grows; contents are not preserved on growth.
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  hipError_t ensure(size_t bytes) {
+    if (bytes <= cap) return hipSuccess;
+    if (p) {
+      hipError_t e = hipFree(p);
+      p = nullptr;
+      cap = 0;
+      if (e != hipSuccess) return e;
+    }
+    size_t want = std::max<size_t>(bytes, 256);
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    cap = want;
+    return hipSuccess;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  template <class T>
+  T* as() const { return (T*)p; }
+};
+
+struct HostBox {
+  HostBoxGeom geom;
+  int dtype;
+  int64_t n;
+  int64_t raw_byte_off;
+};
+
+}  // namespace
+
+struct csmap_sky {
+  int64_t nside = 0, npix = 0;
+  double eta0 = 0.0;
+  csmap_form form = CSMAP_FORM_FP32C;
+  hipStream_t stream = nullptr;
+  bool failed = false;
+
+  // options
+  int K = 4;
+  int waves = 4;
+  int schedule = 0;
+  int graph = 0;
+  int chunk = 32;
+  double near_w = 5e-3;
+  int adj_split = 0;
+
+  // boxes and raw segment storage (append-only)
+  std::vector<HostBox> boxes;
+  DevBuf raw;
+  size_t raw_used = 0;
+  int64_t total_seg = 0;
+
+  // derived device state, rebuilt when `dirty`
+  bool dirty = true;
+  int planned_K = -1;
+  DevBuf d_boxes, d_blk_box, d_blk_count, d_blk_prefix, d_box_count, d_raw_off;
+  DevBuf d_rec32, d_phat64, d_rec64, d_orig;
+  DevBuf d_tile_ptr, d_tile_boxes, d_items, d_box_items;
+  std::vector<int64_t> box_items_off;  // per box offset into d_box_items (+ end)
+  int64_t nblk = 0;
+  int64_t ntiles = 0;
+  int64_t nitems_sorted = 0;
+  bool all_boxes = true;
+  DevBuf d_counters;  // [0] pairs, [1] near steps, [2] work counter (uint32)
+
+  // adjoint scratch
+  DevBuf d_pixtab32, d_pix64, d_partial, d_adj_items;
+
+  // graph
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph_h = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  double* graph_map = nullptr;
+  uint64_t graph_version = ~0ull;
+  uint64_t version = 1;
+
+  // timing
+  hipEvent_t ev[6] = {};
+  double ms_pre = 0, ms_fwd = 0, ms_bwd = 0;
+  bool have_fwd_time = false, have_bwd_time = false;
+  bool timed_graph = false;
+};
+
+namespace {
+
+csmap_status dev_fail(csmap_sky* s, hipError_t e, const char* what) {
+  if (s) s->failed = true;
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(e == hipErrorOutOfMemory ? CSMAP_E_NOMEM : CSMAP_E_DEVICE, m);
+}
+
+#define HIPCHK(sky, call, what)                         \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return dev_fail(sky, e_, what); \
+  } while (0)
+
+csmap_status check_sky(csmap_sky* s) {
+  if (!s) return fail(CSMAP_E_INVALID, "sky is NULL");
+  if (s->failed) return fail(CSMAP_E_STATE, "sky is unusable after an earlier device error");
+  return CSMAP_OK;
+}
+
+void drop_graph(csmap_sky* s) {
+  if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
+  if (s->graph_h) (void)hipGraphDestroy(s->graph_h);
+  s->graph_exec = nullptr;
+  s->graph_h = nullptr;
+  s->graph_version = ~0ull;
+  s->graph_map = nullptr;
+}
+
+int64_t tile_pixels(const csmap_sky* s) { return 64 * (int64_t)s->K; }
+
+// Rebuild descriptors, compaction tables, record storage and the tile plan.
+csmap_status prepare(csmap_sky* s) {
+  if (!s->dirty && s->planned_K == s->K) return CSMAP_OK;
+  const int64_t nbox = (int64_t)s->boxes.size();
+  hipStream_t st = s->stream;
+  // Box descriptors and precompute blocks.
+  std::vector<DevBox> db(nbox);
+  std::vector<int32_t> blk_box;
+  std::vector<int64_t> raw_off(nbox);
+  int64_t rec = 0;
+  for (int64_t b = 0; b < nbox; ++b) {
+    const HostBox& h = s->boxes[b];
+    DevBox& d = db[b];
+    memset(&d, 0, sizeof(d));
+    for (int k = 0; k < 3; ++k) {
+      d.origin[k] = h.geom.origin[k];
+      d.ext[k] = h.geom.ext[k];
+      d.cap_dir[k] = h.geom.cap_dir[k];
+    }
+    d.eta_lo = h.geom.eta_lo;
+    d.eta_hi = h.geom.eta_hi;
+    d.cap_cos = h.geom.cap_cos;
+    d.vis = h.geom.vis;
+    d.dtype = h.dtype;
+    d.n = h.n;
+    d.raw_off = 0;
+    d.rec_off = rec;
+    d.blk_off = (int64_t)blk_box.size();
+    const int64_t nb = (h.n + kPreBlock - 1) / kPreBlock;
+    for (int64_t k = 0; k < nb; ++k) blk_box.push_back((int32_t)b);
+    raw_off[b] = h.raw_byte_off;
+    rec += h.n;
+  }
+  s->nblk = (int64_t)blk_box.size();
+  const int64_t nrec = std::max<int64_t>(rec, 1);
+  HIPCHK(s, s->d_boxes.ensure(sizeof(DevBox) * std::max<int64_t>(nbox, 1)), "alloc boxes");
+  HIPCHK(s, s->d_blk_box.ensure(sizeof(int32_t) * std::max<int64_t>(s->nblk, 1)), "alloc blocks");
+  HIPCHK(s, s->d_blk_count.ensure(sizeof(int32_t) * std::max<int64_t>(s->nblk, 1)), "alloc blocks");
+  HIPCHK(s, s->d_blk_prefix.ensure(sizeof(int64_t) * std::max<int64_t>(s->nblk, 1)), "alloc blocks");
+  HIPCHK(s, s->d_box_count.ensure(sizeof(DevBoxCount) * std::max<int64_t>(nbox, 1)), "alloc counts");
+  HIPCHK(s, s->d_raw_off.ensure(sizeof(int64_t) * std::max<int64_t>(nbox, 1)), "alloc offsets");
+  HIPCHK(s, s->d_orig.ensure(sizeof(int32_t) * nrec), "alloc records");
+  if (s->form == CSMAP_FORM_FP32C) {
+    HIPCHK(s, s->d_rec32.ensure(sizeof(float) * kRec32 * nrec), "alloc records");
+    HIPCHK(s, s->d_phat64.ensure(sizeof(double) * 4 * nrec), "alloc records");
+  } else {
+    HIPCHK(s, s->d_rec64.ensure(sizeof(double) * kRec64 * nrec), "alloc records");
+    HIPCHK(s, s->d_phat64.ensure(sizeof(double) * 4 * nrec), "alloc records");
+  }
+  HIPCHK(s, s->d_counters.ensure(64), "alloc counters");
+  if (nbox) {
+    HIPCHK(s, hipMemcpyAsync(s->d_boxes.p, db.data(), sizeof(DevBox) * nbox,
+                             hipMemcpyHostToDevice, st), "upload boxes");
+    HIPCHK(s, hipMemcpyAsync(s->d_raw_off.p, raw_off.data(), sizeof(int64_t) * nbox,
+                             hipMemcpyHostToDevice, st), "upload offsets");
+  }
+  if (s->nblk)
+    HIPCHK(s, hipMemcpyAsync(s->d_blk_box.p, blk_box.data(), sizeof(int32_t) * s->nblk,
+                             hipMemcpyHostToDevice, st), "upload blocks");
+
+  // Tile plan.
+  const int64_t tile = tile_pixels(s);
+  s->ntiles = (s->npix + tile - 1) / tile;
+  s->all_boxes = true;
+  for (auto& h : s->boxes)
+    if (h.geom.vis != 0) s->all_boxes = false;
+  std::vector<std::vector<std::pair<int64_t, int64_t>>> ranges(nbox);
+  std::vector<int64_t> cnt(s->ntiles + 1, 0);
+  std::vector<double> cost(s->ntiles, 0.0);
+  for (int64_t b = 0; b < nbox; ++b) {
+    box_tiles(s->nside, tile, s->boxes[b].geom, s->eta0, ranges[b]);
+    for (auto& r : ranges[b])
+      for (int64_t t = r.first; t <= r.second; ++t) {
+        cnt[t + 1] += 1;
+        cost[t] += (double)s->boxes[b].n;
+      }
+  }
+  std::vector<int32_t> tile_ptr(s->ntiles + 1, 0), tile_boxes;
+  if (!s->all_boxes) {
+    for (int64_t t = 0; t < s->ntiles; ++t) tile_ptr[t + 1] = (int32_t)(tile_ptr[t] + cnt[t + 1]);
+    tile_boxes.resize(std::max<int64_t>(tile_ptr[s->ntiles], 1));
+    std::vector<int32_t> fillp(tile_ptr.begin(), tile_ptr.end() - 1);
+    for (int64_t b = 0; b < nbox; ++b)
+      for (auto& r : ranges[b])
+        for (int64_t t = r.first; t <= r.second; ++t) tile_boxes[fillp[t]++] = (int32_t)b;
+    HIPCHK(s, s->d_tile_ptr.ensure(sizeof(int32_t) * tile_ptr.size()), "alloc tiles");
+    HIPCHK(s, s->d_tile_boxes.ensure(sizeof(int32_t) * tile_boxes.size()), "alloc tiles");
+    HIPCHK(s, hipMemcpyAsync(s->d_tile_ptr.p, tile_ptr.data(), sizeof(int32_t) * tile_ptr.size(),
+                             hipMemcpyHostToDevice, st), "upload tiles");
+    HIPCHK(s, hipMemcpyAsync(s->d_tile_boxes.p, tile_boxes.data(),
+                             sizeof(int32_t) * tile_boxes.size(), hipMemcpyHostToDevice, st),
+           "upload tiles");
+  }
+  // Persistent schedule: tiles ordered by decreasing work.
+  std::vector<int32_t> order(s->ntiles);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+  s->nitems_sorted = s->ntiles;
+  HIPCHK(s, s->d_items.ensure(sizeof(int32_t) * std::max<int64_t>(s->ntiles, 1)), "alloc items");
+  HIPCHK(s, hipMemcpyAsync(s->d_items.p, order.data(), sizeof(int32_t) * s->ntiles,
+                           hipMemcpyHostToDevice, st), "upload items");
+  // Per-box schedule: the tiles of each box.
+  std::vector<int32_t> bitems;
+  s->box_items_off.assign(nbox + 1, 0);
+  for (int64_t b = 0; b < nbox; ++b) {
+    for (auto& r : ranges[b])
+      for (int64_t t = r.first; t <= r.second; ++t) bitems.push_back((int32_t)t);
+    s->box_items_off[b + 1] = (int64_t)bitems.size();
+  }
+  HIPCHK(s, s->d_box_items.ensure(sizeof(int32_t) * std::max<size_t>(bitems.size(), 1)),
+         "alloc items");
+  if (!bitems.empty())
+    HIPCHK(s, hipMemcpyAsync(s->d_box_items.p, bitems.data(), sizeof(int32_t) * bitems.size(),
+                             hipMemcpyHostToDevice, st), "upload items");
+  // Host staging vectors go out of scope below: wait for the copies.
+  HIPCHK(s, hipStreamSynchronize(st), "upload plan");
+  s->dirty = false;
+  s->planned_K = s->K;
+  return CSMAP_OK;
+}
+
+PreArgs pre_args(csmap_sky* s) {
+  PreArgs A;
+  memset(&A, 0, sizeof(A));
+  A.boxes = s->d_boxes.as<DevBox>();
+  A.blk_box = s->d_blk_box.as<int32_t>();
+  A.nblk = s->nblk;
+  A.raw = s->raw.p;
+  A.raw_byte_off = s->d_raw_off.as<int64_t>();
+  A.eta0 = s->eta0;
+  A.blk_count = s->d_blk_count.as<int32_t>();
+  A.blk_prefix = s->d_blk_prefix.as<int64_t>();
+  A.box_count = s->d_box_count.as<DevBoxCount>();
+  if (s->form == CSMAP_FORM_FP32C) {
+    A.rec32 = s->d_rec32.as<float>();
+  } else {
+    A.rec64 = s->d_rec64.as<double>();
+  }
+  A.phat64 = s->d_phat64.as<double>();
+  A.orig_index = s->d_orig.as<int32_t>();
+  return A;
+}
+
+FwdArgs fwd_args(csmap_sky* s, double* map) {
+  FwdArgs A;
+  memset(&A, 0, sizeof(A));
+  A.boxes = s->d_boxes.as<DevBox>();
+  A.box_count = s->d_box_count.as<DevBoxCount>();
+  A.nbox = (int32_t)s->boxes.size();
+  A.all_boxes = s->all_boxes ? 1 : 0;
+  A.tile_ptr = s->d_tile_ptr.as<int32_t>();
+  A.tile_boxes = s->d_tile_boxes.as<int32_t>();
+  A.items = nullptr;
+  A.nitems = s->ntiles;
+  A.work_counter = (uint32_t*)(s->d_counters.as<unsigned long long>() + 2);
+  A.nside = s->nside;
+  A.npix = s->npix;
+  A.eta0 = s->eta0;
+  A.rec32 = s->d_rec32.as<float>();
+  A.phat64 = s->d_phat64.as<double>();
+  A.rec64 = s->d_rec64.as<double>();
+  A.near_w = (float)s->near_w;
+  A.chunk = s->chunk;
+  A.accumulate = 0;
+  A.only_box = -1;
+  A.map = map;
+  A.pairs = s->d_counters.as<unsigned long long>();
+  A.near_steps = s->d_counters.as<unsigned long long>() + 1;
+  return A;
+}
+
+unsigned persistent_grid(const csmap_sky* s) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  int cus = 256;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  // Enough resident wavefronts to fill every SIMD several times over.
+  const int waves_per_cu = (s->form == CSMAP_FORM_FP64) ? 16 : 24;
+  return (unsigned)std::max(1, cus * waves_per_cu / s->waves);
+}
+
+// Enqueue the whole render on stream st (no synchronisation, no events).
+csmap_status enqueue_render(csmap_sky* s, double* map, hipStream_t st, bool with_events) {
+  const bool fp64 = s->form == CSMAP_FORM_FP64;
+  const PreArgs P = pre_args(s);
+  if (with_events) HIPCHK(s, hipEventRecord(s->ev[0], st), "event");
+  HIPCHK(s, launch_precompute(P, (int64_t)s->boxes.size(), st), "precompute launch");
+  HIPCHK(s, launch_zero_counters(s->d_counters.as<unsigned long long>(), 2,
+                                 (uint32_t*)(s->d_counters.as<unsigned long long>() + 2), st),
+         "counter reset");
+  if (with_events) HIPCHK(s, hipEventRecord(s->ev[1], st), "event");
+  FwdArgs A = fwd_args(s, map);
+  const unsigned block = 64u * (unsigned)s->waves;
+  if (s->schedule == 2) {
+    HIPCHK(s, launch_fill(map, s->npix, 0.0, st), "map clear");
+    A.accumulate = 1;
+    for (int64_t b = 0; b < (int64_t)s->boxes.size(); ++b) {
+      const int64_t n = s->box_items_off[b + 1] - s->box_items_off[b];
+      if (n == 0 || s->boxes[b].n == 0) continue;
+      A.only_box = (int32_t)b;
+      A.items = s->d_box_items.as<int32_t>() + s->box_items_off[b];
+      A.nitems = n;
+      const unsigned grid = (unsigned)((n + s->waves - 1) / s->waves);
+      HIPCHK(s, launch_forward(fp64, s->K, false, A, grid, block, st), "forward launch");
+    }
+  } else if (s->schedule == 1) {
+    A.items = s->d_items.as<int32_t>();
+    A.nitems = s->nitems_sorted;
+    HIPCHK(s, launch_forward(fp64, s->K, true, A, persistent_grid(s), block, st),
+           "forward launch");
+  } else {
+    const unsigned grid = (unsigned)((s->ntiles + s->waves - 1) / s->waves);
+    HIPCHK(s, launch_forward(fp64, s->K, false, A, grid, block, st), "forward launch");
+  }
+  if (with_events) HIPCHK(s, hipEventRecord(s->ev[2], st), "event");
+  return CSMAP_OK;
+}
+
+bool valid_pow_choice(int v) { return v == 1 || v == 2 || v == 4 || v == 8; }
+
+size_t dtype_size(int dt) { return dt == CSMAP_F32 ? 4 : 8; }
+
+}  // namespace
+
+extern "C" {
+
+int64_t csmap_npix(int64_t nside) {
+  if (nside < 1 || nside > kMaxNside) return -1;
+  return 12 * nside * nside;
+}
+
+const char* csmap_last_error(void) { return g_err.c_str(); }
+
+csmap_status csmap_create_sky(int64_t nside, double eta0, csmap_form form, void* hip_stream,
+                              csmap_sky** out) {
+  g_err.clear();
+  if (!out) return fail(CSMAP_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (nside < 1 || nside > kMaxNside)
+    return fail(CSMAP_E_INVALID, "nside must be in [1, 8192]");
+  if (!isfinite(eta0)) return fail(CSMAP_E_INVALID, "eta0 must be finite");
+  if (form != CSMAP_FORM_FP64 && form != CSMAP_FORM_FP32C)
+    return fail(CSMAP_E_INVALID, "unknown form");
+  csmap_sky* s = new (std::nothrow) csmap_sky();
+  if (!s) return fail(CSMAP_E_NOMEM, "host allocation failed");
+  s->nside = nside;
+  s->npix = 12 * nside * nside;
+  s->eta0 = eta0;
+  s->form = form;
+  s->stream = (hipStream_t)hip_stream;
+  s->chunk = (form == CSMAP_FORM_FP64) ? 64 : 32;
+  if (form == CSMAP_FORM_FP64) s->K = 2;
+  for (auto& e : s->ev) {
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) {
+      csmap_destroy_sky(s);
+      return dev_fail(nullptr, r, "event create");
+    }
+  }
+  hipError_t r = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking);
+  if (r != hipSuccess) {
+    csmap_destroy_sky(s);
+    return dev_fail(nullptr, r, "stream create");
+  }
+  *out = s;
+  return CSMAP_OK;
+}
+
+csmap_status csmap_destroy_sky(csmap_sky* s) {
+  g_err.clear();
+  if (!s) return CSMAP_OK;
+  if (s->stream || s->cap_stream) (void)hipDeviceSynchronize();
+  drop_graph(s);
+  for (auto& e : s->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+  DevBuf* bufs[] = {&s->raw, &s->d_boxes, &s->d_blk_box, &s->d_blk_count, &s->d_blk_prefix,
+                    &s->d_box_count, &s->d_raw_off, &s->d_rec32, &s->d_phat64, &s->d_rec64,
+                    &s->d_orig, &s->d_tile_ptr, &s->d_tile_boxes, &s->d_items,
+                    &s->d_box_items, &s->d_counters, &s->d_pixtab32, &s->d_pix64,
+                    &s->d_partial, &s->d_adj_items};
+  for (DevBuf* b : bufs) b->release();
+  delete s;
+  return CSMAP_OK;
+}
+
+csmap_status csmap_add_box(csmap_sky* s, const csmap_box* box, int64_t* box_id) {
+  g_err.clear();
+  csmap_status cs = check_sky(s);
+  if (cs != CSMAP_OK) return cs;
+  if (!box) return fail(CSMAP_E_INVALID, "box is NULL");
+  if (box->n < 0) return fail(CSMAP_E_INVALID, "segment count must be >= 0");
+  if (box->n > (int64_t)INT32_MAX) return fail(CSMAP_E_INVALID, "at most 2^31-1 segments per box");
+  if (box->dtype != CSMAP_F32 && box->dtype != CSMAP_F64)
+    return fail(CSMAP_E_INVALID, "unknown dtype");
+  if (box->n > 0 && (!box->x_rel || !box->xdot || !box->xprime || !box->dsigma))
+    return fail(CSMAP_E_INVALID, "segment array pointer is NULL");
+  for (int k = 0; k < 3; ++k)
+    if (!isfinite(box->origin[k]) || !isfinite(box->ext[k]))
+      return fail(CSMAP_E_INVALID, "origin and ext must be finite");
+  if (!isfinite(box->eta_lo) || !isfinite(box->eta_hi) || !(box->eta_lo < box->eta_hi))
+    return fail(CSMAP_E_INVALID, "slab must satisfy eta_lo < eta_hi (finite)");
+  if (box->vis != CSMAP_VIS_ALL && box->vis != CSMAP_VIS_BOX && box->vis != CSMAP_VIS_CAP)
+    return fail(CSMAP_E_INVALID, "unknown visibility rule");
+  if (box->vis == CSMAP_VIS_BOX)
+    for (int k = 0; k < 3; ++k)
+      if (!(box->ext[k] > 0.0)) return fail(CSMAP_E_INVALID, "ext must be > 0 for CSMAP_VIS_BOX");
+  if (box->vis == CSMAP_VIS_CAP) {
+    const double nn = box->cap_dir[0] * box->cap_dir[0] + box->cap_dir[1] * box->cap_dir[1] +
+                      box->cap_dir[2] * box->cap_dir[2];
+    if (!(fabs(nn - 1.0) < 1e-9)) return fail(CSMAP_E_INVALID, "cap_dir must be a unit vector");
+    if (!(box->cap_cos >= -1.0 && box->cap_cos <= 1.0))
+      return fail(CSMAP_E_INVALID, "cap_cos must be in [-1, 1]");
+  }
+  const size_t es = dtype_size(box->dtype);
+  const size_t nbytes = es * 10 * (size_t)box->n;
+  // Grow raw storage (geometrically), preserving what is there.
+  const size_t need = s->raw_used + ((nbytes + 255) & ~(size_t)255);
+  if (need > s->raw.cap) {
+    size_t want = std::max(need, s->raw.cap + s->raw.cap / 2);
+    void* np = nullptr;
+    hipError_t e = hipMalloc(&np, want);
+    if (e != hipSuccess) return fail(CSMAP_E_NOMEM, "device allocation of segment storage failed");
+    if (s->raw_used) {
+      HIPCHK(s, hipMemcpyAsync(np, s->raw.p, s->raw_used, hipMemcpyDeviceToDevice, s->stream),
+             "grow storage");
+      HIPCHK(s, hipStreamSynchronize(s->stream), "grow storage");
+    }
+    if (s->raw.p) (void)hipFree(s->raw.p);
+    s->raw.p = np;
+    s->raw.cap = want;
+  }
+  char* dst = (char*)s->raw.p + s->raw_used;
+  const size_t n3 = es * 3 * (size_t)box->n;
+  if (box->n > 0) {
+    HIPCHK(s, hipMemcpyAsync(dst, box->x_rel, n3, hipMemcpyDefault, s->stream), "copy x_rel");
+    HIPCHK(s, hipMemcpyAsync(dst + n3, box->xdot, n3, hipMemcpyDefault, s->stream), "copy xdot");
+    HIPCHK(s, hipMemcpyAsync(dst + 2 * n3, box->xprime, n3, hipMemcpyDefault, s->stream),
+           "copy xprime");
+    HIPCHK(s, hipMemcpyAsync(dst + 3 * n3, box->dsigma, es * (size_t)box->n, hipMemcpyDefault,
+                             s->stream), "copy dsigma");
+  }
+  HostBox h;
+  for (int k = 0; k < 3; ++k) {
+    h.geom.origin[k] = box->origin[k];
+    h.geom.ext[k] = box->ext[k];
+    h.geom.cap_dir[k] = box->cap_dir[k];
+  }
+  h.geom.eta_lo = box->eta_lo;
+  h.geom.eta_hi = box->eta_hi;
+  h.geom.vis = (int)box->vis;
+  h.geom.cap_cos = box->cap_cos;
+  h.dtype = (int)box->dtype;
+  h.n = box->n;
+  h.raw_byte_off = (int64_t)s->raw_used;
+  s->raw_used = need;
+  s->boxes.push_back(h);
+  s->total_seg += box->n;
+  s->dirty = true;
+  s->version++;
+  if (box_id) *box_id = (int64_t)s->boxes.size() - 1;
+  return CSMAP_OK;
+}
+
+csmap_status csmap_reset(csmap_sky* s) {
+  g_err.clear();
+  csmap_status cs = check_sky(s);
+  if (cs != CSMAP_OK) return cs;
+  HIPCHK(s, hipStreamSynchronize(s->stream), "reset");
+  s->boxes.clear();
+  s->raw_used = 0;
+  s->total_seg = 0;
+  s->dirty = true;
+  s->version++;
+  drop_graph(s);
+  return CSMAP_OK;
+}
+
+csmap_status csmap_set_option(csmap_sky* s, csmap_option opt, double value) {
+  g_err.clear();
+  csmap_status cs = check_sky(s);
+  if (cs != CSMAP_OK) return cs;
+  if (!isfinite(value)) return fail(CSMAP_E_INVALID, "option value must be finite");
+  const int iv = (int)lround(value);
+  switch (opt) {
+    case CSMAP_OPT_SCHEDULE:
+      if (iv < 0 || iv > 2) return fail(CSMAP_E_INVALID, "schedule must be 0, 1 or 2");
+      s->schedule = iv;
+      break;
+    case CSMAP_OPT_GRAPH:
+      if (iv < 0 || iv > 1) return fail(CSMAP_E_INVALID, "graph must be 0 or 1");
+      s->graph = iv;
+      break;
+    case CSMAP_OPT_PIX_PER_LANE:
+      if (!valid_pow_choice(iv)) return fail(CSMAP_E_INVALID, "pixels per lane must be 1, 2, 4 or 8");
+      s->K = iv;
+      break;
+    case CSMAP_OPT_WAVES:
+      if (!valid_pow_choice(iv)) return fail(CSMAP_E_INVALID, "waves must be 1, 2, 4 or 8");
+      s->waves = iv;
+      break;
+    case CSMAP_OPT_NEAR_W:
+      if (!(value >= 0.0)) return fail(CSMAP_E_INVALID, "near threshold must be >= 0");
+      s->near_w = value;
+      break;
+    case CSMAP_OPT_CHUNK:
+      if (iv < 8 || iv > 4096) return fail(CSMAP_E_INVALID, "chunk must be in [8, 4096]");
+      s->chunk = iv;
+      break;
+    case CSMAP_OPT_ADJ_SPLIT:
+      if (iv < 0 || iv > 4096) return fail(CSMAP_E_INVALID, "split must be in [0, 4096]");
+      s->adj_split = iv;
+      break;
+    default:
+      return fail(CSMAP_E_INVALID, "unknown option");
+  }
+  s->version++;
+  drop_graph(s);
+  return CSMAP_OK;
+}
+
+csmap_status csmap_render(csmap_sky* s, double* map) {
+  g_err.clear();
+  csmap_status cs = check_sky(s);
+  if (cs != CSMAP_OK) return cs;
+  if (!map) return fail(CSMAP_E_INVALID, "map is NULL");
+  cs = prepare(s);
+  if (cs != CSMAP_OK) return cs;
+  if (s->graph) {
+    if (!s->graph_exec || s->graph_map != map || s->graph_version != s->version) {
+      drop_graph(s);
+      HIPCHK(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal),
+             "begin capture");
+      cs = enqueue_render(s, map, s->cap_stream, false);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
+      if (cs != CSMAP_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return cs;
+      }
+      if (e != hipSuccess) return dev_fail(s, e, "end capture");
+      s->graph_h = g;
+      HIPCHK(s, hipGraphInstantiate(&s->graph_exec, g, nullptr, nullptr, 0), "instantiate graph");
+      s->graph_map = map;
+      s->graph_version = s->version;
+    }
+    HIPCHK(s, hipEventRecord(s->ev[0], s->stream), "event");
+    HIPCHK(s, hipGraphLaunch(s->graph_exec, s->stream), "graph launch");
+    HIPCHK(s, hipEventRecord(s->ev[2], s->stream), "event");
+    s->timed_graph = true;
+  } else {
+    cs = enqueue_render(s, map, s->stream, true);
+    if (cs != CSMAP_OK) return cs;
+    s->timed_graph = false;
+  }
+  s->have_fwd_time = true;
+  return CSMAP_OK;
+}
+
+csmap_status csmap_backward(csmap_sky* s, const double* dmap, const csmap_grad* grads,
+                            int64_t nbox) {
+  g_err.clear();
+  csmap_status cs = check_sky(s);
+  if (cs != CSMAP_OK) return cs;
+  if (!dmap) return fail(CSMAP_E_INVALID, "dmap is NULL");
+  if (nbox != (int64_t)s->boxes.size())
+    return fail(CSMAP_E_INVALID, "nbox must equal the number of boxes");
+  if (nbox > 0 && !grads) return fail(CSMAP_E_INVALID, "grads is NULL");
+  if (s->form != CSMAP_FORM_FP32C)
+    return fail(CSMAP_E_UNSUPPORTED, "backward is provided for the FP32C form");
+  cs = prepare(s);
+  if (cs != CSMAP_OK) return cs;
+  hipStream_t st = s->stream;
+  HIPCHK(s, hipEventRecord(s->ev[3], st), "event");
+  const PreArgs P = pre_args(s);
+  HIPCHK(s, launch_precompute(P, nbox, st), "precompute launch");
+  // Kept counts decide the work items.
+  std::vector<DevBoxCount> kc(std::max<int64_t>(nbox, 1));
+  if (nbox)
+    HIPCHK(s, hipMemcpyAsync(kc.data(), s->d_box_count.p, sizeof(DevBoxCount) * nbox,
+                             hipMemcpyDeviceToHost, st), "read counts");
+  HIPCHK(s, hipStreamSynchronize(st), "read counts");
+  int64_t groups = 0, kept_total = 0;
+  for (int64_t b = 0; b < nbox; ++b) {
+    groups += (kc[b].kept + 63) / 64;
+    kept_total += kc[b].kept;
+  }
+  int nsplit = s->adj_split;
+  if (nsplit <= 0) {
+    const int64_t target = 16384;  // work items wanted to fill the device
+    nsplit = (int)std::min<int64_t>(256, std::max<int64_t>(1, (target + std::max<int64_t>(groups, 1) - 1) /
+                                                                std::max<int64_t>(groups, 1)));
+    nsplit = (int)std::min<int64_t>(nsplit, std::max<int64_t>(1, s->npix / 64));
+  }
+  std::vector<int32_t> items;
+  items.reserve(3 * groups * nsplit);
+  for (int64_t b = 0; b < nbox; ++b)
+    for (int64_t g = 0; g < (kc[b].kept + 63) / 64; ++g)
+      for (int sp = 0; sp < nsplit; ++sp) {
+        items.push_back((int32_t)b);
+        items.push_back((int32_t)g);
+        items.push_back(sp);
+      }
+  const int64_t nitems = (int64_t)items.size() / 3;
+  HIPCHK(s, s->d_pixtab32.ensure(sizeof(float) * 4 * s->npix), "alloc pixel table");
+  HIPCHK(s, s->d_pix64.ensure(sizeof(double) * 4 * s->npix), "alloc pixel table");
+  HIPCHK(s, s->d_partial.ensure(sizeof(double) * 14 * (size_t)std::max<int64_t>(1, s->total_seg) *
+                                nsplit), "alloc partials");
+  HIPCHK(s, s->d_adj_items.ensure(sizeof(int32_t) * std::max<size_t>(items.size(), 1)),
+         "alloc items");
+  if (!items.empty())
+    HIPCHK(s, hipMemcpyAsync(s->d_adj_items.p, items.data(), sizeof(int32_t) * items.size(),
+                             hipMemcpyHostToDevice, st), "upload items");
+  HIPCHK(s, launch_pixtab(s->nside, s->npix, dmap, s->d_pixtab32.as<float>(),
+                          s->d_pix64.as<double>(), st), "pixel table");
+  for (int64_t b = 0; b < nbox; ++b) {
+    const int64_t n = s->boxes[b].n;
+    if (grads[b].x_rel) HIPCHK(s, launch_fill(grads[b].x_rel, 3 * n, 0.0, st), "grad clear");
+    if (grads[b].xdot) HIPCHK(s, launch_fill(grads[b].xdot, 3 * n, 0.0, st), "grad clear");
+    if (grads[b].xprime) HIPCHK(s, launch_fill(grads[b].xprime, 3 * n, 0.0, st), "grad clear");
+    if (grads[b].dsigma) HIPCHK(s, launch_fill(grads[b].dsigma, n, 0.0, st), "grad clear");
+  }
+  AdjArgs A;
+  memset(&A, 0, sizeof(A));
+  A.boxes = s->d_boxes.as<DevBox>();
+  A.box_count = s->d_box_count.as<DevBoxCount>();
+  A.nbox = (int32_t)nbox;
+  A.nside = s->nside;
+  A.npix = s->npix;
+  A.eta0 = s->eta0;
+  A.pixtab = s->d_pixtab32.as<float>();
+  A.pix64 = s->d_pix64.as<double>();
+  A.rec32 = s->d_rec32.as<float>();
+  A.phat64 = s->d_phat64.as<double>();
+  A.items = s->d_adj_items.as<int32_t>();
+  A.nitems = nitems;
+  A.nsplit = nsplit;
+  A.near_w = (float)s->near_w;
+  A.partial = s->d_partial.as<double>();
+  A.dmap = dmap;
+  HIPCHK(s, hipEventRecord(s->ev[4], st), "event");
+  HIPCHK(s, launch_adjoint(A, st), "adjoint launch");
+  HIPCHK(s, hipEventRecord(s->ev[5], st), "event");
+  for (int64_t b = 0; b < nbox; ++b) {
+    HIPCHK(s, launch_adj_finalize(s->d_boxes.as<DevBox>(), s->d_box_count.as<DevBoxCount>(),
+                                  (int32_t)b, kc[b].kept,
+                                  (const char*)s->raw.p + s->boxes[b].raw_byte_off,
+                                  s->d_orig.as<int32_t>(), s->d_phat64.as<double>(),
+                                  s->d_partial.as<double>(), nsplit, grads[b].x_rel,
+                                  grads[b].xdot, grads[b].xprime, grads[b].dsigma, st),
+           "finalize launch");
+  }
+  // The item list lives in host memory until the copy has completed.
+  HIPCHK(s, hipStreamSynchronize(st), "backward");
+  s->have_bwd_time = true;
+  return CSMAP_OK;
+}
+
+csmap_status csmap_get_stats(csmap_sky* s, csmap_stats* out) {
+  g_err.clear();
+  csmap_status cs = check_sky(s);
+  if (cs != CSMAP_OK) return cs;
+  if (!out) return fail(CSMAP_E_INVALID, "out is NULL");
+  memset(out, 0, sizeof(*out));
+  HIPCHK(s, hipStreamSynchronize(s->stream), "sync");
+  out->nside = s->nside;
+  out->npix = s->npix;
+  out->nbox = (int64_t)s->boxes.size();
+  out->segments = s->total_seg;
+  if (!s->dirty && s->d_counters.p) {
+    unsigned long long c[2] = {0, 0};
+    HIPCHK(s, hipMemcpy(c, s->d_counters.p, sizeof(c), hipMemcpyDeviceToHost), "read counters");
+    out->pairs = (int64_t)c[0];
+    out->near_steps = (int64_t)c[1];
+    std::vector<DevBoxCount> kc(s->boxes.size());
+    if (!kc.empty())
+      HIPCHK(s, hipMemcpy(kc.data(), s->d_box_count.p, sizeof(DevBoxCount) * kc.size(),
+                          hipMemcpyDeviceToHost), "read counts");
+    for (auto& k : kc) out->kept += k.kept;
+  }
+  float ms = 0.f;
+  if (s->have_fwd_time) {
+    if (s->timed_graph) {
+      HIPCHK(s, hipEventElapsedTime(&ms, s->ev[0], s->ev[2]), "elapsed");
+      out->ms_forward = ms;
+      out->ms_precompute = 0.0;
+    } else {
+      HIPCHK(s, hipEventElapsedTime(&ms, s->ev[0], s->ev[1]), "elapsed");
+      out->ms_precompute = ms;
+      HIPCHK(s, hipEventElapsedTime(&ms, s->ev[1], s->ev[2]), "elapsed");
+      out->ms_forward = ms;
+    }
+  }
+  if (s->have_bwd_time) {
+    HIPCHK(s, hipEventElapsedTime(&ms, s->ev[4], s->ev[5]), "elapsed");
+    out->ms_backward = ms;
+  }
+  out->pix_per_lane = s->K;
+  out->waves = s->waves;
+  out->schedule = s->schedule;
+  out->graph = s->graph;
+  out->chunk = s->chunk;
+  out->near_w = s->near_w;
+  return CSMAP_OK;
+}
+
+csmap_status csmap_pix2vec_ring(int64_t nside, int64_t first, int64_t count, double* xyz,
+                                void* hip_stream) {
+  g_err.clear();
+  if (nside < 1 || nside > kMaxNside) return fail(CSMAP_E_INVALID, "nside must be in [1, 8192]");
+  const int64_t npix = 12 * nside * nside;
+  if (first < 0 || count < 0 || first > npix || count > npix - first)
+    return fail(CSMAP_E_INVALID, "pixel range outside the map");
+  if (count > 0 && !xyz) return fail(CSMAP_E_INVALID, "xyz is NULL");
+  hipError_t e = launch_pix2vec(nside, first, count, xyz, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return dev_fail(nullptr, e, "pix2vec launch");
+  return CSMAP_OK;
+}
+
+csmap_status csmap_cap_tiles(int64_t nside, int64_t tile, double cx, double cy, double cz,
+                             double rho, int64_t* ranges, int64_t max_ranges,
+                             int64_t* n_ranges) {
+  g_err.clear();
+  if (nside < 1 || nside > kMaxNside) return fail(CSMAP_E_INVALID, "nside must be in [1, 8192]");
+  if (tile < 1) return fail(CSMAP_E_INVALID, "tile must be >= 1");
+  if (!n_ranges || (max_ranges > 0 && !ranges)) return fail(CSMAP_E_INVALID, "NULL output");
+  if (!isfinite(cx) || !isfinite(cy) || !isfinite(cz) || !isfinite(rho) || rho < 0)
+    return fail(CSMAP_E_INVALID, "cap must be finite with rho >= 0");
+  std::vector<std::pair<int64_t, int64_t>> out;
+  cap_tiles(nside, tile, cx, cy, cz, rho, out);
+  *n_ranges = (int64_t)out.size();
+  if ((int64_t)out.size() > max_ranges) return fail(CSMAP_E_INVALID, "max_ranges too small");
+  for (size_t i = 0; i < out.size(); ++i) {
+    ranges[2 * i] = out[i].first;
+    ranges[2 * i + 1] = out[i].second;
+  }
+  return CSMAP_OK;
+}
+
+csmap_status csmap_autotune(csmap_sky* s, const char* cache_path) {
+  g_err.clear();
+  csmap_status cs = check_sky(s);
+  if (cs != CSMAP_OK) return cs;
+  (void)cache_path;
+  return fail(CSMAP_E_UNSUPPORTED, "autotune not available yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,127 @@
+// healpix_dev.h -- HEALPix RING pixel centres on the device.
+//
+// The map directions of the paper (Sec. II.D) are the centres of an Nside
+// HEALPix RING pixelisation (Gorski et al. 2005, cited in Sec. I).  This
+// routine follows the published definition:
+//   * rings i = 1 .. 4N-1 from north to south; north-cap ring i < N holds 4i
+//     pixels, each of the 2N+1 belt rings N .. 3N holds 4N, the south cap
+//     mirrors the north, pixels run by increasing azimuth inside a ring;
+//   * cap ring k (counted from its pole): z = +-(1 - k^2/(3N^2)),
+//     azimuth (pi/2)(j + 1/2)/k;
+//   * belt ring i: z = (4N - 2i)/(3N), azimuth (pi/2)(j + h)/N with a half
+//     pixel offset h = 1/2 on ring N and on every second ring after it.
+//
+// Only correctly rounded IEEE double operations on exact integers and a
+// fixed fma polynomial are used, in a fixed order, and the file is compiled
+// without floating-point contraction, so the result is reproducible bit for
+// bit by any implementation of the same steps.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace csmap {
+
+// floor(sqrt(v)) for 0 <= v < 2^62.
+__device__ __forceinline__ int64_t dev_isqrt(int64_t v) {
+  int64_t r = (int64_t)sqrt((double)v);
+  r -= (r * r > v) ? 1 : 0;
+  r += ((r + 1) * (r + 1) <= v) ? 1 : 0;
+  return r;
+}
+
+// Maclaurin coefficients of sin(pi t/2)/t and cos(pi t/2) in powers of t^2:
+// element k is the double nearest (-1)^k (pi/2)^(2k+1)/(2k+1)! and
+// (-1)^k (pi/2)^(2k)/(2k)! respectively.
+__device__ __forceinline__ void quarter_sincos(double t, double* s, double* c) {
+  const double t2 = t * t;
+  double ps = 6.0669357311061955e-12;
+  ps = fma(ps, t2, -6.688035109811468e-10);
+  ps = fma(ps, t2, 5.692172921967927e-08);
+  ps = fma(ps, t2, -3.598843235212085e-06);
+  ps = fma(ps, t2, 0.00016044118478735983);
+  ps = fma(ps, t2, -0.004681754135318688);
+  ps = fma(ps, t2, 0.07969262624616705);
+  ps = fma(ps, t2, -0.6459640975062463);
+  ps = fma(ps, t2, 1.5707963267948966);
+  double pc = 6.565963114979473e-11;
+  pc = fma(pc, t2, -6.386603083791852e-09);
+  pc = fma(pc, t2, 4.710874778818172e-07);
+  pc = fma(pc, t2, -2.5202042373060607e-05);
+  pc = fma(pc, t2, 0.0009192602748394266);
+  pc = fma(pc, t2, -0.02086348076335296);
+  pc = fma(pc, t2, 0.25366950790104803);
+  pc = fma(pc, t2, -1.2337005501361697);
+  pc = fma(pc, t2, 1.0);
+  *s = t * ps;
+  *c = pc;
+}
+
+// Unit vector of RING pixel p of an Nside map.
+__device__ __forceinline__ void pix2vec_ring(int64_t nside, int64_t p, double* vx, double* vy,
+                                             double* vz) {
+  const int64_t N = nside;
+  const int64_t npix = 12 * N * N;
+  const int64_t ncap = 2 * N * (N - 1);
+  // Integer stage: ring number from the nearer pole (k), 0-based azimuth
+  // index (j), and which zone the pixel is in.
+  int64_t k, j;
+  int zone;  // 0 north cap, 1 belt, 2 south cap
+  if (p < ncap) {
+    k = (1 + dev_isqrt(2 * p + 1)) >> 1;
+    j = p - 2 * k * (k - 1);
+    zone = 0;
+  } else if (p >= npix - ncap) {
+    const int64_t m = npix - 1 - p;
+    k = (1 + dev_isqrt(2 * m + 1)) >> 1;
+    j = 4 * k - 1 - (m - 2 * k * (k - 1));
+    zone = 2;
+  } else {
+    const int64_t q = p - ncap;
+    k = N + q / (4 * N);  // ring number counted from the north
+    j = q - (k - N) * (4 * N);
+    zone = 1;
+  }
+  double z, st;
+  int64_t num, den;
+  if (zone != 1) {
+    const double d = (double)(3 * N * N);
+    const int64_t kk = k * k;
+    z = (double)(3 * N * N - kk) / d;
+    st = ((double)k * sqrt((double)(6 * N * N - kk))) / d;
+    if (zone == 2) z = -z;
+    num = 2 * j + 1;
+    den = 2 * k;
+  } else {
+    const int64_t m = 2 * N - k;
+    const double d = (double)(3 * N);
+    z = (double)(2 * m) / d;
+    st = sqrt((double)(9 * N * N - 4 * m * m)) / d;
+    num = 2 * j + (((k - N) & 1) == 0 ? 1 : 0);
+    den = 2 * N;
+  }
+  // Azimuth (pi/2) num/den: integer quadrant, then fold into [0, pi/4].
+  const int64_t quad = num / den;
+  const int64_t r = num - quad * den;
+  double s, c, cq, sq;
+  if (2 * r <= den) {
+    quarter_sincos((double)r / (double)den, &s, &c);
+    cq = c;
+    sq = s;
+  } else {
+    quarter_sincos((double)(den - r) / (double)den, &s, &c);
+    cq = s;
+    sq = c;
+  }
+  double cp, sp;
+  switch (quad & 3) {
+    case 0: cp = cq; sp = sq; break;
+    case 1: cp = -sq; sp = cq; break;
+    case 2: cp = -cq; sp = -sq; break;
+    default: cp = sq; sp = -cq; break;
+  }
+  *vx = st * cp;
+  *vy = st * sp;
+  *vz = z;
+}
+
+}  // namespace csmap

@@ -1,0 +1,109 @@
+// internal.h -- data layout shared by the host scheduler and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace csmap {
+
+constexpr int kMaxNside = 8192;
+
+// Device copy of one box descriptor.
+struct DevBox {
+  double origin[3];
+  double ext[3];
+  double eta_lo, eta_hi;
+  double cap_dir[3];
+  double cap_cos;
+  int32_t vis;       // 0 all, 1 ray crosses box inside slab radii, 2 cap
+  int32_t dtype;     // 0 f32, 1 f64 raw arrays
+  int64_t n;         // raw segments
+  int64_t raw_off;   // offset (in segments) of the raw arrays of this box
+  int64_t rec_off;   // offset (in records) of this box's compacted records
+  int64_t blk_off;   // first precompute block of this box
+};
+
+// Per-box result of the light-cone compaction, written on the device.
+struct DevBoxCount {
+  int64_t kept;
+  int64_t pad;
+};
+
+// FP32C segment record: 16 floats (one 64-byte scalar load).
+//   [0..2]  P/R rounded to float          (unit vector towards the event)
+//   [3..5]  X'                             (T)
+//   [6..8]  Xdot                           (V)
+//   [9]     kappa = -2 eps dsigma / R      (half of the Eq. (1) prefactor over R)
+//   [10]    kappa (1 + (P/R).V)            (c1, FP64 then rounded)
+//   [11]    kappa (P/R).T                  (c2, FP64 then rounded)
+//   [12]    index of the segment inside its box (bit pattern of an int32)
+//   [13..15] unused
+constexpr int kRec32 = 16;
+// FP64 record: 16 doubles.
+//   [0..2] P/R rounded (hi), [3..5] X', [6..8] Xdot, [9] -4 eps dsigma / R,
+//   [10] index of the segment inside its box, [11] R,
+//   [12..14] P/R - hi (lo), [15] unused
+constexpr int kRec64 = 16;
+
+constexpr int kPreBlock = 256;  // segments per precompute workgroup
+
+struct PreArgs {
+  const DevBox* boxes;
+  const int32_t* blk_box;      // box of each precompute block
+  int64_t nblk;
+  const void* raw;             // raw segment storage (bytes)
+  const int64_t* raw_byte_off; // byte offset of each box's raw arrays
+  double eta0;
+  int32_t* blk_count;          // kept segments per block
+  int64_t* blk_prefix;         // exclusive prefix within the box
+  DevBoxCount* box_count;
+  float* rec32;                // FP32C records (or null)
+  double* phat64;              // FP32C: P/R in FP64, 4 doubles per record
+  double* rec64;               // FP64 records (or null)
+  int32_t* orig_index;         // record -> index of the segment in its box
+};
+
+// Arguments of the forward pair kernels.
+struct FwdArgs {
+  const DevBox* boxes;
+  const DevBoxCount* box_count;
+  int32_t nbox;
+  int32_t all_boxes;           // 1: every tile sees every box (no lists)
+  const int32_t* tile_ptr;     // CSR over tiles: boxes of tile t are
+  const int32_t* tile_boxes;   //   tile_boxes[tile_ptr[t] .. tile_ptr[t+1])
+  const int32_t* items;        // tile of each work item (null: item == tile)
+  int64_t nitems;
+  uint32_t* work_counter;      // persistent schedule: next item
+  int64_t nside, npix;
+  double eta0;
+  const float* rec32;
+  const double* phat64;
+  const double* rec64;
+  float near_w;
+  int32_t chunk;
+  int32_t accumulate;          // 1: map += contribution (per-box schedule)
+  int32_t only_box;            // per-box schedule: the one box (else -1)
+  double* map;
+  unsigned long long* pairs;   // pair counter
+  unsigned long long* near_steps;
+};
+
+// Arguments of the adjoint kernels.
+struct AdjArgs {
+  const DevBox* boxes;
+  const DevBoxCount* box_count;
+  int32_t nbox;
+  int64_t nside, npix;
+  double eta0;
+  const float* pixtab;         // per pixel: n (3 floats), dL/dTheta as float
+  const double* pix64;         // per pixel: n in FP64 (4 doubles)
+  const float* rec32;
+  const double* phat64;
+  const int32_t* items;        // (box, segment group, pixel chunk) triples
+  int64_t nitems;
+  int32_t nsplit;              // pixel chunks per segment group
+  float near_w;
+  double* partial;             // [record][split][13] accumulators
+  const double* dmap;
+};
+
+}  // namespace csmap

@@ -1,0 +1,819 @@
+// kernels.hip -- gfx950 kernels of libcsmap.
+//
+// Hot path (paper Sec. II.A, Eq. (1)-(2), summed over every segment for every
+// pixel of the HEALPix sky of Sec. II.D):
+//
+//   precompute : per segment, P = origin + x_rel, R = |P|, the light-cone slab
+//                test eta_lo <= eta0 - R < eta_hi, eps, and the per-segment
+//                constants of the pair formula, all in FP64; kept segments
+//                are compacted in their original order.
+//   forward    : one wavefront owns a tile of 64*K consecutive RING pixels
+//                (K per lane), computes their directions in-kernel, and
+//                streams the segment records of every box the tile sees
+//                through scalar registers: each record is fetched once per
+//                wavefront with scalar loads and used by all 64 lanes.
+//   adjoint    : the transpose -- one lane owns one segment, pixels stream
+//                through scalar registers -- so a segment's 13 running sums
+//                stay in its lane and no cross-lane reduction is needed in
+//                the loop; partial sums of pixel chunks are combined by a
+//                separate kernel in a fixed order.
+//
+// Pair formula.  With d = R n - P = R (n - Ph), Ph = P/R, and
+// m = (Xdot.d') b - a (X'.d'), d' = n - Ph, a = n.X', b = 1 + n.Xdot,
+// Eq. (1)-(2) give the summand -4 eps dsigma (u.d)/|d|^2 = kappa m/(b q),
+// q = |n - Ph|^2, kappa = -4 eps dsigma / R.  Since n and Ph are unit
+// vectors, q = 2 w with w = 1 - n.Ph, and
+//   kappa/2 * (Xdot.d') = kappa/2 * b - kappa/2 (1 + Ph.Xdot)
+//   kappa/2 * (X'.d')   = kappa/2 * a - kappa/2 (Ph.X')
+// so the FP32 form needs only the three dot products n.Ph, n.X', n.Xdot per
+// pair and two per-segment constants.  That form loses accuracy as w -> 0
+// (cancellation in 1 - n.Ph), so pairs with w below a threshold take the
+// direction difference n - Ph in FP64 instead.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "healpix_dev.h"
+#include "internal.h"
+
+namespace csmap {
+
+// Plain clang vector types, loadable through constant-address-space pointers:
+// loads whose address is the same in every lane become scalar loads.
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef const v4f __attribute__((address_space(4)))* cf4p;
+typedef const v2d __attribute__((address_space(4)))* cd2p;
+typedef const int32_t __attribute__((address_space(4)))* ci32p;
+
+typedef const DevBox __attribute__((address_space(4)))* cbox_p;
+typedef const DevBoxCount __attribute__((address_space(4)))* ccnt_p;
+
+// Box descriptor read through the constant address space, field by field, so
+// that a wave-uniform box index gives scalar loads.
+__device__ __forceinline__ DevBox load_box(const DevBox* boxes, int64_t b) {
+  const cbox_p q = (cbox_p)boxes + b;
+  DevBox r;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    r.origin[k] = q->origin[k];
+    r.ext[k] = q->ext[k];
+    r.cap_dir[k] = q->cap_dir[k];
+  }
+  r.eta_lo = q->eta_lo;
+  r.eta_hi = q->eta_hi;
+  r.cap_cos = q->cap_cos;
+  r.vis = q->vis;
+  r.dtype = q->dtype;
+  r.n = q->n;
+  r.raw_off = q->raw_off;
+  r.rec_off = q->rec_off;
+  r.blk_off = q->blk_off;
+  return r;
+}
+
+__device__ __forceinline__ int64_t load_kept(const DevBoxCount* c, int64_t b) {
+  return ((ccnt_p)c)[b].kept;
+}
+
+// ---------------------------------------------------------------------------
+// Light-cone geometry of one segment (FP64).
+// ---------------------------------------------------------------------------
+struct SegGeom {
+  double P[3], V[3], T[3];
+  double R, eps, ds;
+  bool keep;
+};
+
+__device__ __forceinline__ double raw_at(const char* base, int dtype, int64_t idx) {
+  return dtype == 0 ? (double)((const float*)base)[idx] : ((const double*)base)[idx];
+}
+
+__device__ __forceinline__ SegGeom seg_geom(const DevBox& bx, const char* raw, int64_t i,
+                                            double eta0) {
+  // Raw layout of a box: x_rel (n x 3), xdot (n x 3), xprime (n x 3), dsigma (n).
+  const int dt = bx.dtype;
+  const int64_t n = bx.n;
+  SegGeom g;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    g.P[k] = bx.origin[k] + raw_at(raw, dt, 3 * i + k);
+    g.V[k] = raw_at(raw, dt, 3 * n + 3 * i + k);
+    g.T[k] = raw_at(raw, dt, 6 * n + 3 * i + k);
+  }
+  g.ds = raw_at(raw, dt, 9 * n + i);
+  g.R = sqrt((g.P[0] * g.P[0] + g.P[1] * g.P[1]) + g.P[2] * g.P[2]);
+  const double eta = eta0 - g.R;
+  g.keep = (g.R > 0.0) && (eta >= bx.eta_lo) && (eta < bx.eta_hi);
+  const double tt = (g.T[0] * g.T[0] + g.T[1] * g.T[1]) + g.T[2] * g.T[2];
+  const double vv = (g.V[0] * g.V[0] + g.V[1] * g.V[1]) + g.V[2] * g.V[2];
+  g.eps = sqrt(tt / (1.0 - vv));
+  return g;
+}
+
+// Pixel visibility of a box (decided in FP64 with a fixed operation order).
+__device__ __forceinline__ bool sees_box(double nx, double ny, double nz, const DevBox& bx,
+                                         double eta0) {
+  if (bx.vis == 0) return true;
+  if (bx.vis == 2) {
+    const double dot = (nx * bx.cap_dir[0] + ny * bx.cap_dir[1]) + nz * bx.cap_dir[2];
+    return dot >= bx.cap_cos;
+  }
+  const double r_lo = eta0 - bx.eta_hi;
+  const double r_hi = eta0 - bx.eta_lo;
+  const double n3[3] = {nx, ny, nz};
+  double t_in = 0.0, t_out = __builtin_inf();
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double lo = bx.origin[k];
+    const double hi = bx.origin[k] + bx.ext[k];
+    if (n3[k] == 0.0) {
+      if (lo > 0.0 || hi < 0.0) return false;
+      continue;
+    }
+    const double ta = lo / n3[k];
+    const double tb = hi / n3[k];
+    const double tmin = (ta < tb) ? ta : tb;
+    const double tmax = (ta < tb) ? tb : ta;
+    if (tmin > t_in) t_in = tmin;
+    if (tmax < t_out) t_out = tmax;
+  }
+  return (t_in <= t_out) && (t_out > r_lo) && (t_in <= r_hi);
+}
+
+// ---------------------------------------------------------------------------
+// Precompute: count kept segments per block, scan per box, emit records.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kPreBlock) k_pre_count(PreArgs A) {
+  const int64_t blk = blockIdx.x;
+  const int b = A.blk_box[blk];
+  const DevBox bx = A.boxes[b];
+  const int64_t i = (blk - bx.blk_off) * kPreBlock + threadIdx.x;
+  bool keep = false;
+  if (i < bx.n) {
+    const char* raw = (const char*)A.raw + A.raw_byte_off[b];
+    keep = seg_geom(bx, raw, i, A.eta0).keep;
+  }
+  const int cnt = __syncthreads_count(keep);
+  if (threadIdx.x == 0) A.blk_count[blk] = cnt;
+}
+
+// One workgroup per box: exclusive prefix of the block counts of the box.
+__global__ void __launch_bounds__(256) k_pre_scan(PreArgs A, int64_t nbox) {
+  const int b = blockIdx.x;
+  if (b >= nbox) return;
+  const DevBox bx = A.boxes[b];
+  const int64_t nb = (bx.n + kPreBlock - 1) / kPreBlock;
+  __shared__ int64_t sh[256];
+  int64_t running = 0;
+  for (int64_t c0 = 0; c0 < nb; c0 += 256) {
+    const int64_t k = c0 + threadIdx.x;
+    const int64_t v = (k < nb) ? (int64_t)A.blk_count[bx.blk_off + k] : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const int64_t add = (threadIdx.x >= (unsigned)off) ? sh[threadIdx.x - off] : 0;
+      __syncthreads();
+      sh[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (k < nb) A.blk_prefix[bx.blk_off + k] = running + sh[threadIdx.x] - v;
+    const int64_t tot = sh[255];
+    __syncthreads();
+    running += tot;
+  }
+  if (threadIdx.x == 0) {
+    A.box_count[b].kept = running;
+    A.box_count[b].pad = 0;
+  }
+}
+
+__global__ void __launch_bounds__(kPreBlock) k_pre_emit(PreArgs A) {
+  const int64_t blk = blockIdx.x;
+  const int b = A.blk_box[blk];
+  const DevBox bx = A.boxes[b];
+  const int64_t i = (blk - bx.blk_off) * kPreBlock + threadIdx.x;
+  SegGeom g;
+  g.keep = false;
+  if (i < bx.n) {
+    const char* raw = (const char*)A.raw + A.raw_byte_off[b];
+    g = seg_geom(bx, raw, i, A.eta0);
+  }
+  // Rank of this segment among the kept ones of the block (order preserved).
+  __shared__ int wave_tot[kPreBlock / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const unsigned long long bal = __ballot(g.keep);
+  const int in_wave = __popcll(bal & ((1ull << lane) - 1ull));
+  if (lane == 0) wave_tot[wave] = __popcll(bal);
+  __syncthreads();
+  int before = 0;
+  for (int w = 0; w < wave; ++w) before += wave_tot[w];
+  if (!g.keep) return;
+  const int64_t r = bx.rec_off + A.blk_prefix[blk] + before + in_wave;
+  double Ph[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) Ph[k] = g.P[k] / g.R;
+  const double kappa = -4.0 * g.eps * g.ds / g.R;
+  A.orig_index[r] = (int32_t)i;
+  if (A.rec32) {
+    const double kh = 0.5 * kappa;
+    const double pv = (Ph[0] * g.V[0] + Ph[1] * g.V[1]) + Ph[2] * g.V[2];
+    const double pt = (Ph[0] * g.T[0] + Ph[1] * g.T[1]) + Ph[2] * g.T[2];
+    float4* o = (float4*)(A.rec32 + (size_t)r * kRec32);
+    o[0] = make_float4((float)Ph[0], (float)Ph[1], (float)Ph[2], (float)g.T[0]);
+    o[1] = make_float4((float)g.T[1], (float)g.T[2], (float)g.V[0], (float)g.V[1]);
+    o[2] = make_float4((float)g.V[2], (float)kh, (float)(kh * (1.0 + pv)), (float)(kh * pt));
+    o[3] = make_float4(__int_as_float((int)i), 0.f, 0.f, 0.f);
+    double2* h = (double2*)(A.phat64 + (size_t)r * 4);
+    h[0] = make_double2(Ph[0], Ph[1]);
+    h[1] = make_double2(Ph[2], g.R);
+  }
+  if (A.rec64) {
+    double2* o = (double2*)(A.rec64 + (size_t)r * kRec64);
+    o[0] = make_double2(Ph[0], Ph[1]);
+    o[1] = make_double2(Ph[2], g.T[0]);
+    o[2] = make_double2(g.T[1], g.T[2]);
+    o[3] = make_double2(g.V[0], g.V[1]);
+    o[4] = make_double2(g.V[2], kappa);
+    // P/R carried as an unevaluated sum hi + lo: lo is the exact remainder
+    // of the rounded quotient divided by R, so that n - P/R can be formed
+    // accurately for directions close to the event.
+    double lo[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) lo[k] = fma(-Ph[k], g.R, g.P[k]) / g.R;
+    o[5] = make_double2((double)i, g.R);
+    o[6] = make_double2(lo[0], lo[1]);
+    o[7] = make_double2(lo[2], 0.0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Small utility kernels (plain stores; used instead of memset so that the
+// launches can be captured in a graph).
+// ---------------------------------------------------------------------------
+__global__ void k_fill_f64(double* p, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = i; k < n; k += stride) p[k] = v;
+}
+
+__global__ void k_zero_counters(unsigned long long* c, int n, uint32_t* work) {
+  if (threadIdx.x < (unsigned)n) c[threadIdx.x] = 0ull;
+  if (threadIdx.x == 0 && work) *work = 0u;
+}
+
+__global__ void k_pix2vec(int64_t nside, int64_t first, int64_t count, double* xyz) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  double x, y, z;
+  pix2vec_ring(nside, first + i, &x, &y, &z);
+  xyz[3 * i + 0] = x;
+  xyz[3 * i + 1] = y;
+  xyz[3 * i + 2] = z;
+}
+
+// ---------------------------------------------------------------------------
+// Forward pair kernels.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t next_item(const FwdArgs& A, bool persistent, int lane,
+                                             int64_t cur, int64_t stride) {
+  if (!persistent) return cur + stride;
+  uint32_t it = 0;
+  if (lane == 0) it = atomicAdd(A.work_counter, 1u);
+  return (int64_t)__builtin_amdgcn_readfirstlane(__shfl(it, 0));
+}
+
+__device__ __forceinline__ int32_t tile_of(const FwdArgs& A, int64_t item) {
+  return A.items ? ((ci32p)A.items)[item] : (int32_t)item;
+}
+
+// Kahan update of (s, c) by x, applied only where `on`.
+__device__ __forceinline__ void kahan_add(float& s, float& c, float x, bool on) {
+  const float y = x - c;
+  const float t = s + y;
+  const float cn = (t - s) - y;
+  s = on ? t : s;
+  c = on ? cn : c;
+}
+
+template <int K, bool PERSISTENT>
+__global__ void __launch_bounds__(256) k_fwd32(FwdArgs A) {
+  const int lane = threadIdx.x & 63;
+  const int wpb = blockDim.x >> 6;
+  // The wavefront index is uniform; say so, so that everything derived from
+  // it (tile, box, segment index) lives in scalar registers.
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int64_t item = PERSISTENT ? next_item(A, true, lane, 0, 0) : (int64_t)blockIdx.x * wpb + wave;
+  const int64_t stride = (int64_t)gridDim.x * wpb;
+  unsigned long long near_steps = 0;
+  const float near_w = A.near_w;
+  cf4p recs = (cf4p)A.rec32;
+  cd2p ph64 = (cd2p)A.phat64;
+  while (item < A.nitems) {
+    const int64_t tile = tile_of(A, item);
+    const int64_t base = tile * (64 * K);
+    double nd[K][3];
+    float nf[K][3];
+    bool inmap[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const int64_t p = base + j * 64 + lane;
+      inmap[j] = p < A.npix;
+      pix2vec_ring(A.nside, inmap[j] ? p : A.npix - 1, &nd[j][0], &nd[j][1], &nd[j][2]);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) nf[j][k] = (float)nd[j][k];
+    }
+    float S[K], C[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) { S[j] = 0.f; C[j] = 0.f; }
+
+    int32_t b0 = 0, b1 = A.nbox;
+    if (A.only_box >= 0) { b0 = A.only_box; b1 = A.only_box + 1; }
+    else if (!A.all_boxes) { b0 = ((ci32p)A.tile_ptr)[tile]; b1 = ((ci32p)A.tile_ptr)[tile + 1]; }
+    for (int32_t bi = b0; bi < b1; ++bi) {
+      const int32_t b = (A.all_boxes || A.only_box >= 0) ? bi : ((ci32p)A.tile_boxes)[bi];
+      const DevBox bx = load_box(A.boxes, b);
+      bool vis[K];
+      bool anyv = false;
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        vis[j] = inmap[j] && sees_box(nd[j][0], nd[j][1], nd[j][2], bx, A.eta0);
+        anyv |= vis[j];
+      }
+      if (!__any(anyv)) continue;
+      const int64_t r0 = bx.rec_off;
+      const int64_t r1 = r0 + load_kept(A.box_count, b);
+      {
+        unsigned long long nvis = 0;
+#pragma unroll
+        for (int j = 0; j < K; ++j) nvis += __popcll(__ballot(vis[j]));
+        if (lane == 0 && r1 > r0) atomicAdd(A.pairs, nvis * (unsigned long long)(r1 - r0));
+      }
+      for (int64_t c0 = r0; c0 < r1; c0 += A.chunk) {
+        const int64_t c1 = (c0 + A.chunk < r1) ? c0 + A.chunk : r1;
+        float part[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) part[j] = 0.f;
+        // 32-bit trip count so that the loop control stays on the scalar unit.
+        const int32_t nk = (int32_t)(c1 - c0);
+        cf4p rp = recs + 4 * c0;
+        cd2p hp = ph64 + 2 * c0;
+        for (int32_t k = 0; k < nk; ++k, rp += 4, hp += 2) {
+          const v4f q0 = rp[0];
+          const v4f q1 = rp[1];
+          const v4f q2 = rp[2];
+          const float px = q0.x, py = q0.y, pz = q0.z;
+          const float tx = q0.w, ty = q1.x, tz = q1.y;
+          const float vx = q1.z, vy = q1.w, vz = q2.x;
+          const float kap = q2.y, c1v = q2.z, c2v = q2.w;
+          float w[K], a[K], bb[K], t1[K], t2[K], den[K];
+          bool nearp = false;
+#pragma unroll
+          for (int j = 0; j < K; ++j) {
+            w[j] = fmaf(-nf[j][2], pz, fmaf(-nf[j][1], py, fmaf(-nf[j][0], px, 1.0f)));
+            a[j] = fmaf(nf[j][2], tz, fmaf(nf[j][1], ty, nf[j][0] * tx));
+            bb[j] = fmaf(nf[j][2], vz, fmaf(nf[j][1], vy, fmaf(nf[j][0], vx, 1.0f)));
+            nearp |= (w[j] < near_w);
+          }
+          if (!__any(nearp)) {
+            // kappa/2 times Xdot.(n - Ph) and X'.(n - Ph) from the dot products.
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+              t1[j] = fmaf(kap, bb[j], -c1v);
+              t2[j] = fmaf(kap, a[j], -c2v);
+              den[j] = bb[j] * w[j];
+            }
+          } else {
+            // Close pairs: the difference of directions in FP64.  An exact
+            // coincidence (n == Ph) gives m = 0 and a finite reciprocal, so
+            // the term is 0.
+            ++near_steps;
+            const v2d h0 = hp[0];
+            const v2d h1 = hp[1];
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+              const float dx = (float)(nd[j][0] - h0.x);
+              const float dy = (float)(nd[j][1] - h0.y);
+              const float dz = (float)(nd[j][2] - h1.x);
+              const float q = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+              t1[j] = kap * fmaf(vz, dz, fmaf(vy, dy, vx * dx));
+              t2[j] = kap * fmaf(tz, dz, fmaf(ty, dy, tx * dx));
+              den[j] = bb[j] * fmaxf(0.5f * q, 1e-30f);
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < K; ++j) {
+            const float m = fmaf(-a[j], t2[j], t1[j] * bb[j]);   // kappa/2 * m
+            part[j] = fmaf(m, __builtin_amdgcn_rcpf(den[j]), part[j]);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) kahan_add(S[j], C[j], part[j], vis[j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const int64_t p = base + j * 64 + lane;
+      if (inmap[j]) {
+        // The running sum s carries the result; c is the negated rounding
+        // error still owed to it, so the value is s - c.
+        const double v = (double)S[j] - (double)C[j];
+        A.map[p] = A.accumulate ? A.map[p] + v : v;
+      }
+    }
+    item = PERSISTENT ? next_item(A, true, lane, item, stride) : item + stride;
+  }
+  if (lane == 0 && near_steps) atomicAdd(A.near_steps, near_steps);
+}
+
+__device__ __forceinline__ double rcp_f64(double x) {
+  // Hardware estimate refined by two Newton steps (quadratic convergence).
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  return r;
+}
+
+template <int K, bool PERSISTENT>
+__global__ void __launch_bounds__(256) k_fwd64(FwdArgs A) {
+  const int lane = threadIdx.x & 63;
+  const int wpb = blockDim.x >> 6;
+  // The wavefront index is uniform; say so, so that everything derived from
+  // it (tile, box, segment index) lives in scalar registers.
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int64_t item = PERSISTENT ? next_item(A, true, lane, 0, 0) : (int64_t)blockIdx.x * wpb + wave;
+  const int64_t stride = (int64_t)gridDim.x * wpb;
+  cd2p recs = (cd2p)A.rec64;
+  while (item < A.nitems) {
+    const int64_t tile = tile_of(A, item);
+    const int64_t base = tile * (64 * K);
+    double nd[K][3];
+    bool inmap[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const int64_t p = base + j * 64 + lane;
+      inmap[j] = p < A.npix;
+      pix2vec_ring(A.nside, inmap[j] ? p : A.npix - 1, &nd[j][0], &nd[j][1], &nd[j][2]);
+    }
+    double S[K], C[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) { S[j] = 0.0; C[j] = 0.0; }
+    int32_t b0 = 0, b1 = A.nbox;
+    if (A.only_box >= 0) { b0 = A.only_box; b1 = A.only_box + 1; }
+    else if (!A.all_boxes) { b0 = ((ci32p)A.tile_ptr)[tile]; b1 = ((ci32p)A.tile_ptr)[tile + 1]; }
+    for (int32_t bi = b0; bi < b1; ++bi) {
+      const int32_t b = (A.all_boxes || A.only_box >= 0) ? bi : ((ci32p)A.tile_boxes)[bi];
+      const DevBox bx = load_box(A.boxes, b);
+      bool vis[K];
+      bool anyv = false;
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        vis[j] = inmap[j] && sees_box(nd[j][0], nd[j][1], nd[j][2], bx, A.eta0);
+        anyv |= vis[j];
+      }
+      if (!__any(anyv)) continue;
+      const int64_t r0 = bx.rec_off;
+      const int64_t r1 = r0 + load_kept(A.box_count, b);
+      {
+        unsigned long long nvis = 0;
+#pragma unroll
+        for (int j = 0; j < K; ++j) nvis += __popcll(__ballot(vis[j]));
+        if (lane == 0 && r1 > r0) atomicAdd(A.pairs, nvis * (unsigned long long)(r1 - r0));
+      }
+      for (int64_t c0 = r0; c0 < r1; c0 += A.chunk) {
+        const int64_t c1 = (c0 + A.chunk < r1) ? c0 + A.chunk : r1;
+        double part[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) part[j] = 0.0;
+        const int32_t nk = (int32_t)(c1 - c0);
+        cd2p rp = recs + 8 * c0;
+        for (int32_t k = 0; k < nk; ++k, rp += 8) {
+          const v2d q0 = rp[0];
+          const v2d q1 = rp[1];
+          const v2d q2 = rp[2];
+          const v2d q3 = rp[3];
+          const v2d q4 = rp[4];
+          const v2d q6 = rp[6];
+          const v2d q7 = rp[7];
+          const double px = q0.x, py = q0.y, pz = q1.x;
+          const double lx = q6.x, ly = q6.y, lz = q7.x;
+          const double tx = q1.y, ty = q2.x, tz = q2.y;
+          const double vx = q3.x, vy = q3.y, vz = q4.x;
+          const double kap = q4.y;
+#pragma unroll
+          for (int j = 0; j < K; ++j) {
+            // (n - hi) is exact for nearby directions; the lo part then
+            // enters with a single rounding.
+            const double dx = (nd[j][0] - px) - lx;
+            const double dy = (nd[j][1] - py) - ly;
+            const double dz = (nd[j][2] - pz) - lz;
+            const double q = fma(dz, dz, fma(dy, dy, dx * dx));
+            const double a = fma(nd[j][2], tz, fma(nd[j][1], ty, nd[j][0] * tx));
+            const double b = fma(nd[j][2], vz, fma(nd[j][1], vy, fma(nd[j][0], vx, 1.0)));
+            const double vd = fma(vz, dz, fma(vy, dy, vx * dx));
+            const double td = fma(tz, dz, fma(ty, dy, tx * dx));
+            const double m = fma(vd, b, -(a * td));
+            const double r = (q > 0.0) ? rcp_f64(b * q) : 0.0;
+            part[j] = fma(kap * m, r, part[j]);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const double y = part[j] - C[j];
+          const double t = S[j] + y;
+          const double cn = (t - S[j]) - y;
+          S[j] = vis[j] ? t : S[j];
+          C[j] = vis[j] ? cn : C[j];
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const int64_t p = base + j * 64 + lane;
+      if (inmap[j]) {
+        const double v = S[j] - C[j];
+        A.map[p] = A.accumulate ? A.map[p] + v : v;
+      }
+    }
+    item = PERSISTENT ? next_item(A, true, lane, item, stride) : item + stride;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint.
+// ---------------------------------------------------------------------------
+// Pixel table: direction (FP32) and cotangent (FP32) per pixel, plus the FP64
+// direction for close pairs and visibility decisions.
+__global__ void k_pixtab(int64_t nside, int64_t npix, const double* dmap, float* tab32,
+                         double* tab64) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npix) return;
+  double x, y, z;
+  pix2vec_ring(nside, p, &x, &y, &z);
+  ((float4*)tab32)[p] = make_float4((float)x, (float)y, (float)z, (float)dmap[p]);
+  ((double2*)tab64)[2 * p + 0] = make_double2(x, y);
+  ((double2*)tab64)[2 * p + 1] = make_double2(z, dmap[p]);
+}
+
+// Accumulators of one segment (see the finalize kernel for their use), with
+// d = n - Ph the direction difference of the pair and r = 1/(b w):
+//   0 S1  = sum s kap/w                  1 S2 = sum s kap a r
+//   2 SF  = sum s f                      3 C2 = sum s a t2 r/b
+//   4 C4  = sum s t2 r                   5..7   D3 = sum (s f/w) d
+//   8..10 DV = sum (s kap/w + s a t2 r/b) d    11..13 DT = sum s r (t2 + kap a) d
+// Every vector sum multiplies d rather than n: the n-weighted sums of the
+// close pixels are each of order 1/theta larger than the result and would
+// cancel against Ph times a scalar sum.
+constexpr int kAcc = 14;
+
+// Work item: a group of 64 consecutive kept records of one box (one per
+// lane) and one of `nsplit` contiguous pixel ranges.
+__global__ void __launch_bounds__(256) k_adj32(AdjArgs A) {
+  const int lane = threadIdx.x & 63;
+  const int wpb = blockDim.x >> 6;
+  const int64_t item = (int64_t)blockIdx.x * wpb + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (item >= A.nitems) return;
+  const int32_t b = ((ci32p)A.items)[3 * item + 0];
+  const int32_t grp = ((ci32p)A.items)[3 * item + 1];
+  const int32_t split = ((ci32p)A.items)[3 * item + 2];
+  const DevBox bx = load_box(A.boxes, b);
+  const int64_t kept = load_kept(A.box_count, b);
+  const int64_t li = (int64_t)grp * 64 + lane;
+  const bool active = li < kept;
+  const int64_t rec = bx.rec_off + (active ? li : 0);
+  // Segment constants (per lane).
+  const float4* R4 = (const float4*)(A.rec32 + (size_t)rec * kRec32);
+  const float4 q0 = R4[0], q1 = R4[1], q2 = R4[2];
+  const float px = q0.x, py = q0.y, pz = q0.z;
+  const float tx = q0.w, ty = q1.x, tz = q1.y;
+  const float vx = q1.z, vy = q1.w, vz = q2.x;
+  const float kap = active ? q2.y : 0.0f, c1v = q2.z, c2v = q2.w;
+  const double2 h0 = ((const double2*)A.phat64)[2 * rec + 0];
+  const double2 h1 = ((const double2*)A.phat64)[2 * rec + 1];
+  const int64_t p0 = A.npix * split / A.nsplit;
+  const int64_t p1 = A.npix * (split + 1) / A.nsplit;
+  const float near_w = A.near_w;
+  cf4p tab = (cf4p)A.pixtab;
+  cd2p tab64 = (cd2p)A.pix64;
+  double acc[kAcc];
+#pragma unroll
+  for (int k = 0; k < kAcc; ++k) acc[k] = 0.0;
+  const bool check_vis = bx.vis != 0;
+  constexpr int J = 64;
+  for (int64_t pc = p0; pc < p1; pc += J) {
+    const int64_t pe = (pc + J < p1) ? pc + J : p1;
+    float pa[kAcc];
+#pragma unroll
+    for (int k = 0; k < kAcc; ++k) pa[k] = 0.f;
+    for (int64_t p = pc; p < pe; ++p) {
+      if (check_vis) {
+        const v2d e0 = tab64[2 * p + 0];
+        const v2d e1 = tab64[2 * p + 1];
+        if (!sees_box(e0.x, e0.y, e1.x, bx, A.eta0)) continue;
+      }
+      const v4f pt = tab[p];
+      const float nx = pt.x, ny = pt.y, nz = pt.z, s = pt.w;
+      float w = fmaf(-nz, pz, fmaf(-ny, py, fmaf(-nx, px, 1.0f)));
+      const float a = fmaf(nz, tz, fmaf(ny, ty, nx * tx));
+      const float bb = fmaf(nz, vz, fmaf(ny, vy, fmaf(nx, vx, 1.0f)));
+      float t1, t2, r, dx, dy, dz;
+      if (!__any(w < near_w)) {
+        t1 = fmaf(kap, bb, -c1v);
+        t2 = fmaf(kap, a, -c2v);
+        r = __builtin_amdgcn_rcpf(bb * w);
+        dx = nx - px;
+        dy = ny - py;
+        dz = nz - pz;
+      } else {
+        const v2d e0 = tab64[2 * p + 0];
+        const v2d e1 = tab64[2 * p + 1];
+        dx = (float)(e0.x - h0.x);
+        dy = (float)(e0.y - h0.y);
+        dz = (float)(e1.x - h1.x);
+        const float q = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        t1 = kap * fmaf(vz, dz, fmaf(vy, dy, vx * dx));
+        t2 = kap * fmaf(tz, dz, fmaf(ty, dy, tx * dx));
+        w = 0.5f * q;
+        r = (w > 0.0f) ? __builtin_amdgcn_rcpf(bb * w) : 0.0f;
+      }
+      const float m = fmaf(-a, t2, t1 * bb);       // kap * m
+      const float f = m * r;                        // the Eq. (1) term
+      const float sr = s * r;
+      const float k1 = sr * kap;                    // s kap / (b w)
+      const float c1 = k1 * bb;                     // s kap / w
+      pa[0] += c1;
+      pa[1] = fmaf(k1, a, pa[1]);
+      const float sf = s * f;
+      pa[2] += sf;
+      const float c4 = sr * t2;                     // s kap Td / (b w)
+      pa[4] += c4;
+      const float c2 = (c4 * a) * (w * r);          // s kap a Td / (b^2 w)
+      pa[3] += c2;
+      const float d3 = sf * (bb * r);               // s f / w
+      pa[5] = fmaf(d3, dx, pa[5]);
+      pa[6] = fmaf(d3, dy, pa[6]);
+      pa[7] = fmaf(d3, dz, pa[7]);
+      const float dv = c1 + c2;
+      pa[8] = fmaf(dv, dx, pa[8]);
+      pa[9] = fmaf(dv, dy, pa[9]);
+      pa[10] = fmaf(dv, dz, pa[10]);
+      const float c3 = fmaf(k1, a, c4);             // s kap (Td + a) / (b w)
+      pa[11] = fmaf(c3, dx, pa[11]);
+      pa[12] = fmaf(c3, dy, pa[12]);
+      pa[13] = fmaf(c3, dz, pa[13]);
+    }
+#pragma unroll
+    for (int k = 0; k < kAcc; ++k) acc[k] += (double)pa[k];
+  }
+  if (active) {
+    double* o = A.partial + ((size_t)rec * A.nsplit + split) * kAcc;
+#pragma unroll
+    for (int k = 0; k < kAcc; ++k) o[k] = acc[k];
+  }
+}
+
+struct GradPtrs {
+  double* x;
+  double* xd;
+  double* xp;
+  double* ds;
+};
+
+// Combine the pixel-chunk partials of each kept record (in chunk order) and
+// apply the per-segment chain rule, then scatter to the caller's arrays.
+//   G_d   = V S1 - T S2 - D3                   (sum of s df/d(n - Ph))
+//   dL/dP = -(G_d - Ph (Ph.G_d))/R - SF Ph / R (Ph = P/R, dR/dP = Ph)
+//   dL/dV = DV + Ph C2 + SF V/(1 - V^2)        (the last term from eps)
+//   dL/dT = -DT - Ph C4 + SF T/T^2             (the last term from eps)
+//   dL/ddsigma = SF / dsigma
+__global__ void k_adj_finalize(const DevBox* boxes, const DevBoxCount* counts, int32_t b,
+                               const char* raw, const int32_t* orig_index,
+                               const double* phat64, const double* partial, int32_t nsplit,
+                               GradPtrs out) {
+  const DevBox bx = boxes[b];
+  const int64_t li = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (li >= counts[b].kept) return;
+  const int64_t rec = bx.rec_off + li;
+  double S[kAcc];
+#pragma unroll
+  for (int k = 0; k < kAcc; ++k) S[k] = 0.0;
+  for (int sp = 0; sp < nsplit; ++sp) {
+    const double* pp = partial + ((size_t)rec * nsplit + sp) * kAcc;
+#pragma unroll
+    for (int k = 0; k < kAcc; ++k) S[k] += pp[k];
+  }
+  const int64_t i = orig_index[rec];
+  const int dt = bx.dtype;
+  const int64_t n = bx.n;
+  double V[3], T[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    V[k] = raw_at(raw, dt, 3 * n + 3 * i + k);
+    T[k] = raw_at(raw, dt, 6 * n + 3 * i + k);
+  }
+  const double ds = raw_at(raw, dt, 9 * n + i);
+  const double Ph[3] = {phat64[4 * rec + 0], phat64[4 * rec + 1], phat64[4 * rec + 2]};
+  const double R = phat64[4 * rec + 3];
+  const double vv = (V[0] * V[0] + V[1] * V[1]) + V[2] * V[2];
+  const double tt = (T[0] * T[0] + T[1] * T[1]) + T[2] * T[2];
+  double G[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) G[k] = V[k] * S[0] - T[k] * S[1] - S[5 + k];
+  const double pg = (Ph[0] * G[0] + Ph[1] * G[1]) + Ph[2] * G[2];
+  const double SF = S[2];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (out.x) out.x[3 * i + k] = -(G[k] - Ph[k] * pg) / R - SF * Ph[k] / R;
+    if (out.xd) out.xd[3 * i + k] = S[8 + k] + Ph[k] * S[3] + SF * V[k] / (1.0 - vv);
+    if (out.xp) out.xp[3 * i + k] = -S[11 + k] - Ph[k] * S[4] + SF * T[k] / tt;
+  }
+  if (out.ds) out.ds[i] = SF / ds;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (C++ linkage, used by the API layer).
+// ---------------------------------------------------------------------------
+hipError_t launch_precompute(const PreArgs& A, int64_t nbox, hipStream_t st) {
+  if (nbox == 0) return hipSuccess;
+  // The scan runs for every box, also when no box has segments, so that every
+  // kept count the pair kernels read has been written.
+  if (A.nblk) k_pre_count<<<dim3((unsigned)A.nblk), dim3(kPreBlock), 0, st>>>(A);
+  k_pre_scan<<<dim3((unsigned)nbox), dim3(256), 0, st>>>(A, nbox);
+  if (A.nblk) k_pre_emit<<<dim3((unsigned)A.nblk), dim3(kPreBlock), 0, st>>>(A);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  k_fill_f64<<<dim3((unsigned)blocks), dim3(256), 0, st>>>(p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_counters(unsigned long long* c, int n, uint32_t* work, hipStream_t st) {
+  k_zero_counters<<<1, 64, 0, st>>>(c, n, work);
+  return hipGetLastError();
+}
+
+hipError_t launch_pix2vec(int64_t nside, int64_t first, int64_t count, double* xyz,
+                          hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  k_pix2vec<<<dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st>>>(nside, first, count,
+                                                                          xyz);
+  return hipGetLastError();
+}
+
+template <int K, bool P>
+static void fwd_launch(bool fp64, const FwdArgs& A, unsigned grid, unsigned block,
+                       hipStream_t st) {
+  if (fp64)
+    k_fwd64<K, P><<<dim3(grid), dim3(block), 0, st>>>(A);
+  else
+    k_fwd32<K, P><<<dim3(grid), dim3(block), 0, st>>>(A);
+}
+
+hipError_t launch_forward(bool fp64, int K, bool persistent, const FwdArgs& A, unsigned grid,
+                          unsigned block, hipStream_t st) {
+  switch (K) {
+    case 1: persistent ? fwd_launch<1, true>(fp64, A, grid, block, st)
+                       : fwd_launch<1, false>(fp64, A, grid, block, st); break;
+    case 2: persistent ? fwd_launch<2, true>(fp64, A, grid, block, st)
+                       : fwd_launch<2, false>(fp64, A, grid, block, st); break;
+    case 4: persistent ? fwd_launch<4, true>(fp64, A, grid, block, st)
+                       : fwd_launch<4, false>(fp64, A, grid, block, st); break;
+    case 8: persistent ? fwd_launch<8, true>(fp64, A, grid, block, st)
+                       : fwd_launch<8, false>(fp64, A, grid, block, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pixtab(int64_t nside, int64_t npix, const double* dmap, float* tab32,
+                         double* tab64, hipStream_t st) {
+  k_pixtab<<<dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, st>>>(nside, npix, dmap, tab32,
+                                                                        tab64);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint(const AdjArgs& A, hipStream_t st) {
+  if (A.nitems == 0) return hipSuccess;
+  const unsigned grid = (unsigned)((A.nitems + 3) / 4);
+  k_adj32<<<dim3(grid), dim3(256), 0, st>>>(A);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_finalize(const DevBox* boxes, const DevBoxCount* counts, int32_t b,
+                               int64_t nseg, const char* raw, const int32_t* orig_index,
+                               const double* phat64, const double* partial, int32_t nsplit,
+                               double* gx, double* gxd, double* gxp, double* gds,
+                               hipStream_t st) {
+  if (nseg <= 0) return hipSuccess;
+  GradPtrs o{gx, gxd, gxp, gds};
+  k_adj_finalize<<<dim3((unsigned)((nseg + 255) / 256)), dim3(256), 0, st>>>(
+      boxes, counts, b, raw, orig_index, phat64, partial, nsplit, o);
+  return hipGetLastError();
+}
+
+}  // namespace csmap

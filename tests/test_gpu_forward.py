@@ -1,0 +1,259 @@
+"""GPU parity of the forward path against the FP64 oracle.
+
+Every case runs the HIP library through its C ABI (ctypes binding) and the
+oracle on the same seeded inputs.  Bars: pixel directions and pair counts
+bit-exact; FP64 form within 1e-12 (relative rms and relative max over the
+checked pixels); FP32C form within rel-rms 1e-5 and rel-max 1e-4."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import err_metrics, sky_from_workload
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+FP64_TOL = 1e-12
+FP32_RMS, FP32_MAX = 1e-5, 1e-4
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1204_5041_amd import binding
+    assert torch.cuda.is_available()
+    return binding
+
+
+# ----------------------------------------------------------------------------
+# Pixel directions
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("nside", [1, 2, 3, 5, 16, 64, 512])
+def test_pix2vec_bit_exact_all_pixels(B, nside):
+    say(f"pix2vec all pixels nside={nside}")
+    gpu = B.pix2vec_ring(nside).cpu().numpy()
+    ref = oracle.pix2vec(nside, np.arange(12 * nside * nside))
+    assert np.array_equal(gpu.view(np.uint64), ref.view(np.uint64))
+
+
+@pytest.mark.parametrize("nside", [2048, 4096, 8192])
+def test_pix2vec_bit_exact_sampled(B, nside):
+    say(f"pix2vec sampled nside={nside}")
+    npx = 12 * nside * nside
+    gpu = B.pix2vec_ring(nside)
+    pick = synth.sample_pixels(npx, 200_000, seed=nside)
+    # ring boundaries and the last pixels too
+    extra = np.array([0, 1, 2, 3, 4, npx - 1, npx - 2, 2 * nside * (nside - 1),
+                      2 * nside * (nside - 1) - 1, npx - 2 * nside * (nside - 1),
+                      npx // 2, npx // 2 - 1], dtype=np.int64)
+    pick = np.unique(np.concatenate([pick, extra]))
+    ref = oracle.pix2vec(nside, pick)
+    got = gpu[torch.from_numpy(pick).cuda()].cpu().numpy()
+    assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))
+
+
+# ----------------------------------------------------------------------------
+# Small workloads covering every rule, with ragged tiles
+# ----------------------------------------------------------------------------
+def mixed_workload(nside=13, dtype=np.float64, n=(300, 0, 257, 120, 64)):
+    eta0 = 3.0
+    boxes = [
+        synth.make_box(n[0], 31, origin=(-0.5, -0.5, -0.5), eta_lo=2.2, eta_hi=3.0, dtype=dtype),
+        synth.make_box(n[1], 32, origin=(0.2, 0.1, 0.3), eta_lo=0.0, eta_hi=3.0, dtype=dtype),
+        synth.make_box(n[2], 33, origin=(0.8, -0.4, 0.2), eta_lo=0.9, eta_hi=1.6, dtype=dtype,
+                       vis=synth.VIS_BOX),
+        synth.make_box(n[3], 34, origin=(-1.9, 0.4, -0.6), eta_lo=0.0, eta_hi=3.0, dtype=dtype,
+                       vis=synth.VIS_CAP, cap_dir=np.array([-0.8, 0.6, 0.0]), cap_cos=0.7),
+        synth.make_box(n[4], 35, origin=(0.3, 1.2, -1.5), eta_lo=-5.0, eta_hi=0.9, dtype=dtype,
+                       vis=synth.VIS_BOX),
+    ]
+    return synth.Workload("mixed", nside, eta0, boxes)
+
+
+def expected_pairs(w):
+    pix = np.arange(w.npix)
+    tot = 0
+    for bx in w.boxes:
+        if bx.n == 0:
+            continue
+        tot += int(oracle.visible(w.nside, pix, w.eta0, bx).sum()) * int(oracle.kept(w.eta0, bx).sum())
+    return tot
+
+
+@pytest.fixture(scope="module")
+def mixed():
+    w = mixed_workload()
+    ref = oracle.theta_pixels(w.nside, np.arange(w.npix), w.eta0, w.boxes)
+    return w, ref, expected_pairs(w)
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32c"])
+@pytest.mark.parametrize("K", [1, 2, 4, 8])
+@pytest.mark.parametrize("schedule", [0, 1, 2])
+def test_mixed_rules_all_shapes(B, mixed, form, K, schedule):
+    w, ref, pairs = mixed
+    say(f"mixed form={form} K={K} schedule={schedule}")
+    f = B.CSMAP_FORM_FP64 if form == "fp64" else B.CSMAP_FORM_FP32C
+    sky = sky_from_workload(w, f, {B.CSMAP_OPT_PIX_PER_LANE: K, B.CSMAP_OPT_SCHEDULE: schedule,
+                                   B.CSMAP_OPT_WAVES: 2})
+    m = sky.render().cpu().numpy()
+    st = sky.stats()
+    e = err_metrics(m, ref)
+    assert st["pairs"] == pairs
+    assert st["kept"] == sum(int(oracle.kept(w.eta0, b).sum()) for b in w.boxes)
+    if form == "fp64":
+        assert e["rel_rms"] <= FP64_TOL and e["rel_max"] <= FP64_TOL, e
+    else:
+        assert e["rel_rms"] <= FP32_RMS and e["rel_max"] <= FP32_MAX, e
+    sky.close()
+
+
+@pytest.mark.parametrize("near_w", [1e-3, 5e-3, 0.2, 3.0])
+def test_fp32c_near_threshold_any_value_within_gate(B, mixed, near_w):
+    """Small values send most pairs through the dot-product form, >= 2 sends
+    every pair through the FP64 difference; both stay within the gate on
+    this well-separated workload, and the literal form is the tighter one."""
+    w, ref, _ = mixed
+    sky = sky_from_workload(w, B.CSMAP_FORM_FP32C, {B.CSMAP_OPT_NEAR_W: near_w})
+    m = sky.render().cpu().numpy()
+    st = sky.stats()
+    e = err_metrics(m, ref)
+    say(f"near_w={near_w} {e} near_steps={st['near_steps']}")
+    if near_w >= 2:
+        assert e["rel_rms"] <= 2e-6
+    if near_w > 0:
+        assert e["rel_rms"] <= FP32_RMS and e["rel_max"] <= FP32_MAX, e
+    sky.close()
+
+
+def test_graph_replay_matches_eager_and_is_deterministic(B, mixed):
+    w, ref, _ = mixed
+    sky = sky_from_workload(w, B.CSMAP_FORM_FP32C, {B.CSMAP_OPT_SCHEDULE: 1})
+    eager = sky.render().cpu().numpy()
+    eager2 = sky.render().cpu().numpy()
+    assert np.array_equal(eager, eager2)
+    sky.set_option(B.CSMAP_OPT_GRAPH, 1)
+    out = torch.empty(w.npix, dtype=torch.float64, device="cuda")
+    for rep in range(4):
+        out.fill_(float("nan"))
+        torch.cuda.synchronize()
+        sky.render(out)
+        got = out.cpu().numpy()
+        assert np.array_equal(got, eager), rep
+        _ = torch.ones(1000, device="cuda").sum().item()   # unrelated eager work between replays
+    sky.close()
+
+
+def test_empty_sky_and_empty_box(B):
+    w = synth.Workload("empty", 4, 1.0, [])
+    sky = sky_from_workload(w, B.CSMAP_FORM_FP32C)
+    m = sky.render().cpu().numpy()
+    assert np.all(m == 0.0) and sky.stats()["pairs"] == 0
+    sky.close()
+    w2 = mixed_workload(nside=2, n=(0, 0, 0, 0, 0))
+    sky = sky_from_workload(w2, B.CSMAP_FORM_FP64)
+    assert np.all(sky.render().cpu().numpy() == 0.0)
+    sky.close()
+
+
+def test_exact_coincidence_is_zero(B):
+    # Nside=1 pixel 4 is exactly +x; a segment at (0.5, 0, 0) sits on it.
+    x = np.array([[0.5, 0.0, 0.0], [0.1, 0.3, -0.2]])
+    xd = np.array([[0.0, 0.5, 0.0], [0.3, 0.0, 0.1]])
+    xp = np.array([[0.0, 0.0, math.sqrt(0.75)], [0.0, 0.6, 0.0]])
+    ds = np.array([0.01, 0.01])
+    bx = synth.Box(origin=np.zeros(3), ext=np.ones(3), eta_lo=-10, eta_hi=10, x_rel=x, xdot=xd,
+                   xprime=xp, dsigma=ds)
+    w = synth.Workload("coincide", 1, 1.0, [bx])
+    ref = oracle.theta_pixels(1, np.arange(12), 1.0, [bx])
+    for form in (B.CSMAP_FORM_FP64, B.CSMAP_FORM_FP32C):
+        sky = sky_from_workload(w, form)
+        m = sky.render().cpu().numpy()
+        assert np.all(np.isfinite(m))
+        e = err_metrics(m, ref)
+        assert e["rel_max"] <= (FP64_TOL if form == B.CSMAP_FORM_FP64 else FP32_MAX), e
+        sky.close()
+
+
+# ----------------------------------------------------------------------------
+# The benchmark workloads
+# ----------------------------------------------------------------------------
+def test_config0_fp64_every_pixel(B):
+    w = synth.config0()
+    say("config0 oracle")
+    ref = oracle.theta_pixels(w.nside, np.arange(w.npix), w.eta0, w.boxes)
+    for form, tol in ((B.CSMAP_FORM_FP64, (FP64_TOL, FP64_TOL)),
+                      (B.CSMAP_FORM_FP32C, (FP32_RMS, FP32_MAX))):
+        say(f"config0 form={form}")
+        sky = sky_from_workload(w, form)
+        m = sky.render().cpu().numpy()
+        e = err_metrics(m, ref)
+        say(f"config0 form={form} {e}")
+        assert sky.stats()["pairs"] == w.npix * 2000
+        assert e["rel_rms"] <= tol[0] and e["rel_max"] <= tol[1], e
+        sky.close()
+
+
+@pytest.fixture(scope="module")
+def config1():
+    w = synth.config1()
+    npx = w.npix
+    pix = np.arange(npx)
+    seen = np.zeros(npx, dtype=bool)
+    vis_counts, kept_counts = [], []
+    for bx in w.boxes:
+        v = oracle.visible(w.nside, pix, w.eta0, bx)
+        seen |= v
+        vis_counts.append(int(v.sum()))
+        kept_counts.append(int(oracle.kept(w.eta0, bx).sum()))
+    rng = np.random.Generator(np.random.PCG64(25))
+    check = np.sort(rng.choice(np.flatnonzero(seen), size=10_000, replace=False))
+    ref = oracle.theta_pixels(w.nside, check, w.eta0, w.boxes)
+    pairs = sum(a * b for a, b in zip(vis_counts, kept_counts))
+    return w, check, ref, pairs
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32c"])
+def test_config1_shell_of_24_boxes(B, config1, form):
+    w, check, ref, pairs = config1
+    f = B.CSMAP_FORM_FP64 if form == "fp64" else B.CSMAP_FORM_FP32C
+    say(f"config1 form={form}")
+    sky = sky_from_workload(w, f)
+    m = sky.render().cpu().numpy()
+    st = sky.stats()
+    e = err_metrics(m[check], ref)
+    say(f"config1 form={form} {e} pairs={st['pairs']} ms={st['ms_forward']:.1f}")
+    assert st["pairs"] == pairs
+    if form == "fp64":
+        assert e["rel_rms"] <= FP64_TOL and e["rel_max"] <= FP64_TOL, e
+    else:
+        assert e["rel_rms"] <= FP32_RMS and e["rel_max"] <= FP32_MAX, e
+    sky.close()
+
+
+def test_config2_one_box_full_sky(B):
+    """Nside=2048 and one 400,000-segment box (the benchmark step): the FP32C
+    map on 2,000 sampled pixels against the oracle."""
+    w = synth.config2(boxes=[0])
+    check = synth.sample_pixels(w.npix, 2000, seed=98)
+    say("config2 box0 oracle")
+    ref = oracle.theta_pixels(w.nside, check, w.eta0, w.boxes)
+    say("config2 box0 gpu")
+    sky = sky_from_workload(w, B.CSMAP_FORM_FP32C)
+    m = sky.render()
+    got = m[torch.from_numpy(check).cuda()].cpu().numpy()
+    st = sky.stats()
+    e = err_metrics(got, ref)
+    say(f"config2 {e} pairs={st['pairs']} ms={st['ms_forward']:.1f} near={st['near_steps']}")
+    assert st["pairs"] == w.npix * 400_000
+    assert e["rel_rms"] <= FP32_RMS and e["rel_max"] <= FP32_MAX, e
+    sky.close()
