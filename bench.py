@@ -72,6 +72,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=6000)
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="before the timed region, run one plain device copy of this many "
+                         "MiB (a known-size reference for hardware traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -81,6 +84,15 @@ def main():
     import torch
     from paper_1204_5041_amd import binding as B
     assert torch.cuda.is_available(), "no GPU visible"
+
+    if args.copy_calib_mib > 0:
+        n = args.copy_calib_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     W, K = args.warmup, args.steps
     _log(f"bench: generating {W + K} boxes of {args.nseg:,} segments")
