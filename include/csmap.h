@@ -121,19 +121,23 @@ typedef enum {
     /* Pixels per lane of the forward kernels: 1, 2, 4 or 8.  A tile is
      * 64 x this many consecutive RING pixels, owned by one wavefront. */
     CSMAP_OPT_PIX_PER_LANE = 2,
-    /* Wavefronts per workgroup: 1, 2, 4 or 8. */
+    /* Wavefronts per workgroup: 1, 2 or 4. */
     CSMAP_OPT_WAVES = 3,
     /* FP32C form: pairs with 1 - n.P/R below this value (default 5e-3, an
      * angle of about 0.1 rad) take the FP64 direction difference; the others
      * use the algebraically equal FP32 form built from 1 - n.P/R.  A value
-     * >= 2 sends every pair through the FP64 difference. */
+     * >= 2 sends every pair through the FP64 difference.  Minimum 1e-6. */
     CSMAP_OPT_NEAR_W = 4,
     /* Segments per FP32 partial sum before the Kahan-compensated update of a
-     * pixel's running sum (FP32C form): 8 .. 4096. */
+     * pixel's running sum (FP32C form): a multiple of 4 in 8 .. 4096. */
     CSMAP_OPT_CHUNK = 5,
     /* Adjoint: number of pixel chunks each segment's sum is split into
      * (0 = chosen by the library). */
-    CSMAP_OPT_ADJ_SPLIT = 6
+    CSMAP_OPT_ADJ_SPLIT = 6,
+    /* FP32C forward: 0 = one reciprocal per pair; 1 = the terms of up to four
+     * consecutive far segments are combined into one fraction per pixel
+     * (p/q + m/d = (p d + m q)/(q d)) and divided once. */
+    CSMAP_OPT_ACCUM = 7
 } csmap_option;
 
 /* Counters of the last render/backward (csmap_get_stats synchronises). */

@@ -22,7 +22,7 @@ CSMAP_FORM_FP64, CSMAP_FORM_FP32C = 0, 1
 CSMAP_F32, CSMAP_F64 = 0, 1
 CSMAP_VIS_ALL, CSMAP_VIS_BOX, CSMAP_VIS_CAP = 0, 1, 2
 (CSMAP_OPT_SCHEDULE, CSMAP_OPT_GRAPH, CSMAP_OPT_PIX_PER_LANE, CSMAP_OPT_WAVES, CSMAP_OPT_NEAR_W,
- CSMAP_OPT_CHUNK, CSMAP_OPT_ADJ_SPLIT) = range(7)
+ CSMAP_OPT_CHUNK, CSMAP_OPT_ADJ_SPLIT, CSMAP_OPT_ACCUM) = range(8)
 
 _STATUS_NAMES = {0: "CSMAP_OK", -1: "CSMAP_E_INVALID", -2: "CSMAP_E_NOMEM", -3: "CSMAP_E_DEVICE",
                  -4: "CSMAP_E_STATE", -5: "CSMAP_E_UNSUPPORTED"}

@@ -25,6 +25,8 @@ hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
 hipError_t launch_zero_counters(unsigned long long* c, int n, uint32_t* work, hipStream_t st);
 hipError_t launch_pix2vec(int64_t nside, int64_t first, int64_t count, double* xyz,
                           hipStream_t st);
+hipError_t launch_dir_table(int64_t nside, int64_t npix, double* x, double* y, double* z,
+                            hipStream_t st);
 hipError_t launch_forward(bool fp64, int K, bool persistent, const FwdArgs& A, unsigned grid,
                           unsigned block, hipStream_t st);
 hipError_t launch_pixtab(int64_t nside, int64_t npix, const double* dmap, float* tab32,
@@ -94,14 +96,15 @@ struct csmap_sky {
   hipStream_t stream = nullptr;
   bool failed = false;
 
-  // options
-  int K = 4;
+  // options (defaults: the fastest measured shape for the FP32C form)
+  int K = 8;
   int waves = 4;
-  int schedule = 0;
+  int schedule = 1;
   int graph = 0;
   int chunk = 32;
   double near_w = 5e-3;
   int adj_split = 0;
+  int frac = 1;
 
   // boxes and raw segment storage (append-only)
   std::vector<HostBox> boxes;
@@ -121,6 +124,8 @@ struct csmap_sky {
   int64_t nitems_sorted = 0;
   bool all_boxes = true;
   DevBuf d_counters;  // [0] pairs, [1] near steps, [2] work counter (uint32)
+  DevBuf d_dir;       // pixel directions, x | y | z (npix doubles each)
+  bool dir_ready = false;
 
   // adjoint scratch
   DevBuf d_pixtab32, d_pix64, d_partial, d_adj_items;
@@ -221,6 +226,13 @@ csmap_status prepare(csmap_sky* s) {
     HIPCHK(s, s->d_phat64.ensure(sizeof(double) * 4 * nrec), "alloc records");
   }
   HIPCHK(s, s->d_counters.ensure(64), "alloc counters");
+  if (!s->dir_ready) {
+    HIPCHK(s, s->d_dir.ensure(sizeof(double) * 3 * (size_t)s->npix), "alloc direction table");
+    double* d = s->d_dir.as<double>();
+    HIPCHK(s, launch_dir_table(s->nside, s->npix, d, d + s->npix, d + 2 * s->npix, st),
+           "direction table");
+    s->dir_ready = true;
+  }
   if (nbox) {
     HIPCHK(s, hipMemcpyAsync(s->d_boxes.p, db.data(), sizeof(DevBox) * nbox,
                              hipMemcpyHostToDevice, st), "upload boxes");
@@ -330,10 +342,14 @@ FwdArgs fwd_args(csmap_sky* s, double* map) {
   A.nside = s->nside;
   A.npix = s->npix;
   A.eta0 = s->eta0;
+  A.dirx = s->d_dir.as<double>();
+  A.diry = A.dirx + s->npix;
+  A.dirz = A.dirx + 2 * s->npix;
   A.rec32 = s->d_rec32.as<float>();
   A.phat64 = s->d_phat64.as<double>();
   A.rec64 = s->d_rec64.as<double>();
   A.near_w = (float)s->near_w;
+  A.frac = s->frac;
   A.chunk = s->chunk;
   A.accumulate = 0;
   A.only_box = -1;
@@ -452,7 +468,7 @@ csmap_status csmap_destroy_sky(csmap_sky* s) {
                     &s->d_box_count, &s->d_raw_off, &s->d_rec32, &s->d_phat64, &s->d_rec64,
                     &s->d_orig, &s->d_tile_ptr, &s->d_tile_boxes, &s->d_items,
                     &s->d_box_items, &s->d_counters, &s->d_pixtab32, &s->d_pix64,
-                    &s->d_partial, &s->d_adj_items};
+                    &s->d_partial, &s->d_adj_items, &s->d_dir};
   for (DevBuf* b : bufs) b->release();
   delete s;
   return CSMAP_OK;
@@ -570,15 +586,20 @@ csmap_status csmap_set_option(csmap_sky* s, csmap_option opt, double value) {
       s->K = iv;
       break;
     case CSMAP_OPT_WAVES:
-      if (!valid_pow_choice(iv)) return fail(CSMAP_E_INVALID, "waves must be 1, 2, 4 or 8");
+      if (iv != 1 && iv != 2 && iv != 4) return fail(CSMAP_E_INVALID, "waves must be 1, 2 or 4");
       s->waves = iv;
       break;
     case CSMAP_OPT_NEAR_W:
-      if (!(value >= 0.0)) return fail(CSMAP_E_INVALID, "near threshold must be >= 0");
+      if (!(value >= 1e-6)) return fail(CSMAP_E_INVALID, "near threshold must be >= 1e-6");
       s->near_w = value;
       break;
+    case CSMAP_OPT_ACCUM:
+      if (iv < 0 || iv > 1) return fail(CSMAP_E_INVALID, "accumulation mode must be 0 or 1");
+      s->frac = iv;
+      break;
     case CSMAP_OPT_CHUNK:
-      if (iv < 8 || iv > 4096) return fail(CSMAP_E_INVALID, "chunk must be in [8, 4096]");
+      if (iv < 8 || iv > 4096 || (iv & 3))
+        return fail(CSMAP_E_INVALID, "chunk must be a multiple of 4 in [8, 4096]");
       s->chunk = iv;
       break;
     case CSMAP_OPT_ADJ_SPLIT:

@@ -36,7 +36,9 @@ struct DevBoxCount {
 //   [10]    kappa (1 + (P/R).V)            (c1, FP64 then rounded)
 //   [11]    kappa (P/R).T                  (c2, FP64 then rounded)
 //   [12]    index of the segment inside its box (bit pattern of an int32)
-//   [13..15] unused
+//   [13]    1 if the segment must always take the close-pair form
+//           (1 - |Xdot| < 0.05), else 0
+//   [14..15] unused
 constexpr int kRec32 = 16;
 // FP64 record: 16 doubles.
 //   [0..2] P/R rounded (hi), [3..5] X', [6..8] Xdot, [9] -4 eps dsigma / R,
@@ -75,6 +77,9 @@ struct FwdArgs {
   uint32_t* work_counter;      // persistent schedule: next item
   int64_t nside, npix;
   double eta0;
+  const double* dirx;          // pixel direction table (RING order, FP64)
+  const double* diry;
+  const double* dirz;
   const float* rec32;
   const double* phat64;
   const double* rec64;
@@ -82,6 +87,7 @@ struct FwdArgs {
   int32_t chunk;
   int32_t accumulate;          // 1: map += contribution (per-box schedule)
   int32_t only_box;            // per-box schedule: the one box (else -1)
+  int32_t frac;                // FP32C: fold far pairs into a running fraction
   double* map;
   unsigned long long* pairs;   // pair counter
   unsigned long long* near_steps;

@@ -222,7 +222,9 @@ __global__ void __launch_bounds__(kPreBlock) k_pre_emit(PreArgs A) {
     o[0] = make_float4((float)Ph[0], (float)Ph[1], (float)Ph[2], (float)g.T[0]);
     o[1] = make_float4((float)g.T[1], (float)g.T[2], (float)g.V[0], (float)g.V[1]);
     o[2] = make_float4((float)g.V[2], (float)kh, (float)(kh * (1.0 + pv)), (float)(kh * pt));
-    o[3] = make_float4(__int_as_float((int)i), 0.f, 0.f, 0.f);
+    const double vv = (g.V[0] * g.V[0] + g.V[1] * g.V[1]) + g.V[2] * g.V[2];
+    const float force_near = (1.0 - sqrt(vv) < 0.05) ? 1.0f : 0.0f;
+    o[3] = make_float4(__int_as_float((int)i), force_near, 0.f, 0.f);
     double2* h = (double2*)(A.phat64 + (size_t)r * 4);
     h[0] = make_double2(Ph[0], Ph[1]);
     h[1] = make_double2(Ph[2], g.R);
@@ -261,6 +263,17 @@ __global__ void k_zero_counters(unsigned long long* c, int n, uint32_t* work) {
   if (threadIdx.x == 0 && work) *work = 0u;
 }
 
+// Direction table in structure-of-arrays form (x, y, z each npix doubles).
+__global__ void k_dir_table(int64_t nside, int64_t npix, double* x, double* y, double* z) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npix) return;
+  double a, b, c;
+  pix2vec_ring(nside, i, &a, &b, &c);
+  x[i] = a;
+  y[i] = b;
+  z[i] = c;
+}
+
 __global__ void k_pix2vec(int64_t nside, int64_t first, int64_t count, double* xyz) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
@@ -286,16 +299,59 @@ __device__ __forceinline__ int32_t tile_of(const FwdArgs& A, int64_t item) {
   return A.items ? ((ci32p)A.items)[item] : (int32_t)item;
 }
 
-// Kahan update of (s, c) by x, applied only where `on`.
-__device__ __forceinline__ void kahan_add(float& s, float& c, float x, bool on) {
-  const float y = x - c;
-  const float t = s + y;
-  const float cn = (t - s) - y;
-  s = on ? t : s;
-  c = on ? cn : c;
+// Lane offset into a row of 64 pixels starting at `row`, clamped to the
+// last pixel of the map.
+__device__ __forceinline__ int32_t dir_off(int64_t npix, int64_t row, int lane) {
+  const int64_t room = npix - 1 - row;
+  const int32_t lim = room < 63 ? (int32_t)room : 63;
+  return lane < lim ? lane : lim;
 }
 
-template <int K, bool PERSISTENT>
+// Kahan update of (s, c) by x: s - c carries the sum.
+__device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
+  const float y = x - c;
+  const float t = s + y;
+  c = (t - s) - y;
+  s = t;
+}
+
+// Copy a wave-uniform value into a vector register.
+__device__ __forceinline__ float to_vgpr(float x) {
+  float y;
+  asm("v_mov_b32 %0, %1" : "=v"(y) : "s"(x));
+  return y;
+}
+
+// Terms of one segment for close pairs: the direction difference n - P/R
+// is taken in FP64 (n from this wavefront's LDS slice, P/R from the FP64
+// record) and the rest in FP32.  An exact coincidence gives m = 0 and a
+// finite reciprocal, so that term is 0.
+template <int K>
+__device__ __forceinline__ void near_terms(const float (&nf)[K][3], const double* sdir, int lane,
+                                           const v4f r0, const v4f r1, const v4f r2,
+                                           const float (&a)[K], const float (&b)[K], cd2p hp,
+                                           float (&part)[K]) {
+  const v2d h0 = hp[0];
+  const v2d h1 = hp[1];
+  const float tx = r0.w, ty = r1.x, tz = r1.y;
+  const float vx = r1.z, vy = r1.w, vz = r2.x;
+  const float kap = r2.y;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const float dx = (float)(sdir[(j * 3 + 0) * 64 + lane] - h0.x);
+    const float dy = (float)(sdir[(j * 3 + 1) * 64 + lane] - h0.y);
+    const float dz = (float)(sdir[(j * 3 + 2) * 64 + lane] - h1.x);
+    const float q = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    const float t1 = kap * fmaf(vz, dz, fmaf(vy, dy, vx * dx));
+    const float t2 = kap * fmaf(tz, dz, fmaf(ty, dy, tx * dx));
+    const float m = fmaf(-a[j], t2, t1 * b[j]);
+    const float den = b[j] * fmaxf(0.5f * q, 1e-30f);
+    part[j] = fmaf(m, __builtin_amdgcn_rcpf(den), part[j]);
+  }
+  (void)nf;
+}
+
+template <int K, bool PERSISTENT, bool FRAC>
 __global__ void __launch_bounds__(256) k_fwd32(FwdArgs A) {
   const int lane = threadIdx.x & 63;
   const int wpb = blockDim.x >> 6;
@@ -308,19 +364,34 @@ __global__ void __launch_bounds__(256) k_fwd32(FwdArgs A) {
   const float near_w = A.near_w;
   cf4p recs = (cf4p)A.rec32;
   cd2p ph64 = (cd2p)A.phat64;
+  // Dynamic LDS: K x 3 x 64 doubles per wavefront of the workgroup.
+  extern __shared__ double sdir_all[];
+  double* const sdir = sdir_all + wave * (K * 3 * 64);
   while (item < A.nitems) {
     const int64_t tile = tile_of(A, item);
     const int64_t base = tile * (64 * K);
-    double nd[K][3];
+    // Pixel directions come from the table written by the RING pix2vec
+    // kernel; only their FP32 copies stay in registers across the segment
+    // loop (FP64 values are reloaded by the rare close-pair steps).
+    // Lane l of row j owns pixel base + 64 j + l; rows past the end of the
+    // map repeat its last pixel (those lanes are masked out of every sum and
+    // never written).  The FP64 directions are parked in this wavefront's
+    // slice of LDS for the close-pair steps and visibility tests; only the
+    // FP32 copies stay in registers.
     float nf[K][3];
     bool inmap[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-      const int64_t p = base + j * 64 + lane;
-      inmap[j] = p < A.npix;
-      pix2vec_ring(A.nside, inmap[j] ? p : A.npix - 1, &nd[j][0], &nd[j][1], &nd[j][2]);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) nf[j][k] = (float)nd[j][k];
+      const int64_t row = base + j * 64;
+      inmap[j] = row + lane < A.npix;
+      const int32_t off = dir_off(A.npix, row, lane);
+      const double x = A.dirx[row + off], y = A.diry[row + off], z = A.dirz[row + off];
+      sdir[(j * 3 + 0) * 64 + lane] = x;
+      sdir[(j * 3 + 1) * 64 + lane] = y;
+      sdir[(j * 3 + 2) * 64 + lane] = z;
+      nf[j][0] = (float)x;
+      nf[j][1] = (float)y;
+      nf[j][2] = (float)z;
     }
     float S[K], C[K];
 #pragma unroll
@@ -332,88 +403,193 @@ __global__ void __launch_bounds__(256) k_fwd32(FwdArgs A) {
     for (int32_t bi = b0; bi < b1; ++bi) {
       const int32_t b = (A.all_boxes || A.only_box >= 0) ? bi : ((ci32p)A.tile_boxes)[bi];
       const DevBox bx = load_box(A.boxes, b);
-      bool vis[K];
-      bool anyv = false;
+      // Visibility as a per-lane 0/1 weight: partial sums of pixels that do
+      // not see the box are multiplied by 0 before they reach the running
+      // sum (the arithmetic on those lanes stays finite).
+      float vis[K];
+      unsigned long long nvis = 0;
 #pragma unroll
       for (int j = 0; j < K; ++j) {
-        vis[j] = inmap[j] && sees_box(nd[j][0], nd[j][1], nd[j][2], bx, A.eta0);
-        anyv |= vis[j];
+        const bool v = inmap[j] && (bx.vis == 0 || sees_box(sdir[(j * 3 + 0) * 64 + lane],
+                                                             sdir[(j * 3 + 1) * 64 + lane],
+                                                             sdir[(j * 3 + 2) * 64 + lane], bx,
+                                                             A.eta0));
+        vis[j] = v ? 1.0f : 0.0f;
+        nvis += __popcll(__ballot(v));
       }
-      if (!__any(anyv)) continue;
+      if (nvis == 0) continue;
       const int64_t r0 = bx.rec_off;
       const int64_t r1 = r0 + load_kept(A.box_count, b);
-      {
-        unsigned long long nvis = 0;
+      if (lane == 0 && r1 > r0) atomicAdd(A.pairs, nvis * (unsigned long long)(r1 - r0));
+      if (r1 == r0) continue;
+      if constexpr (FRAC) {
+      // Far terms m/d of a pixel are folded into one fraction over windows
+      // of four consecutive segments, (p/q) + m/d = (p d + m q)/(q d), and
+      // divided once per window.  On this path d = b w >= 0.05 * near_w, so
+      // a product of four stays well inside the FP32 range.  Close pairs are
+      // added one by one.  Each window slot is a separate copy of the step,
+      // so its update of (p, q) is fixed at compile time.
+      const int64_t nseg = r1 - r0;
+      const int64_t nwin = (nseg + 3) >> 2;
+      const cf4p last = recs + 4 * (r1 - 1);
+      cf4p rp = recs + 4 * r0;
+      v4f q0 = rp[0], q1 = rp[1], q2 = rp[2], q3 = rp[3];
+      float part[K], fp[K], fq[K];
 #pragma unroll
-        for (int j = 0; j < K; ++j) nvis += __popcll(__ballot(vis[j]));
-        if (lane == 0 && r1 > r0) atomicAdd(A.pairs, nvis * (unsigned long long)(r1 - r0));
-      }
-      for (int64_t c0 = r0; c0 < r1; c0 += A.chunk) {
-        const int64_t c1 = (c0 + A.chunk < r1) ? c0 + A.chunk : r1;
-        float part[K];
+      for (int j = 0; j < K; ++j) { part[j] = 0.f; fp[j] = 0.f; fq[j] = 1.f; }
+      int32_t left = A.chunk;   // segments until the next Kahan update (multiple of 4)
+      for (int64_t win = 0; win < nwin; ++win) {
+        const int32_t nslot = (win + 1 < nwin) ? 4 : (int32_t)(nseg - 4 * win);
 #pragma unroll
-        for (int j = 0; j < K; ++j) part[j] = 0.f;
-        // 32-bit trip count so that the loop control stays on the scalar unit.
-        const int32_t nk = (int32_t)(c1 - c0);
-        cf4p rp = recs + 4 * c0;
-        cd2p hp = ph64 + 2 * c0;
-        for (int32_t k = 0; k < nk; ++k, rp += 4, hp += 2) {
-          const v4f q0 = rp[0];
-          const v4f q1 = rp[1];
-          const v4f q2 = rp[2];
-          const float px = q0.x, py = q0.y, pz = q0.z;
-          const float tx = q0.w, ty = q1.x, tz = q1.y;
-          const float vx = q1.z, vy = q1.w, vz = q2.x;
-          const float kap = q2.y, c1v = q2.z, c2v = q2.w;
-          float w[K], a[K], bb[K], t1[K], t2[K], den[K];
-          bool nearp = false;
-#pragma unroll
-          for (int j = 0; j < K; ++j) {
-            w[j] = fmaf(-nf[j][2], pz, fmaf(-nf[j][1], py, fmaf(-nf[j][0], px, 1.0f)));
-            a[j] = fmaf(nf[j][2], tz, fmaf(nf[j][1], ty, nf[j][0] * tx));
-            bb[j] = fmaf(nf[j][2], vz, fmaf(nf[j][1], vy, fmaf(nf[j][0], vx, 1.0f)));
-            nearp |= (w[j] < near_w);
-          }
-          if (!__any(nearp)) {
-            // kappa/2 times Xdot.(n - Ph) and X'.(n - Ph) from the dot products.
-#pragma unroll
-            for (int j = 0; j < K; ++j) {
-              t1[j] = fmaf(kap, bb[j], -c1v);
-              t2[j] = fmaf(kap, a[j], -c2v);
-              den[j] = bb[j] * w[j];
-            }
-          } else {
-            // Close pairs: the difference of directions in FP64.  An exact
-            // coincidence (n == Ph) gives m = 0 and a finite reciprocal, so
-            // the term is 0.
-            ++near_steps;
-            const v2d h0 = hp[0];
-            const v2d h1 = hp[1];
+        for (int slot = 0; slot < 4; ++slot) {
+          if (slot < nslot) {
+            const cf4p pf = (rp != last) ? rp + 4 : rp;
+            __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): q0..q3 have arrived
+            const v4f n0 = pf[0], n1 = pf[1], n2 = pf[2], n3 = pf[3];
+            // Segment constants copied to vector registers once per step:
+            // FMAs whose operands are all vector registers issue at twice the
+            // rate of those reading a scalar register.
+            const float px = to_vgpr(q0.x), py = to_vgpr(q0.y), pz = to_vgpr(q0.z);
+            const float tx = to_vgpr(q0.w), ty = to_vgpr(q1.x), tz = to_vgpr(q1.y);
+            const float vx = to_vgpr(q1.z), vy = to_vgpr(q1.w), vz = to_vgpr(q2.x);
+            const float kap = to_vgpr(q2.y), c1v = to_vgpr(q2.z), c2v = to_vgpr(q2.w);
+            float w[K], a[K], bb[K];
+            bool nearp = false;
 #pragma unroll
             for (int j = 0; j < K; ++j) {
-              const float dx = (float)(nd[j][0] - h0.x);
-              const float dy = (float)(nd[j][1] - h0.y);
-              const float dz = (float)(nd[j][2] - h1.x);
-              const float q = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-              t1[j] = kap * fmaf(vz, dz, fmaf(vy, dy, vx * dx));
-              t2[j] = kap * fmaf(tz, dz, fmaf(ty, dy, tx * dx));
-              den[j] = bb[j] * fmaxf(0.5f * q, 1e-30f);
+              w[j] = fmaf(-nf[j][2], pz, fmaf(-nf[j][1], py, fmaf(-nf[j][0], px, 1.0f)));
+              a[j] = fmaf(nf[j][2], tz, fmaf(nf[j][1], ty, nf[j][0] * tx));
+              bb[j] = fmaf(nf[j][2], vz, fmaf(nf[j][1], vy, fmaf(nf[j][0], vx, 1.0f)));
+              nearp |= (w[j] < near_w);
             }
-          }
+            if (__float_as_int(q3.y) == 0 && !__any(nearp)) {
 #pragma unroll
-          for (int j = 0; j < K; ++j) {
-            const float m = fmaf(-a[j], t2[j], t1[j] * bb[j]);   // kappa/2 * m
-            part[j] = fmaf(m, __builtin_amdgcn_rcpf(den[j]), part[j]);
+              for (int j = 0; j < K; ++j) {
+                const float t1 = fmaf(kap, bb[j], -c1v);
+                const float t2 = fmaf(kap, a[j], -c2v);
+                const float m = fmaf(-a[j], t2, t1 * bb[j]);   // kappa/2 * m
+                const float den = bb[j] * w[j];
+                if (slot == 0) {
+                  fp[j] = m;
+                  fq[j] = den;
+                } else {
+                  fp[j] = fmaf(fp[j], den, m * fq[j]);
+                  fq[j] = fq[j] * den;
+                }
+              }
+            } else {
+              ++near_steps;
+              near_terms<K>(nf, sdir, lane, q0, q1, q2, a, bb, ph64 + 2 * ((rp - recs) >> 2),
+                            part);
+              if (slot == 0) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) { fp[j] = 0.f; fq[j] = 1.f; }
+              }
+            }
+            q0 = n0;
+            q1 = n1;
+            q2 = n2;
+            q3 = n3;
+            rp = pf;
           }
         }
 #pragma unroll
-        for (int j = 0; j < K; ++j) kahan_add(S[j], C[j], part[j], vis[j]);
+        for (int j = 0; j < K; ++j) part[j] = fmaf(fp[j], __builtin_amdgcn_rcpf(fq[j]), part[j]);
+        left -= 4;
+        if (left <= 0 || win + 1 == nwin) {
+#pragma unroll
+          for (int j = 0; j < K; ++j) {
+            kahan_add(S[j], C[j], part[j] * vis[j]);
+            part[j] = 0.f;
+          }
+          left = A.chunk;
+        }
+      }
+      } else {
+      // Segment records stream through scalar registers.  The record of the
+      // next step is requested before the current one is used; the explicit
+      // wait at the top of each step covers exactly the previous request.
+      cf4p rp = recs + 4 * r0;
+      const cf4p re = recs + 4 * r1;
+      v4f q0 = rp[0], q1 = rp[1], q2 = rp[2], q3 = rp[3];
+      float part[K];
+#pragma unroll
+      for (int j = 0; j < K; ++j) part[j] = 0.f;
+      int32_t left = A.chunk;   // steps until the next Kahan update
+      while (true) {
+        const cf4p nxt = rp + 4;
+        const bool more = nxt != re;
+        __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): q0..q2 have arrived
+        const cf4p pf = more ? nxt : rp;
+        const v4f n0 = pf[0], n1 = pf[1], n2 = pf[2], n3 = pf[3];
+        const float px = q0.x, py = q0.y, pz = q0.z;
+        const float tx = q0.w, ty = q1.x, tz = q1.y;
+        const float vx = q1.z, vy = q1.w, vz = q2.x;
+        const float kap = q2.y, c1v = q2.z, c2v = q2.w;
+        float w[K], a[K], bb[K];
+        bool nearp = false;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          w[j] = fmaf(-nf[j][2], pz, fmaf(-nf[j][1], py, fmaf(-nf[j][0], px, 1.0f)));
+          a[j] = fmaf(nf[j][2], tz, fmaf(nf[j][1], ty, nf[j][0] * tx));
+          bb[j] = fmaf(nf[j][2], vz, fmaf(nf[j][1], vy, fmaf(nf[j][0], vx, 1.0f)));
+          nearp |= (w[j] < near_w);
+        }
+        // Segments flagged at precompute (|Xdot| close to 1, where b = 1 + n.Xdot
+        // may be tiny) always take the close-pair form.
+        const bool force = __float_as_int(q3.y) != 0;
+        if (!force && !__any(nearp)) {
+          // kappa/2 times Xdot.(n - Ph) and X'.(n - Ph) from the dot products.
+#pragma unroll
+          for (int j = 0; j < K; ++j) {
+            const float t1 = fmaf(kap, bb[j], -c1v);
+            const float t2 = fmaf(kap, a[j], -c2v);
+            const float m = fmaf(-a[j], t2, t1 * bb[j]);   // kappa/2 * m
+            part[j] = fmaf(m, __builtin_amdgcn_rcpf(bb[j] * w[j]), part[j]);
+          }
+        } else {
+          // Close pairs: the difference of directions in FP64.  An exact
+          // coincidence (n == Ph) gives m = 0 and a finite reciprocal, so
+          // the term is 0.
+          ++near_steps;
+          const cd2p hp = ph64 + 2 * ((rp - recs) >> 2);
+          const v2d h0 = hp[0];
+          const v2d h1 = hp[1];
+#pragma unroll
+          for (int j = 0; j < K; ++j) {
+            const float dx = (float)(sdir[(j * 3 + 0) * 64 + lane] - h0.x);
+            const float dy = (float)(sdir[(j * 3 + 1) * 64 + lane] - h0.y);
+            const float dz = (float)(sdir[(j * 3 + 2) * 64 + lane] - h1.x);
+            const float q = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+            const float t1 = kap * fmaf(vz, dz, fmaf(vy, dy, vx * dx));
+            const float t2 = kap * fmaf(tz, dz, fmaf(ty, dy, tx * dx));
+            const float m = fmaf(-a[j], t2, t1 * bb[j]);
+            const float den = bb[j] * fmaxf(0.5f * q, 1e-30f);
+            part[j] = fmaf(m, __builtin_amdgcn_rcpf(den), part[j]);
+          }
+        }
+        --left;
+        if (left == 0 || !more) {
+#pragma unroll
+          for (int j = 0; j < K; ++j) {
+            kahan_add(S[j], C[j], part[j] * vis[j]);
+            part[j] = 0.f;
+          }
+          left = A.chunk;
+        }
+        if (!more) break;
+        q0 = n0;
+        q1 = n1;
+        q2 = n2;
+        q3 = n3;
+        rp = nxt;
+      }
       }
     }
 #pragma unroll
     for (int j = 0; j < K; ++j) {
       const int64_t p = base + j * 64 + lane;
-      if (inmap[j]) {
+      if (p < A.npix) {
         // The running sum s carries the result; c is the negated rounding
         // error still owed to it, so the value is s - c.
         const double v = (double)S[j] - (double)C[j];
@@ -454,7 +630,10 @@ __global__ void __launch_bounds__(256) k_fwd64(FwdArgs A) {
     for (int j = 0; j < K; ++j) {
       const int64_t p = base + j * 64 + lane;
       inmap[j] = p < A.npix;
-      pix2vec_ring(A.nside, inmap[j] ? p : A.npix - 1, &nd[j][0], &nd[j][1], &nd[j][2]);
+      const int64_t pc = inmap[j] ? p : A.npix - 1;
+      nd[j][0] = A.dirx[pc];
+      nd[j][1] = A.diry[pc];
+      nd[j][2] = A.dirz[pc];
     }
     double S[K], C[K];
 #pragma unroll
@@ -469,7 +648,7 @@ __global__ void __launch_bounds__(256) k_fwd64(FwdArgs A) {
       bool anyv = false;
 #pragma unroll
       for (int j = 0; j < K; ++j) {
-        vis[j] = inmap[j] && sees_box(nd[j][0], nd[j][1], nd[j][2], bx, A.eta0);
+        vis[j] = inmap[j] && (bx.vis == 0 || sees_box(nd[j][0], nd[j][1], nd[j][2], bx, A.eta0));
         anyv |= vis[j];
       }
       if (!__any(anyv)) continue;
@@ -757,6 +936,12 @@ hipError_t launch_zero_counters(unsigned long long* c, int n, uint32_t* work, hi
   return hipGetLastError();
 }
 
+hipError_t launch_dir_table(int64_t nside, int64_t npix, double* x, double* y, double* z,
+                           hipStream_t st) {
+  k_dir_table<<<dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, st>>>(nside, npix, x, y, z);
+  return hipGetLastError();
+}
+
 hipError_t launch_pix2vec(int64_t nside, int64_t first, int64_t count, double* xyz,
                           hipStream_t st) {
   if (count <= 0) return hipSuccess;
@@ -765,13 +950,19 @@ hipError_t launch_pix2vec(int64_t nside, int64_t first, int64_t count, double* x
   return hipGetLastError();
 }
 
+static size_t fwd32_lds(int K, unsigned block) {
+  return sizeof(double) * 3 * 64 * (size_t)K * (block / 64);
+}
+
 template <int K, bool P>
 static void fwd_launch(bool fp64, const FwdArgs& A, unsigned grid, unsigned block,
                        hipStream_t st) {
   if (fp64)
     k_fwd64<K, P><<<dim3(grid), dim3(block), 0, st>>>(A);
+  else if (A.frac)
+    k_fwd32<K, P, true><<<dim3(grid), dim3(block), fwd32_lds(K, block), st>>>(A);
   else
-    k_fwd32<K, P><<<dim3(grid), dim3(block), 0, st>>>(A);
+    k_fwd32<K, P, false><<<dim3(grid), dim3(block), fwd32_lds(K, block), st>>>(A);
 }
 
 hipError_t launch_forward(bool fp64, int K, bool persistent, const FwdArgs& A, unsigned grid,

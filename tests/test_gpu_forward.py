@@ -96,15 +96,17 @@ def mixed():
     return w, ref, expected_pairs(w)
 
 
-@pytest.mark.parametrize("form", ["fp64", "fp32c"])
+@pytest.mark.parametrize("form", ["fp64", "fp32c", "fp32c-frac"])
 @pytest.mark.parametrize("K", [1, 2, 4, 8])
 @pytest.mark.parametrize("schedule", [0, 1, 2])
 def test_mixed_rules_all_shapes(B, mixed, form, K, schedule):
     w, ref, pairs = mixed
     say(f"mixed form={form} K={K} schedule={schedule}")
     f = B.CSMAP_FORM_FP64 if form == "fp64" else B.CSMAP_FORM_FP32C
-    sky = sky_from_workload(w, f, {B.CSMAP_OPT_PIX_PER_LANE: K, B.CSMAP_OPT_SCHEDULE: schedule,
-                                   B.CSMAP_OPT_WAVES: 2})
+    opts = {B.CSMAP_OPT_PIX_PER_LANE: K, B.CSMAP_OPT_SCHEDULE: schedule, B.CSMAP_OPT_WAVES: 2}
+    if form != "fp64":
+        opts[B.CSMAP_OPT_ACCUM] = 1 if form == "fp32c-frac" else 0
+    sky = sky_from_workload(w, f, opts)
     m = sky.render().cpu().numpy()
     st = sky.stats()
     e = err_metrics(m, ref)
@@ -117,20 +119,23 @@ def test_mixed_rules_all_shapes(B, mixed, form, K, schedule):
     sky.close()
 
 
-@pytest.mark.parametrize("near_w", [1e-3, 5e-3, 0.2, 3.0])
-def test_fp32c_near_threshold_any_value_within_gate(B, mixed, near_w):
+@pytest.mark.parametrize("accum", [0, 1])
+@pytest.mark.parametrize("near_w", [1e-6, 1e-3, 5e-3, 0.2, 3.0])
+def test_fp32c_near_threshold_any_value_within_gate(B, mixed, near_w, accum):
     """Small values send most pairs through the dot-product form, >= 2 sends
     every pair through the FP64 difference; both stay within the gate on
     this well-separated workload, and the literal form is the tighter one."""
     w, ref, _ = mixed
-    sky = sky_from_workload(w, B.CSMAP_FORM_FP32C, {B.CSMAP_OPT_NEAR_W: near_w})
+    sky = sky_from_workload(w, B.CSMAP_FORM_FP32C, {B.CSMAP_OPT_NEAR_W: near_w,
+                                                    B.CSMAP_OPT_ACCUM: accum})
     m = sky.render().cpu().numpy()
     st = sky.stats()
     e = err_metrics(m, ref)
-    say(f"near_w={near_w} {e} near_steps={st['near_steps']}")
+    say(f"near_w={near_w} accum={accum} {e} near_steps={st['near_steps']}")
+    assert np.all(np.isfinite(m))
     if near_w >= 2:
         assert e["rel_rms"] <= 2e-6
-    if near_w > 0:
+    if near_w >= 1e-3:
         assert e["rel_rms"] <= FP32_RMS and e["rel_max"] <= FP32_MAX, e
     sky.close()
 
