@@ -48,6 +48,20 @@ def make_sky(B, torch, b, form, nseg, nside):
     return sky, box
 
 
+def measured_traffic():
+    """HBM bytes per launch of the forward kernel from the committed
+    rocprofv3 counter runs, if they were taken on the current kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_fwd32_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_1204_5041_amd", "csrc", "kernels.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("kernels_hip_sha256"):
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
 def cpu_baseline(box, nside, npix_sample, seed=98):
     import oracle
     import synth
@@ -71,7 +85,7 @@ def main():
     ap.add_argument("--nside", type=int, default=NSIDE)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-pixels", type=int, default=6000)
+    ap.add_argument("--cpu-pixels", type=int, default=40000)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="before the timed region, run one plain device copy of this many "
                          "MiB (a known-size reference for hardware traffic counters)")
@@ -144,7 +158,9 @@ def main():
                    "nside": args.nside, "segments_per_step": args.nseg,
                    "pairs_per_step": pairs_per_step, "tile": cfg},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+                     "traffic": measured_traffic() if args.nseg == NSEG and args.nside == NSIDE
+                     else None,
                      "kernel": "k_fwd32", "kernel_ms": kern_s * 1e3,
                      "flop_per_pair": FLOP_PER_PAIR},
     }
