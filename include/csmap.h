@@ -207,11 +207,16 @@ csmap_status csmap_set_option(csmap_sky *sky, csmap_option opt, double value);
 /* Counters and timings of the last render/backward; synchronises the stream. */
 csmap_status csmap_get_stats(csmap_sky *sky, csmap_stats *out);
 
-/* Time the forward kernel over a grid of tile shapes on this sky's boxes and
- * keep the fastest (pixels per lane, waves per workgroup, schedule).  If
- * cache_path is not NULL the choice is read from / appended to that text
- * file, keyed by device name, form, Nside and workload shape.  Writes to
- * scratch memory only; synchronises the stream. */
+/* Time the forward kernel over a grid of launch shapes (pixels per lane,
+ * wavefronts per workgroup, schedule 0 or 1, accumulation mode) on this
+ * sky's boxes, evaluating the same sample of pixel rows (up to 2,048 rows of
+ * 512 RING pixels spread over the map) for every candidate, and keep the
+ * fastest.  If cache_path is not NULL the choice is first looked up in, and
+ * afterwards appended to, that text file, keyed by device architecture,
+ * form, Nside, box count, visibility rules and segment count (rounded to a
+ * power of two).  Allocates a scratch map of 12 Nside^2 doubles for the
+ * duration of the call; synchronises the stream; results of later renders
+ * are unchanged up to rounding (the sum order within a pixel may change). */
 csmap_status csmap_autotune(csmap_sky *sky, const char *cache_path);
 
 /* Host-side helper, no device work: the RING pixel tiles of `tile` pixels

@@ -29,6 +29,7 @@ hipError_t launch_dir_table(int64_t nside, int64_t npix, double* x, double* y, d
                             hipStream_t st);
 hipError_t launch_forward(bool fp64, int K, bool persistent, const FwdArgs& A, unsigned grid,
                           unsigned block, hipStream_t st);
+int forward_blocks_per_cu(bool fp64, bool frac, int K, unsigned block);
 hipError_t launch_pixtab(int64_t nside, int64_t npix, const double* dmap, float* tab32,
                          double* tab64, hipStream_t st);
 hipError_t launch_adjoint(const AdjArgs& A, hipStream_t st);
@@ -364,9 +365,12 @@ unsigned persistent_grid(const csmap_sky* s) {
   (void)hipGetDevice(&dev);
   int cus = 256;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  // Enough resident wavefronts to fill every SIMD several times over.
-  const int waves_per_cu = (s->form == CSMAP_FORM_FP64) ? 16 : 24;
-  return (unsigned)std::max(1, cus * waves_per_cu / s->waves);
+  // Exactly the workgroups that are resident at once: every wavefront pulls
+  // tiles until the queue is empty.
+  int per_cu = forward_blocks_per_cu(s->form == CSMAP_FORM_FP64, s->frac != 0, s->K,
+                                     64u * (unsigned)s->waves);
+  if (per_cu <= 0) per_cu = 1;
+  return (unsigned)std::max(1, cus * per_cu);
 }
 
 // Enqueue the whole render on stream st (no synchronisation, no events).
@@ -836,8 +840,118 @@ csmap_status csmap_autotune(csmap_sky* s, const char* cache_path) {
   g_err.clear();
   csmap_status cs = check_sky(s);
   if (cs != CSMAP_OK) return cs;
-  (void)cache_path;
-  return fail(CSMAP_E_UNSUPPORTED, "autotune not available yet");
+  const bool fp64 = s->form == CSMAP_FORM_FP64;
+  const int64_t nbox = (int64_t)s->boxes.size();
+  int dev = 0;
+  HIPCHK(s, hipGetDevice(&dev), "device");
+  hipDeviceProp_t prop;
+  HIPCHK(s, hipGetDeviceProperties(&prop, dev), "device properties");
+  bool all = true;
+  for (auto& h : s->boxes)
+    if (h.geom.vis != 0) all = false;
+  // Workload key: device, form, Nside, box count, visibility rules, and the
+  // segment count rounded to a power of two.
+  int seg_log2 = 0;
+  while (((int64_t)1 << seg_log2) < std::max<int64_t>(1, s->total_seg)) ++seg_log2;
+  std::ostringstream key;
+  key << prop.gcnArchName << "|" << (fp64 ? "fp64" : "fp32c") << "|" << s->nside << "|" << nbox
+      << "|" << (all ? "all" : "subset") << "|" << seg_log2;
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      std::istringstream ls(line);
+      std::string k;
+      int K, W, S, F;
+      if (ls >> k >> K >> W >> S >> F && k == key.str()) {
+        s->K = K;
+        s->waves = W;
+        s->schedule = S;
+        s->frac = F;
+        s->version++;
+        drop_graph(s);
+        return CSMAP_OK;
+      }
+    }
+  }
+  if (nbox == 0 || s->total_seg == 0) return CSMAP_OK;
+  // Sample: rows of 512 consecutive pixels spread evenly over the map (at
+  // most 2048 of them); every candidate evaluates exactly these pixels.
+  const int64_t rowpix = 512;
+  const int64_t nrows_all = (s->npix + rowpix - 1) / rowpix;
+  const int64_t nrows = std::min<int64_t>(nrows_all, 2048);
+  std::vector<int64_t> rows(nrows);
+  for (int64_t r = 0; r < nrows; ++r) rows[r] = r * nrows_all / nrows;
+  DevBuf scratch, items;
+  HIPCHK(s, scratch.ensure(sizeof(double) * (size_t)s->npix), "alloc scratch map");
+  struct Cand { int K, W, S, F; };
+  std::vector<Cand> cands;
+  for (int K : {1, 2, 4, 8})
+    for (int W : {1, 2, 4})
+      for (int S : {0, 1})
+        for (int F : {0, 1}) {
+          if (fp64 && F) continue;
+          if (!fp64 && K == 1) continue;
+          cands.push_back({K, W, S, F});
+        }
+  const int saveK = s->K, saveW = s->waves, saveS = s->schedule, saveF = s->frac;
+  double best_ms = 1e300;
+  Cand best = {saveK, saveW, saveS, saveF};
+  hipStream_t st = s->stream;
+  for (const Cand& c : cands) {
+    s->K = c.K;
+    s->waves = c.W;
+    s->schedule = c.S;
+    s->frac = c.F;
+    cs = prepare(s);
+    if (cs != CSMAP_OK) break;
+    const int64_t tile = 64 * (int64_t)c.K;
+    std::vector<int32_t> it;
+    for (int64_t r : rows)
+      for (int64_t t = r * rowpix / tile; t < std::min(s->ntiles, (r + 1) * rowpix / tile); ++t)
+        it.push_back((int32_t)t);
+    HIPCHK(s, items.ensure(sizeof(int32_t) * it.size()), "alloc items");
+    HIPCHK(s, hipMemcpy(items.p, it.data(), sizeof(int32_t) * it.size(), hipMemcpyHostToDevice),
+           "upload items");
+    const PreArgs P = pre_args(s);
+    HIPCHK(s, launch_precompute(P, nbox, st), "precompute launch");
+    FwdArgs A = fwd_args(s, scratch.as<double>());
+    A.items = items.as<int32_t>();
+    A.nitems = (int64_t)it.size();
+    const unsigned block = 64u * (unsigned)c.W;
+    const unsigned grid = c.S ? persistent_grid(s) : (unsigned)((A.nitems + c.W - 1) / c.W);
+    double ms_min = 1e300;
+    for (int rep = 0; rep < 3; ++rep) {
+      HIPCHK(s, launch_zero_counters(s->d_counters.as<unsigned long long>(), 2, A.work_counter, st),
+             "counter reset");
+      HIPCHK(s, hipEventRecord(s->ev[0], st), "event");
+      HIPCHK(s, launch_forward(fp64, c.K, c.S == 1, A, grid, block, st), "forward launch");
+      HIPCHK(s, hipEventRecord(s->ev[1], st), "event");
+      HIPCHK(s, hipEventSynchronize(s->ev[1]), "sync");
+      float ms = 0.f;
+      HIPCHK(s, hipEventElapsedTime(&ms, s->ev[0], s->ev[1]), "elapsed");
+      if (rep > 0) ms_min = std::min(ms_min, (double)ms);
+    }
+    if (ms_min < best_ms) {
+      best_ms = ms_min;
+      best = c;
+    }
+  }
+  scratch.release();
+  items.release();
+  s->K = best.K;
+  s->waves = best.W;
+  s->schedule = best.S;
+  s->frac = best.F;
+  s->have_fwd_time = false;
+  s->version++;
+  drop_graph(s);
+  if (cs != CSMAP_OK) return cs;
+  if (cache_path) {
+    std::ofstream out(cache_path, std::ios::app);
+    out << key.str() << " " << best.K << " " << best.W << " " << best.S << " " << best.F << "\n";
+  }
+  return CSMAP_OK;
 }
 
 }  // extern "C"

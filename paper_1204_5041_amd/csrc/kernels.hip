@@ -965,6 +965,32 @@ static void fwd_launch(bool fp64, const FwdArgs& A, unsigned grid, unsigned bloc
     k_fwd32<K, P, false><<<dim3(grid), dim3(block), fwd32_lds(K, block), st>>>(A);
 }
 
+template <int K, bool P>
+static int fwd_occupancy(bool fp64, bool frac, unsigned block) {
+  int nb = 0;
+  hipError_t e;
+  if (fp64)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd64<K, P>, (int)block, 0);
+  else if (frac)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd32<K, P, true>, (int)block,
+                                                      fwd32_lds(K, block));
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fwd32<K, P, false>, (int)block,
+                                                      fwd32_lds(K, block));
+  return e == hipSuccess ? nb : 0;
+}
+
+// Workgroups of the persistent forward kernel that fit on one CU at once.
+int forward_blocks_per_cu(bool fp64, bool frac, int K, unsigned block) {
+  switch (K) {
+    case 1: return fwd_occupancy<1, true>(fp64, frac, block);
+    case 2: return fwd_occupancy<2, true>(fp64, frac, block);
+    case 4: return fwd_occupancy<4, true>(fp64, frac, block);
+    case 8: return fwd_occupancy<8, true>(fp64, frac, block);
+  }
+  return 0;
+}
+
 hipError_t launch_forward(bool fp64, int K, bool persistent, const FwdArgs& A, unsigned grid,
                           unsigned block, hipStream_t st) {
   switch (K) {

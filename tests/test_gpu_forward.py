@@ -262,3 +262,61 @@ def test_config2_one_box_full_sky(B):
     assert st["pairs"] == w.npix * 400_000
     assert e["rel_rms"] <= FP32_RMS and e["rel_max"] <= FP32_MAX, e
     sky.close()
+
+
+def test_autotune_keeps_parity_and_caches(B, mixed, tmp_path):
+    w, ref, pairs = mixed
+    sky = sky_from_workload(w, B.CSMAP_FORM_FP32C)
+    cache = str(tmp_path / "tune.txt")
+    sky.autotune(cache)
+    st0 = sky.stats()
+    m = sky.render().cpu().numpy()
+    st = sky.stats()
+    e = err_metrics(m, ref)
+    assert st["pairs"] == pairs
+    assert e["rel_rms"] <= FP32_RMS and e["rel_max"] <= FP32_MAX, e
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 1 and "fp32c" in lines[0]
+    # a second sky with the same shape takes the cached choice without timing
+    sky2 = sky_from_workload(w, B.CSMAP_FORM_FP32C)
+    sky2.autotune(cache)
+    s2 = sky2.stats()
+    for k in ("pix_per_lane", "waves", "schedule"):
+        assert s2[k] == st0[k]
+    assert len(open(cache).read().strip().splitlines()) == 1
+    sky.close()
+    sky2.close()
+
+
+def test_batched_uneven_caps_persistent_graph(B):
+    """A reduced copy of the batched workload (Nside 256, 64 boxes with
+    lognormal segment counts scaled by 1/20 and cap visibility): persistent
+    schedule with per-tile box lists, captured in a graph, against the oracle
+    on 3,000 pixels that see at least one box; the per-box schedule agrees."""
+    w = synth.config3(nbox=64, nside=256, count_scale=0.05)
+    pix = np.arange(w.npix)
+    seen = np.zeros(w.npix, dtype=bool)
+    pairs = 0
+    for bx in w.boxes:
+        v = oracle.visible(w.nside, pix, w.eta0, bx)
+        seen |= v
+        pairs += int(v.sum()) * int(oracle.kept(w.eta0, bx).sum())
+    check = np.sort(np.random.default_rng(398).choice(np.flatnonzero(seen), 3000, replace=False))
+    ref = oracle.theta_pixels(w.nside, check, w.eta0, w.boxes)
+    sky = sky_from_workload(w, B.CSMAP_FORM_FP32C, {B.CSMAP_OPT_SCHEDULE: 1, B.CSMAP_OPT_GRAPH: 1})
+    out = torch.empty(w.npix, dtype=torch.float64, device="cuda")
+    for rep in range(3):
+        sky.render(out)
+        m = out.cpu().numpy()
+        st = sky.stats()
+        e = err_metrics(m[check], ref)
+        say(f"batched rep={rep} {e} pairs={st['pairs']}")
+        assert st["pairs"] == pairs
+        assert e["rel_rms"] <= FP32_RMS and e["rel_max"] <= FP32_MAX, e
+        assert np.all(m[~seen] == 0.0)
+    sky.set_option(B.CSMAP_OPT_SCHEDULE, 2)
+    sky.set_option(B.CSMAP_OPT_GRAPH, 0)
+    m2 = sky.render().cpu().numpy()
+    e2 = err_metrics(m2[check], ref)
+    assert e2["rel_rms"] <= FP32_RMS and e2["rel_max"] <= FP32_MAX, e2
+    sky.close()
