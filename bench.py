@@ -86,6 +86,13 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=40000)
+    ap.add_argument("--workload", default="config2",
+                    choices=["config2", "config3", "config4"],
+                    help="config2: the headline Nside=2048 line (default); config3: the "
+                         "batched uneven 256-box Nside=4096 sky; config4: forward + adjoint at "
+                         "Nside=1024")
+    ap.add_argument("--count-scale", type=float, default=1.0,
+                    help="config3: scale of the per-box segment counts")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="before the timed region, run one plain device copy of this many "
                          "MiB (a known-size reference for hardware traffic counters)")
@@ -98,6 +105,10 @@ def main():
     import torch
     from paper_1204_5041_amd import binding as B
     assert torch.cuda.is_available(), "no GPU visible"
+    if args.workload == "config3":
+        return bench_config3(args, B, torch)
+    if args.workload == "config4":
+        return bench_config4(args, B, torch)
 
     if args.copy_calib_mib > 0:
         n = args.copy_calib_mib * (1 << 20) // 4
@@ -191,6 +202,95 @@ def main():
         out["cpu_baseline"] = cpu_baseline(box0, args.nside, args.cpu_pixels)
 
     print(json.dumps(out), flush=True)
+
+
+def _sky_from(B, torch, w, form):
+    sky = B.Sky(w.nside, w.eta0, form)
+    for bx in w.boxes:
+        t = [torch.from_numpy(np.ascontiguousarray(a)).cuda()
+             for a in (bx.x_rel, bx.xdot, bx.xprime, bx.dsigma)]
+        kw = {}
+        if bx.cap_dir is not None:
+            kw = {"cap_dir": tuple(float(v) for v in bx.cap_dir), "cap_cos": float(bx.cap_cos)}
+        sky.add_box(*t, origin=tuple(float(v) for v in bx.origin), eta_lo=bx.eta_lo,
+                    eta_hi=bx.eta_hi, vis=bx.vis, ext=tuple(float(v) for v in bx.ext), **kw)
+    return sky
+
+
+def bench_config3(args, B, torch):
+    """256 boxes of lognormal size, each seen by a cap of 0.1%-5% of an
+    Nside=4096 sky: one persistent launch over per-tile box lists, captured
+    in a graph, launch shape from the autotuner; compared with one launch
+    per box."""
+    import synth
+    _log("bench config3: generating 256 boxes")
+    w = synth.config3(count_scale=args.count_scale)
+    _log(f"bench config3: {sum(b.n for b in w.boxes):,} segments; uploading")
+    sky = _sky_from(B, torch, w, B.CSMAP_FORM_FP32C)
+    out = torch.empty(w.npix, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    _log("bench config3: autotune")
+    t0 = time.perf_counter()
+    sky.autotune(None)
+    tune_s = time.perf_counter() - t0
+    _log(f"bench config3: autotune done in {tune_s:.1f} s: {sky.stats()}")
+    sky.set_option(B.CSMAP_OPT_SCHEDULE, 1)
+    sky.set_option(B.CSMAP_OPT_GRAPH, 1)
+    sky.render(out)                               # capture + warm-up
+    torch.cuda.synchronize()
+    _log(f"bench config3: warm-up render done ({sky.stats()['ms_forward']:.0f} ms)")
+    K = max(1, args.steps)
+    t0 = time.perf_counter()
+    for _ in range(K):
+        sky.render(out)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / K
+    st = sky.stats()
+    res = {"metric": "config3 batched pairs/s", "value": st["pairs"] / el, "unit": "pairs/s",
+           "ms_per_step": el * 1e3, "pairs": st["pairs"], "kept": st["kept"],
+           "segments": st["segments"], "tile": {k: st[k] for k in ("pix_per_lane", "waves",
+                                                                   "schedule", "graph")},
+           "autotune_s": tune_s}
+    res["achieved_tflops"] = FLOP_PER_PAIR * res["value"] / 1e12
+    res["frac_fp32_peak"] = res["achieved_tflops"] / FP32_PEAK_TFLOPS
+    _log(f"bench config3: batched render {el * 1e3:.0f} ms; per-box launches next")
+    sky.set_option(B.CSMAP_OPT_GRAPH, 0)
+    sky.set_option(B.CSMAP_OPT_SCHEDULE, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sky.render(out)
+    torch.cuda.synchronize()
+    el2 = time.perf_counter() - t0
+    res["per_box_launches_pairs_per_s"] = sky.stats()["pairs"] / el2
+    res["speedup_batched_over_per_box"] = el2 / el
+    print(json.dumps(res), flush=True)
+
+
+def bench_config4(args, B, torch):
+    """Nside=1024, 8 boxes x 50,000 segments: FP32C forward and the adjoint
+    of L = sum_p w_p Theta_p^2."""
+    import synth
+    w = synth.config4()
+    sky = _sky_from(B, torch, w, B.CSMAP_FORM_FP32C)
+    wts = torch.from_numpy(synth.config4_weights(w.npix)).cuda()
+    m = sky.render()
+    g = 2.0 * wts * m
+    sky.backward(g)                               # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m = sky.render()
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    sky.backward(2.0 * wts * m)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    st = sky.stats()
+    pairs = st["pairs"]
+    res = {"metric": "config4 forward + adjoint pairs/s", "forward_pairs_per_s": pairs / tf,
+           "adjoint_pairs_per_s": pairs / tb, "pairs": pairs, "forward_ms": tf * 1e3,
+           "adjoint_ms": tb * 1e3, "adjoint_kernel_ms": st["ms_backward"]}
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

@@ -208,10 +208,10 @@ csmap_status csmap_set_option(csmap_sky *sky, csmap_option opt, double value);
 csmap_status csmap_get_stats(csmap_sky *sky, csmap_stats *out);
 
 /* Time the forward kernel over a grid of launch shapes (pixels per lane,
- * wavefronts per workgroup, schedule 0 or 1, accumulation mode) on this
- * sky's boxes, evaluating the same sample of pixel rows (up to 2,048 rows of
- * 512 RING pixels spread over the map) for every candidate, and keep the
- * fastest.  If cache_path is not NULL the choice is first looked up in, and
+ * wavefronts per workgroup, accumulation mode; persistent schedule) on this
+ * sky's boxes, evaluating the same sample for every candidate (up to 49,152
+ * rows of 512 RING pixels spread over the map, each limited to the first
+ * 2,048 segments of every box it sees), and keep the fastest.  If cache_path is not NULL the choice is first looked up in, and
  * afterwards appended to, that text file, keyed by device architecture,
  * form, Nside, box count, visibility rules and segment count (rounded to a
  * power of two).  Allocates a scratch map of 12 Nside^2 doubles for the

@@ -4,6 +4,7 @@
 #include <math.h>
 #include <stdint.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -876,24 +877,28 @@ csmap_status csmap_autotune(csmap_sky* s, const char* cache_path) {
   }
   if (nbox == 0 || s->total_seg == 0) return CSMAP_OK;
   // Sample: rows of 512 consecutive pixels spread evenly over the map (at
-  // most 2048 of them); every candidate evaluates exactly these pixels.
+  // most 49,152 of them, enough to give every resident wavefront many work
+  // items), each tile limited to its first 2,048 segments per box so that
+  // every candidate measures steady-state throughput on the same pixels.
   const int64_t rowpix = 512;
   const int64_t nrows_all = (s->npix + rowpix - 1) / rowpix;
-  const int64_t nrows = std::min<int64_t>(nrows_all, 2048);
+  const int64_t nrows = std::min<int64_t>(nrows_all, 49152);
   std::vector<int64_t> rows(nrows);
   for (int64_t r = 0; r < nrows; ++r) rows[r] = r * nrows_all / nrows;
   DevBuf scratch, items;
   HIPCHK(s, scratch.ensure(sizeof(double) * (size_t)s->npix), "alloc scratch map");
   struct Cand { int K, W, S, F; };
   std::vector<Cand> cands;
+  // The persistent schedule (tiles pulled most expensive first) is kept for
+  // every candidate: it was never slower than one-tile-per-wavefront launches
+  // on uniform skies and it bounds the tail on uneven ones.
   for (int K : {1, 2, 4, 8})
     for (int W : {1, 2, 4})
-      for (int S : {0, 1})
-        for (int F : {0, 1}) {
-          if (fp64 && F) continue;
-          if (!fp64 && K == 1) continue;
-          cands.push_back({K, W, S, F});
-        }
+      for (int F : {0, 1}) {
+        if (fp64 && F) continue;
+        if (!fp64 && K == 1) continue;
+        cands.push_back({K, W, 1, F});
+      }
   const int saveK = s->K, saveW = s->waves, saveS = s->schedule, saveF = s->frac;
   double best_ms = 1e300;
   Cand best = {saveK, saveW, saveS, saveF};
@@ -918,6 +923,7 @@ csmap_status csmap_autotune(csmap_sky* s, const char* cache_path) {
     FwdArgs A = fwd_args(s, scratch.as<double>());
     A.items = items.as<int32_t>();
     A.nitems = (int64_t)it.size();
+    A.seg_cap = 2048;
     const unsigned block = 64u * (unsigned)c.W;
     const unsigned grid = c.S ? persistent_grid(s) : (unsigned)((A.nitems + c.W - 1) / c.W);
     double ms_min = 1e300;
@@ -932,6 +938,9 @@ csmap_status csmap_autotune(csmap_sky* s, const char* cache_path) {
       HIPCHK(s, hipEventElapsedTime(&ms, s->ev[0], s->ev[1]), "elapsed");
       if (rep > 0) ms_min = std::min(ms_min, (double)ms);
     }
+    if (getenv("CSMAP_TUNE_LOG"))
+      fprintf(stderr, "csmap_autotune: K=%d waves=%d schedule=%d accum=%d items=%lld %.3f ms\n",
+              c.K, c.W, c.S, c.F, (long long)it.size(), ms_min);
     if (ms_min < best_ms) {
       best_ms = ms_min;
       best = c;

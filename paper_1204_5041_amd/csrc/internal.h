@@ -88,6 +88,7 @@ struct FwdArgs {
   int32_t accumulate;          // 1: map += contribution (per-box schedule)
   int32_t only_box;            // per-box schedule: the one box (else -1)
   int32_t frac;                // FP32C: fold far pairs into a running fraction
+  int32_t seg_cap;             // >0: at most this many segments per box (tuning samples)
   double* map;
   unsigned long long* pairs;   // pair counter
   unsigned long long* near_steps;

@@ -419,7 +419,8 @@ __global__ void __launch_bounds__(256) k_fwd32(FwdArgs A) {
       }
       if (nvis == 0) continue;
       const int64_t r0 = bx.rec_off;
-      const int64_t r1 = r0 + load_kept(A.box_count, b);
+      int64_t r1 = r0 + load_kept(A.box_count, b);
+      if (A.seg_cap > 0 && r1 - r0 > A.seg_cap) r1 = r0 + A.seg_cap;
       if (lane == 0 && r1 > r0) atomicAdd(A.pairs, nvis * (unsigned long long)(r1 - r0));
       if (r1 == r0) continue;
       if constexpr (FRAC) {
@@ -653,7 +654,8 @@ __global__ void __launch_bounds__(256) k_fwd64(FwdArgs A) {
       }
       if (!__any(anyv)) continue;
       const int64_t r0 = bx.rec_off;
-      const int64_t r1 = r0 + load_kept(A.box_count, b);
+      int64_t r1 = r0 + load_kept(A.box_count, b);
+      if (A.seg_cap > 0 && r1 - r0 > A.seg_cap) r1 = r0 + A.seg_cap;
       {
         unsigned long long nvis = 0;
 #pragma unroll
