@@ -143,13 +143,15 @@ def main():
         fwd_ms.append(st["ms_forward"])
         pairs += st["pairs"]
         _log(f"bench: step {k} box {W + k}: pairs={st['pairs']} forward {st['ms_forward']:.1f} ms "
-             f"precompute {st['ms_precompute']:.2f} ms near_steps={st['near_steps']}")
+             f"precompute {st['ms_precompute']:.2f} ms fp64_steps={st['near_steps']} "
+             f"mid_steps={st['mid_steps']}")
     value = pairs / elapsed
     kern_s = float(np.mean(fwd_ms)) / 1e3
     pairs_per_step = pairs / K
     achieved = FLOP_PER_PAIR * pairs_per_step / kern_s / 1e12
     cfg = {k: v for k, v in skies[W][0].stats().items()
-           if k in ("pix_per_lane", "waves", "schedule", "graph", "chunk", "near_w")}
+           if k in ("pix_per_lane", "waves", "schedule", "graph", "chunk", "near_w", "far_w",
+                    "tiling")}
     out = {
         "metric": METRIC,
         "value": value,
@@ -249,7 +251,8 @@ def bench_config3(args, B, torch):
     res = {"metric": "config3 batched pairs/s", "value": st["pairs"] / el, "unit": "pairs/s",
            "ms_per_step": el * 1e3, "pairs": st["pairs"], "kept": st["kept"],
            "segments": st["segments"], "tile": {k: st[k] for k in ("pix_per_lane", "waves",
-                                                                   "schedule", "graph")},
+                                                                   "schedule", "graph", "tiling")},
+           "fp64_steps": st["near_steps"], "mid_steps": st["mid_steps"],
            "autotune_s": tune_s}
     res["achieved_tflops"] = FLOP_PER_PAIR * res["value"] / 1e12
     res["frac_fp32_peak"] = res["achieved_tflops"] / FP32_PEAK_TFLOPS

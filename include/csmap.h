@@ -118,15 +118,16 @@ typedef enum {
     /* 1 = capture render's launches in a hipGraph and replay it while the sky
      * and the output pointer are unchanged; 0 = plain launches. */
     CSMAP_OPT_GRAPH = 1,
-    /* Pixels per lane of the forward kernels: 1, 2, 4 or 8.  A tile is
-     * 64 x this many consecutive RING pixels, owned by one wavefront. */
+    /* Pixels per lane of the forward kernels: 1, 2, 4 or 8.  A tile of
+     * 64 x this many pixels (see CSMAP_OPT_TILING) is owned by one
+     * wavefront. */
     CSMAP_OPT_PIX_PER_LANE = 2,
     /* Wavefronts per workgroup: 1, 2 or 4. */
     CSMAP_OPT_WAVES = 3,
-    /* FP32C form: pairs with 1 - n.P/R below this value (default 5e-3, an
-     * angle of about 0.1 rad) take the FP64 direction difference; the others
-     * use the algebraically equal FP32 form built from 1 - n.P/R.  A value
-     * >= 2 sends every pair through the FP64 difference.  Minimum 1e-6. */
+    /* FP32C form: a (wavefront, segment) step in which some pair has
+     * 1 - n.P/R below this value (default 5e-5, an angle of about 0.01 rad)
+     * takes the direction difference n - P/R in FP64.  A value >= 2 sends
+     * every pair through the FP64 difference.  Minimum 1e-6. */
     CSMAP_OPT_NEAR_W = 4,
     /* Segments per FP32 partial sum before the Kahan-compensated update of a
      * pixel's running sum (FP32C form): a multiple of 4 in 8 .. 4096. */
@@ -137,7 +138,21 @@ typedef enum {
     /* FP32C forward: 0 = one reciprocal per pair; 1 = the terms of up to four
      * consecutive far segments are combined into one fraction per pixel
      * (p/q + m/d = (p d + m q)/(q d)) and divided once. */
-    CSMAP_OPT_ACCUM = 7
+    CSMAP_OPT_ACCUM = 7,
+    /* How pixels are grouped into the tiles that wavefronts own:
+     *   0 = automatic (1 when every box sees every pixel, else 2);
+     *   1 = strips of 64 x (pixels per lane) consecutive RING pixels;
+     *   2 = ring blocks: (pixels per lane) consecutive rings x up to 64
+     *       consecutive pixels per ring, azimuth-aligned across the rings,
+     *       so that a tile is a compact patch of sky.
+     * Results agree up to rounding. */
+    CSMAP_OPT_TILING = 8,
+    /* FP32C form: a step in which every pair has 1 - n.P/R at or above this
+     * value (default 5e-3, about 0.1 rad) uses the algebraically equal form
+     * built from the dot products n.P/R, n.X', n.Xdot; a step with some pair
+     * below it and none below CSMAP_OPT_NEAR_W forms n - P/R in FP32.
+     * Minimum 1e-6. */
+    CSMAP_OPT_FAR_W = 9
 } csmap_option;
 
 /* Counters of the last render/backward (csmap_get_stats synchronises). */
@@ -152,6 +167,9 @@ typedef struct {
     double ms_backward;        /* device time of the adjoint kernels of the last backward */
     int64_t pix_per_lane, waves, schedule, graph, chunk;
     double near_w;
+    int64_t tiling;            /* tiling in use: 1 strips, 2 ring blocks */
+    int64_t mid_steps;         /* FP32C: steps that formed n - P/R in FP32 */
+    double far_w;
 } csmap_stats;
 
 /* Number of pixels of an Nside map, 12 Nside^2 (Sec. II.D); -1 if Nside is
@@ -209,9 +227,10 @@ csmap_status csmap_get_stats(csmap_sky *sky, csmap_stats *out);
 
 /* Time the forward kernel over a grid of launch shapes (pixels per lane,
  * wavefronts per workgroup, accumulation mode; persistent schedule) on this
- * sky's boxes, evaluating the same sample for every candidate (up to 49,152
- * rows of 512 RING pixels spread over the map, each limited to the first
- * 2,048 segments of every box it sees), and keep the fastest.  If cache_path is not NULL the choice is first looked up in, and
+ * sky's boxes, each candidate on a sample of its own tiles spread evenly
+ * over the sky (about 25M pixels, each tile limited to the first 2,048
+ * segments of every box it sees), and keep the one with the most pairs per
+ * second.  If cache_path is not NULL the choice is first looked up in, and
  * afterwards appended to, that text file, keyed by device architecture,
  * form, Nside, box count, visibility rules and segment count (rounded to a
  * power of two).  Allocates a scratch map of 12 Nside^2 doubles for the
@@ -229,6 +248,25 @@ csmap_status csmap_autotune(csmap_sky *sky, const char *cache_path);
 csmap_status csmap_cap_tiles(int64_t nside, int64_t tile, double cx, double cy, double cz,
                              double rho, int64_t *ranges, int64_t max_ranges,
                              int64_t *n_ranges);
+
+/* Host-side helper, no device work: the ring-block tiling of
+ * CSMAP_OPT_TILING = 2 at Nside with k rings per block (1 <= k <= 64).  Rings
+ * 1 .. 4 Nside - 1 are grouped k at a time; a block whose longest ring has
+ * L pixels is cut into ceil(L / 64) tiles, and tile c of the block holds,
+ * of each ring of n pixels, the offsets floor(64 c n / L) up to (not
+ * including) min(n, floor(64 (c + 1) n / L)).  Writes k entries per tile,
+ * (first RING pixel of the row << 7) | (pixels in the row), or 0 for an
+ * empty row, for all tiles to rows (k * max_tiles entries available; rows
+ * may be NULL when max_tiles is 0) and the tile count to *n_tiles; returns
+ * CSMAP_E_INVALID if max_tiles is too small (with *n_tiles set). */
+csmap_status csmap_ring_block_rows(int64_t nside, int64_t k, int64_t *rows, int64_t max_tiles,
+                                   int64_t *n_tiles);
+
+/* Host-side helper, no device work: as csmap_cap_tiles, for the tiles of
+ * the ring-block tiling with k rings per block (csmap_ring_block_rows). */
+csmap_status csmap_cap_block_tiles(int64_t nside, int64_t k, double cx, double cy, double cz,
+                                   double rho, int64_t *ranges, int64_t max_ranges,
+                                   int64_t *n_ranges);
 
 #ifdef __cplusplus
 }

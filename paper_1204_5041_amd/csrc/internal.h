@@ -72,6 +72,7 @@ struct FwdArgs {
   int32_t all_boxes;           // 1: every tile sees every box (no lists)
   const int32_t* tile_ptr;     // CSR over tiles: boxes of tile t are
   const int32_t* tile_boxes;   //   tile_boxes[tile_ptr[t] .. tile_ptr[t+1])
+  const int64_t* rows;         // ring-block row table, K per tile (null: strips)
   const int32_t* items;        // tile of each work item (null: item == tile)
   int64_t nitems;
   uint32_t* work_counter;      // persistent schedule: next item
@@ -83,7 +84,8 @@ struct FwdArgs {
   const float* rec32;
   const double* phat64;
   const double* rec64;
-  float near_w;
+  float near_w;                // FP32C: pairs with 1 - n.Ph below this take the FP64 difference
+  float far_w;                 // FP32C: pairs with 1 - n.Ph at or above this use dot products
   int32_t chunk;
   int32_t accumulate;          // 1: map += contribution (per-box schedule)
   int32_t only_box;            // per-box schedule: the one box (else -1)
@@ -92,6 +94,7 @@ struct FwdArgs {
   double* map;
   unsigned long long* pairs;   // pair counter
   unsigned long long* near_steps;
+  unsigned long long* mid_steps;
 };
 
 // Arguments of the adjoint kernels.
@@ -109,6 +112,7 @@ struct AdjArgs {
   int64_t nitems;
   int32_t nsplit;              // pixel chunks per segment group
   float near_w;
+  float far_w;
   double* partial;             // [record][split][13] accumulators
   const double* dmap;
 };

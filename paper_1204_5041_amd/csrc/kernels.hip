@@ -44,6 +44,7 @@ typedef double v2d __attribute__((ext_vector_type(2)));
 typedef const v4f __attribute__((address_space(4)))* cf4p;
 typedef const v2d __attribute__((address_space(4)))* cd2p;
 typedef const int32_t __attribute__((address_space(4)))* ci32p;
+typedef const int64_t __attribute__((address_space(4)))* ci64p;
 
 typedef const DevBox __attribute__((address_space(4)))* cbox_p;
 typedef const DevBoxCount __attribute__((address_space(4)))* ccnt_p;
@@ -299,12 +300,29 @@ __device__ __forceinline__ int32_t tile_of(const FwdArgs& A, int64_t item) {
   return A.items ? ((ci32p)A.items)[item] : (int32_t)item;
 }
 
-// Lane offset into a row of 64 pixels starting at `row`, clamped to the
-// last pixel of the map.
-__device__ __forceinline__ int32_t dir_off(int64_t npix, int64_t row, int lane) {
-  const int64_t room = npix - 1 - row;
-  const int32_t lim = room < 63 ? (int32_t)room : 63;
-  return lane < lim ? lane : lim;
+// Row j of a tile: its first RING pixel and its pixel count (0 .. 64).
+// Ring-block tilings read both from the row table; strips are 64 K
+// consecutive pixels cut at the end of the map.  An empty row reports
+// pixel 0 as its first, so that loads through it stay inside the map.
+template <int K>
+__device__ __forceinline__ void tile_row(const FwdArgs& A, int64_t tile, int j, int64_t& first,
+                                         int32_t& cnt) {
+  if (A.rows) {
+    const int64_t e = ((ci64p)A.rows)[tile * K + j];
+    first = e >> 7;
+    cnt = (int32_t)(e & 127);
+  } else {
+    first = tile * (64 * K) + 64 * j;
+    const int64_t room = A.npix - first;
+    cnt = room >= 64 ? 64 : (room > 0 ? (int32_t)room : 0);
+    if (cnt == 0) first = 0;
+  }
+}
+
+// Lane offset into a row of `cnt` pixels; lanes past the end repeat its
+// last pixel (or pixel `first` of an empty row).
+__device__ __forceinline__ int32_t row_off(int32_t cnt, int lane) {
+  return lane < cnt ? lane : (cnt > 0 ? cnt - 1 : 0);
 }
 
 // Kahan update of (s, c) by x: s - c carries the sum.
@@ -360,8 +378,8 @@ __global__ void __launch_bounds__(256) k_fwd32(FwdArgs A) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   int64_t item = PERSISTENT ? next_item(A, true, lane, 0, 0) : (int64_t)blockIdx.x * wpb + wave;
   const int64_t stride = (int64_t)gridDim.x * wpb;
-  unsigned long long near_steps = 0;
-  const float near_w = A.near_w;
+  unsigned long long near_steps = 0, mid_steps = 0;
+  const float near_w = A.near_w, far_w = A.far_w;
   cf4p recs = (cf4p)A.rec32;
   cd2p ph64 = (cd2p)A.phat64;
   // Dynamic LDS: K x 3 x 64 doubles per wavefront of the workgroup.
@@ -369,22 +387,21 @@ __global__ void __launch_bounds__(256) k_fwd32(FwdArgs A) {
   double* const sdir = sdir_all + wave * (K * 3 * 64);
   while (item < A.nitems) {
     const int64_t tile = tile_of(A, item);
-    const int64_t base = tile * (64 * K);
     // Pixel directions come from the table written by the RING pix2vec
-    // kernel; only their FP32 copies stay in registers across the segment
-    // loop (FP64 values are reloaded by the rare close-pair steps).
-    // Lane l of row j owns pixel base + 64 j + l; rows past the end of the
-    // map repeat its last pixel (those lanes are masked out of every sum and
+    // kernel.  Lane l of row j owns pixel first_j + l; lanes past the end of
+    // a row repeat its last pixel (they are masked out of every sum and
     // never written).  The FP64 directions are parked in this wavefront's
     // slice of LDS for the close-pair steps and visibility tests; only the
-    // FP32 copies stay in registers.
+    // FP32 copies stay in registers across the segment loop.
     float nf[K][3];
     bool inmap[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-      const int64_t row = base + j * 64;
-      inmap[j] = row + lane < A.npix;
-      const int32_t off = dir_off(A.npix, row, lane);
+      int64_t row;
+      int32_t cnt;
+      tile_row<K>(A, tile, j, row, cnt);
+      inmap[j] = lane < cnt;
+      const int32_t off = row_off(cnt, lane);
       const double x = A.dirx[row + off], y = A.diry[row + off], z = A.dirz[row + off];
       sdir[(j * 3 + 0) * 64 + lane] = x;
       sdir[(j * 3 + 1) * 64 + lane] = y;
@@ -424,12 +441,13 @@ __global__ void __launch_bounds__(256) k_fwd32(FwdArgs A) {
       if (lane == 0 && r1 > r0) atomicAdd(A.pairs, nvis * (unsigned long long)(r1 - r0));
       if (r1 == r0) continue;
       if constexpr (FRAC) {
-      // Far terms m/d of a pixel are folded into one fraction over windows
-      // of four consecutive segments, (p/q) + m/d = (p d + m q)/(q d), and
-      // divided once per window.  On this path d = b w >= 0.05 * near_w, so
-      // a product of four stays well inside the FP32 range.  Close pairs are
-      // added one by one.  Each window slot is a separate copy of the step,
-      // so its update of (p, q) is fixed at compile time.
+      // Terms m/d of a pixel are folded into one fraction over windows of
+      // four consecutive segments, (p/q) + m/d = (p d + m q)/(q d), and
+      // divided once per window.  Folded terms have d = b w >= 0.05 near_w
+      // (b >= 0.05 unless the segment is flagged), so a product of four
+      // stays inside the FP32 range.  Terms of the FP64 path are added one by
+      // one.  Each window slot is a separate copy of the step, so its update
+      // of (p, q) is fixed at compile time.
       const int64_t nseg = r1 - r0;
       const int64_t nwin = (nseg + 3) >> 2;
       const cf4p last = recs + 4 * (r1 - 1);
@@ -461,31 +479,59 @@ __global__ void __launch_bounds__(256) k_fwd32(FwdArgs A) {
               w[j] = fmaf(-nf[j][2], pz, fmaf(-nf[j][1], py, fmaf(-nf[j][0], px, 1.0f)));
               a[j] = fmaf(nf[j][2], tz, fmaf(nf[j][1], ty, nf[j][0] * tx));
               bb[j] = fmaf(nf[j][2], vz, fmaf(nf[j][1], vy, fmaf(nf[j][0], vx, 1.0f)));
-              nearp |= (w[j] < near_w);
+              nearp |= (w[j] < far_w);
             }
-            if (__float_as_int(q3.y) == 0 && !__any(nearp)) {
+            const bool force = __float_as_int(q3.y) != 0;
+            float m[K], den[K];
+            bool fold = true;
+            if (!force && !__any(nearp)) {
+              // Far step: kappa/2 times Xdot.(n - Ph) and X'.(n - Ph) from the
+              // dot products.
 #pragma unroll
               for (int j = 0; j < K; ++j) {
                 const float t1 = fmaf(kap, bb[j], -c1v);
                 const float t2 = fmaf(kap, a[j], -c2v);
-                const float m = fmaf(-a[j], t2, t1 * bb[j]);   // kappa/2 * m
-                const float den = bb[j] * w[j];
-                if (slot == 0) {
-                  fp[j] = m;
-                  fq[j] = den;
-                } else {
-                  fp[j] = fmaf(fp[j], den, m * fq[j]);
-                  fq[j] = fq[j] * den;
-                }
+                m[j] = fmaf(-a[j], t2, t1 * bb[j]);   // kappa/2 * m
+                den[j] = bb[j] * w[j];
               }
             } else {
-              ++near_steps;
-              near_terms<K>(nf, sdir, lane, q0, q1, q2, a, bb, ph64 + 2 * ((rp - recs) >> 2),
-                            part);
-              if (slot == 0) {
+              bool n64 = force;
 #pragma unroll
-                for (int j = 0; j < K; ++j) { fp[j] = 0.f; fq[j] = 1.f; }
+              for (int j = 0; j < K; ++j) n64 |= (w[j] < near_w);
+              if (!__any(n64)) {
+                // Middle step: the direction difference in FP32 (its error,
+                // about 1e-7 absolute, is small against |n - Ph| >= 0.01).
+                ++mid_steps;
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                  const float dx = nf[j][0] - px, dy = nf[j][1] - py, dz = nf[j][2] - pz;
+                  const float q = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                  const float t1 = kap * fmaf(vz, dz, fmaf(vy, dy, vx * dx));
+                  const float t2 = kap * fmaf(tz, dz, fmaf(ty, dy, tx * dx));
+                  m[j] = fmaf(-a[j], t2, t1 * bb[j]);
+                  den[j] = bb[j] * (0.5f * q);
+                }
+              } else {
+                ++near_steps;
+                near_terms<K>(nf, sdir, lane, q0, q1, q2, a, bb, ph64 + 2 * ((rp - recs) >> 2),
+                              part);
+                fold = false;
               }
+            }
+            if (fold) {
+#pragma unroll
+              for (int j = 0; j < K; ++j) {
+                if (slot == 0) {
+                  fp[j] = m[j];
+                  fq[j] = den[j];
+                } else {
+                  fp[j] = fmaf(fp[j], den[j], m[j] * fq[j]);
+                  fq[j] = fq[j] * den[j];
+                }
+              }
+            } else if (slot == 0) {
+#pragma unroll
+              for (int j = 0; j < K; ++j) { fp[j] = 0.f; fq[j] = 1.f; }
             }
             q0 = n0;
             q1 = n1;
@@ -534,11 +580,16 @@ __global__ void __launch_bounds__(256) k_fwd32(FwdArgs A) {
           w[j] = fmaf(-nf[j][2], pz, fmaf(-nf[j][1], py, fmaf(-nf[j][0], px, 1.0f)));
           a[j] = fmaf(nf[j][2], tz, fmaf(nf[j][1], ty, nf[j][0] * tx));
           bb[j] = fmaf(nf[j][2], vz, fmaf(nf[j][1], vy, fmaf(nf[j][0], vx, 1.0f)));
-          nearp |= (w[j] < near_w);
+          nearp |= (w[j] < far_w);
         }
         // Segments flagged at precompute (|Xdot| close to 1, where b = 1 + n.Xdot
-        // may be tiny) always take the close-pair form.
+        // may be tiny) always take the FP64 form.
         const bool force = __float_as_int(q3.y) != 0;
+        bool n64 = force;
+        if (!force && __any(nearp)) {
+#pragma unroll
+          for (int j = 0; j < K; ++j) n64 |= (w[j] < near_w);
+        }
         if (!force && !__any(nearp)) {
           // kappa/2 times Xdot.(n - Ph) and X'.(n - Ph) from the dot products.
 #pragma unroll
@@ -547,6 +598,18 @@ __global__ void __launch_bounds__(256) k_fwd32(FwdArgs A) {
             const float t2 = fmaf(kap, a[j], -c2v);
             const float m = fmaf(-a[j], t2, t1 * bb[j]);   // kappa/2 * m
             part[j] = fmaf(m, __builtin_amdgcn_rcpf(bb[j] * w[j]), part[j]);
+          }
+        } else if (!__any(n64)) {
+          // Middle pairs: the direction difference in FP32.
+          ++mid_steps;
+#pragma unroll
+          for (int j = 0; j < K; ++j) {
+            const float dx = nf[j][0] - px, dy = nf[j][1] - py, dz = nf[j][2] - pz;
+            const float q = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+            const float t1 = kap * fmaf(vz, dz, fmaf(vy, dy, vx * dx));
+            const float t2 = kap * fmaf(tz, dz, fmaf(ty, dy, tx * dx));
+            const float m = fmaf(-a[j], t2, t1 * bb[j]);
+            part[j] = fmaf(m, __builtin_amdgcn_rcpf(bb[j] * (0.5f * q)), part[j]);
           }
         } else {
           // Close pairs: the difference of directions in FP64.  An exact
@@ -589,10 +652,13 @@ __global__ void __launch_bounds__(256) k_fwd32(FwdArgs A) {
     }
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-      const int64_t p = base + j * 64 + lane;
-      if (p < A.npix) {
+      int64_t row;
+      int32_t cnt;
+      tile_row<K>(A, tile, j, row, cnt);
+      if (lane < cnt) {
         // The running sum s carries the result; c is the negated rounding
         // error still owed to it, so the value is s - c.
+        const int64_t p = row + lane;
         const double v = (double)S[j] - (double)C[j];
         A.map[p] = A.accumulate ? A.map[p] + v : v;
       }
@@ -600,6 +666,7 @@ __global__ void __launch_bounds__(256) k_fwd32(FwdArgs A) {
     item = PERSISTENT ? next_item(A, true, lane, item, stride) : item + stride;
   }
   if (lane == 0 && near_steps) atomicAdd(A.near_steps, near_steps);
+  if (lane == 0 && mid_steps) atomicAdd(A.mid_steps, mid_steps);
 }
 
 __device__ __forceinline__ double rcp_f64(double x) {
@@ -624,14 +691,15 @@ __global__ void __launch_bounds__(256) k_fwd64(FwdArgs A) {
   cd2p recs = (cd2p)A.rec64;
   while (item < A.nitems) {
     const int64_t tile = tile_of(A, item);
-    const int64_t base = tile * (64 * K);
     double nd[K][3];
     bool inmap[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-      const int64_t p = base + j * 64 + lane;
-      inmap[j] = p < A.npix;
-      const int64_t pc = inmap[j] ? p : A.npix - 1;
+      int64_t row;
+      int32_t cnt;
+      tile_row<K>(A, tile, j, row, cnt);
+      inmap[j] = lane < cnt;
+      const int64_t pc = row + row_off(cnt, lane);
       nd[j][0] = A.dirx[pc];
       nd[j][1] = A.diry[pc];
       nd[j][2] = A.dirz[pc];
@@ -711,8 +779,11 @@ __global__ void __launch_bounds__(256) k_fwd64(FwdArgs A) {
     }
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-      const int64_t p = base + j * 64 + lane;
-      if (inmap[j]) {
+      int64_t row;
+      int32_t cnt;
+      tile_row<K>(A, tile, j, row, cnt);
+      if (lane < cnt) {
+        const int64_t p = row + lane;
         const double v = S[j] - C[j];
         A.map[p] = A.accumulate ? A.map[p] + v : v;
       }
@@ -765,7 +836,7 @@ __global__ void __launch_bounds__(256) k_adj32(AdjArgs A) {
   const int64_t rec = bx.rec_off + (active ? li : 0);
   // Segment constants (per lane).
   const float4* R4 = (const float4*)(A.rec32 + (size_t)rec * kRec32);
-  const float4 q0 = R4[0], q1 = R4[1], q2 = R4[2];
+  const float4 q0 = R4[0], q1 = R4[1], q2 = R4[2], q3 = R4[3];
   const float px = q0.x, py = q0.y, pz = q0.z;
   const float tx = q0.w, ty = q1.x, tz = q1.y;
   const float vx = q1.z, vy = q1.w, vz = q2.x;
@@ -774,7 +845,9 @@ __global__ void __launch_bounds__(256) k_adj32(AdjArgs A) {
   const double2 h1 = ((const double2*)A.phat64)[2 * rec + 1];
   const int64_t p0 = A.npix * split / A.nsplit;
   const int64_t p1 = A.npix * (split + 1) / A.nsplit;
-  const float near_w = A.near_w;
+  const float near_w = A.near_w, far_w = A.far_w;
+  // Segments flagged at precompute take the FP64 form against every pixel.
+  const bool force = active && __float_as_int(q3.y) != 0;
   cf4p tab = (cf4p)A.pixtab;
   cd2p tab64 = (cd2p)A.pix64;
   double acc[kAcc];
@@ -787,25 +860,43 @@ __global__ void __launch_bounds__(256) k_adj32(AdjArgs A) {
     float pa[kAcc];
 #pragma unroll
     for (int k = 0; k < kAcc; ++k) pa[k] = 0.f;
+    // Pixel records stream through scalar registers one step ahead; the
+    // values are then copied to vector registers so that the per-pair FMAs
+    // read vector operands only (twice the issue rate of scalar operands).
+    v4f cur = tab[pc];
     for (int64_t p = pc; p < pe; ++p) {
+      __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): cur has arrived
+      const v4f pt = cur;
+      cur = tab[(p + 1 < pe) ? p + 1 : p];
+      // Pixels with a zero cotangent contribute nothing.
+      if ((__float_as_int(pt.w) & 0x7fffffff) == 0) continue;
       if (check_vis) {
         const v2d e0 = tab64[2 * p + 0];
         const v2d e1 = tab64[2 * p + 1];
         if (!sees_box(e0.x, e0.y, e1.x, bx, A.eta0)) continue;
       }
-      const v4f pt = tab[p];
-      const float nx = pt.x, ny = pt.y, nz = pt.z, s = pt.w;
+      const float nx = to_vgpr(pt.x), ny = to_vgpr(pt.y), nz = to_vgpr(pt.z), s = to_vgpr(pt.w);
       float w = fmaf(-nz, pz, fmaf(-ny, py, fmaf(-nx, px, 1.0f)));
       const float a = fmaf(nz, tz, fmaf(ny, ty, nx * tx));
       const float bb = fmaf(nz, vz, fmaf(ny, vy, fmaf(nx, vx, 1.0f)));
       float t1, t2, r, dx, dy, dz;
-      if (!__any(w < near_w)) {
+      if (!__any(w < far_w || force)) {
         t1 = fmaf(kap, bb, -c1v);
         t2 = fmaf(kap, a, -c2v);
         r = __builtin_amdgcn_rcpf(bb * w);
         dx = nx - px;
         dy = ny - py;
         dz = nz - pz;
+      } else if (!__any(w < near_w || force)) {
+        // The direction difference in FP32 (see the forward kernel).
+        dx = nx - px;
+        dy = ny - py;
+        dz = nz - pz;
+        const float q = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        t1 = kap * fmaf(vz, dz, fmaf(vy, dy, vx * dx));
+        t2 = kap * fmaf(tz, dz, fmaf(ty, dy, tx * dx));
+        w = 0.5f * q;
+        r = __builtin_amdgcn_rcpf(bb * w);
       } else {
         const v2d e0 = tab64[2 * p + 0];
         const v2d e1 = tab64[2 * p + 1];

@@ -1,9 +1,9 @@
-// sched.cpp -- host-side work planning: which pixel tiles can see a box.
+// sched.cpp -- host-side work planning: how pixels are cut into tiles and
+// which tiles can see a box.
 //
-// A tile is `tile` consecutive RING pixels.  For boxes that do not see the
-// whole sky the kernels test every pixel exactly; this file only has to
-// produce a superset of the tiles that contain a visible pixel, so every
-// quantity here carries a generous margin.
+// For boxes that do not see the whole sky the kernels test every pixel
+// exactly; this file only has to produce a superset of the tiles that
+// contain a visible pixel, so every quantity here carries a margin.
 #include <math.h>
 #include <stdint.h>
 
@@ -24,6 +24,7 @@ struct RingInfo {
   double offset;   // azimuth of pixel 0 in units of the pixel spacing
 };
 
+// Ring i (1 .. 4 Nside - 1) of the HEALPix RING scheme.
 RingInfo ring_info(int64_t nside, int64_t i) {
   const int64_t N = nside;
   RingInfo r;
@@ -47,24 +48,90 @@ RingInfo ring_info(int64_t nside, int64_t i) {
   return r;
 }
 
-void push_pixels(std::vector<std::pair<int64_t, int64_t>>& px, int64_t a, int64_t b) {
-  if (b >= a) px.emplace_back(a, b);
+int64_t ring_len(int64_t nside, int64_t i) {
+  return 4 * std::min(std::min(i, nside), 4 * nside - i);
+}
+
+// Chunk of a ring block that holds offset j of a ring of `len` pixels, in a
+// block whose longest ring has `maxlen`: chunk c starts at
+// floor(64 c len / maxlen), so this is the largest c with that start <= j.
+int64_t chunk_of(int64_t j, int64_t len, int64_t maxlen) {
+  const int64_t num = (j + 1) * maxlen, den = 64 * len;
+  return (num + den - 1) / den - 1;
 }
 
 }  // namespace
 
+void make_strips(int64_t nside, int64_t tile_px, Tiling& t) {
+  t = Tiling();
+  t.nside = nside;
+  t.tile_px = tile_px;
+  t.blocks = false;
+  const int64_t npix = 12 * nside * nside;
+  t.ntiles = (npix + tile_px - 1) / tile_px;
+}
+
+void make_ring_blocks(int64_t nside, int K, Tiling& t) {
+  t = Tiling();
+  t.nside = nside;
+  t.K = K;
+  t.blocks = true;
+  const int64_t nring = 4 * nside - 1;
+  const int64_t nblock = (nring + K - 1) / K;
+  t.block_first.assign(nblock + 1, 0);
+  t.block_maxlen.assign(nblock, 0);
+  for (int64_t rb = 0; rb < nblock; ++rb) {
+    int64_t maxlen = 0;
+    for (int64_t i = 1 + rb * K; i <= std::min(nring, (rb + 1) * K); ++i)
+      maxlen = std::max(maxlen, ring_len(nside, i));
+    t.block_maxlen[rb] = maxlen;
+    t.block_first[rb + 1] = t.block_first[rb] + (maxlen + 63) / 64;
+  }
+  t.ntiles = t.block_first[nblock];
+}
+
+std::pair<int64_t, int64_t> Tiling::ring_span(int64_t i, int64_t j0, int64_t j1) const {
+  const RingInfo r = ring_info(nside, i);
+  if (!blocks) return {(r.first + j0) / tile_px, (r.first + j1) / tile_px};
+  const int64_t rb = (i - 1) / K;
+  const int64_t maxlen = block_maxlen[rb];
+  return {block_first[rb] + chunk_of(j0, r.len, maxlen),
+          block_first[rb] + chunk_of(j1, r.len, maxlen)};
+}
+
+void ring_block_rows(const Tiling& t, std::vector<int64_t>& rows) {
+  rows.assign((size_t)t.ntiles * t.K, 0);
+  const int64_t nring = 4 * t.nside - 1;
+  const int64_t nblock = (int64_t)t.block_maxlen.size();
+  for (int64_t rb = 0; rb < nblock; ++rb) {
+    const int64_t maxlen = t.block_maxlen[rb];
+    const int64_t nchunk = t.block_first[rb + 1] - t.block_first[rb];
+    for (int j = 0; j < t.K; ++j) {
+      const int64_t i = 1 + rb * t.K + j;
+      if (i > nring) continue;
+      const RingInfo r = ring_info(t.nside, i);
+      for (int64_t c = 0; c < nchunk; ++c) {
+        const int64_t a = 64 * c * r.len / maxlen;
+        const int64_t b = std::min(r.len, 64 * (c + 1) * r.len / maxlen);
+        if (b <= a) continue;
+        rows[(size_t)(t.block_first[rb] + c) * t.K + j] = ((r.first + a) << 7) | (b - a);
+      }
+    }
+  }
+}
+
 // Tiles that may hold pixels within angle rho of (cx, cy, cz).
-void cap_tiles(int64_t nside, int64_t tile, double cx, double cy, double cz, double rho,
+void cap_tiles(const Tiling& t, double cx, double cy, double cz, double rho,
                std::vector<std::pair<int64_t, int64_t>>& out) {
   out.clear();
+  const int64_t nside = t.nside;
   const int64_t npix = 12 * nside * nside;
-  const int64_t ntiles = (npix + tile - 1) / tile;
   const double nrm = sqrt(cx * cx + cy * cy + cz * cz);
   // Margin: a few pixel widths plus rounding slack.
   const double pix_ang = sqrt(4.0 * M_PI / (double)npix);
   rho = rho + 2.0 * pix_ang + 1e-9;
   if (!(nrm > 0.0) || rho >= M_PI) {
-    out.emplace_back(0, ntiles - 1);
+    out.emplace_back(0, t.ntiles - 1);
     return;
   }
   cx /= nrm;
@@ -74,7 +141,7 @@ void cap_tiles(int64_t nside, int64_t tile, double cx, double cy, double cz, dou
   const double thc = acos(zc);
   const double phc = atan2(cy, cx);
   const double sc = sin(thc);
-  std::vector<std::pair<int64_t, int64_t>> px;
+  std::vector<std::pair<int64_t, int64_t>> tl;
   for (int64_t i = 1; i < 4 * nside; ++i) {
     const RingInfo r = ring_info(nside, i);
     const double th = acos(std::max(-1.0, std::min(1.0, r.z)));
@@ -91,7 +158,7 @@ void cap_tiles(int64_t nside, int64_t tile, double cx, double cy, double cz, dou
     }
     const double dphi = 2.0 * M_PI / (double)r.len;
     if (half >= M_PI - 2.0 * dphi) {
-      push_pixels(px, r.first, r.first + r.len - 1);
+      tl.push_back(t.ring_span(i, 0, r.len - 1));
       continue;
     }
     // Pixel centres phi_j = (j + offset) dphi; keep j with |phi_j - phc| <= half.
@@ -100,47 +167,42 @@ void cap_tiles(int64_t nside, int64_t tile, double cx, double cy, double cz, dou
     int64_t jlo = (int64_t)floor(lo) - 1;
     int64_t jhi = (int64_t)ceil(hi) + 1;
     if (jhi - jlo + 1 >= r.len) {
-      push_pixels(px, r.first, r.first + r.len - 1);
+      tl.push_back(t.ring_span(i, 0, r.len - 1));
       continue;
     }
     // Wrap into [0, len).
     jlo = ((jlo % r.len) + r.len) % r.len;
     jhi = ((jhi % r.len) + r.len) % r.len;
     if (jlo <= jhi) {
-      push_pixels(px, r.first + jlo, r.first + jhi);
+      tl.push_back(t.ring_span(i, jlo, jhi));
     } else {
-      push_pixels(px, r.first, r.first + jhi);
-      push_pixels(px, r.first + jlo, r.first + r.len - 1);
+      tl.push_back(t.ring_span(i, 0, jhi));
+      tl.push_back(t.ring_span(i, jlo, r.len - 1));
     }
   }
-  // Pixel ranges -> merged tile ranges.
-  std::vector<std::pair<int64_t, int64_t>> tl;
-  tl.reserve(px.size());
-  for (auto& p : px) tl.emplace_back(p.first / tile, p.second / tile);
+  // Merge the tile ranges.
   std::sort(tl.begin(), tl.end());
-  for (auto& t : tl) {
-    if (!out.empty() && t.first <= out.back().second + 1)
-      out.back().second = std::max(out.back().second, t.second);
+  for (auto& x : tl) {
+    if (!out.empty() && x.first <= out.back().second + 1)
+      out.back().second = std::max(out.back().second, x.second);
     else
-      out.push_back(t);
+      out.push_back(x);
   }
 }
 
 // Tiles of a box: all, the tiles of its cap, or those of a cap bounding the
 // box (for the ray-crosses-box rule); none when the box lies entirely
 // outside the slab's radii.
-void box_tiles(int64_t nside, int64_t tile, const HostBoxGeom& g, double eta0,
+void box_tiles(const Tiling& t, const HostBoxGeom& g, double eta0,
                std::vector<std::pair<int64_t, int64_t>>& out) {
   out.clear();
-  const int64_t npix = 12 * nside * nside;
-  const int64_t ntiles = (npix + tile - 1) / tile;
   if (g.vis == 0) {
-    out.emplace_back(0, ntiles - 1);
+    out.emplace_back(0, t.ntiles - 1);
     return;
   }
   if (g.vis == 2) {
     const double c = std::max(-1.0, std::min(1.0, g.cap_cos));
-    cap_tiles(nside, tile, g.cap_dir[0], g.cap_dir[1], g.cap_dir[2], acos(c), out);
+    cap_tiles(t, g.cap_dir[0], g.cap_dir[1], g.cap_dir[2], acos(c), out);
     return;
   }
   double ctr[3], half = 0.0, dmin2 = 0.0, dmax2 = 0.0;
@@ -158,10 +220,10 @@ void box_tiles(int64_t nside, int64_t tile, const HostBoxGeom& g, double eta0,
   half = sqrt(half);
   const double d = sqrt(ctr[0] * ctr[0] + ctr[1] * ctr[1] + ctr[2] * ctr[2]);
   if (d <= half * (1.0 + 1e-9)) {
-    out.emplace_back(0, ntiles - 1);
+    out.emplace_back(0, t.ntiles - 1);
     return;
   }
-  cap_tiles(nside, tile, ctr[0], ctr[1], ctr[2], asin(std::min(1.0, half / d)), out);
+  cap_tiles(t, ctr[0], ctr[1], ctr[2], asin(std::min(1.0, half / d)), out);
 }
 
 }  // namespace csmap

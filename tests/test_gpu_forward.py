@@ -99,17 +99,20 @@ def mixed():
 @pytest.mark.parametrize("form", ["fp64", "fp32c", "fp32c-frac"])
 @pytest.mark.parametrize("K", [1, 2, 4, 8])
 @pytest.mark.parametrize("schedule", [0, 1, 2])
-def test_mixed_rules_all_shapes(B, mixed, form, K, schedule):
+@pytest.mark.parametrize("tiling", [1, 2])
+def test_mixed_rules_all_shapes(B, mixed, form, K, schedule, tiling):
     w, ref, pairs = mixed
-    say(f"mixed form={form} K={K} schedule={schedule}")
+    say(f"mixed form={form} K={K} schedule={schedule} tiling={tiling}")
     f = B.CSMAP_FORM_FP64 if form == "fp64" else B.CSMAP_FORM_FP32C
-    opts = {B.CSMAP_OPT_PIX_PER_LANE: K, B.CSMAP_OPT_SCHEDULE: schedule, B.CSMAP_OPT_WAVES: 2}
+    opts = {B.CSMAP_OPT_PIX_PER_LANE: K, B.CSMAP_OPT_SCHEDULE: schedule, B.CSMAP_OPT_WAVES: 2,
+            B.CSMAP_OPT_TILING: tiling}
     if form != "fp64":
         opts[B.CSMAP_OPT_ACCUM] = 1 if form == "fp32c-frac" else 0
     sky = sky_from_workload(w, f, opts)
     m = sky.render().cpu().numpy()
     st = sky.stats()
     e = err_metrics(m, ref)
+    assert st["tiling"] == tiling
     assert st["pairs"] == pairs
     assert st["kept"] == sum(int(oracle.kept(w.eta0, b).sum()) for b in w.boxes)
     if form == "fp64":
@@ -136,6 +139,82 @@ def test_fp32c_near_threshold_any_value_within_gate(B, mixed, near_w, accum):
     if near_w >= 2:
         assert e["rel_rms"] <= 2e-6
     if near_w >= 1e-3:
+        assert e["rel_rms"] <= FP32_RMS and e["rel_max"] <= FP32_MAX, e
+    sky.close()
+
+
+@pytest.mark.parametrize("accum", [0, 1])
+@pytest.mark.parametrize("near_w,far_w,path", [(1e-6, 1e-6, "far"), (1e-6, 3.0, "middle"),
+                                               (3.0, 3.0, "fp64"), (5e-5, 5e-3, "default"),
+                                               (1e-3, 0.2, "wide middle")])
+def test_fp32c_three_pair_forms(B, mixed, near_w, far_w, path, accum):
+    """The FP32C form takes one of three forms per (wavefront, segment) step:
+    dot products when every pair is at least far_w from the segment (in
+    1 - n.P/R), the FP32 difference n - P/R when some pair is closer but
+    none below near_w, the FP64 difference otherwise.  Forcing each one in
+    turn leaves the map within the gate (the all-dot-product case excepted,
+    whose close pairs lose precision by design) and the counters say which
+    form ran."""
+    w, ref, pairs = mixed
+    sky = sky_from_workload(w, B.CSMAP_FORM_FP32C, {B.CSMAP_OPT_NEAR_W: near_w,
+                                                    B.CSMAP_OPT_FAR_W: far_w,
+                                                    B.CSMAP_OPT_ACCUM: accum})
+    m = sky.render().cpu().numpy()
+    st = sky.stats()
+    e = err_metrics(m, ref)
+    say(f"{path} accum={accum} {e} fp64_steps={st['near_steps']} mid_steps={st['mid_steps']}")
+    assert st["pairs"] == pairs and np.all(np.isfinite(m))
+    if path == "far":
+        assert st["mid_steps"] == 0
+    elif path == "middle":
+        assert st["mid_steps"] > 0 and st["near_steps"] < st["mid_steps"] // 100
+    elif path == "fp64":
+        assert st["mid_steps"] == 0 and st["near_steps"] > 0
+    if path != "far":
+        assert e["rel_rms"] <= FP32_RMS and e["rel_max"] <= FP32_MAX, e
+    sky.close()
+
+
+def caps_workload(nside=96):
+    """Cap-visibility boxes around a pole, across phi = 0, on the equator
+    and at mid latitude, plus one box every pixel sees: ring blocks with
+    full 64-pixel rows, polar blocks of unequal rings, and the belt."""
+    eta0 = 3.0
+    dirs = [(0.0, 0.0, 1.0), (1.0, 0.0, 0.05), (0.3, -0.95, 0.0), (-0.5, 0.4, -0.77)]
+    boxes = []
+    for b, d in enumerate(dirs):
+        d = np.asarray(d) / np.linalg.norm(d)
+        centre = 1.5 * d
+        boxes.append(synth.make_box(150 + 37 * b, 60 + b, origin=centre - 0.5, eta_lo=0.0,
+                                    eta_hi=3.0, dtype=np.float32, vis=synth.VIS_CAP, cap_dir=d,
+                                    cap_cos=math.cos(0.35 + 0.1 * b)))
+    boxes.append(synth.make_box(90, 65, origin=(-0.5, -0.5, -0.5), eta_lo=0.0, eta_hi=3.0,
+                                dtype=np.float32))
+    return synth.Workload("caps", nside, eta0, boxes)
+
+
+@pytest.fixture(scope="module")
+def caps():
+    w = caps_workload()
+    ref = oracle.theta_pixels(w.nside, np.arange(w.npix), w.eta0, w.boxes)
+    return w, ref, expected_pairs(w)
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32c"])
+@pytest.mark.parametrize("K", [2, 8])
+@pytest.mark.parametrize("tiling", [1, 2])
+def test_cap_sky_both_tilings(B, caps, form, K, tiling):
+    w, ref, pairs = caps
+    say(f"caps form={form} K={K} tiling={tiling}")
+    f = B.CSMAP_FORM_FP64 if form == "fp64" else B.CSMAP_FORM_FP32C
+    sky = sky_from_workload(w, f, {B.CSMAP_OPT_PIX_PER_LANE: K, B.CSMAP_OPT_TILING: tiling})
+    m = sky.render().cpu().numpy()
+    st = sky.stats()
+    e = err_metrics(m, ref)
+    assert st["tiling"] == tiling and st["pairs"] == pairs
+    if form == "fp64":
+        assert e["rel_rms"] <= FP64_TOL and e["rel_max"] <= FP64_TOL, e
+    else:
         assert e["rel_rms"] <= FP32_RMS and e["rel_max"] <= FP32_MAX, e
     sky.close()
 
