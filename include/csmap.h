@@ -148,10 +148,10 @@ typedef enum {
      * Results agree up to rounding. */
     CSMAP_OPT_TILING = 8,
     /* FP32C form: a step in which every pair has 1 - n.P/R at or above this
-     * value (default 5e-3, about 0.1 rad) uses the algebraically equal form
-     * built from the dot products n.P/R, n.X', n.Xdot; a step with some pair
-     * below it and none below CSMAP_OPT_NEAR_W forms n - P/R in FP32.
-     * Minimum 1e-6. */
+     * value (default 5e-3, about 0.1 rad) and above CSMAP_OPT_NEAR_W uses
+     * the algebraically equal form built from the dot products n.P/R, n.X',
+     * n.Xdot; a step with some pair below it and none below
+     * CSMAP_OPT_NEAR_W forms n - P/R in FP32.  Minimum 1e-6. */
     CSMAP_OPT_FAR_W = 9
 } csmap_option;
 

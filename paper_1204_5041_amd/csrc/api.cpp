@@ -379,7 +379,7 @@ FwdArgs fwd_args(csmap_sky* s, double* map) {
   A.phat64 = s->d_phat64.as<double>();
   A.rec64 = s->d_rec64.as<double>();
   A.near_w = (float)s->near_w;
-  A.far_w = (float)s->far_w;
+  A.far_w = (float)std::max(s->far_w, s->near_w);
   A.frac = s->frac;
   A.chunk = s->chunk;
   A.accumulate = 0;
@@ -771,7 +771,7 @@ csmap_status csmap_backward(csmap_sky* s, const double* dmap, const csmap_grad* 
   A.nitems = nitems;
   A.nsplit = nsplit;
   A.near_w = (float)s->near_w;
-  A.far_w = (float)s->far_w;
+  A.far_w = (float)std::max(s->far_w, s->near_w);
   A.partial = s->d_partial.as<double>();
   A.dmap = dmap;
   HIPCHK(s, hipEventRecord(s->ev[4], st), "event");

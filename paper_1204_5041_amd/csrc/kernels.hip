@@ -333,6 +333,18 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
   s = t;
 }
 
+// Fold the term m/d into the running fraction fp/fq of a window; the first
+// slot of a window starts it.
+__device__ __forceinline__ void fold_term(bool first, float& fp, float& fq, float m, float d) {
+  if (first) {
+    fp = m;
+    fq = d;
+  } else {
+    fp = fmaf(fp, d, m * fq);
+    fq = fq * d;
+  }
+}
+
 // Copy a wave-uniform value into a vector register.
 __device__ __forceinline__ float to_vgpr(float x) {
   float y;
@@ -369,6 +381,133 @@ __device__ __forceinline__ void near_terms(const float (&nf)[K][3], const double
   (void)nf;
 }
 
+// One box's kept records [r0, r1) against a wavefront's pixels, with the
+// terms m/d of a pixel folded into one fraction over windows of four
+// consecutive segments, (p/q) + m/d = (p d + m q)/(q d), divided once per
+// window.  Folded terms have d = b w >= 0.05 near_w (b >= 0.05 unless the
+// segment is flagged), so a product of four stays inside the FP32 range.
+// Terms of the FP64 path are added one by one.  Each window slot is a
+// separate copy of the step, so its update of (p, q) is fixed at compile
+// time.  RING: the K pixels of every lane lie on one HEALPix ring and share
+// z, so each dot product n.X takes its z part from a per-segment constant.
+template <int K, bool RING>
+__device__ __forceinline__ void frac_box(const FwdArgs& A, cf4p recs, cd2p ph64, int64_t r0,
+                                         int64_t r1, const float (&nf)[K][3],
+                                         const double* sdir, int lane, const float (&vis)[K],
+                                         float (&S)[K], float (&C)[K],
+                                         unsigned long long& near_steps,
+                                         unsigned long long& mid_steps) {
+  const float near_w = A.near_w, far_w = A.far_w;
+  const int64_t nseg = r1 - r0;
+  const int64_t nwin = (nseg + 3) >> 2;
+  const cf4p last = recs + 4 * (r1 - 1);
+  cf4p rp = recs + 4 * r0;
+  v4f q0 = rp[0], q1 = rp[1], q2 = rp[2], q3 = rp[3];
+  float part[K], fp[K], fq[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) { part[j] = 0.f; fp[j] = 0.f; fq[j] = 1.f; }
+  int32_t left = A.chunk;   // segments until the next Kahan update (multiple of 4)
+  for (int64_t win = 0; win < nwin; ++win) {
+    const int32_t nslot = (win + 1 < nwin) ? 4 : (int32_t)(nseg - 4 * win);
+#pragma unroll
+    for (int slot = 0; slot < 4; ++slot) {
+      if (slot < nslot) {
+        const cf4p pf = (rp != last) ? rp + 4 : rp;
+        __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): q0..q3 have arrived
+        const v4f n0 = pf[0], n1 = pf[1], n2 = pf[2], n3 = pf[3];
+        // Segment constants copied to vector registers once per step: FMAs
+        // whose operands are all vector registers issue at twice the rate of
+        // those reading a scalar register.
+        const float px = to_vgpr(q0.x), py = to_vgpr(q0.y);
+        const float tx = to_vgpr(q0.w), ty = to_vgpr(q1.x);
+        const float vx = to_vgpr(q1.z), vy = to_vgpr(q1.w);
+        const float kap = to_vgpr(q2.y), c1v = to_vgpr(q2.z), c2v = to_vgpr(q2.w);
+        float pz, tz, vz;
+        float w[K], a[K], bb[K];
+        bool nearp = false;
+        if constexpr (RING) {
+          pz = q0.z;
+          tz = q1.y;
+          vz = q2.x;
+          const float zz = nf[0][2];
+          const float cw = fmaf(-zz, pz, 1.0f), ca = zz * tz, cb = fmaf(zz, vz, 1.0f);
+#pragma unroll
+          for (int j = 0; j < K; ++j) {
+            w[j] = fmaf(-nf[j][1], py, fmaf(-nf[j][0], px, cw));
+            a[j] = fmaf(nf[j][1], ty, fmaf(nf[j][0], tx, ca));
+            bb[j] = fmaf(nf[j][1], vy, fmaf(nf[j][0], vx, cb));
+            nearp |= (w[j] < far_w);
+          }
+        } else {
+          pz = to_vgpr(q0.z);
+          tz = to_vgpr(q1.y);
+          vz = to_vgpr(q2.x);
+#pragma unroll
+          for (int j = 0; j < K; ++j) {
+            w[j] = fmaf(-nf[j][2], pz, fmaf(-nf[j][1], py, fmaf(-nf[j][0], px, 1.0f)));
+            a[j] = fmaf(nf[j][2], tz, fmaf(nf[j][1], ty, nf[j][0] * tx));
+            bb[j] = fmaf(nf[j][2], vz, fmaf(nf[j][1], vy, fmaf(nf[j][0], vx, 1.0f)));
+            nearp |= (w[j] < far_w);
+          }
+        }
+        const bool force = __float_as_int(q3.y) != 0;
+        if (!force && !__any(nearp)) {
+          // Far step: kappa/2 times Xdot.(n - Ph) and X'.(n - Ph) from the
+          // dot products.
+#pragma unroll
+          for (int j = 0; j < K; ++j) {
+            const float t1 = fmaf(kap, bb[j], -c1v);
+            const float t2 = fmaf(kap, a[j], -c2v);
+            const float m = fmaf(-a[j], t2, t1 * bb[j]);   // kappa/2 * m
+            fold_term(slot == 0, fp[j], fq[j], m, bb[j] * w[j]);
+          }
+        } else {
+          bool n64 = force;
+#pragma unroll
+          for (int j = 0; j < K; ++j) n64 |= (w[j] < near_w);
+          if (!__any(n64)) {
+            // Middle step: the direction difference in FP32 (its error,
+            // about 1e-7 absolute, is small against |n - Ph| >= 0.01).
+            ++mid_steps;
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+              const float dx = nf[j][0] - px, dy = nf[j][1] - py, dz = nf[j][2] - pz;
+              const float q = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+              const float t1 = kap * fmaf(vz, dz, fmaf(vy, dy, vx * dx));
+              const float t2 = kap * fmaf(tz, dz, fmaf(ty, dy, tx * dx));
+              const float m = fmaf(-a[j], t2, t1 * bb[j]);
+              fold_term(slot == 0, fp[j], fq[j], m, bb[j] * (0.5f * q));
+            }
+          } else {
+            ++near_steps;
+            near_terms<K>(nf, sdir, lane, q0, q1, q2, a, bb, ph64 + 2 * ((rp - recs) >> 2), part);
+            if (slot == 0) {
+#pragma unroll
+              for (int j = 0; j < K; ++j) { fp[j] = 0.f; fq[j] = 1.f; }
+            }
+          }
+        }
+        q0 = n0;
+        q1 = n1;
+        q2 = n2;
+        q3 = n3;
+        rp = pf;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) part[j] = fmaf(fp[j], __builtin_amdgcn_rcpf(fq[j]), part[j]);
+    left -= 4;
+    if (left <= 0 || win + 1 == nwin) {
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        kahan_add(S[j], C[j], part[j] * vis[j]);
+        part[j] = 0.f;
+      }
+      left = A.chunk;
+    }
+  }
+}
+
 template <int K, bool PERSISTENT, bool FRAC>
 __global__ void __launch_bounds__(256) k_fwd32(FwdArgs A) {
   const int lane = threadIdx.x & 63;
@@ -395,6 +534,8 @@ __global__ void __launch_bounds__(256) k_fwd32(FwdArgs A) {
     // FP32 copies stay in registers across the segment loop.
     float nf[K][3];
     bool inmap[K];
+    bool same_ring = true;   // this lane's K pixels share one ring (one z)
+    double z0 = 0.0;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
       int64_t row;
@@ -403,6 +544,8 @@ __global__ void __launch_bounds__(256) k_fwd32(FwdArgs A) {
       inmap[j] = lane < cnt;
       const int32_t off = row_off(cnt, lane);
       const double x = A.dirx[row + off], y = A.diry[row + off], z = A.dirz[row + off];
+      if (j == 0) z0 = z;
+      same_ring = same_ring && z == z0;
       sdir[(j * 3 + 0) * 64 + lane] = x;
       sdir[(j * 3 + 1) * 64 + lane] = y;
       sdir[(j * 3 + 2) * 64 + lane] = z;
@@ -410,6 +553,8 @@ __global__ void __launch_bounds__(256) k_fwd32(FwdArgs A) {
       nf[j][1] = (float)y;
       nf[j][2] = (float)z;
     }
+    // Ring z is computed from integers, so equal z means one ring.
+    const bool ring = __all(same_ring);
     float S[K], C[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) { S[j] = 0.f; C[j] = 0.f; }
@@ -441,117 +586,10 @@ __global__ void __launch_bounds__(256) k_fwd32(FwdArgs A) {
       if (lane == 0 && r1 > r0) atomicAdd(A.pairs, nvis * (unsigned long long)(r1 - r0));
       if (r1 == r0) continue;
       if constexpr (FRAC) {
-      // Terms m/d of a pixel are folded into one fraction over windows of
-      // four consecutive segments, (p/q) + m/d = (p d + m q)/(q d), and
-      // divided once per window.  Folded terms have d = b w >= 0.05 near_w
-      // (b >= 0.05 unless the segment is flagged), so a product of four
-      // stays inside the FP32 range.  Terms of the FP64 path are added one by
-      // one.  Each window slot is a separate copy of the step, so its update
-      // of (p, q) is fixed at compile time.
-      const int64_t nseg = r1 - r0;
-      const int64_t nwin = (nseg + 3) >> 2;
-      const cf4p last = recs + 4 * (r1 - 1);
-      cf4p rp = recs + 4 * r0;
-      v4f q0 = rp[0], q1 = rp[1], q2 = rp[2], q3 = rp[3];
-      float part[K], fp[K], fq[K];
-#pragma unroll
-      for (int j = 0; j < K; ++j) { part[j] = 0.f; fp[j] = 0.f; fq[j] = 1.f; }
-      int32_t left = A.chunk;   // segments until the next Kahan update (multiple of 4)
-      for (int64_t win = 0; win < nwin; ++win) {
-        const int32_t nslot = (win + 1 < nwin) ? 4 : (int32_t)(nseg - 4 * win);
-#pragma unroll
-        for (int slot = 0; slot < 4; ++slot) {
-          if (slot < nslot) {
-            const cf4p pf = (rp != last) ? rp + 4 : rp;
-            __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): q0..q3 have arrived
-            const v4f n0 = pf[0], n1 = pf[1], n2 = pf[2], n3 = pf[3];
-            // Segment constants copied to vector registers once per step:
-            // FMAs whose operands are all vector registers issue at twice the
-            // rate of those reading a scalar register.
-            const float px = to_vgpr(q0.x), py = to_vgpr(q0.y), pz = to_vgpr(q0.z);
-            const float tx = to_vgpr(q0.w), ty = to_vgpr(q1.x), tz = to_vgpr(q1.y);
-            const float vx = to_vgpr(q1.z), vy = to_vgpr(q1.w), vz = to_vgpr(q2.x);
-            const float kap = to_vgpr(q2.y), c1v = to_vgpr(q2.z), c2v = to_vgpr(q2.w);
-            float w[K], a[K], bb[K];
-            bool nearp = false;
-#pragma unroll
-            for (int j = 0; j < K; ++j) {
-              w[j] = fmaf(-nf[j][2], pz, fmaf(-nf[j][1], py, fmaf(-nf[j][0], px, 1.0f)));
-              a[j] = fmaf(nf[j][2], tz, fmaf(nf[j][1], ty, nf[j][0] * tx));
-              bb[j] = fmaf(nf[j][2], vz, fmaf(nf[j][1], vy, fmaf(nf[j][0], vx, 1.0f)));
-              nearp |= (w[j] < far_w);
-            }
-            const bool force = __float_as_int(q3.y) != 0;
-            float m[K], den[K];
-            bool fold = true;
-            if (!force && !__any(nearp)) {
-              // Far step: kappa/2 times Xdot.(n - Ph) and X'.(n - Ph) from the
-              // dot products.
-#pragma unroll
-              for (int j = 0; j < K; ++j) {
-                const float t1 = fmaf(kap, bb[j], -c1v);
-                const float t2 = fmaf(kap, a[j], -c2v);
-                m[j] = fmaf(-a[j], t2, t1 * bb[j]);   // kappa/2 * m
-                den[j] = bb[j] * w[j];
-              }
-            } else {
-              bool n64 = force;
-#pragma unroll
-              for (int j = 0; j < K; ++j) n64 |= (w[j] < near_w);
-              if (!__any(n64)) {
-                // Middle step: the direction difference in FP32 (its error,
-                // about 1e-7 absolute, is small against |n - Ph| >= 0.01).
-                ++mid_steps;
-#pragma unroll
-                for (int j = 0; j < K; ++j) {
-                  const float dx = nf[j][0] - px, dy = nf[j][1] - py, dz = nf[j][2] - pz;
-                  const float q = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                  const float t1 = kap * fmaf(vz, dz, fmaf(vy, dy, vx * dx));
-                  const float t2 = kap * fmaf(tz, dz, fmaf(ty, dy, tx * dx));
-                  m[j] = fmaf(-a[j], t2, t1 * bb[j]);
-                  den[j] = bb[j] * (0.5f * q);
-                }
-              } else {
-                ++near_steps;
-                near_terms<K>(nf, sdir, lane, q0, q1, q2, a, bb, ph64 + 2 * ((rp - recs) >> 2),
-                              part);
-                fold = false;
-              }
-            }
-            if (fold) {
-#pragma unroll
-              for (int j = 0; j < K; ++j) {
-                if (slot == 0) {
-                  fp[j] = m[j];
-                  fq[j] = den[j];
-                } else {
-                  fp[j] = fmaf(fp[j], den[j], m[j] * fq[j]);
-                  fq[j] = fq[j] * den[j];
-                }
-              }
-            } else if (slot == 0) {
-#pragma unroll
-              for (int j = 0; j < K; ++j) { fp[j] = 0.f; fq[j] = 1.f; }
-            }
-            q0 = n0;
-            q1 = n1;
-            q2 = n2;
-            q3 = n3;
-            rp = pf;
-          }
-        }
-#pragma unroll
-        for (int j = 0; j < K; ++j) part[j] = fmaf(fp[j], __builtin_amdgcn_rcpf(fq[j]), part[j]);
-        left -= 4;
-        if (left <= 0 || win + 1 == nwin) {
-#pragma unroll
-          for (int j = 0; j < K; ++j) {
-            kahan_add(S[j], C[j], part[j] * vis[j]);
-            part[j] = 0.f;
-          }
-          left = A.chunk;
-        }
-      }
+        if (ring)
+          frac_box<K, true>(A, recs, ph64, r0, r1, nf, sdir, lane, vis, S, C, near_steps, mid_steps);
+        else
+          frac_box<K, false>(A, recs, ph64, r0, r1, nf, sdir, lane, vis, S, C, near_steps, mid_steps);
       } else {
       // Segment records stream through scalar registers.  The record of the
       // next step is requested before the current one is used; the explicit
