@@ -142,9 +142,11 @@ typedef enum {
     /* How pixels are grouped into the tiles that wavefronts own:
      *   0 = automatic (1 when every box sees every pixel, else 2);
      *   1 = strips of 64 x (pixels per lane) consecutive RING pixels;
-     *   2 = ring blocks: (pixels per lane) consecutive rings x up to 64
-     *       consecutive pixels per ring, azimuth-aligned across the rings,
-     *       so that a tile is a compact patch of sky.
+     *   2 = ring blocks: G consecutive rings (CSMAP_OPT_BLOCK_RINGS) x up to
+     *       64 x (pixels per lane) / G consecutive pixels per ring,
+     *       azimuth-aligned across the rings (see csmap_ring_block_rows), so
+     *       that a tile is a compact patch of sky; each ring of a tile has
+     *       64 / G lanes, so the pixels of a lane share one ring.
      * Results agree up to rounding. */
     CSMAP_OPT_TILING = 8,
     /* FP32C form: a step in which every pair has 1 - n.P/R at or above this
@@ -152,7 +154,10 @@ typedef enum {
      * the algebraically equal form built from the dot products n.P/R, n.X',
      * n.Xdot; a step with some pair below it and none below
      * CSMAP_OPT_NEAR_W forms n - P/R in FP32.  Minimum 1e-6. */
-    CSMAP_OPT_FAR_W = 9
+    CSMAP_OPT_FAR_W = 9,
+    /* Rings per tile G of the ring-block tiling: 0 (default: 2 x pixels per
+     * lane, i.e. rows of 32 pixels) or a power of two in 1 .. 64. */
+    CSMAP_OPT_BLOCK_RINGS = 10
 } csmap_option;
 
 /* Counters of the last render/backward (csmap_get_stats synchronises). */
@@ -250,23 +255,25 @@ csmap_status csmap_cap_tiles(int64_t nside, int64_t tile, double cx, double cy, 
                              int64_t *n_ranges);
 
 /* Host-side helper, no device work: the ring-block tiling of
- * CSMAP_OPT_TILING = 2 at Nside with k rings per block (1 <= k <= 64).  Rings
- * 1 .. 4 Nside - 1 are grouped k at a time; a block whose longest ring has
- * L pixels is cut into ceil(L / 64) tiles, and tile c of the block holds,
- * of each ring of n pixels, the offsets floor(64 c n / L) up to (not
- * including) min(n, floor(64 (c + 1) n / L)).  Writes k entries per tile,
- * (first RING pixel of the row << 7) | (pixels in the row), or 0 for an
- * empty row, for all tiles to rows (k * max_tiles entries available; rows
- * may be NULL when max_tiles is 0) and the tile count to *n_tiles; returns
- * CSMAP_E_INVALID if max_tiles is too small (with *n_tiles set). */
-csmap_status csmap_ring_block_rows(int64_t nside, int64_t k, int64_t *rows, int64_t max_tiles,
-                                   int64_t *n_tiles);
+ * CSMAP_OPT_TILING = 2 at Nside with `rings` rings per block (1 .. 64) and
+ * rows of at most `width` pixels (1 .. 1023; the library uses
+ * width = 64 x pixels per lane / rings).  Rings 1 .. 4 Nside - 1 are grouped
+ * `rings` at a time; a block whose longest ring has L pixels is cut into
+ * ceil(L / width) tiles, and tile c of the block holds, of each ring of n
+ * pixels, the offsets floor(width c n / L) up to (not including)
+ * min(n, floor(width (c + 1) n / L)).  Writes `rings` entries per tile,
+ * (first RING pixel of the row << 10) | (pixels in the row), or 0 for an
+ * empty row, for all tiles to rows (rings * max_tiles entries available;
+ * rows may be NULL when max_tiles is 0) and the tile count to *n_tiles;
+ * returns CSMAP_E_INVALID if max_tiles is too small (with *n_tiles set). */
+csmap_status csmap_ring_block_rows(int64_t nside, int64_t rings, int64_t width, int64_t *rows,
+                                   int64_t max_tiles, int64_t *n_tiles);
 
 /* Host-side helper, no device work: as csmap_cap_tiles, for the tiles of
- * the ring-block tiling with k rings per block (csmap_ring_block_rows). */
-csmap_status csmap_cap_block_tiles(int64_t nside, int64_t k, double cx, double cy, double cz,
-                                   double rho, int64_t *ranges, int64_t max_ranges,
-                                   int64_t *n_ranges);
+ * the ring-block tiling (csmap_ring_block_rows). */
+csmap_status csmap_cap_block_tiles(int64_t nside, int64_t rings, int64_t width, double cx,
+                                   double cy, double cz, double rho, int64_t *ranges,
+                                   int64_t max_ranges, int64_t *n_ranges);
 
 #ifdef __cplusplus
 }

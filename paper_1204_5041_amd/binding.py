@@ -22,7 +22,8 @@ CSMAP_FORM_FP64, CSMAP_FORM_FP32C = 0, 1
 CSMAP_F32, CSMAP_F64 = 0, 1
 CSMAP_VIS_ALL, CSMAP_VIS_BOX, CSMAP_VIS_CAP = 0, 1, 2
 (CSMAP_OPT_SCHEDULE, CSMAP_OPT_GRAPH, CSMAP_OPT_PIX_PER_LANE, CSMAP_OPT_WAVES, CSMAP_OPT_NEAR_W,
- CSMAP_OPT_CHUNK, CSMAP_OPT_ADJ_SPLIT, CSMAP_OPT_ACCUM, CSMAP_OPT_TILING, CSMAP_OPT_FAR_W) = range(10)
+ CSMAP_OPT_CHUNK, CSMAP_OPT_ADJ_SPLIT, CSMAP_OPT_ACCUM, CSMAP_OPT_TILING, CSMAP_OPT_FAR_W,
+ CSMAP_OPT_BLOCK_RINGS) = range(11)
 
 _STATUS_NAMES = {0: "CSMAP_OK", -1: "CSMAP_E_INVALID", -2: "CSMAP_E_NOMEM", -3: "CSMAP_E_DEVICE",
                  -4: "CSMAP_E_STATE", -5: "CSMAP_E_UNSUPPORTED"}
@@ -87,8 +88,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.csmap_autotune.argtypes = [vp, ctypes.c_char_p]
     lib.csmap_cap_tiles.argtypes = [i64, i64, dbl, dbl, dbl, dbl, ctypes.POINTER(i64), i64,
                                     ctypes.POINTER(i64)]
-    lib.csmap_cap_block_tiles.argtypes = lib.csmap_cap_tiles.argtypes
-    lib.csmap_ring_block_rows.argtypes = [i64, i64, ctypes.POINTER(i64), i64, ctypes.POINTER(i64)]
+    lib.csmap_cap_block_tiles.argtypes = [i64, i64, i64, dbl, dbl, dbl, dbl, ctypes.POINTER(i64),
+                                          i64, ctypes.POINTER(i64)]
+    lib.csmap_ring_block_rows.argtypes = [i64, i64, i64, ctypes.POINTER(i64), i64,
+                                          ctypes.POINTER(i64)]
     for name in EXPORTED:
         if name not in ("csmap_npix", "csmap_last_error"):
             getattr(lib, name).restype = i32
@@ -175,23 +178,29 @@ def csmap_cap_tiles(nside: int, tile: int, c, rho: float, max_ranges: int = 1 <<
     return [(buf[2 * i], buf[2 * i + 1]) for i in range(n.value)]
 
 
-def csmap_cap_block_tiles(nside: int, k: int, c, rho: float, max_ranges: int = 1 << 16):
+def csmap_cap_block_tiles(nside: int, rings: int, width: int, c, rho: float,
+                          max_ranges: int = 1 << 16):
     buf = (ctypes.c_int64 * (2 * max_ranges))()
     n = ctypes.c_int64()
-    _check(lib().csmap_cap_block_tiles(nside, k, float(c[0]), float(c[1]), float(c[2]),
-                                       float(rho), buf, max_ranges, ctypes.byref(n)))
+    _check(lib().csmap_cap_block_tiles(nside, rings, width, float(c[0]), float(c[1]),
+                                       float(c[2]), float(rho), buf, max_ranges, ctypes.byref(n)))
     return [(buf[2 * i], buf[2 * i + 1]) for i in range(n.value)]
 
 
-def csmap_ring_block_rows(nside: int, k: int):
-    """Row table of the ring-block tiling as an (ntiles, k) int64 numpy array."""
+ROW_COUNT_BITS = 10
+
+
+def csmap_ring_block_rows(nside: int, rings: int, width: int):
+    """Row table of the ring-block tiling as an (ntiles, rings) int64 numpy
+    array of (first pixel << ROW_COUNT_BITS) | count entries."""
     import numpy as np
     n = ctypes.c_int64()
-    st = lib().csmap_ring_block_rows(nside, k, None, 0, ctypes.byref(n))
+    st = lib().csmap_ring_block_rows(nside, rings, width, None, 0, ctypes.byref(n))
     if st != CSMAP_OK and n.value <= 0:
         _check(st)
-    out = np.zeros((n.value, k), dtype=np.int64)
-    _check(lib().csmap_ring_block_rows(nside, k, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+    out = np.zeros((n.value, rings), dtype=np.int64)
+    _check(lib().csmap_ring_block_rows(nside, rings, width,
+                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                        n.value, ctypes.byref(n)))
     return out
 

@@ -109,6 +109,7 @@ struct csmap_sky {
   int adj_split = 0;
   int frac = 1;
   int tiling = 0;   // 0 auto, 1 strips, 2 ring blocks
+  int block_rings = 0;  // ring blocks: rings per tile (0: chosen from K)
 
   // boxes and raw segment storage (append-only)
   std::vector<HostBox> boxes;
@@ -120,6 +121,7 @@ struct csmap_sky {
   bool dirty = true;
   int planned_K = -1;
   int planned_tiling = -1;
+  int planned_rings = -1;
   Tiling plan;
   DevBuf d_rows;     // ring-block row table (empty for strips)
   DevBuf d_boxes, d_blk_box, d_blk_count, d_blk_prefix, d_box_count, d_raw_off;
@@ -194,9 +196,14 @@ bool use_blocks(const csmap_sky* s) {
   return false;
 }
 
+// Rings per ring-block tile: 2 K rows of 32 pixels unless set.
+int block_rings(const csmap_sky* s) { return s->block_rings > 0 ? s->block_rings : 2 * s->K; }
+
 // Rebuild descriptors, compaction tables, record storage and the tile plan.
 csmap_status prepare(csmap_sky* s) {
-  if (!s->dirty && s->planned_K == s->K && s->planned_tiling == s->tiling) return CSMAP_OK;
+  if (!s->dirty && s->planned_K == s->K && s->planned_tiling == s->tiling &&
+      s->planned_rings == block_rings(s))
+    return CSMAP_OK;
   const int64_t nbox = (int64_t)s->boxes.size();
   hipStream_t st = s->stream;
   // Box descriptors and precompute blocks.
@@ -264,7 +271,8 @@ csmap_status prepare(csmap_sky* s) {
   // Tile plan.
   std::vector<int64_t> rows;
   if (use_blocks(s)) {
-    make_ring_blocks(s->nside, s->K, s->plan);
+    const int G = block_rings(s);
+    make_ring_blocks(s->nside, G, 64 * (int64_t)s->K / G, s->plan);
     ring_block_rows(s->plan, rows);
     HIPCHK(s, s->d_rows.ensure(sizeof(int64_t) * rows.size()), "alloc rows");
     HIPCHK(s, hipMemcpyAsync(s->d_rows.p, rows.data(), sizeof(int64_t) * rows.size(),
@@ -331,6 +339,7 @@ csmap_status prepare(csmap_sky* s) {
   s->dirty = false;
   s->planned_K = s->K;
   s->planned_tiling = s->tiling;
+  s->planned_rings = block_rings(s);
   return CSMAP_OK;
 }
 
@@ -366,6 +375,9 @@ FwdArgs fwd_args(csmap_sky* s, double* map) {
   A.tile_ptr = s->d_tile_ptr.as<int32_t>();
   A.tile_boxes = s->d_tile_boxes.as<int32_t>();
   A.rows = s->plan.blocks ? s->d_rows.as<int64_t>() : nullptr;
+  A.ring_g = s->plan.blocks ? s->plan.rings : 1;
+  A.ring_shift = 0;   // log2(64 / ring_g): lane l serves ring l >> ring_shift of its tile
+  while ((1 << A.ring_shift) * A.ring_g < 64) ++A.ring_shift;
   A.items = nullptr;
   A.nitems = s->ntiles;
   A.work_counter = (uint32_t*)(s->d_counters.as<unsigned long long>() + 2);
@@ -391,6 +403,26 @@ FwdArgs fwd_args(csmap_sky* s, double* map) {
   return A;
 }
 
+// Host check, before any forward launch, that the plan matches what the
+// kernels index with: tile count, pixels per lane and the ring-block row
+// table (64 / ring_g lanes per ring, ring_g rows per tile).
+csmap_status check_forward(const csmap_sky* s, const FwdArgs& A, int K) {
+  const Tiling& t = s->plan;
+  if (K != s->planned_K || t.ntiles != s->ntiles)
+    return fail(CSMAP_E_STATE, "forward launch does not match the tile plan");
+  if (A.rows) {
+    if (!t.blocks || A.ring_g != t.rings || (1 << A.ring_shift) * A.ring_g != 64 ||
+        t.width * t.rings != 64 * (int64_t)K ||
+        s->d_rows.cap < sizeof(int64_t) * (size_t)t.ntiles * (size_t)t.rings)
+      return fail(CSMAP_E_STATE, "ring-block row table does not match the launch");
+  } else if (t.blocks || t.tile_px != 64 * (int64_t)K) {
+    return fail(CSMAP_E_STATE, "strip tiling does not match the launch");
+  }
+  if (!A.items && A.nitems > t.ntiles)
+    return fail(CSMAP_E_STATE, "more work items than tiles");
+  return CSMAP_OK;
+}
+
 unsigned persistent_grid(const csmap_sky* s) {
   int dev = 0;
   (void)hipGetDevice(&dev);
@@ -408,13 +440,15 @@ unsigned persistent_grid(const csmap_sky* s) {
 csmap_status enqueue_render(csmap_sky* s, double* map, hipStream_t st, bool with_events) {
   const bool fp64 = s->form == CSMAP_FORM_FP64;
   const PreArgs P = pre_args(s);
+  FwdArgs A = fwd_args(s, map);
+  const csmap_status cs = check_forward(s, A, s->K);
+  if (cs != CSMAP_OK) return cs;
   if (with_events) HIPCHK(s, hipEventRecord(s->ev[0], st), "event");
   HIPCHK(s, launch_precompute(P, (int64_t)s->boxes.size(), st), "precompute launch");
   HIPCHK(s, launch_zero_counters(s->d_counters.as<unsigned long long>(), 4,
                                  (uint32_t*)(s->d_counters.as<unsigned long long>() + 2), st),
          "counter reset");
   if (with_events) HIPCHK(s, hipEventRecord(s->ev[1], st), "event");
-  FwdArgs A = fwd_args(s, map);
   const unsigned block = 64u * (unsigned)s->waves;
   if (s->schedule == 2) {
     HIPCHK(s, launch_fill(map, s->npix, 0.0, st), "map clear");
@@ -648,6 +682,11 @@ csmap_status csmap_set_option(csmap_sky* s, csmap_option opt, double value) {
     case CSMAP_OPT_TILING:
       if (iv < 0 || iv > 2) return fail(CSMAP_E_INVALID, "tiling must be 0, 1 or 2");
       s->tiling = iv;
+      break;
+    case CSMAP_OPT_BLOCK_RINGS:
+      if (iv != 0 && (iv < 1 || iv > 64 || (iv & (iv - 1))))
+        return fail(CSMAP_E_INVALID, "rings per block must be 0 or a power of two in [1, 64]");
+      s->block_rings = iv;
       break;
     default:
       return fail(CSMAP_E_INVALID, "unknown option");
@@ -884,14 +923,16 @@ csmap_status csmap_cap_tiles(int64_t nside, int64_t tile, double cx, double cy, 
   return write_cap_ranges(t, cx, cy, cz, rho, ranges, max_ranges, n_ranges);
 }
 
-csmap_status csmap_ring_block_rows(int64_t nside, int64_t k, int64_t* rows, int64_t max_tiles,
-                                   int64_t* n_tiles) {
+csmap_status csmap_ring_block_rows(int64_t nside, int64_t rings, int64_t width, int64_t* rows,
+                                   int64_t max_tiles, int64_t* n_tiles) {
   g_err.clear();
   if (nside < 1 || nside > kMaxNside) return fail(CSMAP_E_INVALID, "nside must be in [1, 8192]");
-  if (k < 1 || k > 64) return fail(CSMAP_E_INVALID, "k must be in [1, 64]");
+  if (rings < 1 || rings > 64) return fail(CSMAP_E_INVALID, "rings must be in [1, 64]");
+  if (width < 1 || width >= (1 << kRowCountBits))
+    return fail(CSMAP_E_INVALID, "width must be in [1, 1023]");
   if (!n_tiles || (max_tiles > 0 && !rows)) return fail(CSMAP_E_INVALID, "NULL output");
   Tiling t;
-  make_ring_blocks(nside, (int)k, t);
+  make_ring_blocks(nside, (int)rings, width, t);
   *n_tiles = t.ntiles;
   if (t.ntiles > max_tiles) return fail(CSMAP_E_INVALID, "max_tiles too small");
   std::vector<int64_t> r;
@@ -900,17 +941,19 @@ csmap_status csmap_ring_block_rows(int64_t nside, int64_t k, int64_t* rows, int6
   return CSMAP_OK;
 }
 
-csmap_status csmap_cap_block_tiles(int64_t nside, int64_t k, double cx, double cy, double cz,
-                                   double rho, int64_t* ranges, int64_t max_ranges,
-                                   int64_t* n_ranges) {
+csmap_status csmap_cap_block_tiles(int64_t nside, int64_t rings, int64_t width, double cx,
+                                   double cy, double cz, double rho, int64_t* ranges,
+                                   int64_t max_ranges, int64_t* n_ranges) {
   g_err.clear();
   if (nside < 1 || nside > kMaxNside) return fail(CSMAP_E_INVALID, "nside must be in [1, 8192]");
-  if (k < 1 || k > 64) return fail(CSMAP_E_INVALID, "k must be in [1, 64]");
+  if (rings < 1 || rings > 64) return fail(CSMAP_E_INVALID, "rings must be in [1, 64]");
+  if (width < 1 || width >= (1 << kRowCountBits))
+    return fail(CSMAP_E_INVALID, "width must be in [1, 1023]");
   if (!n_ranges || (max_ranges > 0 && !ranges)) return fail(CSMAP_E_INVALID, "NULL output");
   if (!isfinite(cx) || !isfinite(cy) || !isfinite(cz) || !isfinite(rho) || rho < 0)
     return fail(CSMAP_E_INVALID, "cap must be finite with rho >= 0");
   Tiling t;
-  make_ring_blocks(nside, (int)k, t);
+  make_ring_blocks(nside, (int)rings, width, t);
   return write_cap_ranges(t, cx, cy, cz, rho, ranges, max_ranges, n_ranges);
 }
 
@@ -998,6 +1041,8 @@ csmap_status csmap_autotune(csmap_sky* s, const char* cache_path) {
     A.items = items.as<int32_t>();
     A.nitems = (int64_t)it.size();
     A.seg_cap = 2048;
+    cs = check_forward(s, A, c.K);
+    if (cs != CSMAP_OK) break;
     const unsigned block = 64u * (unsigned)c.W;
     const unsigned grid = c.S ? persistent_grid(s) : (unsigned)((A.nitems + c.W - 1) / c.W);
     double ms_min = 1e300;

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "tiling.h"
+
 namespace csmap {
 
 constexpr int kMaxNside = 8192;
@@ -72,7 +74,9 @@ struct FwdArgs {
   int32_t all_boxes;           // 1: every tile sees every box (no lists)
   const int32_t* tile_ptr;     // CSR over tiles: boxes of tile t are
   const int32_t* tile_boxes;   //   tile_boxes[tile_ptr[t] .. tile_ptr[t+1])
-  const int64_t* rows;         // ring-block row table, K per tile (null: strips)
+  const int64_t* rows;         // ring-block row table, ring_g per tile (null: strips)
+  int32_t ring_g;              // rings per tile (1 for strips)
+  int32_t ring_shift;          // log2 of the lanes per ring, 64 / ring_g
   const int32_t* items;        // tile of each work item (null: item == tile)
   int64_t nitems;
   uint32_t* work_counter;      // persistent schedule: next item

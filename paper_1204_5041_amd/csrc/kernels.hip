@@ -44,7 +44,6 @@ typedef double v2d __attribute__((ext_vector_type(2)));
 typedef const v4f __attribute__((address_space(4)))* cf4p;
 typedef const v2d __attribute__((address_space(4)))* cd2p;
 typedef const int32_t __attribute__((address_space(4)))* ci32p;
-typedef const int64_t __attribute__((address_space(4)))* ci64p;
 
 typedef const DevBox __attribute__((address_space(4)))* cbox_p;
 typedef const DevBoxCount __attribute__((address_space(4)))* ccnt_p;
@@ -300,29 +299,43 @@ __device__ __forceinline__ int32_t tile_of(const FwdArgs& A, int64_t item) {
   return A.items ? ((ci32p)A.items)[item] : (int32_t)item;
 }
 
-// Row j of a tile: its first RING pixel and its pixel count (0 .. 64).
-// Ring-block tilings read both from the row table; strips are 64 K
-// consecutive pixels cut at the end of the map.  An empty row reports
-// pixel 0 as its first, so that loads through it stay inside the map.
+// The pixels of one lane in a tile: slot j is pixel first + pos0 + j step,
+// present when pos0 + j step < cnt.  Ring-block tilings give each ring of
+// the tile 64 / G lanes (G rings per tile) and read the ring's row from the
+// table, so all K pixels of a lane lie on one ring; strips are 64 K
+// consecutive pixels cut at the end of the map.  An empty row reports pixel
+// 0 as its first, so that loads through it stay inside the map.
+struct LaneRow {
+  int64_t first;
+  int32_t cnt, pos0, step;
+};
+
 template <int K>
-__device__ __forceinline__ void tile_row(const FwdArgs& A, int64_t tile, int j, int64_t& first,
-                                         int32_t& cnt) {
+__device__ __forceinline__ LaneRow lane_row(const FwdArgs& A, int64_t tile, int lane) {
+  LaneRow r;
   if (A.rows) {
-    const int64_t e = ((ci64p)A.rows)[tile * K + j];
-    first = e >> 7;
-    cnt = (int32_t)(e & 127);
+    const int g = lane >> A.ring_shift;
+    const int64_t e = A.rows[tile * A.ring_g + g];
+    r.first = e >> kRowCountBits;
+    r.cnt = (int32_t)(e & ((1 << kRowCountBits) - 1));
+    r.pos0 = lane - (g << A.ring_shift);
+    r.step = 1 << A.ring_shift;
   } else {
-    first = tile * (64 * K) + 64 * j;
-    const int64_t room = A.npix - first;
-    cnt = room >= 64 ? 64 : (room > 0 ? (int32_t)room : 0);
-    if (cnt == 0) first = 0;
+    r.first = tile * (64 * K);
+    const int64_t room = A.npix - r.first;
+    r.cnt = room >= 64 * K ? 64 * K : (room > 0 ? (int32_t)room : 0);
+    if (r.cnt == 0) r.first = 0;
+    r.pos0 = lane;
+    r.step = 64;
   }
+  return r;
 }
 
-// Lane offset into a row of `cnt` pixels; lanes past the end repeat its
-// last pixel (or pixel `first` of an empty row).
-__device__ __forceinline__ int32_t row_off(int32_t cnt, int lane) {
-  return lane < cnt ? lane : (cnt > 0 ? cnt - 1 : 0);
+// Offset of slot j of a lane inside its row; slots past the end repeat the
+// row's last pixel (or pixel `first` of an empty row).
+__device__ __forceinline__ int32_t slot_off(const LaneRow& r, int j) {
+  const int32_t pos = r.pos0 + j * r.step;
+  return pos < r.cnt ? pos : (r.cnt > 0 ? r.cnt - 1 : 0);
 }
 
 // Kahan update of (s, c) by x: s - c carries the sum.
@@ -527,23 +540,21 @@ __global__ void __launch_bounds__(256) k_fwd32(FwdArgs A) {
   while (item < A.nitems) {
     const int64_t tile = tile_of(A, item);
     // Pixel directions come from the table written by the RING pix2vec
-    // kernel.  Lane l of row j owns pixel first_j + l; lanes past the end of
-    // a row repeat its last pixel (they are masked out of every sum and
-    // never written).  The FP64 directions are parked in this wavefront's
-    // slice of LDS for the close-pair steps and visibility tests; only the
-    // FP32 copies stay in registers across the segment loop.
+    // kernel.  Slots past the end of a lane's row repeat its last pixel
+    // (they are masked out of every sum and never written).  The FP64
+    // directions are parked in this wavefront's slice of LDS for the
+    // close-pair steps and visibility tests; only the FP32 copies stay in
+    // registers across the segment loop.
     float nf[K][3];
     bool inmap[K];
     bool same_ring = true;   // this lane's K pixels share one ring (one z)
     double z0 = 0.0;
+    const LaneRow lr = lane_row<K>(A, tile, lane);
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-      int64_t row;
-      int32_t cnt;
-      tile_row<K>(A, tile, j, row, cnt);
-      inmap[j] = lane < cnt;
-      const int32_t off = row_off(cnt, lane);
-      const double x = A.dirx[row + off], y = A.diry[row + off], z = A.dirz[row + off];
+      inmap[j] = lr.pos0 + j * lr.step < lr.cnt;
+      const int64_t p = lr.first + slot_off(lr, j);
+      const double x = A.dirx[p], y = A.diry[p], z = A.dirz[p];
       if (j == 0) z0 = z;
       same_ring = same_ring && z == z0;
       sdir[(j * 3 + 0) * 64 + lane] = x;
@@ -688,15 +699,13 @@ __global__ void __launch_bounds__(256) k_fwd32(FwdArgs A) {
       }
       }
     }
+    const LaneRow lw = lane_row<K>(A, tile, lane);
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-      int64_t row;
-      int32_t cnt;
-      tile_row<K>(A, tile, j, row, cnt);
-      if (lane < cnt) {
+      if (lw.pos0 + j * lw.step < lw.cnt) {
         // The running sum s carries the result; c is the negated rounding
         // error still owed to it, so the value is s - c.
-        const int64_t p = row + lane;
+        const int64_t p = lw.first + lw.pos0 + j * lw.step;
         const double v = (double)S[j] - (double)C[j];
         A.map[p] = A.accumulate ? A.map[p] + v : v;
       }
@@ -731,13 +740,11 @@ __global__ void __launch_bounds__(256) k_fwd64(FwdArgs A) {
     const int64_t tile = tile_of(A, item);
     double nd[K][3];
     bool inmap[K];
+    const LaneRow lr = lane_row<K>(A, tile, lane);
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-      int64_t row;
-      int32_t cnt;
-      tile_row<K>(A, tile, j, row, cnt);
-      inmap[j] = lane < cnt;
-      const int64_t pc = row + row_off(cnt, lane);
+      inmap[j] = lr.pos0 + j * lr.step < lr.cnt;
+      const int64_t pc = lr.first + slot_off(lr, j);
       nd[j][0] = A.dirx[pc];
       nd[j][1] = A.diry[pc];
       nd[j][2] = A.dirz[pc];
@@ -815,13 +822,11 @@ __global__ void __launch_bounds__(256) k_fwd64(FwdArgs A) {
         }
       }
     }
+    const LaneRow lw = lane_row<K>(A, tile, lane);
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-      int64_t row;
-      int32_t cnt;
-      tile_row<K>(A, tile, j, row, cnt);
-      if (lane < cnt) {
-        const int64_t p = row + lane;
+      if (lw.pos0 + j * lw.step < lw.cnt) {
+        const int64_t p = lw.first + lw.pos0 + j * lw.step;
         const double v = S[j] - C[j];
         A.map[p] = A.accumulate ? A.map[p] + v : v;
       }

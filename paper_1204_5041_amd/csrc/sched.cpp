@@ -53,10 +53,11 @@ int64_t ring_len(int64_t nside, int64_t i) {
 }
 
 // Chunk of a ring block that holds offset j of a ring of `len` pixels, in a
-// block whose longest ring has `maxlen`: chunk c starts at
-// floor(64 c len / maxlen), so this is the largest c with that start <= j.
-int64_t chunk_of(int64_t j, int64_t len, int64_t maxlen) {
-  const int64_t num = (j + 1) * maxlen, den = 64 * len;
+// block whose longest ring has `maxlen`, chunks `width` wide: chunk c starts
+// at floor(width c len / maxlen), so this is the largest c with that
+// start <= j.
+int64_t chunk_of(int64_t j, int64_t len, int64_t maxlen, int64_t width) {
+  const int64_t num = (j + 1) * maxlen, den = width * len;
   return (num + den - 1) / den - 1;
 }
 
@@ -71,21 +72,22 @@ void make_strips(int64_t nside, int64_t tile_px, Tiling& t) {
   t.ntiles = (npix + tile_px - 1) / tile_px;
 }
 
-void make_ring_blocks(int64_t nside, int K, Tiling& t) {
+void make_ring_blocks(int64_t nside, int rings, int64_t width, Tiling& t) {
   t = Tiling();
   t.nside = nside;
-  t.K = K;
+  t.rings = rings;
+  t.width = width;
   t.blocks = true;
   const int64_t nring = 4 * nside - 1;
-  const int64_t nblock = (nring + K - 1) / K;
+  const int64_t nblock = (nring + rings - 1) / rings;
   t.block_first.assign(nblock + 1, 0);
   t.block_maxlen.assign(nblock, 0);
   for (int64_t rb = 0; rb < nblock; ++rb) {
     int64_t maxlen = 0;
-    for (int64_t i = 1 + rb * K; i <= std::min(nring, (rb + 1) * K); ++i)
+    for (int64_t i = 1 + rb * rings; i <= std::min(nring, (rb + 1) * rings); ++i)
       maxlen = std::max(maxlen, ring_len(nside, i));
     t.block_maxlen[rb] = maxlen;
-    t.block_first[rb + 1] = t.block_first[rb] + (maxlen + 63) / 64;
+    t.block_first[rb + 1] = t.block_first[rb] + (maxlen + width - 1) / width;
   }
   t.ntiles = t.block_first[nblock];
 }
@@ -93,28 +95,30 @@ void make_ring_blocks(int64_t nside, int K, Tiling& t) {
 std::pair<int64_t, int64_t> Tiling::ring_span(int64_t i, int64_t j0, int64_t j1) const {
   const RingInfo r = ring_info(nside, i);
   if (!blocks) return {(r.first + j0) / tile_px, (r.first + j1) / tile_px};
-  const int64_t rb = (i - 1) / K;
+  const int64_t rb = (i - 1) / rings;
   const int64_t maxlen = block_maxlen[rb];
-  return {block_first[rb] + chunk_of(j0, r.len, maxlen),
-          block_first[rb] + chunk_of(j1, r.len, maxlen)};
+  return {block_first[rb] + chunk_of(j0, r.len, maxlen, width),
+          block_first[rb] + chunk_of(j1, r.len, maxlen, width)};
 }
 
 void ring_block_rows(const Tiling& t, std::vector<int64_t>& rows) {
-  rows.assign((size_t)t.ntiles * t.K, 0);
+  rows.assign((size_t)t.ntiles * t.rings, 0);
   const int64_t nring = 4 * t.nside - 1;
   const int64_t nblock = (int64_t)t.block_maxlen.size();
+  const int64_t W = t.width;
   for (int64_t rb = 0; rb < nblock; ++rb) {
     const int64_t maxlen = t.block_maxlen[rb];
     const int64_t nchunk = t.block_first[rb + 1] - t.block_first[rb];
-    for (int j = 0; j < t.K; ++j) {
-      const int64_t i = 1 + rb * t.K + j;
+    for (int g = 0; g < t.rings; ++g) {
+      const int64_t i = 1 + rb * t.rings + g;
       if (i > nring) continue;
       const RingInfo r = ring_info(t.nside, i);
       for (int64_t c = 0; c < nchunk; ++c) {
-        const int64_t a = 64 * c * r.len / maxlen;
-        const int64_t b = std::min(r.len, 64 * (c + 1) * r.len / maxlen);
+        const int64_t a = W * c * r.len / maxlen;
+        const int64_t b = std::min(r.len, W * (c + 1) * r.len / maxlen);
         if (b <= a) continue;
-        rows[(size_t)(t.block_first[rb] + c) * t.K + j] = ((r.first + a) << 7) | (b - a);
+        rows[(size_t)(t.block_first[rb] + c) * t.rings + g] =
+            ((r.first + a) << kRowCountBits) | (b - a);
       }
     }
   }

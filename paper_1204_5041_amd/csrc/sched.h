@@ -5,6 +5,8 @@
 #include <utility>
 #include <vector>
 
+#include "tiling.h"
+
 namespace csmap {
 
 struct HostBoxGeom {
@@ -19,17 +21,18 @@ struct HostBoxGeom {
 // Strips: tile t is the `tile_px` consecutive RING pixels starting at
 // t * tile_px (the last tile is cut at the end of the map).
 //
-// Ring blocks: rings 1 .. 4 Nside - 1 are grouped K at a time; a block is cut
-// along azimuth into chunks of at most 64 pixels per ring, aligned so that
-// chunk c covers the same azimuth range in every ring of the block (rings of
-// a block differ in length only near the poles).  Tile = (block, chunk): K
-// rows of up to 64 consecutive pixels, one row per ring, so a tile is a
-// compact patch of sky instead of a strip along one ring.  Every pixel lies
-// in exactly one row of one tile.
+// Ring blocks: rings 1 .. 4 Nside - 1 are grouped `rings` at a time; a block
+// is cut along azimuth into chunks of at most `width` pixels per ring,
+// aligned so that chunk c covers the same azimuth range in every ring of the
+// block (rings of a block differ in length only near the poles).  Tile =
+// (block, chunk): one row of up to `width` consecutive pixels in each ring of
+// the block, a compact patch of sky instead of a strip along one ring.
+// Every pixel lies in exactly one row of one tile.
 struct Tiling {
   int64_t nside = 0;
   int64_t tile_px = 0;       // strips: pixels per tile
-  int K = 1;                 // ring blocks: rings per block (rows per tile)
+  int rings = 1;             // ring blocks: rings per block (rows per tile)
+  int64_t width = 64;        // ring blocks: most pixels of a row
   bool blocks = false;
   int64_t ntiles = 0;
   std::vector<int64_t> block_first;   // ring blocks: first tile of each block (+ end)
@@ -40,11 +43,11 @@ struct Tiling {
 };
 
 void make_strips(int64_t nside, int64_t tile_px, Tiling& t);
-void make_ring_blocks(int64_t nside, int K, Tiling& t);
+void make_ring_blocks(int64_t nside, int rings, int64_t width, Tiling& t);
 
-// Row table of a ring-block tiling: K entries per tile, entry (t, j) =
-// (first RING pixel of the row << 7) | (pixels in the row, 0..64); an empty
-// row (a block past the last ring) is stored as 0.
+// Row table of a ring-block tiling: `rings` entries per tile, entry (t, g) =
+// (first RING pixel of the row << kRowCountBits) | (pixels in the row); an
+// empty row (a block past the last ring, or a short ring) is stored as 0.
 void ring_block_rows(const Tiling& t, std::vector<int64_t>& rows);
 
 // Tiles that may hold pixels within angle rho of (cx, cy, cz), as merged

@@ -89,56 +89,57 @@ def _ring_of(nside, pix):
     return oracle.ring_of_pixel(nside, np.asarray(pix, dtype=np.int64))[0]
 
 
-@pytest.mark.parametrize("nside", [1, 2, 3, 8, 13, 64])
-@pytest.mark.parametrize("k", [1, 2, 4, 8])
-def test_ring_blocks_cover_every_pixel_once(nside, k):
-    """Rows of the ring-block tiling: every RING pixel in exactly one row, each
-    row inside one ring, the rows of a tile on k consecutive rings of one
-    block, and at most 64 pixels a row."""
+def _split(rows):
     from paper_1204_5041_amd import binding as B
-    rows = B.csmap_ring_block_rows(nside, k)
+    return rows >> B.ROW_COUNT_BITS, rows & ((1 << B.ROW_COUNT_BITS) - 1)
+
+
+@pytest.mark.parametrize("nside", [1, 2, 3, 8, 13, 64])
+@pytest.mark.parametrize("rings,width", [(1, 64), (2, 64), (4, 64), (8, 64), (4, 128), (16, 16),
+                                         (8, 32), (64, 8), (1, 512)])
+def test_ring_blocks_cover_every_pixel_once(nside, rings, width):
+    """Rows of the ring-block tiling: every RING pixel in exactly one row, each
+    row inside one ring, row g of every tile on ring (block * rings + g + 1),
+    and at most `width` pixels a row."""
+    from paper_1204_5041_amd import binding as B
+    rows = B.csmap_ring_block_rows(nside, rings, width)
     npx = 12 * nside * nside
-    first = rows >> 7
-    cnt = rows & 127
-    assert (cnt <= 64).all() and (cnt >= 0).all()
+    first, cnt = _split(rows)
+    assert (cnt <= width).all() and (cnt >= 0).all()
     assert (first[cnt == 0] == 0).all()
     pix = np.concatenate([np.arange(f, f + c) for f, c in zip(first.ravel(), cnt.ravel()) if c])
     assert np.array_equal(np.sort(pix), np.arange(npx))
     nz = cnt > 0
-    ring_a = np.zeros_like(first)
-    ring_b = np.zeros_like(first)
-    ring_a[nz] = _ring_of(nside, first[nz])
-    ring_b[nz] = _ring_of(nside, first[nz] + cnt[nz] - 1)
-    assert np.array_equal(ring_a[nz], ring_b[nz])
-    # Row j of every tile lies on ring (block * k + j + 1): the rings of a tile
-    # are consecutive and in order.
-    t_idx, j_idx = np.nonzero(nz)
-    blocks = (ring_a[nz] - 1 - j_idx) // k
-    assert ((ring_a[nz] - 1 - j_idx) % k == 0).all()
+    ring_a = _ring_of(nside, first[nz])
+    ring_b = _ring_of(nside, first[nz] + cnt[nz] - 1)
+    assert np.array_equal(ring_a, ring_b)
+    t_idx, g_idx = np.nonzero(nz)
+    assert ((ring_a - 1 - g_idx) % rings == 0).all()
+    blocks = (ring_a - 1 - g_idx) // rings
     assert (np.diff(blocks[np.argsort(t_idx, kind="stable")]) >= 0).all()
 
 
-@pytest.mark.parametrize("nside,k", [(8, 4), (16, 8), (32, 2), (64, 8)])
-def test_ring_block_tiles_are_azimuth_aligned(nside, k):
-    """Chunk c of a block covers azimuths [2 pi 64 c / L, 2 pi 64 (c+1) / L] in
-    every ring of the block (L = longest ring), up to one pixel spacing of
-    the ring: tiles are compact patches, not strips."""
+@pytest.mark.parametrize("nside,rings,width", [(8, 4, 64), (16, 8, 64), (32, 2, 64),
+                                               (64, 8, 64), (64, 4, 128), (64, 16, 16)])
+def test_ring_block_tiles_are_azimuth_aligned(nside, rings, width):
+    """Chunk c of a block covers azimuths [2 pi w c / L, 2 pi w (c+1) / L] in
+    every ring of the block (w = width, L = longest ring), up to one pixel
+    spacing of the ring: tiles are compact patches, not strips."""
     from paper_1204_5041_amd import binding as B
-    rows = B.csmap_ring_block_rows(nside, k)
-    first = rows >> 7
-    cnt = rows & 127
+    rows = B.csmap_ring_block_rows(nside, rings, width)
+    first, cnt = _split(rows)
     nring = 4 * nside - 1
     ringlen = lambda i: 4 * min(i, nside, 4 * nside - i)
     tile = 0
-    for blk in range((nring + k - 1) // k):
-        rings = list(range(1 + blk * k, min(nring, (blk + 1) * k) + 1))
-        L = max(ringlen(i) for i in rings)
-        for c in range((L + 63) // 64):
-            lo, hi = 2 * math.pi * 64 * c / L, 2 * math.pi * 64 * (c + 1) / L
-            for j, i in enumerate(rings):
-                if cnt[tile, j] == 0:
+    for blk in range((nring + rings - 1) // rings):
+        rs = list(range(1 + blk * rings, min(nring, (blk + 1) * rings) + 1))
+        L = max(ringlen(i) for i in rs)
+        for c in range((L + width - 1) // width):
+            lo, hi = 2 * math.pi * width * c / L, 2 * math.pi * width * (c + 1) / L
+            for g, i in enumerate(rs):
+                if cnt[tile, g] == 0:
                     continue
-                px = np.arange(first[tile, j], first[tile, j] + cnt[tile, j])
+                px = np.arange(first[tile, g], first[tile, g] + cnt[tile, g])
                 v = oracle.pix2vec(nside, px)
                 phi = np.mod(np.arctan2(v[:, 1], v[:, 0]), 2 * math.pi)
                 step = 2 * math.pi / ringlen(i)
@@ -147,19 +148,19 @@ def test_ring_block_tiles_are_azimuth_aligned(nside, k):
     assert tile == rows.shape[0]
 
 
-@pytest.mark.parametrize("nside,k", [(16, 4), (64, 8), (37, 2), (128, 4)])
-def test_cap_block_tiles_cover_every_visible_pixel(nside, k):
+@pytest.mark.parametrize("nside,rings,width", [(16, 4, 64), (64, 8, 64), (37, 2, 64),
+                                               (128, 4, 64), (128, 16, 16), (64, 4, 128)])
+def test_cap_block_tiles_cover_every_visible_pixel(nside, rings, width):
     from paper_1204_5041_amd import binding as B
-    rng = np.random.default_rng(7 * nside + k)
-    rows = B.csmap_ring_block_rows(nside, k)
+    rng = np.random.default_rng(7 * nside + rings)
+    rows = B.csmap_ring_block_rows(nside, rings, width)
     npx = 12 * nside * nside
     tile_of_pix = np.empty(npx, dtype=np.int64)
-    first = rows >> 7
-    cnt = rows & 127
+    first, cnt = _split(rows)
     for t in range(rows.shape[0]):
-        for j in range(k):
-            if cnt[t, j]:
-                tile_of_pix[first[t, j]:first[t, j] + cnt[t, j]] = t
+        for g in range(rings):
+            if cnt[t, g]:
+                tile_of_pix[first[t, g]:first[t, g] + cnt[t, g]] = t
     pix = np.arange(npx)
     for trial in range(12):
         c = synth.uniform_directions(1, 2000 + trial + nside)[0]
@@ -172,7 +173,7 @@ def test_cap_block_tiles_cover_every_visible_pixel(nside, k):
                         x_rel=np.zeros((0, 3)), xdot=np.zeros((0, 3)), xprime=np.zeros((0, 3)),
                         dsigma=np.zeros(0), vis=synth.VIS_CAP, cap_dir=c, cap_cos=math.cos(rho))
         vis = oracle.visible(nside, pix, 1.0, box)
-        ranges = B.csmap_cap_block_tiles(nside, k, c, rho)
+        ranges = B.csmap_cap_block_tiles(nside, rings, width, c, rho)
         covered = np.zeros(rows.shape[0], dtype=bool)
         for a, b in ranges:
             covered[a:b + 1] = True
@@ -181,21 +182,63 @@ def test_cap_block_tiles_cover_every_visible_pixel(nside, k):
             assert b0 + 1 < a1
 
 
-def test_ring_blocks_carry_fewer_idle_lanes_than_strips():
+@pytest.mark.parametrize("rings,width", [(4, 64), (8, 32), (16, 16)])
+def test_ring_blocks_carry_fewer_idle_lanes_than_strips(rings, width):
     """At Nside 4096, caps of 0.1%-5% of the sky: the tiles listed for a cap
-    hold fewer pixels with ring blocks (4 rings x 64) than with strips of 256
+    hold fewer pixels with ring blocks of 256 pixels than with strips of 256
     consecutive pixels, and not many more than the cap itself."""
     from paper_1204_5041_amd import binding as B
-    nside, k = 4096, 4
+    nside = 4096
     npx = 12 * nside * nside
-    cnt = B.csmap_ring_block_rows(nside, k) & 127
-    tile_px = cnt.sum(axis=1)
-    cum = np.concatenate([[0], np.cumsum(tile_px)])
+    _, cnt = _split(B.csmap_ring_block_rows(nside, rings, width))
+    cum = np.concatenate([[0], np.cumsum(cnt.sum(axis=1))])
     for i, frac in enumerate((0.001, 0.005, 0.05)):
         c = synth.uniform_directions(1, 3000 + i)[0]
         rho = math.acos(1.0 - 2.0 * frac)
-        blocks = sum(int(cum[b + 1] - cum[a]) for a, b in B.csmap_cap_block_tiles(nside, k, c, rho))
-        strips = sum(min(npx, 64 * k * (b + 1)) - 64 * k * a
-                     for a, b in B.csmap_cap_tiles(nside, 64 * k, c, rho))
+        blocks = sum(int(cum[b + 1] - cum[a])
+                     for a, b in B.csmap_cap_block_tiles(nside, rings, width, c, rho))
+        strips = sum(min(npx, 256 * (b + 1)) - 256 * a
+                     for a, b in B.csmap_cap_tiles(nside, 256, c, rho))
         assert blocks < strips, (frac, blocks, strips)
         assert blocks < 1.3 * frac * npx, (frac, blocks / (frac * npx))
+
+
+@pytest.mark.parametrize("nside", [3, 16, 40])
+@pytest.mark.parametrize("K", [1, 2, 4, 8])
+@pytest.mark.parametrize("rings", [1, 2, 4, 16, 64])
+def test_ring_block_lane_mapping_covers_map_once(nside, K, rings):
+    """The forward kernels' reading of a ring-block tile (rows of
+    64 K / rings pixels): lane l serves row l >> s of its tile, with
+    s = log2(64 / rings), and holds slots pos0 + j (64 / rings) of that row.
+    Every table read stays inside the table, every pixel load inside the
+    map, a lane's present slots lie on one ring, and the present slots of
+    all tiles cover each pixel exactly once."""
+    from paper_1204_5041_amd import binding as B
+    width = 64 * K // rings
+    rows = B.csmap_ring_block_rows(nside, rings, width).ravel()
+    ntiles = rows.size // rings
+    npx = 12 * nside * nside
+    shift = int(math.log2(64 // rings))
+    assert (1 << shift) * rings == 64
+    lane = np.arange(64)
+    g = lane >> shift
+    pos0 = lane - (g << shift)
+    step = 1 << shift
+    seen = np.zeros(npx, dtype=np.int64)
+    for t in range(ntiles):
+        idx = t * rings + g
+        assert idx.max() < rows.size
+        e = rows[idx]
+        first, cnt = e >> B.ROW_COUNT_BITS, e & ((1 << B.ROW_COUNT_BITS) - 1)
+        ring_of_lane = None
+        for j in range(K):
+            pos = pos0 + j * step
+            present = pos < cnt
+            off = np.where(present, pos, np.maximum(cnt - 1, 0))
+            pix = first + off
+            assert pix.min() >= 0 and pix.max() < npx
+            np.add.at(seen, pix[present], 1)
+            r = _ring_of(nside, pix)
+            ring_of_lane = r if ring_of_lane is None else ring_of_lane
+            assert np.array_equal(r[present], ring_of_lane[present])
+    assert (seen == 1).all()

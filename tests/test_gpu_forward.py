@@ -204,12 +204,15 @@ def caps():
 
 @pytest.mark.parametrize("form", ["fp64", "fp32c"])
 @pytest.mark.parametrize("K", [2, 8])
-@pytest.mark.parametrize("tiling", [1, 2])
-def test_cap_sky_both_tilings(B, caps, form, K, tiling):
+@pytest.mark.parametrize("tiling,rings", [(1, 0), (2, 0), (2, 1), (2, 4), (2, 64)])
+def test_cap_sky_both_tilings(B, caps, form, K, tiling, rings):
+    """Strips and ring blocks of 1 to 64 rings per tile (64 rings: one lane
+    per ring) give the oracle's map."""
     w, ref, pairs = caps
-    say(f"caps form={form} K={K} tiling={tiling}")
+    say(f"caps form={form} K={K} tiling={tiling} rings={rings}")
     f = B.CSMAP_FORM_FP64 if form == "fp64" else B.CSMAP_FORM_FP32C
-    sky = sky_from_workload(w, f, {B.CSMAP_OPT_PIX_PER_LANE: K, B.CSMAP_OPT_TILING: tiling})
+    sky = sky_from_workload(w, f, {B.CSMAP_OPT_PIX_PER_LANE: K, B.CSMAP_OPT_TILING: tiling,
+                                   B.CSMAP_OPT_BLOCK_RINGS: rings})
     m = sky.render().cpu().numpy()
     st = sky.stats()
     e = err_metrics(m, ref)
