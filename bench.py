@@ -144,7 +144,7 @@ def main():
         pairs += st["pairs"]
         _log(f"bench: step {k} box {W + k}: pairs={st['pairs']} forward {st['ms_forward']:.1f} ms "
              f"precompute {st['ms_precompute']:.2f} ms fp64_steps={st['near_steps']} "
-             f"mid_steps={st['mid_steps']}")
+             f"mid_steps={st['mid_steps']} steps={st['steps']}")
     value = pairs / elapsed
     kern_s = float(np.mean(fwd_ms)) / 1e3
     pairs_per_step = pairs / K
@@ -252,7 +252,7 @@ def bench_config3(args, B, torch):
            "ms_per_step": el * 1e3, "pairs": st["pairs"], "kept": st["kept"],
            "segments": st["segments"], "tile": {k: st[k] for k in ("pix_per_lane", "waves",
                                                                    "schedule", "graph", "tiling")},
-           "fp64_steps": st["near_steps"], "mid_steps": st["mid_steps"],
+           "fp64_steps": st["near_steps"], "mid_steps": st["mid_steps"], "steps": st["steps"],
            "autotune_s": tune_s}
     res["achieved_tflops"] = FLOP_PER_PAIR * res["value"] / 1e12
     res["frac_fp32_peak"] = res["achieved_tflops"] / FP32_PEAK_TFLOPS

@@ -175,6 +175,7 @@ typedef struct {
     int64_t tiling;            /* tiling in use: 1 strips, 2 ring blocks */
     int64_t mid_steps;         /* FP32C: steps that formed n - P/R in FP32 */
     double far_w;
+    int64_t steps;             /* FP32C: (wavefront, segment) steps of every form */
 } csmap_stats;
 
 /* Number of pixels of an Nside map, 12 Nside^2 (Sec. II.D); -1 if Nside is

@@ -56,7 +56,8 @@ class csmap_stats(ctypes.Structure):
                 ("pix_per_lane", ctypes.c_int64), ("waves", ctypes.c_int64),
                 ("schedule", ctypes.c_int64), ("graph", ctypes.c_int64), ("chunk", ctypes.c_int64),
                 ("near_w", ctypes.c_double), ("tiling", ctypes.c_int64),
-                ("mid_steps", ctypes.c_int64), ("far_w", ctypes.c_double)]
+                ("mid_steps", ctypes.c_int64), ("far_w", ctypes.c_double),
+                ("steps", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

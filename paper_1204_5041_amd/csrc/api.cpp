@@ -132,7 +132,8 @@ struct csmap_sky {
   int64_t ntiles = 0;
   int64_t nitems_sorted = 0;
   bool all_boxes = true;
-  DevBuf d_counters;  // [0] pairs, [1] FP64 steps, [2] work counter (uint32), [3] middle steps
+  DevBuf d_counters;  // [0] pairs, [1] FP64 steps, [2] work counter (uint32), [3] middle steps,
+                      // [4] all steps
   DevBuf d_dir;       // pixel directions, x | y | z (npix doubles each)
   bool dir_ready = false;
 
@@ -400,6 +401,7 @@ FwdArgs fwd_args(csmap_sky* s, double* map) {
   A.pairs = s->d_counters.as<unsigned long long>();
   A.near_steps = s->d_counters.as<unsigned long long>() + 1;
   A.mid_steps = s->d_counters.as<unsigned long long>() + 3;
+  A.steps = s->d_counters.as<unsigned long long>() + 4;
   return A;
 }
 
@@ -445,7 +447,7 @@ csmap_status enqueue_render(csmap_sky* s, double* map, hipStream_t st, bool with
   if (cs != CSMAP_OK) return cs;
   if (with_events) HIPCHK(s, hipEventRecord(s->ev[0], st), "event");
   HIPCHK(s, launch_precompute(P, (int64_t)s->boxes.size(), st), "precompute launch");
-  HIPCHK(s, launch_zero_counters(s->d_counters.as<unsigned long long>(), 4,
+  HIPCHK(s, launch_zero_counters(s->d_counters.as<unsigned long long>(), 5,
                                  (uint32_t*)(s->d_counters.as<unsigned long long>() + 2), st),
          "counter reset");
   if (with_events) HIPCHK(s, hipEventRecord(s->ev[1], st), "event");
@@ -843,11 +845,12 @@ csmap_status csmap_get_stats(csmap_sky* s, csmap_stats* out) {
   out->nbox = (int64_t)s->boxes.size();
   out->segments = s->total_seg;
   if (!s->dirty && s->d_counters.p) {
-    unsigned long long c[4] = {0, 0, 0, 0};
+    unsigned long long c[5] = {0, 0, 0, 0, 0};
     HIPCHK(s, hipMemcpy(c, s->d_counters.p, sizeof(c), hipMemcpyDeviceToHost), "read counters");
     out->pairs = (int64_t)c[0];
     out->near_steps = (int64_t)c[1];
     out->mid_steps = (int64_t)c[3];
+    out->steps = (int64_t)c[4];
     std::vector<DevBoxCount> kc(s->boxes.size());
     if (!kc.empty())
       HIPCHK(s, hipMemcpy(kc.data(), s->d_box_count.p, sizeof(DevBoxCount) * kc.size(),
@@ -1048,7 +1051,7 @@ csmap_status csmap_autotune(csmap_sky* s, const char* cache_path) {
     double ms_min = 1e300;
     unsigned long long pairs = 0;
     for (int rep = 0; rep < 3; ++rep) {
-      HIPCHK(s, launch_zero_counters(s->d_counters.as<unsigned long long>(), 4, A.work_counter, st),
+      HIPCHK(s, launch_zero_counters(s->d_counters.as<unsigned long long>(), 5, A.work_counter, st),
              "counter reset");
       HIPCHK(s, hipEventRecord(s->ev[0], st), "event");
       HIPCHK(s, launch_forward(fp64, c.K, c.S == 1, A, grid, block, st), "forward launch");

@@ -99,6 +99,7 @@ struct FwdArgs {
   unsigned long long* pairs;   // pair counter
   unsigned long long* near_steps;
   unsigned long long* mid_steps;
+  unsigned long long* steps;     // FP32C: (wavefront, segment) steps of every form
 };
 
 // Arguments of the adjoint kernels.

@@ -358,6 +358,13 @@ __device__ __forceinline__ void fold_term(bool first, float& fp, float& fq, floa
   }
 }
 
+// A 64-bit value every lane holds alike, moved to scalar registers.
+__device__ __forceinline__ int64_t uniform_i64(int64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Copy a wave-uniform value into a vector register.
 __device__ __forceinline__ float to_vgpr(float x) {
   float y;
@@ -530,7 +537,7 @@ __global__ void __launch_bounds__(256) k_fwd32(FwdArgs A) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   int64_t item = PERSISTENT ? next_item(A, true, lane, 0, 0) : (int64_t)blockIdx.x * wpb + wave;
   const int64_t stride = (int64_t)gridDim.x * wpb;
-  unsigned long long near_steps = 0, mid_steps = 0;
+  unsigned long long near_steps = 0, mid_steps = 0, all_steps = 0;
   const float near_w = A.near_w, far_w = A.far_w;
   cf4p recs = (cf4p)A.rec32;
   cd2p ph64 = (cd2p)A.phat64;
@@ -596,6 +603,7 @@ __global__ void __launch_bounds__(256) k_fwd32(FwdArgs A) {
       if (A.seg_cap > 0 && r1 - r0 > A.seg_cap) r1 = r0 + A.seg_cap;
       if (lane == 0 && r1 > r0) atomicAdd(A.pairs, nvis * (unsigned long long)(r1 - r0));
       if (r1 == r0) continue;
+      all_steps += (unsigned long long)(r1 - r0);
       if constexpr (FRAC) {
         if (ring)
           frac_box<K, true>(A, recs, ph64, r0, r1, nf, sdir, lane, vis, S, C, near_steps, mid_steps);
@@ -714,6 +722,7 @@ __global__ void __launch_bounds__(256) k_fwd32(FwdArgs A) {
   }
   if (lane == 0 && near_steps) atomicAdd(A.near_steps, near_steps);
   if (lane == 0 && mid_steps) atomicAdd(A.mid_steps, mid_steps);
+  if (lane == 0 && all_steps) atomicAdd(A.steps, all_steps);
 }
 
 __device__ __forceinline__ double rcp_f64(double x) {
@@ -862,6 +871,39 @@ __global__ void k_pixtab(int64_t nside, int64_t npix, const double* dmap, float*
 // cancel against Ph times a scalar sum.
 constexpr int kAcc = 14;
 
+// Add one pair to the accumulators (see their list above): s the pixel's
+// cotangent, w = 1 - n.Ph, t1 = kap Xdot.d, t2 = kap X'.d, r = 1/(b w),
+// d = n - Ph.
+__device__ __forceinline__ void adj_accumulate(float (&pa)[kAcc], float s, float kap, float a,
+                                               float bb, float w, float t1, float t2, float r,
+                                               float dx, float dy, float dz) {
+  const float m = fmaf(-a, t2, t1 * bb);       // kap * m
+  const float f = m * r;                        // the Eq. (1) term
+  const float sr = s * r;
+  const float k1 = sr * kap;                    // s kap / (b w)
+  const float c1 = k1 * bb;                     // s kap / w
+  pa[0] += c1;
+  pa[1] = fmaf(k1, a, pa[1]);
+  const float sf = s * f;
+  pa[2] += sf;
+  const float c4 = sr * t2;                     // s kap Td / (b w)
+  pa[4] += c4;
+  const float c2 = (c4 * a) * (w * r);          // s kap a Td / (b^2 w)
+  pa[3] += c2;
+  const float d3 = sf * (bb * r);               // s f / w
+  pa[5] = fmaf(d3, dx, pa[5]);
+  pa[6] = fmaf(d3, dy, pa[6]);
+  pa[7] = fmaf(d3, dz, pa[7]);
+  const float dv = c1 + c2;
+  pa[8] = fmaf(dv, dx, pa[8]);
+  pa[9] = fmaf(dv, dy, pa[9]);
+  pa[10] = fmaf(dv, dz, pa[10]);
+  const float c3 = fmaf(k1, a, c4);             // s kap (Td + a) / (b w)
+  pa[11] = fmaf(c3, dx, pa[11]);
+  pa[12] = fmaf(c3, dy, pa[12]);
+  pa[13] = fmaf(c3, dz, pa[13]);
+}
+
 // Work item: a group of 64 consecutive kept records of one box (one per
 // lane) and one of `nsplit` contiguous pixel ranges.
 __global__ void __launch_bounds__(256) k_adj32(AdjArgs A) {
@@ -886,11 +928,14 @@ __global__ void __launch_bounds__(256) k_adj32(AdjArgs A) {
   const float kap = active ? q2.y : 0.0f, c1v = q2.z, c2v = q2.w;
   const double2 h0 = ((const double2*)A.phat64)[2 * rec + 0];
   const double2 h1 = ((const double2*)A.phat64)[2 * rec + 1];
-  const int64_t p0 = A.npix * split / A.nsplit;
-  const int64_t p1 = A.npix * (split + 1) / A.nsplit;
+  // The pixel range is uniform; computing it through readfirstlane keeps it
+  // (and the loop bound) in scalar registers.
+  const int64_t p0 = uniform_i64(A.npix * split / A.nsplit);
+  const int64_t p1 = uniform_i64(A.npix * (split + 1) / A.nsplit);
   const float near_w = A.near_w, far_w = A.far_w;
-  // Segments flagged at precompute take the FP64 form against every pixel.
-  const bool force = active && __float_as_int(q3.y) != 0;
+  // A group holding a segment flagged at precompute takes the FP64 form
+  // against every pixel.
+  const bool force = __any(active && __float_as_int(q3.y) != 0);
   cf4p tab = (cf4p)A.pixtab;
   cd2p tab64 = (cd2p)A.pix64;
   double acc[kAcc];
@@ -907,10 +952,12 @@ __global__ void __launch_bounds__(256) k_adj32(AdjArgs A) {
     // values are then copied to vector registers so that the per-pair FMAs
     // read vector operands only (twice the issue rate of scalar operands).
     v4f cur = tab[pc];
-    for (int64_t p = pc; p < pe; ++p) {
+    const int32_t np = (int32_t)(pe - pc);   // at most J
+    for (int32_t i = 0; i < np; ++i) {
+      const int64_t p = pc + i;
       __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): cur has arrived
       const v4f pt = cur;
-      cur = tab[(p + 1 < pe) ? p + 1 : p];
+      cur = tab[pc + ((i + 1 < np) ? i + 1 : i)];
       // Pixels with a zero cotangent contribute nothing.
       if ((__float_as_int(pt.w) & 0x7fffffff) == 0) continue;
       if (check_vis) {
@@ -918,65 +965,33 @@ __global__ void __launch_bounds__(256) k_adj32(AdjArgs A) {
         const v2d e1 = tab64[2 * p + 1];
         if (!sees_box(e0.x, e0.y, e1.x, bx, A.eta0)) continue;
       }
-      const float nx = to_vgpr(pt.x), ny = to_vgpr(pt.y), nz = to_vgpr(pt.z), s = to_vgpr(pt.w);
+      const float nx = to_vgpr(pt.x), ny = to_vgpr(pt.y), nz = to_vgpr(pt.z);
+      float s = to_vgpr(pt.w);
       float w = fmaf(-nz, pz, fmaf(-ny, py, fmaf(-nx, px, 1.0f)));
       const float a = fmaf(nz, tz, fmaf(ny, ty, nx * tx));
       const float bb = fmaf(nz, vz, fmaf(ny, vy, fmaf(nx, vx, 1.0f)));
-      float t1, t2, r, dx, dy, dz;
-      if (!__any(w < far_w || force)) {
-        t1 = fmaf(kap, bb, -c1v);
-        t2 = fmaf(kap, a, -c2v);
-        r = __builtin_amdgcn_rcpf(bb * w);
-        dx = nx - px;
-        dy = ny - py;
-        dz = nz - pz;
-      } else if (!__any(w < near_w || force)) {
-        // The direction difference in FP32 (see the forward kernel).
-        dx = nx - px;
-        dy = ny - py;
-        dz = nz - pz;
+      // The far form's values; a close pixel (for some lane) overwrites them
+      // in place, which lets the far form run without register copies.
+      float dx = nx - px, dy = ny - py, dz = nz - pz;
+      float t1 = fmaf(kap, bb, -c1v), t2 = fmaf(kap, a, -c2v);
+      if (force || __any(w < far_w)) {
+        // Middle form: the direction difference in FP32 (see the forward
+        // kernel); FP64 form: from the FP64 directions.
+        if (force || __any(w < near_w)) {
+          const v2d e0 = tab64[2 * p + 0];
+          const v2d e1 = tab64[2 * p + 1];
+          dx = (float)(e0.x - h0.x);
+          dy = (float)(e0.y - h0.y);
+          dz = (float)(e1.x - h1.x);
+        }
         const float q = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
         t1 = kap * fmaf(vz, dz, fmaf(vy, dy, vx * dx));
         t2 = kap * fmaf(tz, dz, fmaf(ty, dy, tx * dx));
-        w = 0.5f * q;
-        r = __builtin_amdgcn_rcpf(bb * w);
-      } else {
-        const v2d e0 = tab64[2 * p + 0];
-        const v2d e1 = tab64[2 * p + 1];
-        dx = (float)(e0.x - h0.x);
-        dy = (float)(e0.y - h0.y);
-        dz = (float)(e1.x - h1.x);
-        const float q = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        t1 = kap * fmaf(vz, dz, fmaf(vy, dy, vx * dx));
-        t2 = kap * fmaf(tz, dz, fmaf(ty, dy, tx * dx));
-        w = 0.5f * q;
-        r = (w > 0.0f) ? __builtin_amdgcn_rcpf(bb * w) : 0.0f;
+        // An exact coincidence (q = 0) contributes nothing.
+        w = (q > 0.0f) ? 0.5f * q : 1.0f;
+        s = (q > 0.0f) ? s : 0.0f;
       }
-      const float m = fmaf(-a, t2, t1 * bb);       // kap * m
-      const float f = m * r;                        // the Eq. (1) term
-      const float sr = s * r;
-      const float k1 = sr * kap;                    // s kap / (b w)
-      const float c1 = k1 * bb;                     // s kap / w
-      pa[0] += c1;
-      pa[1] = fmaf(k1, a, pa[1]);
-      const float sf = s * f;
-      pa[2] += sf;
-      const float c4 = sr * t2;                     // s kap Td / (b w)
-      pa[4] += c4;
-      const float c2 = (c4 * a) * (w * r);          // s kap a Td / (b^2 w)
-      pa[3] += c2;
-      const float d3 = sf * (bb * r);               // s f / w
-      pa[5] = fmaf(d3, dx, pa[5]);
-      pa[6] = fmaf(d3, dy, pa[6]);
-      pa[7] = fmaf(d3, dz, pa[7]);
-      const float dv = c1 + c2;
-      pa[8] = fmaf(dv, dx, pa[8]);
-      pa[9] = fmaf(dv, dy, pa[9]);
-      pa[10] = fmaf(dv, dz, pa[10]);
-      const float c3 = fmaf(k1, a, c4);             // s kap (Td + a) / (b w)
-      pa[11] = fmaf(c3, dx, pa[11]);
-      pa[12] = fmaf(c3, dy, pa[12]);
-      pa[13] = fmaf(c3, dz, pa[13]);
+      adj_accumulate(pa, s, kap, a, bb, w, t1, t2, __builtin_amdgcn_rcpf(bb * w), dx, dy, dz);
     }
 #pragma unroll
     for (int k = 0; k < kAcc; ++k) acc[k] += (double)pa[k];
