@@ -10,8 +10,9 @@ pair kernel, FP32C form.  Step k uses box W+k (warm-up steps use boxes
 
 Printed: one JSON line with pairs/s of the FP32C form, the FP64 form's
 pairs/s on one box, the forward kernel's achieved FLOP/s against the FP32
-vector peak (36 algorithmic FLOP per pair), and the FP64 CPU oracle timed on
-a sample of the same workload on this host.
+vector peak (36 algorithmic FLOP per pair), the FP64 CPU oracle timed on a
+sample of the same workload on this host, and the error of both GPU forms
+against the oracle on that sample (the last timed box).
 """
 from __future__ import annotations
 
@@ -62,18 +63,26 @@ def measured_traffic():
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
-def cpu_baseline(box, nside, npix_sample, seed=98):
+def cpu_baseline(box, b, nside, pix):
+    """The oracle on sampled pixels of one box: its rate, and its values."""
     import oracle
-    import synth
-    pix = synth.sample_pixels(12 * nside * nside, npix_sample, seed=seed)
     t0 = time.perf_counter()
-    oracle.theta_pixels(nside, pix, 16.0, [box])
+    ref = oracle.theta_pixels(nside, pix, 16.0, [box])
     dt = time.perf_counter() - t0
     pairs = len(pix) * box.n
     return {"value": pairs / dt, "unit": "pairs/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"{len(pix)} random pixels x box 0 ({box.n:,} segments) at Nside={nside}: "
-                      f"{pairs:.3e} pairs in {dt:.1f} s"}
+            "sample": f"{len(pix)} random pixels x box {b} ({box.n:,} segments) at Nside={nside}: "
+                      f"{pairs:.3e} pairs in {dt:.1f} s"}, ref
+
+
+def err_metrics(got, ref):
+    """Errors in Theta/GU over the sampled pixels: relative rms and relative
+    max (normalised by the reference's rms and max), max-abs and rms."""
+    d = np.asarray(got, dtype=np.float64) - ref
+    return {"rel_rms": float(np.linalg.norm(d) / np.linalg.norm(ref)),
+            "rel_max": float(np.max(np.abs(d)) / np.max(np.abs(ref))),
+            "max_abs": float(np.max(np.abs(d))), "rms": float(np.sqrt(np.mean(d * d)))}
 
 
 def main():
@@ -138,6 +147,12 @@ def main():
         sky.render(maps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    # The last timed map, at the pixels the oracle will evaluate.
+    import synth
+    last = W + K - 1
+    pix = synth.sample_pixels(npix, args.cpu_pixels, seed=98)
+    pix_t = torch.from_numpy(pix).cuda()
+    got32 = maps[pix_t].cpu().numpy()
     for k in range(K):
         st = skies[W + k][0].stats()
         fwd_ms.append(st["ms_forward"])
@@ -180,9 +195,10 @@ def main():
     del skies
     torch.cuda.synchronize()
 
+    got64 = None
     if not args.no_fp64:
-        _log("bench: FP64 form, one box")
-        sky64, _ = make_sky(B, torch, 0, B.CSMAP_FORM_FP64, args.nseg, args.nside)
+        _log(f"bench: FP64 form, box {last}")
+        sky64, _ = make_sky(B, torch, last, B.CSMAP_FORM_FP64, args.nseg, args.nside)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         sky64.render(maps)
@@ -194,14 +210,19 @@ def main():
         out["fp64"] = {"value": v64, "unit": "pairs/s", "ms_per_step": e64 * 1e3,
                        "kernel_ms": st["ms_forward"], "achieved_tflops": a64,
                        "frac_fp64_peak": a64 / FP64_PEAK_TFLOPS}
+        got64 = maps[pix_t].cpu().numpy()
         out["speedup_fp32_over_fp64"] = value / v64
         sky64.close()
 
     if not args.no_cpu:
-        import synth
         _log("bench: CPU oracle baseline")
-        box0 = synth.config2_box(0, args.nseg)
-        out["cpu_baseline"] = cpu_baseline(box0, args.nside, args.cpu_pixels)
+        box = synth.config2_box(last, args.nseg)
+        out["cpu_baseline"], ref = cpu_baseline(box, last, args.nside, pix)
+        acc = {"box": last, "pixels": int(len(pix)), "unit": "Theta/GU",
+               "fp32c": err_metrics(got32, ref)}
+        if got64 is not None:
+            acc["fp64"] = err_metrics(got64, ref)
+        out["accuracy_vs_oracle"] = acc
 
     print(json.dumps(out), flush=True)
 
@@ -256,6 +277,7 @@ def bench_config3(args, B, torch):
            "autotune_s": tune_s}
     res["achieved_tflops"] = FLOP_PER_PAIR * res["value"] / 1e12
     res["frac_fp32_peak"] = res["achieved_tflops"] / FP32_PEAK_TFLOPS
+    res["accuracy_vs_oracle"] = _sampled_accuracy(torch, w, out, 4000, seed=397)
     _log(f"bench config3: batched render {el * 1e3:.0f} ms; per-box launches next")
     sky.set_option(B.CSMAP_OPT_GRAPH, 0)
     sky.set_option(B.CSMAP_OPT_SCHEDULE, 2)
@@ -267,6 +289,19 @@ def bench_config3(args, B, torch):
     res["per_box_launches_pairs_per_s"] = sky.stats()["pairs"] / el2
     res["speedup_batched_over_per_box"] = el2 / el
     print(json.dumps(res), flush=True)
+
+
+def _sampled_accuracy(torch, w, gpu_map, count, seed):
+    """Errors of a rendered map against the oracle on `count` random pixels."""
+    import oracle
+    import synth
+    pix = synth.sample_pixels(w.npix, count, seed=seed)
+    got = gpu_map[torch.from_numpy(pix).cuda()].cpu().numpy()
+    _log(f"bench: oracle on {count} sampled pixels")
+    ref = oracle.theta_pixels(w.nside, pix, w.eta0, w.boxes)
+    acc = {"pixels": int(count), "unit": "Theta/GU"}
+    acc.update(err_metrics(got, ref))
+    return acc
 
 
 def bench_config4(args, B, torch):
@@ -292,7 +327,8 @@ def bench_config4(args, B, torch):
     pairs = st["pairs"]
     res = {"metric": "config4 forward + adjoint pairs/s", "forward_pairs_per_s": pairs / tf,
            "adjoint_pairs_per_s": pairs / tb, "pairs": pairs, "forward_ms": tf * 1e3,
-           "adjoint_ms": tb * 1e3, "adjoint_kernel_ms": st["ms_backward"]}
+           "adjoint_ms": tb * 1e3, "adjoint_kernel_ms": st["ms_backward"],
+           "forward_accuracy_vs_oracle": _sampled_accuracy(torch, w, m, 4000, seed=213)}
     print(json.dumps(res), flush=True)
 
 
