@@ -56,6 +56,8 @@ def lib() -> ctypes.CDLL:
         _lib.oracle_isqrt.restype = i64
         _lib.oracle_pix2vec_many.argtypes = [i64, i64, i64p, f64p]
         _lib.oracle_ring_many.argtypes = [i64, i64, i64p, i64p, i64p]
+        _lib.oracle_cone_events.argtypes = [i64, f64p, f64p, f64p, ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_double, f64p, f64p, u8p]
         _lib.oracle_theta_dirs.argtypes = [i64, f64p, ctypes.c_double, i64, f64p, i64p,
                                            f64p, f64p, f64p, f64p, ctypes.c_int, f64p]
         _lib.oracle_theta_pixels.argtypes = [i64, i64, i64p, ctypes.c_double, i64, f64p, i64p,
@@ -214,3 +216,24 @@ def grad(nside: int, pix, cotangent, eta0: float, boxes: Sequence, sel) -> np.nd
                       float(eta0), *pk.args(), s.size, _p(s, ctypes.c_int64),
                       _p(out, ctypes.c_double))
     return out
+
+
+def cone_events(x_rel, xdot, origin, eta0: float, eta_lo: float, eta_hi: float):
+    """Light-cone crossings of segments given at the slab start eta_lo
+    (straight worldlines P0 + Xdot (eta - eta_lo), P0 = origin + x_rel).
+
+    Returns (pos (n,3) observer-relative event positions, delta (n,) crossing
+    time after eta_lo, keep (n,) bool); positions and delta are NaN where
+    the crossing is outside [eta_lo, eta_hi)."""
+    x = _f64(x_rel).reshape(-1, 3)
+    v = _f64(xdot).reshape(-1, 3)
+    o = _f64(origin).reshape(3)
+    n = x.shape[0]
+    pos = np.empty((n, 3), dtype=np.float64)
+    delta = np.empty(n, dtype=np.float64)
+    keep = np.empty(n, dtype=np.uint8)
+    lib().oracle_cone_events(n, _p(x, ctypes.c_double), _p(v, ctypes.c_double),
+                             _p(o, ctypes.c_double), float(eta0), float(eta_lo), float(eta_hi),
+                             _p(pos, ctypes.c_double), _p(delta, ctypes.c_double),
+                             _p(keep, ctypes.c_uint8))
+    return pos, delta, keep.astype(bool)

@@ -476,3 +476,65 @@ int oracle_num_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------ */
+/* Light-cone event recording from a snapshot (the step that precedes the   */
+/* sum, Sec. II.B: as the strings evolve, photons are propagated and every   */
+/* segment crossing the observer's past light cone is recorded).  A segment  */
+/* known at the start eta_lo of a time slab, at observer-relative position   */
+/* P0 = origin + x_rel with velocity Xdot, moves on the straight worldline   */
+/* P(eta) = P0 + Xdot (eta - eta_lo) during the slab.  The past light cone   */
+/* at conformal time eta is the sphere |P| = eta0 - eta.  With              */
+/* D = eta - eta_lo and R0 = eta0 - eta_lo, the crossing solves              */
+/*     h(D) = |P0 + Xdot D| + D - R0 = 0.                                    */
+/* For |Xdot| < 1, h is strictly increasing (its slope is at least           */
+/* 1 - |Xdot| > 0), so there is exactly one crossing; it is an event of this */
+/* slab when 0 <= D < eta_hi - eta_lo.  Here it is found by bisection on h,  */
+/* which needs nothing but the sign of h: plain, slow and obviously right.   */
+/* Segments with |Xdot| >= 1 record no event.                               */
+/* ------------------------------------------------------------------------ */
+static double cone_gap(const double P0[3], const double V[3], double D, double R0)
+{
+    double p[3];
+    for (int k = 0; k < 3; ++k) p[k] = P0[k] + V[k] * D;
+    return sqrt(dot3(p, p)) + D - R0;
+}
+
+/* For every segment: keep[i] = 1 if its worldline crosses the past light
+ * cone inside the slab, with delta[i] the crossing's D and pos[3i..3i+2]
+ * the observer-relative event position P0 + Xdot D; otherwise keep[i] = 0
+ * and delta[i], pos[3i..3i+2] are NaN. */
+void oracle_cone_events(int64_t n, const double *x_rel, const double *xdot,
+                        const double origin[3], double eta0, double eta_lo, double eta_hi,
+                        double *pos, double *delta, uint8_t *keep)
+{
+    const double R0 = eta0 - eta_lo;
+    const double width = eta_hi - eta_lo;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double P0[3], V[3];
+        for (int k = 0; k < 3; ++k) {
+            P0[k] = origin[k] + x_rel[3 * i + k];
+            V[k] = xdot[3 * i + k];
+        }
+        keep[i] = 0;
+        delta[i] = NAN;
+        for (int k = 0; k < 3; ++k) pos[3 * i + k] = NAN;
+        if (!(dot3(V, V) < 1.0) || !(width > 0.0)) continue;
+        /* The crossing lies in [0, width) iff h(0) <= 0 < h(width). */
+        if (cone_gap(P0, V, 0.0, R0) > 0.0) continue;
+        if (!(cone_gap(P0, V, width, R0) > 0.0)) continue;
+        double lo = 0.0, hi = width;            /* h(lo) <= 0 < h(hi) */
+        for (;;) {
+            const double mid = 0.5 * (lo + hi);
+            if (mid <= lo || mid >= hi) break;  /* no double strictly between */
+            if (cone_gap(P0, V, mid, R0) > 0.0) hi = mid;
+            else lo = mid;
+        }
+        /* Of the two neighbours, the one where |h| is smaller. */
+        const double D = (fabs(cone_gap(P0, V, lo, R0)) <= fabs(cone_gap(P0, V, hi, R0))) ? lo : hi;
+        keep[i] = 1;
+        delta[i] = D;
+        for (int k = 0; k < 3; ++k) pos[3 * i + k] = P0[k] + V[k] * D;
+    }
+}
