@@ -96,10 +96,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=40000)
     ap.add_argument("--workload", default="config2",
-                    choices=["config2", "config3", "config4"],
+                    choices=["config2", "config3", "config4", "events"],
                     help="config2: the headline Nside=2048 line (default); config3: the "
                          "batched uneven 256-box Nside=4096 sky; config4: forward + adjoint at "
-                         "Nside=1024")
+                         "Nside=1024; events: light-cone event recording from slab-start "
+                         "snapshots (25.6M segments)")
     ap.add_argument("--count-scale", type=float, default=1.0,
                     help="config3: scale of the per-box segment counts")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -118,6 +119,8 @@ def main():
         return bench_config3(args, B, torch)
     if args.workload == "config4":
         return bench_config4(args, B, torch)
+    if args.workload == "events":
+        return bench_events(args, B, torch)
 
     if args.copy_calib_mib > 0:
         n = args.copy_calib_mib * (1 << 20) // 4
@@ -302,6 +305,57 @@ def _sampled_accuracy(torch, w, gpu_map, count, seed):
     acc = {"pixels": int(count), "unit": "Theta/GU"}
     acc.update(err_metrics(got, ref))
     return acc
+
+
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
+EVENT_BYTES = 24 + 33       # read x_rel, xdot (FP32); write position, D (FP64), keep (byte)
+
+
+def bench_events(args, B, torch):
+    """Light-cone event recording: 25.6M FP32 segments (the segment count of
+    the 64-box Nside=2048 set) of a 1 Gpc box at ~5 Gpc, known at the start of
+    the slab [11, 11.6) of eta0 = 16, each moved along its velocity to its
+    crossing of the past light cone.  The kernel streams 57 bytes per
+    segment, so its bound is HBM bandwidth."""
+    import oracle
+    import synth
+    n = 25_600_000
+    _log(f"bench events: generating {n:,} segments")
+    x, xd, _, _ = synth.segments(n, 510, np.float32)
+    rng = np.random.default_rng(511)
+    v = rng.uniform(0.0, 0.95, n).astype(np.float32)
+    xd = (xd / np.linalg.norm(xd, axis=1, keepdims=True) * v[:, None]).astype(np.float32)
+    origin = (3.7, -2.1, 1.4)
+    eta0, eta_lo, eta_hi = 16.0, 11.0, 11.6
+    xt, vt = torch.from_numpy(x).cuda(), torch.from_numpy(xd).cuda()
+    pos, d, keep = B.cone_events(xt, vt, origin, eta0, eta_lo, eta_hi)   # warm-up
+    torch.cuda.synchronize()
+    K = max(1, args.steps) * 10
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(K):
+        pos, d, keep = B.cone_events(xt, vt, origin, eta0, eta_lo, eta_hi)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / K
+    kern = e0.elapsed_time(e1) / 1e3 / K
+    gbs = EVENT_BYTES * n / kern / 1e9
+    res = {"metric": "light-cone events recorded per second (segments/s)", "value": n / kern,
+           "unit": "segments/s", "segments": n, "kept": int(keep.sum().item()),
+           "ms_per_launch": kern * 1e3, "wall_ms_per_launch": wall * 1e3,
+           "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": gbs / HBM_PEAK_GBS, "bytes_per_segment": EVENT_BYTES}}
+    # Agreement with the oracle on a sample of 200,000 segments.
+    sel = synth.sample_pixels(n, 200_000, seed=512)
+    rp, rd, rk = oracle.cone_events(x[sel], xd[sel], np.array(origin), eta0, eta_lo, eta_hi)
+    k = keep.cpu().numpy()[sel]
+    dd = d.cpu().numpy()[sel]
+    both = k & rk
+    res["accuracy_vs_oracle"] = {"segments": int(sel.size),
+                                 "keep_mismatches": int(np.sum(k != rk)),
+                                 "max_abs_delta_error": float(np.max(np.abs(dd[both] - rd[both])))}
+    print(json.dumps(res), flush=True)
 
 
 def bench_config4(args, B, torch):

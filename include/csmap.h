@@ -195,6 +195,32 @@ csmap_status csmap_create_sky(int64_t nside, double eta0, csmap_form form, void 
  * (0, 1, ... in call order). */
 csmap_status csmap_add_box(csmap_sky *sky, const csmap_box *box, int64_t *box_id);
 
+/* Add one box of segments known at the start eta_lo of its slab, rather than
+ * on the light cone (Sec. II.B: as the strings evolve, photons are followed
+ * and every segment crossing the past light cone is recorded).  Segment s is
+ * taken to move on the straight worldline P0 + Xdot (eta - eta_lo),
+ * P0 = origin + x_rel, during the slab; its event is where that worldline
+ * meets the past light cone |P| = eta0 - eta, found in FP64 (see
+ * csmap_cone_events), and the box contributes the events with
+ * eta_lo <= eta < eta_hi, with the segment's Xdot, X' and dsigma.  Segments
+ * with |Xdot| >= 1 record no event.  Arrays are copied as by csmap_add_box.
+ * CSMAP_E_UNSUPPORTED for the CSMAP_VIS_BOX rule (events move out of the
+ * box); csmap_backward is not provided for skies holding such boxes. */
+csmap_status csmap_add_snapshot_box(csmap_sky *sky, const csmap_box *box, int64_t *box_id);
+
+/* The light-cone events of a box of slab-start segments, on their own (the
+ * crossing csmap_add_snapshot_box uses).  For segment i, with
+ * P0 = origin + x_rel[i], D the smaller root of
+ *     (Xdot.Xdot - 1) D^2 + 2 (P0.Xdot + R0) D + (P0.P0 - R0^2) = 0,
+ * R0 = eta0 - eta_lo (the root where |P0 + Xdot D| = eta0 - eta_lo - D):
+ * keep[i] = 1 iff |Xdot| < 1 and 0 <= D < eta_hi - eta_lo; then delta[i] = D
+ * and pos[3i..3i+2] = P0 + Xdot D (observer-relative, FP64), else NaN.
+ * Reads box->n, dtype, x_rel, xdot (device), origin, eta_lo, eta_hi; pos
+ * (n x 3 doubles), delta (n doubles) and keep (n bytes) are device arrays
+ * owned by the caller.  Enqueued on hip_stream; no synchronisation. */
+csmap_status csmap_cone_events(const csmap_box *box, double eta0, double *pos, double *delta,
+                               uint8_t *keep, void *hip_stream);
+
 /* Evaluate Theta/GU (Eq. (1)) at every RING pixel centre from all boxes
  * added so far and write it to map (device, 12 Nside^2 doubles, RING order).
  * Each pixel's value is its own sum; results are deterministic for a given

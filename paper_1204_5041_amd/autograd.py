@@ -19,7 +19,7 @@ import torch
 
 from . import binding as B
 
-_GEOM_KEYS = ("origin", "eta_lo", "eta_hi", "vis", "ext", "cap_dir", "cap_cos")
+_GEOM_KEYS = ("origin", "eta_lo", "eta_hi", "vis", "ext", "cap_dir", "cap_cos", "snapshot")
 _SEG_KEYS = ("x_rel", "xdot", "xprime", "dsigma")
 
 

@@ -28,9 +28,10 @@ CSMAP_VIS_ALL, CSMAP_VIS_BOX, CSMAP_VIS_CAP = 0, 1, 2
 _STATUS_NAMES = {0: "CSMAP_OK", -1: "CSMAP_E_INVALID", -2: "CSMAP_E_NOMEM", -3: "CSMAP_E_DEVICE",
                  -4: "CSMAP_E_STATE", -5: "CSMAP_E_UNSUPPORTED"}
 
-EXPORTED = ["csmap_npix", "csmap_create_sky", "csmap_add_box", "csmap_render", "csmap_backward",
-            "csmap_reset", "csmap_destroy_sky", "csmap_last_error", "csmap_pix2vec_ring",
-            "csmap_set_option", "csmap_get_stats", "csmap_autotune", "csmap_cap_tiles", "csmap_ring_block_rows",
+EXPORTED = ["csmap_npix", "csmap_create_sky", "csmap_add_box", "csmap_add_snapshot_box",
+            "csmap_cone_events", "csmap_render", "csmap_backward", "csmap_reset",
+            "csmap_destroy_sky", "csmap_last_error", "csmap_pix2vec_ring", "csmap_set_option",
+            "csmap_get_stats", "csmap_autotune", "csmap_cap_tiles", "csmap_ring_block_rows",
             "csmap_cap_block_tiles"]
 
 
@@ -78,6 +79,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.csmap_npix.restype = i64
     lib.csmap_create_sky.argtypes = [i64, dbl, i32, vp, ctypes.POINTER(vp)]
     lib.csmap_add_box.argtypes = [vp, ctypes.POINTER(csmap_box), ctypes.POINTER(i64)]
+    lib.csmap_add_snapshot_box.argtypes = [vp, ctypes.POINTER(csmap_box), ctypes.POINTER(i64)]
+    lib.csmap_cone_events.argtypes = [ctypes.POINTER(csmap_box), ctypes.c_double, vp, vp, vp, vp]
     lib.csmap_render.argtypes = [vp, vp]
     lib.csmap_backward.argtypes = [vp, vp, ctypes.POINTER(csmap_grad), i64]
     lib.csmap_reset.argtypes = [vp]
@@ -130,6 +133,18 @@ def csmap_add_box(sky: int, box: csmap_box) -> int:
     bid = ctypes.c_int64()
     _check(lib().csmap_add_box(sky, ctypes.byref(box), ctypes.byref(bid)))
     return bid.value
+
+
+def csmap_add_snapshot_box(sky: int, box: csmap_box) -> int:
+    bid = ctypes.c_int64()
+    _check(lib().csmap_add_snapshot_box(sky, ctypes.byref(box), ctypes.byref(bid)))
+    return bid.value
+
+
+def csmap_cone_events(box: csmap_box, eta0: float, pos_ptr: int, delta_ptr: int, keep_ptr: int,
+                      stream: int = 0):
+    _check(lib().csmap_cone_events(ctypes.byref(box), float(eta0), pos_ptr, delta_ptr, keep_ptr,
+                                   stream))
 
 
 def csmap_render(sky: int, map_ptr: int):
@@ -241,7 +256,11 @@ class Sky:
         self.box_dtypes = []
 
     def add_box(self, x_rel, xdot, xprime, dsigma, origin, eta_lo, eta_hi,
-                vis=CSMAP_VIS_ALL, ext=(1.0, 1.0, 1.0), cap_dir=(0.0, 0.0, 1.0), cap_cos=-1.0):
+                vis=CSMAP_VIS_ALL, ext=(1.0, 1.0, 1.0), cap_dir=(0.0, 0.0, 1.0), cap_cos=-1.0,
+                snapshot=False):
+        """Add a box of light-cone events (csmap_add_box), or with
+        snapshot=True a box of segments at the slab start whose light-cone
+        crossings the library records (csmap_add_snapshot_box)."""
         torch = _torch()
         dt = x_rel.dtype
         if dt not in (torch.float32, torch.float64):
@@ -262,7 +281,7 @@ class Sky:
         b.vis = int(vis)
         b.cap_dir = (ctypes.c_double * 3)(*[float(v) for v in cap_dir])
         b.cap_cos = float(cap_cos)
-        bid = csmap_add_box(self.handle, b)
+        bid = (csmap_add_snapshot_box if snapshot else csmap_add_box)(self.handle, b)
         self._keep.append((x_rel, xdot, xprime, dsigma))
         self.box_shapes.append(n)
         self.box_dtypes.append(dt)
@@ -324,6 +343,31 @@ class Sky:
             self.close()
         except Exception:
             pass
+
+
+def cone_events(x_rel, xdot, origin, eta0: float, eta_lo: float, eta_hi: float, stream=None):
+    """Light-cone events of slab-start segments (csmap_cone_events): returns
+    (pos (n,3) float64, delta (n,) float64, keep (n,) bool) CUDA tensors."""
+    torch = _torch()
+    n = int(x_rel.shape[0])
+    if x_rel.dtype not in (torch.float32, torch.float64) or xdot.dtype != x_rel.dtype:
+        raise TypeError("x_rel and xdot must share a float32 or float64 dtype")
+    if tuple(x_rel.shape) != (n, 3) or tuple(xdot.shape) != (n, 3):
+        raise ValueError("x_rel and xdot must have shape (n, 3)")
+    pos = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    delta = torch.empty(n, dtype=torch.float64, device="cuda")
+    keep = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = csmap_box()
+    b.n = n
+    b.dtype = CSMAP_F32 if x_rel.dtype == torch.float32 else CSMAP_F64
+    if n:
+        b.x_rel, b.xdot = _dev_ptr(x_rel), _dev_ptr(xdot)
+    b.origin = (ctypes.c_double * 3)(*[float(v) for v in origin])
+    b.eta_lo, b.eta_hi = float(eta_lo), float(eta_hi)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    csmap_cone_events(b, eta0, pos.data_ptr() if n else None, delta.data_ptr() if n else None,
+                      keep.data_ptr() if n else None, st.cuda_stream)
+    return pos, delta, keep.bool()
 
 
 def pix2vec_ring(nside: int, first: int = 0, count: int | None = None):

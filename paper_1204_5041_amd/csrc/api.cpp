@@ -28,6 +28,9 @@ hipError_t launch_pix2vec(int64_t nside, int64_t first, int64_t count, double* x
                           hipStream_t st);
 hipError_t launch_dir_table(int64_t nside, int64_t npix, double* x, double* y, double* z,
                             hipStream_t st);
+hipError_t launch_cone_events(int64_t n, int dtype, const void* x_rel, const void* xdot,
+                              const double origin[3], double eta0, double eta_lo, double eta_hi,
+                              double* pos, double* delta, uint8_t* keep, hipStream_t st);
 hipError_t launch_forward(bool fp64, int K, bool persistent, const FwdArgs& A, unsigned grid,
                           unsigned block, hipStream_t st);
 int forward_blocks_per_cu(bool fp64, bool frac, int K, unsigned block);
@@ -84,6 +87,7 @@ struct DevBuf {
 
 struct HostBox {
   HostBoxGeom geom;
+  int snapshot;     // 1: positions at the slab start (csmap_add_snapshot_box)
   int dtype;
   int64_t n;
   int64_t raw_byte_off;
@@ -226,6 +230,7 @@ csmap_status prepare(csmap_sky* s) {
     d.cap_cos = h.geom.cap_cos;
     d.vis = h.geom.vis;
     d.dtype = h.dtype;
+    d.snapshot = h.snapshot;
     d.n = h.n;
     d.raw_off = 0;
     d.rec_off = rec;
@@ -545,11 +550,15 @@ csmap_status csmap_destroy_sky(csmap_sky* s) {
   return CSMAP_OK;
 }
 
-csmap_status csmap_add_box(csmap_sky* s, const csmap_box* box, int64_t* box_id) {
+static csmap_status add_box_impl(csmap_sky* s, const csmap_box* box, int snapshot,
+                                 int64_t* box_id) {
   g_err.clear();
   csmap_status cs = check_sky(s);
   if (cs != CSMAP_OK) return cs;
   if (!box) return fail(CSMAP_E_INVALID, "box is NULL");
+  if (snapshot && box->vis == CSMAP_VIS_BOX)
+    return fail(CSMAP_E_UNSUPPORTED,
+                "CSMAP_VIS_BOX is not provided for snapshot boxes (their events leave the box)");
   if (box->n < 0) return fail(CSMAP_E_INVALID, "segment count must be >= 0");
   if (box->n > (int64_t)INT32_MAX) return fail(CSMAP_E_INVALID, "at most 2^31-1 segments per box");
   if (box->dtype != CSMAP_F32 && box->dtype != CSMAP_F64)
@@ -602,6 +611,7 @@ csmap_status csmap_add_box(csmap_sky* s, const csmap_box* box, int64_t* box_id) 
                              s->stream), "copy dsigma");
   }
   HostBox h;
+  h.snapshot = snapshot;
   for (int k = 0; k < 3; ++k) {
     h.geom.origin[k] = box->origin[k];
     h.geom.ext[k] = box->ext[k];
@@ -620,6 +630,35 @@ csmap_status csmap_add_box(csmap_sky* s, const csmap_box* box, int64_t* box_id) 
   s->dirty = true;
   s->version++;
   if (box_id) *box_id = (int64_t)s->boxes.size() - 1;
+  return CSMAP_OK;
+}
+
+csmap_status csmap_add_box(csmap_sky* s, const csmap_box* box, int64_t* box_id) {
+  return add_box_impl(s, box, 0, box_id);
+}
+
+csmap_status csmap_add_snapshot_box(csmap_sky* s, const csmap_box* box, int64_t* box_id) {
+  return add_box_impl(s, box, 1, box_id);
+}
+
+csmap_status csmap_cone_events(const csmap_box* box, double eta0, double* pos, double* delta,
+                               uint8_t* keep, void* hip_stream) {
+  g_err.clear();
+  if (!box) return fail(CSMAP_E_INVALID, "box is NULL");
+  if (box->n < 0) return fail(CSMAP_E_INVALID, "segment count must be >= 0");
+  if (box->dtype != CSMAP_F32 && box->dtype != CSMAP_F64)
+    return fail(CSMAP_E_INVALID, "unknown dtype");
+  if (box->n > 0 && (!box->x_rel || !box->xdot || !pos || !delta || !keep))
+    return fail(CSMAP_E_INVALID, "array pointer is NULL");
+  for (int k = 0; k < 3; ++k)
+    if (!isfinite(box->origin[k])) return fail(CSMAP_E_INVALID, "origin must be finite");
+  if (!isfinite(eta0) || !isfinite(box->eta_lo) || !isfinite(box->eta_hi) ||
+      !(box->eta_lo < box->eta_hi))
+    return fail(CSMAP_E_INVALID, "eta0 and the slab must be finite with eta_lo < eta_hi");
+  hipError_t e = launch_cone_events(box->n, (int)box->dtype, box->x_rel, box->xdot, box->origin,
+                                    eta0, box->eta_lo, box->eta_hi, pos, delta, keep,
+                                    (hipStream_t)hip_stream);
+  if (e != hipSuccess) return dev_fail(nullptr, e, "cone events launch");
   return CSMAP_OK;
 }
 
@@ -747,6 +786,9 @@ csmap_status csmap_backward(csmap_sky* s, const double* dmap, const csmap_grad* 
   if (nbox > 0 && !grads) return fail(CSMAP_E_INVALID, "grads is NULL");
   if (s->form != CSMAP_FORM_FP32C)
     return fail(CSMAP_E_UNSUPPORTED, "backward is provided for the FP32C form");
+  for (auto& h : s->boxes)
+    if (h.snapshot)
+      return fail(CSMAP_E_UNSUPPORTED, "backward is not provided for snapshot boxes");
   cs = prepare(s);
   if (cs != CSMAP_OK) return cs;
   hipStream_t st = s->stream;

@@ -18,6 +18,8 @@ struct DevBox {
   double cap_cos;
   int32_t vis;       // 0 all, 1 ray crosses box inside slab radii, 2 cap
   int32_t dtype;     // 0 f32, 1 f64 raw arrays
+  int32_t snapshot;  // 1: positions at eta_lo, events are the worldlines' light-cone crossings
+  int32_t pad;
   int64_t n;         // raw segments
   int64_t raw_off;   // offset (in segments) of the raw arrays of this box
   int64_t rec_off;   // offset (in records) of this box's compacted records

@@ -64,6 +64,7 @@ __device__ __forceinline__ DevBox load_box(const DevBox* boxes, int64_t b) {
   r.cap_cos = q->cap_cos;
   r.vis = q->vis;
   r.dtype = q->dtype;
+  r.snapshot = q->snapshot;
   r.n = q->n;
   r.raw_off = q->raw_off;
   r.rec_off = q->rec_off;
@@ -88,6 +89,42 @@ __device__ __forceinline__ double raw_at(const char* base, int dtype, int64_t id
   return dtype == 0 ? (double)((const float*)base)[idx] : ((const double*)base)[idx];
 }
 
+// Light-cone crossing of a straight worldline.  A segment at P0 when the
+// slab starts (eta_lo), moving with velocity V (|V| < 1), is at P0 + V D at
+// eta = eta_lo + D; it meets the past light cone |P| = eta0 - eta where
+//   (V.V - 1) D^2 + 2 (P0.V + R0) D + (P0.P0 - R0^2) = 0,  R0 = eta0 - eta_lo.
+// The crossing is the smaller root (the other lies beyond D = R0, on the
+// future branch).  Both roots come from q = -(b + sign(b) sqrt(b^2 - a c)) as
+// q / a and c / q, so that neither subtracts nearly equal numbers, and
+// c = (|P0| - R0)(|P0| + R0) avoids cancelling the two Gpc-scale squares.
+__device__ __forceinline__ double cone_crossing(const double P0[3], const double V[3], double R0,
+                                                double vv) {
+  const double a = vv - 1.0;
+  const double b = ((P0[0] * V[0] + P0[1] * V[1]) + P0[2] * V[2]) + R0;
+  const double r = sqrt((P0[0] * P0[0] + P0[1] * P0[1]) + P0[2] * P0[2]);
+  const double c = (r - R0) * (r + R0);
+  double disc = b * b - a * c;
+  disc = disc > 0.0 ? disc : 0.0;
+  const double sq = sqrt(disc);
+  const double q = (b >= 0.0) ? -(b + sq) : (sq - b);
+  if (q == 0.0) return 0.0;   // double root at D = 0 (b = 0 and c = 0)
+  const double r1 = q / a, r2 = c / q;
+  return r1 < r2 ? r1 : r2;
+}
+
+// Event of a snapshot segment in the slab [eta_lo, eta_hi): its crossing D,
+// and whether 0 <= D < eta_hi - eta_lo (|V| >= 1 records no event).
+__device__ __forceinline__ bool snapshot_event(const double P0[3], const double V[3],
+                                               double eta0, double eta_lo, double eta_hi,
+                                               double vv, double& D) {
+  if (!(vv < 1.0)) {
+    D = __builtin_nan("");
+    return false;
+  }
+  D = cone_crossing(P0, V, eta0 - eta_lo, vv);
+  return D >= 0.0 && D < eta_hi - eta_lo;
+}
+
 __device__ __forceinline__ SegGeom seg_geom(const DevBox& bx, const char* raw, int64_t i,
                                             double eta0) {
   // Raw layout of a box: x_rel (n x 3), xdot (n x 3), xprime (n x 3), dsigma (n).
@@ -101,11 +138,24 @@ __device__ __forceinline__ SegGeom seg_geom(const DevBox& bx, const char* raw, i
     g.T[k] = raw_at(raw, dt, 6 * n + 3 * i + k);
   }
   g.ds = raw_at(raw, dt, 9 * n + i);
-  g.R = sqrt((g.P[0] * g.P[0] + g.P[1] * g.P[1]) + g.P[2] * g.P[2]);
-  const double eta = eta0 - g.R;
-  g.keep = (g.R > 0.0) && (eta >= bx.eta_lo) && (eta < bx.eta_hi);
   const double tt = (g.T[0] * g.T[0] + g.T[1] * g.T[1]) + g.T[2] * g.T[2];
   const double vv = (g.V[0] * g.V[0] + g.V[1] * g.V[1]) + g.V[2] * g.V[2];
+  if (bx.snapshot) {
+    // Positions are at the slab start: the event is where the worldline
+    // meets the past light cone, if that happens inside the slab.
+    double D;
+    const bool in = snapshot_event(g.P, g.V, eta0, bx.eta_lo, bx.eta_hi, vv, D);
+    if (in) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) g.P[k] = g.P[k] + g.V[k] * D;
+    }
+    g.R = sqrt((g.P[0] * g.P[0] + g.P[1] * g.P[1]) + g.P[2] * g.P[2]);
+    g.keep = in && (g.R > 0.0);
+  } else {
+    g.R = sqrt((g.P[0] * g.P[0] + g.P[1] * g.P[1]) + g.P[2] * g.P[2]);
+    const double eta = eta0 - g.R;
+    g.keep = (g.R > 0.0) && (eta >= bx.eta_lo) && (eta < bx.eta_hi);
+  }
   g.eps = sqrt(tt / (1.0 - vv));
   return g;
 }
@@ -246,6 +296,46 @@ __global__ void __launch_bounds__(kPreBlock) k_pre_emit(PreArgs A) {
     o[6] = make_double2(lo[0], lo[1]);
     o[7] = make_double2(lo[2], 0.0);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Light-cone events of a snapshot box, on their own (the same crossing as the
+// render path): per segment the observer-relative event position, D, and
+// whether the event falls inside the slab.  Coalesced: thread i reads
+// segment i's position and velocity and writes its outputs.
+// ---------------------------------------------------------------------------
+__global__ void k_cone_events(int64_t n, int dtype, const void* x_rel, const void* xdot,
+                              double o0, double o1, double o2, double eta0, double eta_lo,
+                              double eta_hi, double* pos, double* delta, uint8_t* keep) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const char* xr = (const char*)x_rel;
+  const char* xd = (const char*)xdot;
+  double P0[3], V[3];
+  const double o[3] = {o0, o1, o2};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    P0[k] = o[k] + raw_at(xr, dtype, 3 * i + k);
+    V[k] = raw_at(xd, dtype, 3 * i + k);
+  }
+  const double vv = (V[0] * V[0] + V[1] * V[1]) + V[2] * V[2];
+  double D;
+  const bool in = snapshot_event(P0, V, eta0, eta_lo, eta_hi, vv, D);
+  const double nan = __builtin_nan("");
+#pragma unroll
+  for (int k = 0; k < 3; ++k) pos[3 * i + k] = in ? P0[k] + V[k] * D : nan;
+  delta[i] = in ? D : nan;
+  keep[i] = in ? 1 : 0;
+}
+
+hipError_t launch_cone_events(int64_t n, int dtype, const void* x_rel, const void* xdot,
+                              const double origin[3], double eta0, double eta_lo, double eta_hi,
+                              double* pos, double* delta, uint8_t* keep, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_cone_events<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(
+      n, dtype, x_rel, xdot, origin[0], origin[1], origin[2], eta0, eta_lo, eta_hi, pos, delta,
+      keep);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

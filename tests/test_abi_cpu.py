@@ -52,6 +52,15 @@ def test_invalid_arguments_rejected_on_host():
     assert L.csmap_npix(1) == 12 and L.csmap_npix(8192) == 12 * 8192 ** 2 and L.csmap_npix(0) == -1
     assert L.csmap_pix2vec_ring(16, 0, 10**9, None, None) == B.CSMAP_E_INVALID
     assert L.csmap_pix2vec_ring(16, -1, 1, None, None) == B.CSMAP_E_INVALID
+    assert L.csmap_add_snapshot_box(None, None, None) == B.CSMAP_E_INVALID
+    assert L.csmap_cone_events(None, 1.0, None, None, None, None) == B.CSMAP_E_INVALID
+    bx = B.csmap_box()
+    bx.n, bx.dtype, bx.eta_lo, bx.eta_hi = 5, B.CSMAP_F32, 1.0, 0.5   # empty slab
+    assert L.csmap_cone_events(ctypes.byref(bx), 2.0, None, None, None, None) == B.CSMAP_E_INVALID
+    bx.eta_hi = 2.0                                                   # arrays missing
+    assert L.csmap_cone_events(ctypes.byref(bx), 2.0, None, None, None, None) == B.CSMAP_E_INVALID
+    bx.n = 0                                                          # nothing to do
+    assert L.csmap_cone_events(ctypes.byref(bx), 2.0, None, None, None, None) == B.CSMAP_OK
 
 
 @pytest.mark.parametrize("nside,tile", [(16, 64), (64, 256), (128, 512), (37, 128)])
