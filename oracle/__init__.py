@@ -56,6 +56,11 @@ def lib() -> ctypes.CDLL:
         _lib.oracle_isqrt.restype = i64
         _lib.oracle_pix2vec_many.argtypes = [i64, i64, i64p, f64p]
         _lib.oracle_ring_many.argtypes = [i64, i64, i64p, i64p, i64p]
+        _lib.oracle_lambda_lm.argtypes = [i64, i64, ctypes.c_double, ctypes.c_double, f64p]
+        _lib.oracle_alm_index.argtypes = [i64, i64, i64]
+        _lib.oracle_alm_index.restype = i64
+        _lib.oracle_map2alm.argtypes = [i64, i64, f64p, f64p, f64p]
+        _lib.oracle_alm2cl.argtypes = [i64, f64p, f64p, f64p]
         _lib.oracle_cone_events.argtypes = [i64, f64p, f64p, f64p, ctypes.c_double,
                                             ctypes.c_double, ctypes.c_double, f64p, f64p, u8p]
         _lib.oracle_theta_dirs.argtypes = [i64, f64p, ctypes.c_double, i64, f64p, i64p,
@@ -237,3 +242,44 @@ def cone_events(x_rel, xdot, origin, eta0: float, eta_lo: float, eta_hi: float):
                              _p(pos, ctypes.c_double), _p(delta, ctypes.c_double),
                              _p(keep, ctypes.c_uint8))
     return pos, delta, keep.astype(bool)
+
+
+def lambda_lm(lmax: int, m: int, z: float, s: float) -> np.ndarray:
+    """Orthonormal associated Legendre functions lambda_lm(cos theta) for
+    l = m .. lmax (Condon-Shortley phase), with z = cos theta, s = sin theta."""
+    out = np.empty(lmax - m + 1, dtype=np.float64)
+    lib().oracle_lambda_lm(lmax, m, float(z), float(s), _p(out, ctypes.c_double))
+    return out
+
+
+def alm_index(lmax: int, l: int, m: int) -> int:
+    """Position of a_lm (0 <= m <= l <= lmax): m (2 lmax + 1 - m) / 2 + l."""
+    return int(lib().oracle_alm_index(lmax, l, m))
+
+
+def alm_size(lmax: int) -> int:
+    return (lmax + 1) * (lmax + 2) // 2
+
+
+def map2alm(nside: int, lmax: int, hmap) -> np.ndarray:
+    """a_lm = (4 pi / Npix) sum_p map_p conj(Y_lm(n_p)) (complex128, index
+    alm_index), by direct summation over pixels."""
+    m = _f64(hmap).ravel()
+    if m.size != 12 * nside * nside:
+        raise ValueError("map size does not match nside")
+    re = np.empty(alm_size(lmax), dtype=np.float64)
+    im = np.empty(alm_size(lmax), dtype=np.float64)
+    lib().oracle_map2alm(nside, lmax, _p(m, ctypes.c_double), _p(re, ctypes.c_double),
+                         _p(im, ctypes.c_double))
+    return re + 1j * im
+
+
+def alm2cl(lmax: int, alm) -> np.ndarray:
+    """C_l = sum_{m=-l}^{l} |a_lm|^2 / (2l + 1) of a real map's a_lm (m >= 0 stored)."""
+    a = np.asarray(alm, dtype=np.complex128)
+    re = np.ascontiguousarray(a.real)
+    im = np.ascontiguousarray(a.imag)
+    cl = np.empty(lmax + 1, dtype=np.float64)
+    lib().oracle_alm2cl(lmax, _p(re, ctypes.c_double), _p(im, ctypes.c_double),
+                        _p(cl, ctypes.c_double))
+    return cl

@@ -538,3 +538,124 @@ void oracle_cone_events(int64_t n, const double *x_rel, const double *xdot,
         for (int k = 0; k < 3; ++k) pos[3 * i + k] = P0[k] + V[k] * D;
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Spherical-harmonic analysis of a RING map (the angular power spectrum of  */
+/* Sec. III, Fig. 4).  With Y_lm(theta, phi) = lambda_lm(cos theta) e^{i m   */
+/* phi}, lambda_lm the associated Legendre function normalised so that the   */
+/* Y_lm are orthonormal on the sphere and carrying the Condon-Shortley phase  */
+/* (-1)^m:                                                                    */
+/*     a_lm = (4 pi / Npix) sum_p map_p conj(Y_lm(n_p)),  0 <= m <= l <= lmax */
+/*     C_l  = (|a_l0|^2 + 2 sum_{m>0} |a_lm|^2) / (2l + 1),                   */
+/* i.e. each pixel weighted by its area at its centre.  lambda_lm comes from  */
+/* the textbook recursions                                                    */
+/*     lambda_00 = 1/sqrt(4 pi),                                              */
+/*     lambda_mm = -sqrt((2m+1)/(2m)) sin(theta) lambda_{m-1,m-1},            */
+/*     lambda_{m+1,m} = sqrt(2m+3) cos(theta) lambda_mm,                      */
+/*     lambda_lm = A_lm (cos(theta) lambda_{l-1,m} - B_lm lambda_{l-2,m}),    */
+/*     A_lm = sqrt((4l^2-1)/(l^2-m^2)), B_lm = sqrt(((l-1)^2-m^2)/(4(l-1)^2-1)),*/
+/* carried as v * 2^(600 e) so that the factor sin^m(theta), far below the   */
+/* double range for large m near the poles, is not lost before the l         */
+/* recursion brings the value back up.                                        */
+/* a_lm is stored at index m (2 lmax + 1 - m) / 2 + l (the order HEALPix      */
+/* software uses), real and imaginary parts in separate arrays.              */
+/* ------------------------------------------------------------------------ */
+#define LEG_SCALE 600
+#define ORACLE_PI 3.14159265358979323846   /* rounds to the double nearest pi */
+
+/* lambda_lm(cos theta) for l = m .. lmax into out[l - m]. */
+void oracle_lambda_lm(int64_t lmax, int64_t m, double z, double s, double *out)
+{
+    double v = 1.0 / sqrt(4.0 * ORACLE_PI);
+    int e = 0;
+    for (int64_t k = 1; k <= m; ++k) {
+        v = -sqrt((2.0 * k + 1.0) / (2.0 * k)) * s * v;
+        if (fabs(v) < ldexp(1.0, -LEG_SCALE)) {
+            v = ldexp(v, LEG_SCALE);
+            e -= 1;
+        }
+    }
+    double prev = 0.0, cur = v;   /* lambda_{l-1,m}, lambda_{l,m}, scaled alike */
+    for (int64_t l = m; l <= lmax; ++l) {
+        if (l > m) {
+            double next;
+            if (l == m + 1) {
+                next = sqrt(2.0 * m + 3.0) * z * cur;
+            } else {
+                const double ll = (double)l, mm = (double)m;
+                const double A = sqrt((4.0 * ll * ll - 1.0) / (ll * ll - mm * mm));
+                const double B = sqrt(((ll - 1.0) * (ll - 1.0) - mm * mm) /
+                                      (4.0 * (ll - 1.0) * (ll - 1.0) - 1.0));
+                next = A * (z * cur - B * prev);
+            }
+            prev = cur;
+            cur = next;
+            if (fabs(cur) > ldexp(1.0, LEG_SCALE) && e < 0) {
+                cur = ldexp(cur, -LEG_SCALE);
+                prev = ldexp(prev, -LEG_SCALE);
+                e += 1;
+            }
+        }
+        out[l - m] = (e == 0) ? cur : ldexp(cur, LEG_SCALE * e);
+    }
+}
+
+int64_t oracle_alm_index(int64_t lmax, int64_t l, int64_t m)
+{
+    return m * (2 * lmax + 1 - m) / 2 + l;
+}
+
+void oracle_map2alm(int64_t nside, int64_t lmax, const double *map, double *alm_re,
+                    double *alm_im)
+{
+    const int64_t npix = 12 * nside * nside;
+    const double w = 4.0 * ORACLE_PI / (double)npix;
+#pragma omp parallel
+    {
+        double *lam = (double *)malloc(sizeof(double) * (size_t)(lmax + 1));
+        csum_t *sre = (csum_t *)malloc(sizeof(csum_t) * (size_t)(lmax + 1));
+        csum_t *sim = (csum_t *)malloc(sizeof(csum_t) * (size_t)(lmax + 1));
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t m = 0; m <= lmax; ++m) {
+            for (int64_t l = m; l <= lmax; ++l) {
+                sre[l] = (csum_t){0.0, 0.0};
+                sim[l] = (csum_t){0.0, 0.0};
+            }
+            for (int64_t p = 0; p < npix; ++p) {
+                double n[3];
+                oracle_pix2vec(nside, p, n);
+                const double s = sqrt(n[0] * n[0] + n[1] * n[1]);
+                const double phi = atan2(n[1], n[0]);
+                oracle_lambda_lm(lmax, m, n[2], s, lam);
+                /* conj(e^{i m phi}) = cos(m phi) - i sin(m phi) */
+                const double c = cos((double)m * phi), sn = sin((double)m * phi);
+                for (int64_t l = m; l <= lmax; ++l) {
+                    const double t = map[p] * lam[l - m];
+                    cadd(&sre[l], t * c);
+                    cadd(&sim[l], -t * sn);
+                }
+            }
+            for (int64_t l = m; l <= lmax; ++l) {
+                const int64_t i = oracle_alm_index(lmax, l, m);
+                alm_re[i] = w * (sre[l].sum + sre[l].comp);
+                alm_im[i] = w * (sim[l].sum + sim[l].comp);
+            }
+        }
+        free(lam);
+        free(sre);
+        free(sim);
+    }
+}
+
+void oracle_alm2cl(int64_t lmax, const double *alm_re, const double *alm_im, double *cl)
+{
+    for (int64_t l = 0; l <= lmax; ++l) {
+        csum_t acc = {0.0, 0.0};
+        for (int64_t m = 0; m <= l; ++m) {
+            const int64_t i = oracle_alm_index(lmax, l, m);
+            const double p = alm_re[i] * alm_re[i] + alm_im[i] * alm_im[i];
+            cadd(&acc, m == 0 ? p : 2.0 * p);
+        }
+        cl[l] = (acc.sum + acc.comp) / (2.0 * (double)l + 1.0);
+    }
+}
