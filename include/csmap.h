@@ -270,6 +270,25 @@ csmap_status csmap_get_stats(csmap_sky *sky, csmap_stats *out);
  * are unchanged up to rounding (the sum order within a pixel may change). */
 csmap_status csmap_autotune(csmap_sky *sky, const char *cache_path);
 
+/* Spherical-harmonic analysis of a RING map (the angular power spectrum of
+ * Sec. III, Fig. 4): for 0 <= m <= l <= lmax,
+ *     a_lm = (4 pi / Npix) sum_p map_p conj(Y_lm(n_p)),
+ * Y_lm(theta, phi) = lambda_lm(cos theta) e^{i m phi} orthonormal with the
+ * Condon-Shortley phase, n_p the pixel centres.  map: device, 12 Nside^2
+ * doubles (RING order); alm: device, (lmax + 1)(lmax + 2) doubles, a_lm's
+ * real and imaginary parts at positions 2 i and 2 i + 1 with
+ * i = m (2 lmax + 1 - m) / 2 + l.  0 <= lmax <= 4 Nside.  Allocates device
+ * scratch for the duration of the call (about 16 (4 Nside)(lmax + 1) +
+ * 12 (2 Nside)(lmax + 1) + 16 ceil(Nside / 256)(lmax + 1)(lmax + 2)/2
+ * bytes) and synchronises hip_stream before returning. */
+csmap_status csmap_map2alm(int64_t nside, int64_t lmax, const double *map, double *alm,
+                           void *hip_stream);
+
+/* C_l = (|a_l0|^2 + 2 sum_{m=1}^{l} |a_lm|^2) / (2l + 1) for l = 0 .. lmax of
+ * a real map's a_lm (layout of csmap_map2alm); cl: device, lmax + 1
+ * doubles.  Enqueued on hip_stream. */
+csmap_status csmap_alm2cl(int64_t lmax, const double *alm, double *cl, void *hip_stream);
+
 /* Host-side helper, no device work: the RING pixel tiles of `tile` pixels
  * that may contain pixels within angle rho (radians) of the unit vector
  * (cx, cy, cz) at Nside.  Writes up to max_ranges [first, last] tile index

@@ -60,6 +60,7 @@ def lib() -> ctypes.CDLL:
         _lib.oracle_alm_index.argtypes = [i64, i64, i64]
         _lib.oracle_alm_index.restype = i64
         _lib.oracle_map2alm.argtypes = [i64, i64, f64p, f64p, f64p]
+        _lib.oracle_map2alm_m.argtypes = [i64, i64, i64, f64p, f64p, f64p]
         _lib.oracle_alm2cl.argtypes = [i64, f64p, f64p, f64p]
         _lib.oracle_cone_events.argtypes = [i64, f64p, f64p, f64p, ctypes.c_double,
                                             ctypes.c_double, ctypes.c_double, f64p, f64p, u8p]
@@ -283,3 +284,14 @@ def alm2cl(lmax: int, alm) -> np.ndarray:
     lib().oracle_alm2cl(lmax, _p(re, ctypes.c_double), _p(im, ctypes.c_double),
                         _p(cl, ctypes.c_double))
     return cl
+
+
+def map2alm_m(nside: int, lmax: int, m: int, hmap) -> np.ndarray:
+    """a_lm for one m and l = m .. lmax (complex128), by the same direct sum
+    as map2alm; single-threaded."""
+    mp = _f64(hmap).ravel()
+    re = np.empty(lmax - m + 1, dtype=np.float64)
+    im = np.empty(lmax - m + 1, dtype=np.float64)
+    lib().oracle_map2alm_m(nside, lmax, m, _p(mp, ctypes.c_double), _p(re, ctypes.c_double),
+                           _p(im, ctypes.c_double))
+    return re + 1j * im

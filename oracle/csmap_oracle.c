@@ -605,45 +605,60 @@ int64_t oracle_alm_index(int64_t lmax, int64_t l, int64_t m)
     return m * (2 * lmax + 1 - m) / 2 + l;
 }
 
-void oracle_map2alm(int64_t nside, int64_t lmax, const double *map, double *alm_re,
-                    double *alm_im)
+/* a_lm for one m and l = m .. lmax into re[l - m], im[l - m]. */
+void oracle_map2alm_m(int64_t nside, int64_t lmax, int64_t m, const double *map, double *re,
+                      double *im)
 {
     const int64_t npix = 12 * nside * nside;
     const double w = 4.0 * ORACLE_PI / (double)npix;
+    double *lam = (double *)malloc(sizeof(double) * (size_t)(lmax + 1));
+    csum_t *sre = (csum_t *)malloc(sizeof(csum_t) * (size_t)(lmax + 1));
+    csum_t *sim = (csum_t *)malloc(sizeof(csum_t) * (size_t)(lmax + 1));
+    for (int64_t l = m; l <= lmax; ++l) {
+        sre[l] = (csum_t){0.0, 0.0};
+        sim[l] = (csum_t){0.0, 0.0};
+    }
+    for (int64_t p = 0; p < npix; ++p) {
+        double n[3];
+        oracle_pix2vec(nside, p, n);
+        const double s = sqrt(n[0] * n[0] + n[1] * n[1]);
+        const double phi = atan2(n[1], n[0]);
+        oracle_lambda_lm(lmax, m, n[2], s, lam);
+        /* conj(e^{i m phi}) = cos(m phi) - i sin(m phi) */
+        const double c = cos((double)m * phi), sn = sin((double)m * phi);
+        for (int64_t l = m; l <= lmax; ++l) {
+            const double t = map[p] * lam[l - m];
+            cadd(&sre[l], t * c);
+            cadd(&sim[l], -t * sn);
+        }
+    }
+    for (int64_t l = m; l <= lmax; ++l) {
+        re[l - m] = w * (sre[l].sum + sre[l].comp);
+        im[l - m] = w * (sim[l].sum + sim[l].comp);
+    }
+    free(lam);
+    free(sre);
+    free(sim);
+}
+
+void oracle_map2alm(int64_t nside, int64_t lmax, const double *map, double *alm_re,
+                    double *alm_im)
+{
 #pragma omp parallel
     {
-        double *lam = (double *)malloc(sizeof(double) * (size_t)(lmax + 1));
-        csum_t *sre = (csum_t *)malloc(sizeof(csum_t) * (size_t)(lmax + 1));
-        csum_t *sim = (csum_t *)malloc(sizeof(csum_t) * (size_t)(lmax + 1));
+        double *re = (double *)malloc(sizeof(double) * (size_t)(lmax + 1));
+        double *im = (double *)malloc(sizeof(double) * (size_t)(lmax + 1));
 #pragma omp for schedule(dynamic, 1)
         for (int64_t m = 0; m <= lmax; ++m) {
-            for (int64_t l = m; l <= lmax; ++l) {
-                sre[l] = (csum_t){0.0, 0.0};
-                sim[l] = (csum_t){0.0, 0.0};
-            }
-            for (int64_t p = 0; p < npix; ++p) {
-                double n[3];
-                oracle_pix2vec(nside, p, n);
-                const double s = sqrt(n[0] * n[0] + n[1] * n[1]);
-                const double phi = atan2(n[1], n[0]);
-                oracle_lambda_lm(lmax, m, n[2], s, lam);
-                /* conj(e^{i m phi}) = cos(m phi) - i sin(m phi) */
-                const double c = cos((double)m * phi), sn = sin((double)m * phi);
-                for (int64_t l = m; l <= lmax; ++l) {
-                    const double t = map[p] * lam[l - m];
-                    cadd(&sre[l], t * c);
-                    cadd(&sim[l], -t * sn);
-                }
-            }
+            oracle_map2alm_m(nside, lmax, m, map, re, im);
             for (int64_t l = m; l <= lmax; ++l) {
                 const int64_t i = oracle_alm_index(lmax, l, m);
-                alm_re[i] = w * (sre[l].sum + sre[l].comp);
-                alm_im[i] = w * (sim[l].sum + sim[l].comp);
+                alm_re[i] = re[l - m];
+                alm_im[i] = im[l - m];
             }
         }
-        free(lam);
-        free(sre);
-        free(sim);
+        free(re);
+        free(im);
     }
 }
 

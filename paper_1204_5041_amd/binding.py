@@ -29,7 +29,7 @@ _STATUS_NAMES = {0: "CSMAP_OK", -1: "CSMAP_E_INVALID", -2: "CSMAP_E_NOMEM", -3: 
                  -4: "CSMAP_E_STATE", -5: "CSMAP_E_UNSUPPORTED"}
 
 EXPORTED = ["csmap_npix", "csmap_create_sky", "csmap_add_box", "csmap_add_snapshot_box",
-            "csmap_cone_events", "csmap_render", "csmap_backward", "csmap_reset",
+            "csmap_cone_events", "csmap_map2alm", "csmap_alm2cl", "csmap_render", "csmap_backward", "csmap_reset",
             "csmap_destroy_sky", "csmap_last_error", "csmap_pix2vec_ring", "csmap_set_option",
             "csmap_get_stats", "csmap_autotune", "csmap_cap_tiles", "csmap_ring_block_rows",
             "csmap_cap_block_tiles"]
@@ -81,6 +81,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.csmap_add_box.argtypes = [vp, ctypes.POINTER(csmap_box), ctypes.POINTER(i64)]
     lib.csmap_add_snapshot_box.argtypes = [vp, ctypes.POINTER(csmap_box), ctypes.POINTER(i64)]
     lib.csmap_cone_events.argtypes = [ctypes.POINTER(csmap_box), ctypes.c_double, vp, vp, vp, vp]
+    lib.csmap_map2alm.argtypes = [i64, i64, vp, vp, vp]
+    lib.csmap_alm2cl.argtypes = [i64, vp, vp, vp]
     lib.csmap_render.argtypes = [vp, vp]
     lib.csmap_backward.argtypes = [vp, vp, ctypes.POINTER(csmap_grad), i64]
     lib.csmap_reset.argtypes = [vp]
@@ -368,6 +370,37 @@ def cone_events(x_rel, xdot, origin, eta0: float, eta_lo: float, eta_hi: float, 
     csmap_cone_events(b, eta0, pos.data_ptr() if n else None, delta.data_ptr() if n else None,
                       keep.data_ptr() if n else None, st.cuda_stream)
     return pos, delta, keep.bool()
+
+
+def alm_size(lmax: int) -> int:
+    return (lmax + 1) * (lmax + 2) // 2
+
+
+def map2alm(hmap, lmax: int, stream=None):
+    """a_lm of a RING map (csmap_map2alm) as a complex128 CUDA tensor of
+    alm_size(lmax) entries, a_lm at m (2 lmax + 1 - m) / 2 + l."""
+    torch = _torch()
+    npix = int(hmap.numel())
+    nside = int(round((npix / 12) ** 0.5))
+    if 12 * nside * nside != npix or hmap.dtype != torch.float64:
+        raise ValueError("map must be a float64 tensor of 12 Nside^2 pixels")
+    alm = torch.empty(2 * alm_size(lmax), dtype=torch.float64, device="cuda")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().csmap_map2alm(nside, lmax, _dev_ptr(hmap.contiguous()), _dev_ptr(alm),
+                               st.cuda_stream))
+    return torch.view_as_complex(alm.view(-1, 2))
+
+
+def alm2cl(alm, lmax: int, stream=None):
+    """C_l, l = 0 .. lmax, of a real map's a_lm (csmap_alm2cl), float64 CUDA tensor."""
+    torch = _torch()
+    a = torch.view_as_real(alm).contiguous().view(-1)
+    if a.numel() != 2 * alm_size(lmax):
+        raise ValueError("alm size does not match lmax")
+    cl = torch.empty(lmax + 1, dtype=torch.float64, device="cuda")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().csmap_alm2cl(lmax, _dev_ptr(a), _dev_ptr(cl), st.cuda_stream))
+    return cl
 
 
 def pix2vec_ring(nside: int, first: int = 0, count: int | None = None):

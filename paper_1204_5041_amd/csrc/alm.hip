@@ -1,0 +1,336 @@
+// alm.hip -- spherical-harmonic analysis of a RING map on the device.
+//
+// a_lm = (4 pi / Npix) sum_p map_p conj(Y_lm(n_p)) for 0 <= m <= l <= lmax,
+// Y_lm = lambda_lm(cos theta) e^{i m phi} (orthonormal, Condon-Shortley
+// phase), and C_l = (|a_l0|^2 + 2 sum_{m>0} |a_lm|^2) / (2l + 1): the angular
+// power spectrum of a map (Sec. III, Fig. 4).  The pixels of a HEALPix ring
+// share z and are evenly spaced in azimuth, so the sum splits into
+//   1. a Fourier sum along every ring, F_m(r) = sum_j map_{r,j} e^{-i m phi_j};
+//   2. a Legendre sum over rings, a_lm = (4 pi/Npix) sum_r lambda_lm(z_r) F_m(r),
+// where rings r and 4N - r (z and -z) enter together through
+// lambda_lm(-z) = (-1)^(l+m) lambda_lm(z).
+//
+// lambda_lm follows the recursions
+//   lambda_00 = 1/sqrt(4 pi),  lambda_mm = -sqrt((2m+1)/(2m)) sin(theta) lambda_{m-1,m-1},
+//   lambda_{m+1,m} = sqrt(2m+3) z lambda_mm,
+//   lambda_lm = A_lm (z lambda_{l-1,m} - B_lm lambda_{l-2,m}),
+//   A_lm = sqrt((4l^2-1)/(l^2-m^2)),  B_lm = sqrt(((l-1)^2-m^2)/(4(l-1)^2-1)),
+// with values carried as v * 2^(600 e): sin^m(theta) leaves the double range
+// for large m near the poles long before the l recursion brings it back.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "healpix_dev.h"
+
+namespace csmap {
+
+namespace {
+
+constexpr int kLegScale = 600;   // values are v * 2^(600 e)
+constexpr int kRingsPerLane = 8; // ring pairs summed by one lane of the Legendre kernel
+constexpr int kAnchor = 32;      // Fourier twiddles are recomputed exactly every 32 pixels
+
+typedef const double __attribute__((address_space(4)))* cdp;
+
+struct Ring {
+  int64_t first;   // RING index of the ring's first pixel
+  int64_t len;     // pixels in the ring
+  int32_t half;    // 1 if the azimuths carry the half-pixel offset
+};
+
+// Ring i (1 .. 4N-1) of the RING scheme.
+__device__ __forceinline__ Ring ring_of(int64_t N, int64_t i) {
+  Ring r;
+  if (i < N) {
+    r.len = 4 * i;
+    r.first = 2 * i * (i - 1);
+    r.half = 1;
+  } else if (i <= 3 * N) {
+    r.len = 4 * N;
+    r.first = 2 * N * (N - 1) + (i - N) * 4 * N;
+    r.half = ((i - N) % 2 == 0) ? 1 : 0;
+  } else {
+    const int64_t k = 4 * N - i;
+    r.len = 4 * k;
+    r.first = 12 * N * N - 2 * k * (k + 1);
+    r.half = 1;
+  }
+  return r;
+}
+
+__device__ __forceinline__ int64_t alm_idx(int64_t lmax, int64_t l, int64_t m) {
+  return m * (2 * lmax + 1 - m) / 2 + l;
+}
+
+// e^{-i pi t / L} for an integer t in [0, 2L).
+__device__ __forceinline__ void twiddle(int64_t t, int64_t L, double& c, double& s) {
+  double sp, cp;
+  sincospi((double)t / (double)L, &sp, &cp);
+  c = cp;
+  s = -sp;
+}
+
+// Step 1: F[(i-1) M + m] = sum_j map_{i,j} e^{-i m phi_j}, M = mmax + 1.
+// One wavefront per (ring, 64 consecutive m); the ring's pixel values are
+// uniform across the wavefront and stream through scalar registers; each
+// lane advances e^{-i m 2 pi j / L} by one complex multiplication per pixel
+// and recomputes it exactly every kAnchor pixels.
+__global__ void __launch_bounds__(256) k_ring_dft(int64_t nside, int64_t mmax, const double* map,
+                                                 double* F) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) +
+                       __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t mblocks = (mmax + 64) / 64;
+  const int64_t nring = 4 * nside - 1;
+  if (wave >= nring * mblocks) return;
+  const int64_t i = 1 + wave / mblocks;
+  const int64_t m = (wave % mblocks) * 64 + lane;
+  const Ring r = ring_of(nside, i);
+  const int64_t L = r.len;
+  const int64_t mm = m % L;                 // e^{-i m 2pi j/L} depends on m mod L only
+  double oc, os;                            // e^{-i 2 pi m / L}
+  twiddle((2 * mm) % (2 * L), L, oc, os);
+  double acc_re = 0.0, acc_im = 0.0;
+  cdp px = (cdp)(map + r.first);
+  for (int64_t j0 = 0; j0 < L; j0 += kAnchor) {
+    double wc, ws;
+    twiddle((2 * mm * (j0 % L)) % (2 * L), L, wc, ws);
+    const int64_t je = (j0 + kAnchor < L) ? j0 + kAnchor : L;
+    for (int64_t j = j0; j < je; ++j) {
+      const double v = px[j];
+      acc_re = fma(v, wc, acc_re);
+      acc_im = fma(v, ws, acc_im);
+      const double nc = fma(wc, oc, -(ws * os));
+      const double ns = fma(wc, os, ws * oc);
+      wc = nc;
+      ws = ns;
+    }
+  }
+  // The half-pixel azimuth offset: phi_j = 2 pi (j + 1/2) / L, a factor
+  // e^{-i pi m / L} (period 2L in m).
+  if (r.half) {
+    double hc, hs;
+    twiddle(m % (2 * L), L, hc, hs);
+    const double re = fma(acc_re, hc, -(acc_im * hs));
+    const double im = fma(acc_re, hs, acc_im * hc);
+    acc_re = re;
+    acc_im = im;
+  }
+  if (m <= mmax) {
+    double* o = F + 2 * ((i - 1) * (mmax + 1) + m);
+    o[0] = acc_re;
+    o[1] = acc_im;
+  }
+}
+
+// Step 2a: lambda_mm of the north ring of every ring pair q = 1 .. 2N (its
+// z >= 0), for m = 0 .. mmax, as v * 2^(600 e); one thread per ring.
+__global__ void k_lambda_mm(int64_t nside, int64_t mmax, double* lam_v, int32_t* lam_e,
+                            double* ring_z) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t npair = 2 * nside;
+  if (q >= npair) return;
+  const Ring r = ring_of(nside, q + 1);
+  double x, y, z;
+  pix2vec_ring(nside, r.first, &x, &y, &z);
+  const double s = sqrt(x * x + y * y);
+  ring_z[q] = z;
+  double v = 1.0 / sqrt(4.0 * 3.14159265358979323846);
+  int32_t e = 0;
+  const double tiny = ldexp(1.0, -kLegScale);
+  for (int64_t m = 0; m <= mmax; ++m) {
+    if (m > 0) {
+      v = -sqrt((2.0 * m + 1.0) / (2.0 * m)) * s * v;
+      if (fabs(v) < tiny) {
+        v = ldexp(v, kLegScale);
+        e -= 1;
+      }
+    }
+    lam_v[m * npair + q] = v;
+    lam_e[m * npair + q] = e;
+  }
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off);
+  return x;
+}
+
+// Step 2b: partial a_lm of one block of 64 * kRingsPerLane ring pairs, for
+// one m: part[blk * S + idx(l, m)] = sum over the block's pairs of
+// lambda_lm(z) (F_north +- F_south), the sign (-1)^(l+m).
+__global__ void __launch_bounds__(256) k_legendre(int64_t nside, int64_t lmax, int64_t mmax,
+                                                 const double* F, const double* lam_v,
+                                                 const int32_t* lam_e, const double* ring_z,
+                                                 int64_t nblk, double* part) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) +
+                       __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (wave >= (mmax + 1) * nblk) return;
+  const int64_t m = wave / nblk;
+  const int64_t blk = wave % nblk;
+  const int64_t npair = 2 * nside;
+  const int64_t nring = 4 * nside - 1;
+  const int64_t M = mmax + 1;
+  double z[kRingsPerLane], cur[kRingsPerLane], prev[kRingsPerLane];
+  double er[kRingsPerLane], ei[kRingsPerLane], orr[kRingsPerLane], oi[kRingsPerLane];
+  int32_t sc[kRingsPerLane];
+#pragma unroll
+  for (int k = 0; k < kRingsPerLane; ++k) {
+    const int64_t q = (blk * kRingsPerLane + k) * 64 + lane;   // pair index, 0-based
+    z[k] = 0.0;
+    cur[k] = 0.0;
+    prev[k] = 0.0;
+    er[k] = ei[k] = orr[k] = oi[k] = 0.0;
+    sc[k] = 0;
+    if (q < npair) {
+      const int64_t north = q + 1;
+      const int64_t south = nring + 1 - north;   // equal to north for the equator ring
+      const double* fn = F + 2 * ((north - 1) * M + m);
+      double sr = 0.0, si = 0.0;
+      if (south != north) {
+        const double* fs = F + 2 * ((south - 1) * M + m);
+        sr = fs[0];
+        si = fs[1];
+      }
+      er[k] = fn[0] + sr;
+      ei[k] = fn[1] + si;
+      orr[k] = fn[0] - sr;
+      oi[k] = fn[1] - si;
+      z[k] = ring_z[q];
+      cur[k] = lam_v[m * npair + q];
+      sc[k] = lam_e[m * npair + q];
+    }
+  }
+  const double big = ldexp(1.0, kLegScale);
+  double* out = part + 2 * blk * ((lmax + 1) * (lmax + 2) / 2);
+  for (int64_t l = m; l <= lmax; ++l) {
+    if (l > m) {
+      if (l == m + 1) {
+        const double a = sqrt(2.0 * m + 3.0);
+#pragma unroll
+        for (int k = 0; k < kRingsPerLane; ++k) {
+          prev[k] = cur[k];
+          cur[k] = a * z[k] * cur[k];
+        }
+      } else {
+        const double ll = (double)l, mmd = (double)m;
+        const double A = sqrt((4.0 * ll * ll - 1.0) / (ll * ll - mmd * mmd));
+        const double B = sqrt(((ll - 1.0) * (ll - 1.0) - mmd * mmd) /
+                              (4.0 * (ll - 1.0) * (ll - 1.0) - 1.0));
+#pragma unroll
+        for (int k = 0; k < kRingsPerLane; ++k) {
+          const double nx = A * (z[k] * cur[k] - B * prev[k]);
+          prev[k] = cur[k];
+          cur[k] = nx;
+        }
+      }
+      // Bring scaled values back once they have grown (growth over 16 steps
+      // stays far below the 2^423 headroom above 2^600).
+      if (((l - m) & 15) == 0) {
+#pragma unroll
+        for (int k = 0; k < kRingsPerLane; ++k) {
+          if (sc[k] < 0 && fabs(cur[k]) > big) {
+            cur[k] = ldexp(cur[k], -kLegScale);
+            prev[k] = ldexp(prev[k], -kLegScale);
+            sc[k] += 1;
+          }
+        }
+      }
+    }
+    const bool even = ((l + m) & 1) == 0;
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int k = 0; k < kRingsPerLane; ++k) {
+      const double lam = ldexp(cur[k], kLegScale * sc[k]);
+      sr = fma(lam, even ? er[k] : orr[k], sr);
+      si = fma(lam, even ? ei[k] : oi[k], si);
+    }
+    sr = wave_sum(sr);
+    si = wave_sum(si);
+    if (lane == 0) {
+      const int64_t idx = alm_idx(lmax, l, m);
+      out[2 * idx] = sr;
+      out[2 * idx + 1] = si;
+    }
+  }
+}
+
+// Step 3: a_lm = (4 pi / Npix) sum over blocks, in block order.
+__global__ void k_alm_sum(int64_t size, int64_t nblk, double w, const double* part, double* alm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= size) return;
+  double re = 0.0, im = 0.0;
+  for (int64_t b = 0; b < nblk; ++b) {
+    re += part[2 * (b * size + i)];
+    im += part[2 * (b * size + i) + 1];
+  }
+  alm[2 * i] = w * re;
+  alm[2 * i + 1] = w * im;
+}
+
+__global__ void k_alm2cl(int64_t lmax, const double* alm, double* cl) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l > lmax) return;
+  double acc = 0.0;
+  for (int64_t m = 0; m <= l; ++m) {
+    const int64_t i = alm_idx(lmax, l, m);
+    const double p = alm[2 * i] * alm[2 * i] + alm[2 * i + 1] * alm[2 * i + 1];
+    acc += (m == 0) ? p : 2.0 * p;
+  }
+  cl[l] = acc / (2.0 * (double)l + 1.0);
+}
+
+}  // namespace
+
+// Scratch needs of map2alm at (nside, lmax): bytes of the Fourier table,
+// the lambda_mm tables and the block partials.
+size_t map2alm_scratch_bytes(int64_t nside, int64_t lmax) {
+  const int64_t M = lmax + 1;
+  const int64_t nring = 4 * nside - 1, npair = 2 * nside;
+  const int64_t nblk = (npair + 64 * kRingsPerLane - 1) / (64 * kRingsPerLane);
+  const int64_t size = (lmax + 1) * (lmax + 2) / 2;
+  return sizeof(double) * (size_t)(2 * nring * M) + sizeof(double) * (size_t)(M * npair) +
+         sizeof(int32_t) * (size_t)(M * npair) + sizeof(double) * (size_t)npair +
+         sizeof(double) * (size_t)(2 * nblk * size) + 4 * 256;
+}
+
+// All of map2alm on `st`; `scratch` holds map2alm_scratch_bytes(nside, lmax).
+hipError_t launch_map2alm(int64_t nside, int64_t lmax, const double* map, double* alm,
+                          void* scratch, hipStream_t st) {
+  const int64_t M = lmax + 1;
+  const int64_t nring = 4 * nside - 1, npair = 2 * nside;
+  const int64_t nblk = (npair + 64 * kRingsPerLane - 1) / (64 * kRingsPerLane);
+  const int64_t size = (lmax + 1) * (lmax + 2) / 2;
+  auto align = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  char* p = (char*)scratch;
+  double* F = (double*)p;
+  p += align(sizeof(double) * (size_t)(2 * nring * M));
+  double* lam_v = (double*)p;
+  p += align(sizeof(double) * (size_t)(M * npair));
+  int32_t* lam_e = (int32_t*)p;
+  p += align(sizeof(int32_t) * (size_t)(M * npair));
+  double* ring_z = (double*)p;
+  p += align(sizeof(double) * (size_t)npair);
+  double* part = (double*)p;
+  const int64_t mblocks = (lmax + 64) / 64;
+  const int64_t dft_waves = nring * mblocks;
+  k_ring_dft<<<dim3((unsigned)((dft_waves + 3) / 4)), dim3(256), 0, st>>>(nside, lmax, map, F);
+  k_lambda_mm<<<dim3((unsigned)((npair + 255) / 256)), dim3(256), 0, st>>>(nside, lmax, lam_v,
+                                                                          lam_e, ring_z);
+  const int64_t leg_waves = M * nblk;
+  k_legendre<<<dim3((unsigned)((leg_waves + 3) / 4)), dim3(256), 0, st>>>(
+      nside, lmax, lmax, F, lam_v, lam_e, ring_z, nblk, part);
+  const double w = 4.0 * 3.14159265358979323846 / (double)(12 * nside * nside);
+  k_alm_sum<<<dim3((unsigned)((size + 255) / 256)), dim3(256), 0, st>>>(size, nblk, w, part,
+                                                                        alm);
+  return hipGetLastError();
+}
+
+hipError_t launch_alm2cl(int64_t lmax, const double* alm, double* cl, hipStream_t st) {
+  k_alm2cl<<<dim3((unsigned)((lmax + 256) / 256)), dim3(256), 0, st>>>(lmax, alm, cl);
+  return hipGetLastError();
+}
+
+}  // namespace csmap

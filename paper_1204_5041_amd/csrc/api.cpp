@@ -31,6 +31,10 @@ hipError_t launch_dir_table(int64_t nside, int64_t npix, double* x, double* y, d
 hipError_t launch_cone_events(int64_t n, int dtype, const void* x_rel, const void* xdot,
                               const double origin[3], double eta0, double eta_lo, double eta_hi,
                               double* pos, double* delta, uint8_t* keep, hipStream_t st);
+size_t map2alm_scratch_bytes(int64_t nside, int64_t lmax);
+hipError_t launch_map2alm(int64_t nside, int64_t lmax, const double* map, double* alm,
+                          void* scratch, hipStream_t st);
+hipError_t launch_alm2cl(int64_t lmax, const double* alm, double* cl, hipStream_t st);
 hipError_t launch_forward(bool fp64, int K, bool persistent, const FwdArgs& A, unsigned grid,
                           unsigned block, hipStream_t st);
 int forward_blocks_per_cu(bool fp64, bool frac, int K, unsigned block);
@@ -639,6 +643,33 @@ csmap_status csmap_add_box(csmap_sky* s, const csmap_box* box, int64_t* box_id) 
 
 csmap_status csmap_add_snapshot_box(csmap_sky* s, const csmap_box* box, int64_t* box_id) {
   return add_box_impl(s, box, 1, box_id);
+}
+
+csmap_status csmap_map2alm(int64_t nside, int64_t lmax, const double* map, double* alm,
+                           void* hip_stream) {
+  g_err.clear();
+  if (nside < 1 || nside > kMaxNside) return fail(CSMAP_E_INVALID, "nside must be in [1, 8192]");
+  if (lmax < 0 || lmax > 4 * nside) return fail(CSMAP_E_INVALID, "lmax must be in [0, 4 Nside]");
+  if (!map || !alm) return fail(CSMAP_E_INVALID, "map or alm is NULL");
+  hipStream_t st = (hipStream_t)hip_stream;
+  void* scratch = nullptr;
+  hipError_t e = hipMalloc(&scratch, map2alm_scratch_bytes(nside, lmax));
+  if (e != hipSuccess) return fail(CSMAP_E_NOMEM, "device allocation of map2alm scratch failed");
+  e = launch_map2alm(nside, lmax, map, alm, scratch, st);
+  const hipError_t e2 = hipStreamSynchronize(st);
+  (void)hipFree(scratch);
+  if (e != hipSuccess) return dev_fail(nullptr, e, "map2alm launch");
+  if (e2 != hipSuccess) return dev_fail(nullptr, e2, "map2alm");
+  return CSMAP_OK;
+}
+
+csmap_status csmap_alm2cl(int64_t lmax, const double* alm, double* cl, void* hip_stream) {
+  g_err.clear();
+  if (lmax < 0 || lmax > 4 * kMaxNside) return fail(CSMAP_E_INVALID, "lmax out of range");
+  if (!alm || !cl) return fail(CSMAP_E_INVALID, "alm or cl is NULL");
+  hipError_t e = launch_alm2cl(lmax, alm, cl, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return dev_fail(nullptr, e, "alm2cl launch");
+  return CSMAP_OK;
 }
 
 csmap_status csmap_cone_events(const csmap_box* box, double eta0, double* pos, double* delta,
