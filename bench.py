@@ -96,11 +96,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=40000)
     ap.add_argument("--workload", default="config2",
-                    choices=["config2", "config3", "config4", "events"],
+                    choices=["config2", "config3", "config4", "events", "alm"],
                     help="config2: the headline Nside=2048 line (default); config3: the "
                          "batched uneven 256-box Nside=4096 sky; config4: forward + adjoint at "
                          "Nside=1024; events: light-cone event recording from slab-start "
-                         "snapshots (25.6M segments)")
+                         "snapshots (25.6M segments); alm: spherical-harmonic analysis and "
+                         "C_l of a rendered Nside=2048 map, lmax=4096")
     ap.add_argument("--count-scale", type=float, default=1.0,
                     help="config3: scale of the per-box segment counts")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -121,6 +122,8 @@ def main():
         return bench_config4(args, B, torch)
     if args.workload == "events":
         return bench_events(args, B, torch)
+    if args.workload == "alm":
+        return bench_alm(args, B, torch)
 
     if args.copy_calib_mib > 0:
         n = args.copy_calib_mib * (1 << 20) // 4
@@ -355,6 +358,39 @@ def bench_events(args, B, torch):
     res["accuracy_vs_oracle"] = {"segments": int(sel.size),
                                  "keep_mismatches": int(np.sum(k != rk)),
                                  "max_abs_delta_error": float(np.max(np.abs(dd[both] - rd[both])))}
+    print(json.dumps(res), flush=True)
+
+
+def bench_alm(args, B, torch):
+    """Angular power spectrum of a string map: the FP32C map of one 400,000-
+    segment box at Nside=2048 (rendered first, not timed), then a_lm up to
+    lmax = 4096 = 2 Nside and C_l, timed over the whole call (scratch
+    allocation included).  Algorithmic work: 4 FLOP per (pixel, m) for the
+    ring Fourier sums and 8 FLOP per (l, m, ring pair) for the Legendre sums,
+    in FP64."""
+    nside, lmax = NSIDE, 2 * NSIDE
+    sky, _ = make_sky(B, torch, 0, B.CSMAP_FORM_FP32C, args.nseg, nside)
+    hmap = sky.render()
+    torch.cuda.synchronize()
+    alm = B.map2alm(hmap, lmax)                      # warm-up
+    torch.cuda.synchronize()
+    K = max(1, args.steps)
+    t0 = time.perf_counter()
+    for _ in range(K):
+        alm = B.map2alm(hmap, lmax)
+        cl = B.alm2cl(alm, lmax)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / K
+    npix = 12 * nside * nside
+    size = (lmax + 1) * (lmax + 2) // 2
+    flop = 4.0 * npix * (lmax + 1) + 8.0 * (2 * nside) * size
+    tf = flop / el / 1e12
+    c = cl.cpu().numpy()
+    res = {"metric": "map2alm + alm2cl at Nside=2048, lmax=4096 (s per call)", "value": el,
+           "unit": "s", "higher_is_better": False, "alm_per_s": size / el,
+           "roofline": {"bound": "alu", "achieved": tf, "peak": FP64_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": tf / FP64_PEAK_TFLOPS, "flop": flop},
+           "cl_sample": {str(l): float(c[l]) for l in (2, 10, 100, 1000, 4000)}}
     print(json.dumps(res), flush=True)
 
 

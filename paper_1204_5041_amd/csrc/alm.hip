@@ -72,9 +72,13 @@ __device__ __forceinline__ void twiddle(int64_t t, int64_t L, double& c, double&
 
 // Step 1: F[(i-1) M + m] = sum_j map_{i,j} e^{-i m phi_j}, M = mmax + 1.
 // One wavefront per (ring, 64 consecutive m); the ring's pixel values are
-// uniform across the wavefront and stream through scalar registers; each
-// lane advances e^{-i m 2 pi j / L} by one complex multiplication per pixel
-// and recomputes it exactly every kAnchor pixels.
+// uniform across the wavefront and stream through scalar registers.  Ring
+// lengths are multiples of 4, and pixels j, j + L/4, j + L/2, j + 3L/4 see
+// the twiddle of pixel j times (-i)^m, (-1)^m, i^m: the four values are
+// folded first (x0 + x2, x1 + x3, x0 - x2, x3 - x1 combine into the real and
+// imaginary parts for m mod 4), so one complex twiddle serves four pixels.
+// Each lane advances e^{-i m 2 pi j / L} by one complex multiplication per
+// step and recomputes it exactly every kAnchor steps.
 __global__ void __launch_bounds__(256) k_ring_dft(int64_t nside, int64_t mmax, const double* map,
                                                  double* F) {
   const int lane = threadIdx.x & 63;
@@ -87,19 +91,30 @@ __global__ void __launch_bounds__(256) k_ring_dft(int64_t nside, int64_t mmax, c
   const int64_t m = (wave % mblocks) * 64 + lane;
   const Ring r = ring_of(nside, i);
   const int64_t L = r.len;
+  const int64_t Q = L / 4;
   const int64_t mm = m % L;                 // e^{-i m 2pi j/L} depends on m mod L only
   double oc, os;                            // e^{-i 2 pi m / L}
   twiddle((2 * mm) % (2 * L), L, oc, os);
+  // The folded value of a quadruple for this lane's m mod 4:
+  //   re = ca (x0 + x2) + cb (x1 + x3) + cc (x0 - x2),  im = cd (x3 - x1).
+  const int q4 = (int)(m & 3);
+  const double ca = (q4 & 1) ? 0.0 : 1.0;
+  const double cb = (q4 == 0) ? 1.0 : (q4 == 2 ? -1.0 : 0.0);
+  const double cc = (q4 & 1) ? 1.0 : 0.0;
+  const double cd = (q4 == 1) ? 1.0 : (q4 == 3 ? -1.0 : 0.0);
   double acc_re = 0.0, acc_im = 0.0;
   cdp px = (cdp)(map + r.first);
-  for (int64_t j0 = 0; j0 < L; j0 += kAnchor) {
+  for (int64_t j0 = 0; j0 < Q; j0 += kAnchor) {
     double wc, ws;
-    twiddle((2 * mm * (j0 % L)) % (2 * L), L, wc, ws);
-    const int64_t je = (j0 + kAnchor < L) ? j0 + kAnchor : L;
+    twiddle((2 * mm * j0) % (2 * L), L, wc, ws);
+    const int64_t je = (j0 + kAnchor < Q) ? j0 + kAnchor : Q;
     for (int64_t j = j0; j < je; ++j) {
-      const double v = px[j];
-      acc_re = fma(v, wc, acc_re);
-      acc_im = fma(v, ws, acc_im);
+      const double x0 = px[j], x1 = px[j + Q], x2 = px[j + 2 * Q], x3 = px[j + 3 * Q];
+      const double s02 = x0 + x2, s13 = x1 + x3, d02 = x0 - x2, d31 = x3 - x1;
+      const double fr = fma(ca, s02, fma(cb, s13, cc * d02));
+      const double fi = cd * d31;
+      acc_re = fma(fr, wc, fma(-fi, ws, acc_re));
+      acc_im = fma(fr, ws, fma(fi, wc, acc_im));
       const double nc = fma(wc, oc, -(ws * os));
       const double ns = fma(wc, os, ws * oc);
       wc = nc;
