@@ -369,7 +369,7 @@ def cone_events(x_rel, xdot, origin, eta0: float, eta_lo: float, eta_hi: float, 
     st = stream if stream is not None else torch.cuda.current_stream()
     csmap_cone_events(b, eta0, pos.data_ptr() if n else None, delta.data_ptr() if n else None,
                       keep.data_ptr() if n else None, st.cuda_stream)
-    return pos, delta, keep.bool()
+    return pos, delta, keep.view(torch.bool)
 
 
 def alm_size(lmax: int) -> int:

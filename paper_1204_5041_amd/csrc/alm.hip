@@ -166,6 +166,27 @@ __global__ void k_lambda_mm(int64_t nside, int64_t mmax, double* lam_v, int32_t*
   }
 }
 
+// Step 2a': the recursion coefficients of every (l, m), l > m, at a_lm's
+// position: coef[2 i] = A_lm, coef[2 i + 1] = B_lm (B = 0 and A = sqrt(2m+3)
+// at l = m + 1); one thread per m.
+__global__ void k_leg_coef(int64_t lmax, double* coef) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m > lmax) return;
+  const double mmd = (double)m;
+  for (int64_t l = m + 1; l <= lmax; ++l) {
+    const int64_t i = alm_idx(lmax, l, m);
+    if (l == m + 1) {
+      coef[2 * i] = sqrt(2.0 * mmd + 3.0);
+      coef[2 * i + 1] = 0.0;
+    } else {
+      const double ll = (double)l;
+      coef[2 * i] = sqrt((4.0 * ll * ll - 1.0) / (ll * ll - mmd * mmd));
+      coef[2 * i + 1] = sqrt(((ll - 1.0) * (ll - 1.0) - mmd * mmd) /
+                             (4.0 * (ll - 1.0) * (ll - 1.0) - 1.0));
+    }
+  }
+}
+
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off);
@@ -178,7 +199,7 @@ __device__ __forceinline__ double wave_sum(double x) {
 __global__ void __launch_bounds__(256) k_legendre(int64_t nside, int64_t lmax, int64_t mmax,
                                                  const double* F, const double* lam_v,
                                                  const int32_t* lam_e, const double* ring_z,
-                                                 int64_t nblk, double* part) {
+                                                 const double* coef, int64_t nblk, double* part) {
   const int lane = threadIdx.x & 63;
   const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) +
                        __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -220,41 +241,21 @@ __global__ void __launch_bounds__(256) k_legendre(int64_t nside, int64_t lmax, i
   }
   const double big = ldexp(1.0, kLegScale);
   double* out = part + 2 * blk * ((lmax + 1) * (lmax + 2) / 2);
-  for (int64_t l = m; l <= lmax; ++l) {
-    if (l > m) {
-      if (l == m + 1) {
-        const double a = sqrt(2.0 * m + 3.0);
+  cdp cf = (cdp)coef;
+  // lambda_{l,m} from lambda_{l-1,m} (cur) and lambda_{l-2,m} (prev).
+  auto step = [&](int64_t l) {
+    const int64_t i = alm_idx(lmax, l, m);
+    const double A = cf[2 * i], Bc = cf[2 * i + 1];
 #pragma unroll
-        for (int k = 0; k < kRingsPerLane; ++k) {
-          prev[k] = cur[k];
-          cur[k] = a * z[k] * cur[k];
-        }
-      } else {
-        const double ll = (double)l, mmd = (double)m;
-        const double A = sqrt((4.0 * ll * ll - 1.0) / (ll * ll - mmd * mmd));
-        const double B = sqrt(((ll - 1.0) * (ll - 1.0) - mmd * mmd) /
-                              (4.0 * (ll - 1.0) * (ll - 1.0) - 1.0));
-#pragma unroll
-        for (int k = 0; k < kRingsPerLane; ++k) {
-          const double nx = A * (z[k] * cur[k] - B * prev[k]);
-          prev[k] = cur[k];
-          cur[k] = nx;
-        }
-      }
-      // Bring scaled values back once they have grown (growth over 16 steps
-      // stays far below the 2^423 headroom above 2^600).
-      if (((l - m) & 15) == 0) {
-#pragma unroll
-        for (int k = 0; k < kRingsPerLane; ++k) {
-          if (sc[k] < 0 && fabs(cur[k]) > big) {
-            cur[k] = ldexp(cur[k], -kLegScale);
-            prev[k] = ldexp(prev[k], -kLegScale);
-            sc[k] += 1;
-          }
-        }
-      }
+    for (int k = 0; k < kRingsPerLane; ++k) {
+      const double nx = A * (z[k] * cur[k] - Bc * prev[k]);
+      prev[k] = cur[k];
+      cur[k] = nx;
     }
-    const bool even = ((l + m) & 1) == 0;
+  };
+  // a_lm's partial for this block: (F_north + F_south) for even l + m,
+  // (F_north - F_south) for odd.
+  auto emit = [&](int64_t l, bool even) {
     double sr = 0.0, si = 0.0;
 #pragma unroll
     for (int k = 0; k < kRingsPerLane; ++k) {
@@ -268,6 +269,29 @@ __global__ void __launch_bounds__(256) k_legendre(int64_t nside, int64_t lmax, i
       const int64_t idx = alm_idx(lmax, l, m);
       out[2 * idx] = sr;
       out[2 * idx + 1] = si;
+    }
+  };
+  emit(m, true);
+  // Two degrees per iteration, so the parity of l + m is fixed at compile
+  // time in each half.
+  for (int64_t l = m + 1; l <= lmax; l += 2) {
+    // Bring scaled values back once they have grown (growth over 16 steps
+    // stays far below the 2^423 headroom above 2^600).
+    if (((l - m - 1) & 15) == 0) {
+#pragma unroll
+      for (int k = 0; k < kRingsPerLane; ++k) {
+        if (sc[k] < 0 && fabs(cur[k]) > big) {
+          cur[k] = ldexp(cur[k], -kLegScale);
+          prev[k] = ldexp(prev[k], -kLegScale);
+          sc[k] += 1;
+        }
+      }
+    }
+    step(l);
+    emit(l, false);
+    if (l + 1 <= lmax) {
+      step(l + 1);
+      emit(l + 1, true);
     }
   }
 }
@@ -285,16 +309,21 @@ __global__ void k_alm_sum(int64_t size, int64_t nblk, double w, const double* pa
   alm[2 * i + 1] = w * im;
 }
 
-__global__ void k_alm2cl(int64_t lmax, const double* alm, double* cl) {
-  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// C_l: one wavefront per l, lanes stride over m, then a fixed-order
+// wavefront sum.
+__global__ void __launch_bounds__(256) k_alm2cl(int64_t lmax, const double* alm, double* cl) {
+  const int lane = threadIdx.x & 63;
+  const int64_t l = (int64_t)blockIdx.x * (blockDim.x >> 6) +
+                    __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (l > lmax) return;
   double acc = 0.0;
-  for (int64_t m = 0; m <= l; ++m) {
+  for (int64_t m = lane; m <= l; m += 64) {
     const int64_t i = alm_idx(lmax, l, m);
     const double p = alm[2 * i] * alm[2 * i] + alm[2 * i + 1] * alm[2 * i + 1];
     acc += (m == 0) ? p : 2.0 * p;
   }
-  cl[l] = acc / (2.0 * (double)l + 1.0);
+  acc = wave_sum(acc);
+  if (lane == 0) cl[l] = acc / (2.0 * (double)l + 1.0);
 }
 
 }  // namespace
@@ -308,7 +337,8 @@ size_t map2alm_scratch_bytes(int64_t nside, int64_t lmax) {
   const int64_t size = (lmax + 1) * (lmax + 2) / 2;
   return sizeof(double) * (size_t)(2 * nring * M) + sizeof(double) * (size_t)(M * npair) +
          sizeof(int32_t) * (size_t)(M * npair) + sizeof(double) * (size_t)npair +
-         sizeof(double) * (size_t)(2 * nblk * size) + 4 * 256;
+         sizeof(double) * (size_t)(2 * size) + sizeof(double) * (size_t)(2 * nblk * size) +
+         6 * 256;
 }
 
 // All of map2alm on `st`; `scratch` holds map2alm_scratch_bytes(nside, lmax).
@@ -328,15 +358,18 @@ hipError_t launch_map2alm(int64_t nside, int64_t lmax, const double* map, double
   p += align(sizeof(int32_t) * (size_t)(M * npair));
   double* ring_z = (double*)p;
   p += align(sizeof(double) * (size_t)npair);
+  double* coef = (double*)p;
+  p += align(sizeof(double) * (size_t)(2 * size));
   double* part = (double*)p;
   const int64_t mblocks = (lmax + 64) / 64;
   const int64_t dft_waves = nring * mblocks;
   k_ring_dft<<<dim3((unsigned)((dft_waves + 3) / 4)), dim3(256), 0, st>>>(nside, lmax, map, F);
   k_lambda_mm<<<dim3((unsigned)((npair + 255) / 256)), dim3(256), 0, st>>>(nside, lmax, lam_v,
                                                                           lam_e, ring_z);
+  k_leg_coef<<<dim3((unsigned)((M + 63) / 64)), dim3(64), 0, st>>>(lmax, coef);
   const int64_t leg_waves = M * nblk;
   k_legendre<<<dim3((unsigned)((leg_waves + 3) / 4)), dim3(256), 0, st>>>(
-      nside, lmax, lmax, F, lam_v, lam_e, ring_z, nblk, part);
+      nside, lmax, lmax, F, lam_v, lam_e, ring_z, coef, nblk, part);
   const double w = 4.0 * 3.14159265358979323846 / (double)(12 * nside * nside);
   k_alm_sum<<<dim3((unsigned)((size + 255) / 256)), dim3(256), 0, st>>>(size, nblk, w, part,
                                                                         alm);
@@ -344,7 +377,7 @@ hipError_t launch_map2alm(int64_t nside, int64_t lmax, const double* map, double
 }
 
 hipError_t launch_alm2cl(int64_t lmax, const double* alm, double* cl, hipStream_t st) {
-  k_alm2cl<<<dim3((unsigned)((lmax + 256) / 256)), dim3(256), 0, st>>>(lmax, alm, cl);
+  k_alm2cl<<<dim3((unsigned)((lmax + 4) / 4)), dim3(256), 0, st>>>(lmax, alm, cl);
   return hipGetLastError();
 }
 
