@@ -62,6 +62,7 @@ def lib() -> ctypes.CDLL:
         _lib.oracle_map2alm.argtypes = [i64, i64, f64p, f64p, f64p]
         _lib.oracle_map2alm_m.argtypes = [i64, i64, i64, f64p, f64p, f64p]
         _lib.oracle_alm2cl.argtypes = [i64, f64p, f64p, f64p]
+        _lib.oracle_ang2pix_many.argtypes = [i64, i64, f64p, i64p]
         _lib.oracle_cone_events.argtypes = [i64, f64p, f64p, f64p, ctypes.c_double,
                                             ctypes.c_double, ctypes.c_double, f64p, f64p, u8p]
         _lib.oracle_theta_dirs.argtypes = [i64, f64p, ctypes.c_double, i64, f64p, i64p,
@@ -295,3 +296,28 @@ def map2alm_m(nside: int, lmax: int, m: int, hmap) -> np.ndarray:
     lib().oracle_map2alm_m(nside, lmax, m, _p(mp, ctypes.c_double), _p(re, ctypes.c_double),
                            _p(im, ctypes.c_double))
     return re + 1j * im
+
+
+def ang2pix(nside: int, vecs) -> np.ndarray:
+    """HEALPix RING pixel of each direction (n,3) (any positive length)."""
+    v = _f64(vecs).reshape(-1, 3)
+    out = np.empty(v.shape[0], dtype=np.int64)
+    lib().oracle_ang2pix_many(nside, v.shape[0], _p(v, ctypes.c_double), _p(out, ctypes.c_int64))
+    return out
+
+
+def place_segments(x_rel, xdot, xprime, rot, origin):
+    """Segments of a rotated simulation box in the sky frame (Sec. II.C: a
+    box is turned so that its photons travel towards the observer):
+    P = origin + R x_rel, Xdot -> R Xdot, X' -> R X' (FP64; R row-major 3x3,
+    box coordinates to sky coordinates)."""
+    R = _f64(rot).reshape(3, 3)
+    P = _f64(origin).reshape(1, 3) + _f64(x_rel).reshape(-1, 3) @ R.T
+    return P, _f64(xdot).reshape(-1, 3) @ R.T, _f64(xprime).reshape(-1, 3) @ R.T
+
+
+def in_cone(nside_c: int, cone: int, P) -> np.ndarray:
+    """True where the position P lies inside the healpix cone `cone` of the
+    Nside_c stacking grid (Sec. II.C: a box keeps only the strings inside
+    its cone), i.e. where its direction falls in that RING pixel."""
+    return ang2pix(nside_c, P) == cone

@@ -674,3 +674,61 @@ void oracle_alm2cl(int64_t lmax, const double *alm_re, const double *alm_im, dou
         cl[l] = (acc.sum + acc.comp) / (2.0 * (double)l + 1.0);
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* HEALPix RING pixel of a direction (the inverse of pix2vec), used to keep  */
+/* the strings that live inside a healpix cone when simulations are stacked  */
+/* (Sec. II.C: the comoving ball is cut into cones subtending the pixels of  */
+/* a coarse healpix grid, and every box keeps only the strings of its cone).  */
+/* The published construction (Gorski et al. 2005): with z = cos(theta) and  */
+/* t = phi / (pi/2) in [0, 4),                                              */
+/*   |z| <= 2/3: the pixel edges are the lines N (1/2 + t) -+ (3N/4) z =    */
+/*               integer; with a, b the integer parts of those two values,   */
+/*               the ring (counted from z = 2/3) is N + 1 + a - b and the    */
+/*               position in it (a + b - N + shift + 1) / 2 mod 4N;         */
+/*   |z| >  2/3: with s = N sqrt(3 (1 - |z|)) and f the fraction of t, the   */
+/*               ring counted from the pole is floor(f s) + floor((1-f) s)   */
+/*               + 1 and the position floor(t ring) mod 4 ring.             */
+/* 1 - |z| is taken as (x^2 + y^2) / (r (r + |z_v|)) for a vector (x, y, z_v) */
+/* of length r, which keeps its accuracy near the poles.                     */
+/* ------------------------------------------------------------------------ */
+int64_t oracle_ang2pix(int64_t nside, const double v[3])
+{
+    const int64_t N = nside;
+    const double rho2 = v[0] * v[0] + v[1] * v[1];
+    const double r = sqrt(rho2 + v[2] * v[2]);
+    const double z = v[2] / r;
+    double phi = atan2(v[1], v[0]);
+    if (phi < 0.0) phi += 2.0 * ORACLE_PI;
+    double t = phi / (0.5 * ORACLE_PI);
+    if (t >= 4.0) t -= 4.0;
+    const double az = fabs(z);
+    if (az <= 2.0 / 3.0) {
+        const double t1 = (double)N * (0.5 + t);
+        const double t2 = (double)N * z * 0.75;
+        const int64_t a = (int64_t)(t1 - t2);
+        const int64_t b = (int64_t)(t1 + t2);
+        const int64_t ring = N + 1 + a - b;                 /* 1 .. 2N+1 */
+        const int64_t shift = 1 - (ring & 1);
+        int64_t pos = (a + b - N + shift + 1) / 2;
+        pos = ((pos % (4 * N)) + 4 * N) % (4 * N);
+        return 2 * N * (N - 1) + (ring - 1) * 4 * N + pos;
+    }
+    const double f = t - floor(t);
+    const double one_minus = rho2 / (r * (r + fabs(v[2])));
+    const double s = (double)N * sqrt(3.0 * one_minus);
+    const int64_t a = (int64_t)(f * s);
+    const int64_t b = (int64_t)((1.0 - f) * s);
+    int64_t ring = a + b + 1;                               /* from the pole */
+    if (ring > N) ring = N;                                 /* |z| just above 2/3 */
+    int64_t pos = (int64_t)(t * (double)ring);
+    pos = ((pos % (4 * ring)) + 4 * ring) % (4 * ring);
+    if (z > 0.0) return 2 * ring * (ring - 1) + pos;
+    return 12 * N * N - 2 * ring * (ring + 1) + pos;
+}
+
+void oracle_ang2pix_many(int64_t nside, int64_t n, const double *v, int64_t *pix)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) pix[i] = oracle_ang2pix(nside, v + 3 * i);
+}
