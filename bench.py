@@ -96,12 +96,16 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=40000)
     ap.add_argument("--workload", default="config2",
-                    choices=["config2", "config3", "config4", "events", "alm"],
+                    choices=["config2", "config3", "config4", "events", "alm", "stack"],
                     help="config2: the headline Nside=2048 line (default); config3: the "
                          "batched uneven 256-box Nside=4096 sky; config4: forward + adjoint at "
                          "Nside=1024; events: light-cone event recording from slab-start "
                          "snapshots (25.6M segments); alm: spherical-harmonic analysis and "
-                         "C_l of a rendered Nside=2048 map, lmax=4096")
+                         "C_l of a rendered Nside=2048 map, lmax=4096; stack: healpix-cone "
+                         "stacking of 1024 runs x 3 axes into the 3072 Nside_c=16 cones plus "
+                         "12 Nside_c=1 cones (light-cone stage of 3084 placed boxes)")
+    ap.add_argument("--stack-seg", type=int, default=200_000,
+                    help="stack: segments per simulation run")
     ap.add_argument("--count-scale", type=float, default=1.0,
                     help="config3: scale of the per-box segment counts")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -124,6 +128,8 @@ def main():
         return bench_events(args, B, torch)
     if args.workload == "alm":
         return bench_alm(args, B, torch)
+    if args.workload == "stack":
+        return bench_stack(args, B, torch)
 
     if args.copy_calib_mib > 0:
         n = args.copy_calib_mib * (1 << 20) // 4
@@ -358,6 +364,99 @@ def bench_events(args, B, torch):
     res["accuracy_vs_oracle"] = {"segments": int(sel.size),
                                  "keep_mismatches": int(np.sum(k != rk)),
                                  "max_abs_delta_error": float(np.max(np.abs(dd[both] - rd[both])))}
+    print(json.dumps(res), flush=True)
+
+
+STACK_RAW_BYTES = 40    # FP32 x_rel, Xdot, X', dsigma read once per placed segment
+STACK_REC_BYTES = 100   # per kept segment: 64-byte record, FP64 direction + R, index
+
+
+def bench_stack(args, B, torch):
+    """Healpix-cone stacking: the 3072 cones of the Nside_c=16 grid between
+    z=1089 and z=36 filled by 1024 runs used three times each (one per box
+    axis), plus the 12 Nside_c=1 cones down to z=0.2, every run holding
+    --stack-seg FP32 segments in its own box coordinates.  Each box is
+    placed by csmap_cone_place and added with csmap_add_cone_box; one step
+    is the light-cone stage of all 3084 boxes (csmap_precompute): rotation
+    onto the sky in FP64, slab test, cone test (device ang2pix), compaction
+    and record emission.  It streams 40 bytes per placed segment and writes
+    100 bytes per kept one, so its bound is HBM bandwidth."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    import synth
+    plans = [synth.stack_highz(args.stack_seg), synth.stack_lowz(args.stack_seg)]
+    sky = B.Sky(16, plans[0].eta0, B.CSMAP_FORM_FP32C)
+    t0 = time.perf_counter()
+    runs_host = {}
+    nbox = 0
+    for p in plans:
+        _log(f"bench stack: generating {p.nruns} runs of {p.seg_per_run:,} segments ({p.name})")
+        with ThreadPoolExecutor(16) as ex:
+            data = list(ex.map(lambda r: p.run(r), range(p.nruns)))
+        dev = [[torch.from_numpy(a).cuda() for a in d] for d in data]
+        runs_host[p.name] = data[:48]
+        del data
+        for cone, r, axis in p.uses:
+            c, origin, slack = B.cone_place(p.nside_c, cone, axis, p.r_in, p.r_out, p.side)
+            assert slack >= 0, (p.name, cone)
+            sky.add_box(*dev[r], origin=tuple(origin), eta_lo=p.eta_lo, eta_hi=p.eta_hi, cone=c)
+            nbox += 1
+        torch.cuda.synchronize()
+        del dev
+    t_add = time.perf_counter() - t0
+    nseg = sum(len(p.uses) for p in plans) * args.stack_seg
+    _log(f"bench stack: {nbox} boxes, {nseg:,} placed segments, set-up {t_add:.1f} s")
+    for _ in range(max(1, args.warmup)):
+        sky.precompute()
+    torch.cuda.synchronize()
+    K = max(1, args.steps)
+    kern, walls = [], []
+    for _ in range(K):
+        w0 = time.perf_counter()
+        sky.precompute()
+        st = sky.stats()   # synchronises
+        walls.append(time.perf_counter() - w0)
+        kern.append(st["ms_precompute"] / 1e3)
+    kept = st["kept"]
+    k_avg = sum(kern) / K
+    byts = STACK_RAW_BYTES * nseg + STACK_REC_BYTES * kept
+    gbs = byts / k_avg / 1e9
+    hz = plans[0]
+    share = (4 * np.pi / (12 * hz.nside_c ** 2)) * (hz.r_out ** 3 - hz.r_in ** 3) / 3 / hz.side ** 3
+    res = {"metric": "placed segments per second through healpix-cone stacking (segments/s)",
+           "value": nseg / k_avg, "unit": "segments/s", "n_gpus": 1, "steps": K,
+           "warmup": args.warmup, "ms_per_step": k_avg * 1e3,
+           "wall_ms_per_step": 1e3 * sum(walls) / K, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64 geometry, fp32 records",
+           "data": "synthetic", "setup_s": t_add,
+           "config": {"workload": "healpix-cone stacking: 3072 Nside_c=16 cones (1024 runs x 3 "
+                                  "axes) + 12 Nside_c=1 cones", "boxes": nbox,
+                      "segments_per_run": args.stack_seg, "placed_segments": nseg,
+                      "kept": kept, "kept_expected_high_z_share": share},
+           "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                        "bytes": f"{STACK_RAW_BYTES} per placed + {STACK_REC_BYTES} per kept"}}
+    if not args.no_cpu:
+        # The oracle's placement and cone test on the first uses of the
+        # high-z plan (runs 0..47, three axes each): its rate on this host.
+        sample = [u for u in hz.uses if u[1] < 48]
+        t0 = time.perf_counter()
+        kept_cpu = 0
+        for cone, r, axis in sample:
+            x, xd, xp, ds = runs_host[hz.name][r]
+            R, origin = oracle.cone_frame(hz.nside_c, cone, axis, hz.r_out, hz.side)
+            P, V, T = oracle.place_segments(x, xd, xp, R, origin)
+            rr = np.sqrt((P[:, 0] * P[:, 0] + P[:, 1] * P[:, 1]) + P[:, 2] * P[:, 2])
+            eta = hz.eta0 - rr
+            keep = (eta >= hz.eta_lo) & (eta < hz.eta_hi) & oracle.in_cone(hz.nside_c, cone, P)
+            kept_cpu += int(keep.sum())
+        dt = time.perf_counter() - t0
+        n_cpu = len(sample) * args.stack_seg
+        res["cpu_baseline"] = {"value": n_cpu / dt, "unit": "segments/s",
+                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": f"{len(sample)} placed boxes (runs 0-47 x 3 axes), "
+                                         f"{n_cpu:,} segments, {kept_cpu:,} kept, {dt:.1f} s"}
+    sky.close()
     print(json.dumps(res), flush=True)
 
 

@@ -221,6 +221,75 @@ csmap_status csmap_add_snapshot_box(csmap_sky *sky, const csmap_box *box, int64_
 csmap_status csmap_cone_events(const csmap_box *box, double eta0, double *pos, double *delta,
                                uint8_t *keep, void *hip_stream);
 
+/* Placement of a simulation box in one healpix cone of a stacking grid
+ * (Sec. II.C, Fig. 1: the comoving ball between two redshifts is cut into
+ * cones subtending the pixels of a coarse HEALPix grid, each filled by a
+ * rotated simulation box, and only the strings inside a box's cone count). */
+typedef struct {
+    int64_t nside;          /* Nside of the stacking grid, 1 .. 8192; 0: rotation only */
+    int64_t pix;            /* RING pixel of the cone, 0 .. 12 nside^2 - 1 */
+    double rot[9];          /* row-major rotation, box coordinates to sky:
+                               P = origin + rot x_rel, Xdot -> rot Xdot, X' -> rot X';
+                               orthonormal with determinant +1 (to 1e-9) */
+} csmap_cone;
+
+/* Add one box of a stacked simulation (Sec. II.C).  x_rel, xdot and xprime
+ * are in the box's own coordinates; the box is turned onto the sky by
+ * cone->rot (in FP64, per segment, by the light-cone stage of render) and
+ * placed at box->origin, and only events whose position P lies in RING pixel
+ * cone->pix of the Nside cone->nside grid are kept, besides the slab test.
+ * snapshot = 0: the arrays hold events on the light cone, as csmap_add_box;
+ * snapshot = 1: they hold slab-start segments, as csmap_add_snapshot_box
+ * (the crossing is found after the rotation, and the cone test applies to
+ * the event).  CSMAP_VIS_BOX is rejected (CSMAP_E_UNSUPPORTED; its box is
+ * axis-aligned in the sky frame).  csmap_backward returns gradients with
+ * respect to the box-frame arrays.  Arrays are copied as by csmap_add_box. */
+csmap_status csmap_add_cone_box(csmap_sky *sky, const csmap_box *box, const csmap_cone *cone,
+                                int snapshot, int64_t *box_id);
+
+/* Run the light-cone stage of render on its own: every box's segments are
+ * placed (rotation for cone boxes), tested against the slab and the cone,
+ * and the kept ones written as the records the pair kernels read.  Enqueued
+ * on the sky's stream; csmap_get_stats then reports `kept` and, as
+ * ms_precompute, the device time of this stage (ms_forward 0).  Render
+ * repeats the stage itself, so this call is only needed to inspect or time
+ * it. */
+csmap_status csmap_precompute(csmap_sky *sky);
+
+/* RING pixel of each of n directions (Gorski et al. 2005; the inverse of
+ * csmap_pix2vec_ring) at Nside in [1, 8192]: xyz is a device array of n x 3
+ * doubles (vectors of any positive, finite length), pix a device array of n
+ * int64 owned by the caller.  The same device routine makes the cone test of
+ * csmap_add_cone_box.  Enqueued on hip_stream. */
+csmap_status csmap_ang2pix_ring(int64_t nside, int64_t n, const double *xyz, int64_t *pix,
+                                void *hip_stream);
+
+/* Host-side helper, no device work: placement of a cubic box of side `side`
+ * in cone `pix` of the Nside stacking grid for the shell
+ * r_in <= |P| <= r_out (Sec. II.C: photons face the observer, the farthest
+ * pixel fits in the farthest face).  Box axis `axis` (0, 1 or 2; one run is
+ * used three times, once per axis) points out along the cone axis n (the
+ * pixel centre), so photons travelling along -axis in the box travel
+ * towards the observer; the other two axes follow (e_theta + e_phi)/sqrt(2)
+ * and (e_phi - e_theta)/sqrt(2) at the pixel centre, in cyclic order (a
+ * right-handed frame).  The far face (x_axis = side) is the plane
+ * n.P = r_out, centred on the axis.  Writes cone->nside, cone->pix and
+ * cone->rot, origin[3] (where box coordinate 0 lands), and *slack: the
+ * smallest margin, in length units, of the conditions that put the whole
+ * truncated cone inside the box (lateral half-width minus r_out times the
+ * pixel's largest transverse extent, and r_in times its smallest cosine from
+ * the axis minus the near face's distance), computed from 257 points on
+ * each edge of the pixel's closed-form boundary; slack >= 0 means the cone
+ * fits.  0 < r_in < r_out, side > 0. */
+csmap_status csmap_cone_place(int64_t nside, int64_t pix, int axis, double r_in, double r_out,
+                              double side, csmap_cone *cone, double origin[3], double *slack);
+
+/* Host-side helper, no device work: the smallest Nside (a power of two, at
+ * most 256) whose every cone fits a box of side `side` for the shell
+ * r_in .. r_out by the test of csmap_cone_place (the largest healpix cone
+ * fitting inside the box, Sec. II.C); *nside = 0 if none does. */
+csmap_status csmap_cone_min_nside(double r_in, double r_out, double side, int64_t *nside);
+
 /* Evaluate Theta/GU (Eq. (1)) at every RING pixel centre from all boxes
  * added so far and write it to map (device, 12 Nside^2 doubles, RING order).
  * Each pixel's value is its own sum; results are deterministic for a given

@@ -312,8 +312,15 @@ def place_segments(x_rel, xdot, xprime, rot, origin):
     P = origin + R x_rel, Xdot -> R Xdot, X' -> R X' (FP64; R row-major 3x3,
     box coordinates to sky coordinates)."""
     R = _f64(rot).reshape(3, 3)
-    P = _f64(origin).reshape(1, 3) + _f64(x_rel).reshape(-1, 3) @ R.T
-    return P, _f64(xdot).reshape(-1, 3) @ R.T, _f64(xprime).reshape(-1, 3) @ R.T
+    o = _f64(origin).reshape(3)
+
+    def turn(a):
+        # row k of R times a, summed left to right with separate roundings
+        a = _f64(a).reshape(-1, 3)
+        return np.stack([(R[k, 0] * a[:, 0] + R[k, 1] * a[:, 1]) + R[k, 2] * a[:, 2]
+                         for k in range(3)], axis=1)
+
+    return o[None, :] + turn(x_rel), turn(xdot), turn(xprime)
 
 
 def in_cone(nside_c: int, cone: int, P) -> np.ndarray:
@@ -321,3 +328,30 @@ def in_cone(nside_c: int, cone: int, P) -> np.ndarray:
     Nside_c stacking grid (Sec. II.C: a box keeps only the strings inside
     its cone), i.e. where its direction falls in that RING pixel."""
     return ang2pix(nside_c, P) == cone
+
+
+def cone_frame(nside_c: int, cone: int, axis: int, r_out: float, side: float):
+    """Frame of a cubic box of side `side` placed in healpix cone `cone`
+    (Sec. II.C, Fig. 1), as (R (3,3) box-to-sky, origin (3,)):
+      * photons must travel towards the observer: box axis `axis` points out
+        along the cone axis n (the pixel centre), photons moving along -axis;
+      * the farthest pixel must fit in the farthest face: the far face
+        x_axis = side is the plane n.P = r_out, centred on n;
+      * the two other axes are (e_theta + e_phi)/sqrt(2) and
+        (e_phi - e_theta)/sqrt(2) at n, in cyclic order after `axis`
+        (right-handed), so the pixel's diamond lies across the face
+        diagonals.  (The rotation about n is not fixed by the paper; this
+        is the reading taken.)"""
+    n = pix2vec(nside_c, [cone])[0]
+    st = np.hypot(n[0], n[1])
+    cp, sp = n[0] / st, n[1] / st
+    e_th = np.array([n[2] * cp, n[2] * sp, -st])
+    e_ph = np.array([-sp, cp, 0.0])
+    e1 = (e_th + e_ph) / np.sqrt(2.0)
+    e2 = (e_ph - e_th) / np.sqrt(2.0)
+    R = np.empty((3, 3))
+    R[:, axis] = n
+    R[:, (axis + 1) % 3] = e1
+    R[:, (axis + 2) % 3] = e2
+    origin = (r_out - side) * n - 0.5 * side * (e1 + e2)
+    return R, origin

@@ -13,6 +13,8 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcsmap.so")
 
@@ -32,7 +34,8 @@ EXPORTED = ["csmap_npix", "csmap_create_sky", "csmap_add_box", "csmap_add_snapsh
             "csmap_cone_events", "csmap_map2alm", "csmap_alm2cl", "csmap_render", "csmap_backward", "csmap_reset",
             "csmap_destroy_sky", "csmap_last_error", "csmap_pix2vec_ring", "csmap_set_option",
             "csmap_get_stats", "csmap_autotune", "csmap_cap_tiles", "csmap_ring_block_rows",
-            "csmap_cap_block_tiles"]
+            "csmap_cap_block_tiles", "csmap_add_cone_box", "csmap_precompute",
+            "csmap_ang2pix_ring", "csmap_cone_place", "csmap_cone_min_nside"]
 
 
 class csmap_box(ctypes.Structure):
@@ -42,6 +45,10 @@ class csmap_box(ctypes.Structure):
                 ("ext", ctypes.c_double * 3), ("eta_lo", ctypes.c_double),
                 ("eta_hi", ctypes.c_double), ("vis", ctypes.c_int),
                 ("cap_dir", ctypes.c_double * 3), ("cap_cos", ctypes.c_double)]
+
+
+class csmap_cone(ctypes.Structure):
+    _fields_ = [("nside", ctypes.c_int64), ("pix", ctypes.c_int64), ("rot", ctypes.c_double * 9)]
 
 
 class csmap_grad(ctypes.Structure):
@@ -98,6 +105,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                           i64, ctypes.POINTER(i64)]
     lib.csmap_ring_block_rows.argtypes = [i64, i64, i64, ctypes.POINTER(i64), i64,
                                           ctypes.POINTER(i64)]
+    lib.csmap_add_cone_box.argtypes = [vp, ctypes.POINTER(csmap_box), ctypes.POINTER(csmap_cone),
+                                       i32, ctypes.POINTER(i64)]
+    lib.csmap_precompute.argtypes = [vp]
+    lib.csmap_ang2pix_ring.argtypes = [i64, i64, vp, vp, vp]
+    lib.csmap_cone_place.argtypes = [i64, i64, i32, dbl, dbl, dbl, ctypes.POINTER(csmap_cone),
+                                     ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
+    lib.csmap_cone_min_nside.argtypes = [dbl, dbl, dbl, ctypes.POINTER(i64)]
     for name in EXPORTED:
         if name not in ("csmap_npix", "csmap_last_error"):
             getattr(lib, name).restype = i32
@@ -141,6 +155,33 @@ def csmap_add_snapshot_box(sky: int, box: csmap_box) -> int:
     bid = ctypes.c_int64()
     _check(lib().csmap_add_snapshot_box(sky, ctypes.byref(box), ctypes.byref(bid)))
     return bid.value
+
+
+def csmap_add_cone_box(sky: int, box: csmap_box, cone: csmap_cone, snapshot: bool) -> int:
+    bid = ctypes.c_int64()
+    _check(lib().csmap_add_cone_box(sky, ctypes.byref(box), ctypes.byref(cone), int(bool(snapshot)),
+                                    ctypes.byref(bid)))
+    return bid.value
+
+
+def csmap_precompute(sky: int):
+    _check(lib().csmap_precompute(sky))
+
+
+def csmap_cone_place(nside: int, pix: int, axis: int, r_in: float, r_out: float, side: float):
+    """(cone, origin (3,), slack) of a box placed in a healpix cone."""
+    cone = csmap_cone()
+    origin = (ctypes.c_double * 3)()
+    slack = ctypes.c_double()
+    _check(lib().csmap_cone_place(nside, pix, axis, float(r_in), float(r_out), float(side),
+                                  ctypes.byref(cone), origin, ctypes.byref(slack)))
+    return cone, np.array(origin[:]), slack.value
+
+
+def csmap_cone_min_nside(r_in: float, r_out: float, side: float) -> int:
+    out = ctypes.c_int64()
+    _check(lib().csmap_cone_min_nside(float(r_in), float(r_out), float(side), ctypes.byref(out)))
+    return out.value
 
 
 def csmap_cone_events(box: csmap_box, eta0: float, pos_ptr: int, delta_ptr: int, keep_ptr: int,
@@ -259,10 +300,13 @@ class Sky:
 
     def add_box(self, x_rel, xdot, xprime, dsigma, origin, eta_lo, eta_hi,
                 vis=CSMAP_VIS_ALL, ext=(1.0, 1.0, 1.0), cap_dir=(0.0, 0.0, 1.0), cap_cos=-1.0,
-                snapshot=False):
+                snapshot=False, cone=None):
         """Add a box of light-cone events (csmap_add_box), or with
         snapshot=True a box of segments at the slab start whose light-cone
-        crossings the library records (csmap_add_snapshot_box)."""
+        crossings the library records (csmap_add_snapshot_box).  With a
+        `cone` (a csmap_cone, e.g. from cone_place) the arrays are in box
+        coordinates and the box is a stacked simulation placed in that
+        healpix cone (csmap_add_cone_box)."""
         torch = _torch()
         dt = x_rel.dtype
         if dt not in (torch.float32, torch.float64):
@@ -283,7 +327,10 @@ class Sky:
         b.vis = int(vis)
         b.cap_dir = (ctypes.c_double * 3)(*[float(v) for v in cap_dir])
         b.cap_cos = float(cap_cos)
-        bid = (csmap_add_snapshot_box if snapshot else csmap_add_box)(self.handle, b)
+        if cone is not None:
+            bid = csmap_add_cone_box(self.handle, b, cone, snapshot)
+        else:
+            bid = (csmap_add_snapshot_box if snapshot else csmap_add_box)(self.handle, b)
         self._keep.append((x_rel, xdot, xprime, dsigma))
         self.box_shapes.append(n)
         self.box_dtypes.append(dt)
@@ -314,6 +361,10 @@ class Sky:
                                    for t in g]))
         csmap_backward(self.handle, _dev_ptr(dmap.contiguous()), gs)
         return grads
+
+    def precompute(self):
+        """Run the light-cone stage alone (csmap_precompute)."""
+        csmap_precompute(self.handle)
 
     def set_option(self, opt, value):
         csmap_set_option(self.handle, opt, value)
@@ -411,4 +462,43 @@ def pix2vec_ring(nside: int, first: int = 0, count: int | None = None):
         count = npix - first
     out = torch.empty((count, 3), dtype=torch.float64, device="cuda")
     csmap_pix2vec_ring(nside, first, count, _dev_ptr(out), torch.cuda.current_stream().cuda_stream)
+    return out
+
+
+def cone_place(nside: int, pix: int, axis: int, r_in: float, r_out: float, side: float):
+    """Placement of a box of side `side` in healpix cone `pix` of the Nside
+    stacking grid (csmap_cone_place): (cone, origin, slack), cone a
+    csmap_cone for Sky.add_box, origin a (3,) array; slack >= 0 iff the
+    truncated cone r_in .. r_out fits in the box."""
+    return csmap_cone_place(nside, pix, axis, r_in, r_out, side)
+
+
+def cone_rot(cone) -> np.ndarray:
+    """The rotation of a csmap_cone as a (3, 3) array."""
+    return np.array(cone.rot[:]).reshape(3, 3)
+
+
+def make_cone(nside: int, pix: int, rot) -> csmap_cone:
+    c = csmap_cone()
+    c.nside, c.pix = int(nside), int(pix)
+    c.rot = (ctypes.c_double * 9)(*[float(v) for v in np.asarray(rot, dtype=np.float64).ravel()])
+    return c
+
+
+def cone_min_nside(r_in: float, r_out: float, side: float) -> int:
+    return csmap_cone_min_nside(r_in, r_out, side)
+
+
+def ang2pix_ring(nside: int, xyz):
+    """RING pixels (int64 CUDA tensor) of the directions xyz ((n, 3) float64
+    CUDA tensor) from the device routine (csmap_ang2pix_ring)."""
+    torch = _torch()
+    if xyz.dtype != torch.float64 or xyz.dim() != 2 or xyz.shape[1] != 3:
+        raise ValueError("xyz must be a float64 tensor of shape (n, 3)")
+    xyz = xyz.contiguous()
+    n = int(xyz.shape[0])
+    out = torch.empty(n, dtype=torch.int64, device="cuda")
+    _check(lib().csmap_ang2pix_ring(nside, n, _dev_ptr(xyz) if n else None,
+                                    _dev_ptr(out) if n else None,
+                                    torch.cuda.current_stream().cuda_stream))
     return out

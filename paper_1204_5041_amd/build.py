@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libcsmap.so")
 ROOT = os.path.dirname(HERE)
 
 HIP_SOURCES = ["kernels.hip", "alm.hip", "api.cpp"]
-CXX_SOURCES = ["sched.cpp"]
+CXX_SOURCES = ["sched.cpp", "cones.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",

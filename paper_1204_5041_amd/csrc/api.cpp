@@ -18,6 +18,7 @@
 
 #include "../../include/csmap.h"
 #include "internal.h"
+#include "cones.h"
 #include "sched.h"
 
 namespace csmap {
@@ -25,6 +26,8 @@ hipError_t launch_precompute(const PreArgs& A, int64_t nbox, hipStream_t st);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
 hipError_t launch_zero_counters(unsigned long long* c, int n, uint32_t* work, hipStream_t st);
 hipError_t launch_pix2vec(int64_t nside, int64_t first, int64_t count, double* xyz,
+                          hipStream_t st);
+hipError_t launch_ang2pix(int64_t nside, int64_t n, const double* xyz, int64_t* pix,
                           hipStream_t st);
 hipError_t launch_dir_table(int64_t nside, int64_t npix, double* x, double* y, double* z,
                             hipStream_t st);
@@ -92,6 +95,9 @@ struct DevBuf {
 struct HostBox {
   HostBoxGeom geom;
   int snapshot;     // 1: positions at the slab start (csmap_add_snapshot_box)
+  int rotated = 0;  // 1: box-frame arrays turned onto the sky by rot (csmap_add_cone_box)
+  int64_t cone_nside = 0, cone_pix = 0;
+  double rot[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
   int dtype;
   int64_t n;
   int64_t raw_byte_off;
@@ -235,6 +241,10 @@ csmap_status prepare(csmap_sky* s) {
     d.vis = h.geom.vis;
     d.dtype = h.dtype;
     d.snapshot = h.snapshot;
+    d.rotated = h.rotated;
+    d.cone_nside = (int32_t)h.cone_nside;
+    d.cone_pix = h.cone_pix;
+    for (int k = 0; k < 9; ++k) d.rot[k] = h.rot[k];
     d.n = h.n;
     d.raw_off = 0;
     d.rec_off = rec;
@@ -554,8 +564,28 @@ csmap_status csmap_destroy_sky(csmap_sky* s) {
   return CSMAP_OK;
 }
 
+static csmap_status check_cone(const csmap_cone* c) {
+  if (c->nside < 0 || c->nside > kMaxNside)
+    return fail(CSMAP_E_INVALID, "cone nside must be in [0, 8192]");
+  if (c->nside > 0 && (c->pix < 0 || c->pix >= 12 * c->nside * c->nside))
+    return fail(CSMAP_E_INVALID, "cone pix must be in [0, 12 nside^2)");
+  for (int k = 0; k < 9; ++k)
+    if (!isfinite(c->rot[k])) return fail(CSMAP_E_INVALID, "rot must be finite");
+  const double* m = c->rot;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      const double g = m[i] * m[j] + m[3 + i] * m[3 + j] + m[6 + i] * m[6 + j];
+      if (fabs(g - (i == j ? 1.0 : 0.0)) > 1e-9)
+        return fail(CSMAP_E_INVALID, "rot must be orthonormal");
+    }
+  const double det = m[0] * (m[4] * m[8] - m[5] * m[7]) - m[1] * (m[3] * m[8] - m[5] * m[6]) +
+                     m[2] * (m[3] * m[7] - m[4] * m[6]);
+  if (!(det > 0.0)) return fail(CSMAP_E_INVALID, "rot must be a proper rotation (det +1)");
+  return CSMAP_OK;
+}
+
 static csmap_status add_box_impl(csmap_sky* s, const csmap_box* box, int snapshot,
-                                 int64_t* box_id) {
+                                 const csmap_cone* cone, int64_t* box_id) {
   g_err.clear();
   csmap_status cs = check_sky(s);
   if (cs != CSMAP_OK) return cs;
@@ -563,6 +593,13 @@ static csmap_status add_box_impl(csmap_sky* s, const csmap_box* box, int snapsho
   if (snapshot && box->vis == CSMAP_VIS_BOX)
     return fail(CSMAP_E_UNSUPPORTED,
                 "CSMAP_VIS_BOX is not provided for snapshot boxes (their events leave the box)");
+  if (cone && box->vis == CSMAP_VIS_BOX)
+    return fail(CSMAP_E_UNSUPPORTED,
+                "CSMAP_VIS_BOX is not provided for cone boxes (the rule's box is axis-aligned)");
+  if (cone) {
+    cs = check_cone(cone);
+    if (cs != CSMAP_OK) return cs;
+  }
   if (box->n < 0) return fail(CSMAP_E_INVALID, "segment count must be >= 0");
   if (box->n > (int64_t)INT32_MAX) return fail(CSMAP_E_INVALID, "at most 2^31-1 segments per box");
   if (box->dtype != CSMAP_F32 && box->dtype != CSMAP_F64)
@@ -616,6 +653,12 @@ static csmap_status add_box_impl(csmap_sky* s, const csmap_box* box, int snapsho
   }
   HostBox h;
   h.snapshot = snapshot;
+  if (cone) {
+    h.rotated = 1;
+    h.cone_nside = cone->nside;
+    h.cone_pix = cone->pix;
+    for (int k = 0; k < 9; ++k) h.rot[k] = cone->rot[k];
+  }
   for (int k = 0; k < 3; ++k) {
     h.geom.origin[k] = box->origin[k];
     h.geom.ext[k] = box->ext[k];
@@ -638,11 +681,93 @@ static csmap_status add_box_impl(csmap_sky* s, const csmap_box* box, int snapsho
 }
 
 csmap_status csmap_add_box(csmap_sky* s, const csmap_box* box, int64_t* box_id) {
-  return add_box_impl(s, box, 0, box_id);
+  return add_box_impl(s, box, 0, nullptr, box_id);
 }
 
 csmap_status csmap_add_snapshot_box(csmap_sky* s, const csmap_box* box, int64_t* box_id) {
-  return add_box_impl(s, box, 1, box_id);
+  return add_box_impl(s, box, 1, nullptr, box_id);
+}
+
+csmap_status csmap_add_cone_box(csmap_sky* s, const csmap_box* box, const csmap_cone* cone,
+                                int snapshot, int64_t* box_id) {
+  g_err.clear();
+  if (!cone) return fail(CSMAP_E_INVALID, "cone is NULL");
+  if (snapshot != 0 && snapshot != 1) return fail(CSMAP_E_INVALID, "snapshot must be 0 or 1");
+  return add_box_impl(s, box, snapshot, cone, box_id);
+}
+
+csmap_status csmap_precompute(csmap_sky* s) {
+  g_err.clear();
+  csmap_status cs = check_sky(s);
+  if (cs != CSMAP_OK) return cs;
+  cs = prepare(s);
+  if (cs != CSMAP_OK) return cs;
+  hipStream_t st = s->stream;
+  const PreArgs P = pre_args(s);
+  HIPCHK(s, hipEventRecord(s->ev[0], st), "event");
+  HIPCHK(s, launch_precompute(P, (int64_t)s->boxes.size(), st), "precompute launch");
+  HIPCHK(s, launch_zero_counters(s->d_counters.as<unsigned long long>(), 5,
+                                 (uint32_t*)(s->d_counters.as<unsigned long long>() + 2), st),
+         "counter reset");
+  HIPCHK(s, hipEventRecord(s->ev[1], st), "event");
+  HIPCHK(s, hipEventRecord(s->ev[2], st), "event");
+  s->timed_graph = false;
+  s->have_fwd_time = true;
+  return CSMAP_OK;
+}
+
+csmap_status csmap_ang2pix_ring(int64_t nside, int64_t n, const double* xyz, int64_t* pix,
+                                void* hip_stream) {
+  g_err.clear();
+  if (nside < 1 || nside > kMaxNside) return fail(CSMAP_E_INVALID, "nside must be in [1, 8192]");
+  if (n < 0) return fail(CSMAP_E_INVALID, "n must be >= 0");
+  if (n > 0 && (!xyz || !pix)) return fail(CSMAP_E_INVALID, "xyz or pix is NULL");
+  hipError_t e = launch_ang2pix(nside, n, xyz, pix, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return dev_fail(nullptr, e, "ang2pix launch");
+  return CSMAP_OK;
+}
+
+static csmap_status check_shell(double r_in, double r_out, double side) {
+  if (!isfinite(r_in) || !isfinite(r_out) || !isfinite(side) || !(r_in > 0.0) ||
+      !(r_in < r_out) || !(side > 0.0))
+    return fail(CSMAP_E_INVALID, "need finite 0 < r_in < r_out and side > 0");
+  return CSMAP_OK;
+}
+
+csmap_status csmap_cone_place(int64_t nside, int64_t pix, int axis, double r_in, double r_out,
+                              double side, csmap_cone* cone, double origin[3], double* slack) {
+  g_err.clear();
+  if (nside < 1 || nside > kMaxNside) return fail(CSMAP_E_INVALID, "nside must be in [1, 8192]");
+  if (pix < 0 || pix >= 12 * nside * nside)
+    return fail(CSMAP_E_INVALID, "pix must be in [0, 12 nside^2)");
+  if (axis < 0 || axis > 2) return fail(CSMAP_E_INVALID, "axis must be 0, 1 or 2");
+  csmap_status cs = check_shell(r_in, r_out, side);
+  if (cs != CSMAP_OK) return cs;
+  if (!cone || !origin || !slack) return fail(CSMAP_E_INVALID, "output pointer is NULL");
+  ConePlacement pl;
+  cone_place(nside, pix, axis, r_in, r_out, side, pl);
+  cone->nside = nside;
+  cone->pix = pix;
+  for (int k = 0; k < 9; ++k) cone->rot[k] = pl.rot[k];
+  for (int k = 0; k < 3; ++k) origin[k] = pl.origin[k];
+  *slack = pl.slack;
+  return CSMAP_OK;
+}
+
+csmap_status csmap_cone_min_nside(double r_in, double r_out, double side, int64_t* nside) {
+  g_err.clear();
+  csmap_status cs = check_shell(r_in, r_out, side);
+  if (cs != CSMAP_OK) return cs;
+  if (!nside) return fail(CSMAP_E_INVALID, "nside is NULL");
+  *nside = 0;
+  // No cone fits once its depth alone exceeds the box.
+  if (side < r_out - r_in) return CSMAP_OK;
+  for (int64_t n = 1; n <= 256; n *= 2)
+    if (cone_grid_slack(n, r_in, r_out, side) >= 0.0) {
+      *nside = n;
+      break;
+    }
+  return CSMAP_OK;
 }
 
 csmap_status csmap_map2alm(int64_t nside, int64_t lmax, const double* map, double* alm,

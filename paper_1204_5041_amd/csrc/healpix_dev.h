@@ -124,4 +124,55 @@ __device__ __forceinline__ void pix2vec_ring(int64_t nside, int64_t p, double* v
   *vz = z;
 }
 
+// RING pixel of the direction of (x, y, z), a vector of any positive length:
+// the inverse of pix2vec_ring (Gorski et al. 2005).  With c = cos(theta) and
+// t = phi / (pi/2) in [0, 4):
+//   * |c| <= 2/3: the pixel edges are the lines N (1/2 + t) - (3N/4) c = k and
+//     N (1/2 + t) + (3N/4) c = k' for integers k, k'; the cell (k, k') is
+//     belt ring N + 1 + k - k' (of the 2N + 1 belt rings, from the north),
+//     position (k + k' - N + h + 1) / 2 mod 4N, with h = 1 on the belt rings
+//     of even index;
+//   * |c| > 2/3: with s = N sqrt(3 (1 - |c|)) and u the fractional part of t,
+//     the edges are u s = k and (1 - u) s = k'; the cell is cap ring
+//     k + k' + 1 from the nearer pole, position floor(t (k + k' + 1)).
+// 1 - |c| is formed as (x^2 + y^2) / (r (r + |z|)), free of cancellation
+// near the poles.  Used to decide which strings lie inside a healpix cone.
+__device__ __forceinline__ int64_t ang2pix_ring(int64_t nside, double x, double y, double z) {
+  constexpr double kPiD = 3.141592653589793;
+  const int64_t N = nside;
+  const double rho2 = x * x + y * y;
+  const double r = sqrt(rho2 + z * z);
+  const double c = z / r;
+  double phi = atan2(y, x);
+  if (phi < 0.0) phi += 2.0 * kPiD;
+  double t = phi / (0.5 * kPiD);
+  if (t >= 4.0) t -= 4.0;
+  const double ac = fabs(c);
+  if (ac <= 2.0 / 3.0) {
+    const double base = (double)N * (0.5 + t);
+    const double tilt = (double)N * c * 0.75;
+    const int64_t k1 = (int64_t)(base - tilt);  // ascending edge index
+    const int64_t k2 = (int64_t)(base + tilt);  // descending edge index
+    const int64_t bring = N + 1 + k1 - k2;      // 1 .. 2N + 1 among belt rings
+    const int64_t h = 1 - (bring & 1);
+    const int64_t L = 4 * N;
+    int64_t pos = (k1 + k2 - N + h + 1) / 2;
+    pos %= L;
+    if (pos < 0) pos += L;
+    return 2 * N * (N - 1) + (bring - 1) * L + pos;
+  }
+  const double u = t - floor(t);
+  const double one_minus = rho2 / (r * (r + fabs(z)));
+  const double sc = (double)N * sqrt(3.0 * one_minus);
+  const int64_t k1 = (int64_t)(u * sc);
+  const int64_t k2 = (int64_t)((1.0 - u) * sc);
+  int64_t ring = k1 + k2 + 1;  // counted from the nearer pole
+  if (ring > N) ring = N;      // rounding just above |c| = 2/3
+  const int64_t L = 4 * ring;
+  int64_t pos = (int64_t)(t * (double)ring);
+  pos %= L;
+  if (pos < 0) pos += L;
+  return (z > 0.0) ? 2 * ring * (ring - 1) + pos : 12 * N * N - 2 * ring * (ring + 1) + pos;
+}
+
 }  // namespace csmap

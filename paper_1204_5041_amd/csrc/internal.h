@@ -19,11 +19,15 @@ struct DevBox {
   int32_t vis;       // 0 all, 1 ray crosses box inside slab radii, 2 cap
   int32_t dtype;     // 0 f32, 1 f64 raw arrays
   int32_t snapshot;  // 1: positions at eta_lo, events are the worldlines' light-cone crossings
-  int32_t pad;
+  int32_t rotated;   // 1: raw arrays are in box coordinates; sky = rot * box
   int64_t n;         // raw segments
   int64_t raw_off;   // offset (in segments) of the raw arrays of this box
   int64_t rec_off;   // offset (in records) of this box's compacted records
   int64_t blk_off;   // first precompute block of this box
+  int64_t cone_pix;  // cone_nside > 0: RING pixel of the box's healpix cone
+  int32_t cone_nside;  // > 0: keep only events whose direction lies in cone_pix
+  int32_t pad;
+  double rot[9];     // row-major box-to-sky rotation (rotated == 1)
 };
 
 // Per-box result of the light-cone compaction, written on the device.

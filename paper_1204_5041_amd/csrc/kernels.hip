@@ -65,10 +65,15 @@ __device__ __forceinline__ DevBox load_box(const DevBox* boxes, int64_t b) {
   r.vis = q->vis;
   r.dtype = q->dtype;
   r.snapshot = q->snapshot;
+  r.rotated = q->rotated;
   r.n = q->n;
   r.raw_off = q->raw_off;
   r.rec_off = q->rec_off;
   r.blk_off = q->blk_off;
+  r.cone_pix = q->cone_pix;
+  r.cone_nside = q->cone_nside;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) r.rot[k] = q->rot[k];
   return r;
 }
 
@@ -87,6 +92,16 @@ struct SegGeom {
 
 __device__ __forceinline__ double raw_at(const char* base, int dtype, int64_t idx) {
   return dtype == 0 ? (double)((const float*)base)[idx] : ((const double*)base)[idx];
+}
+
+// Row k of a row-major 3x3 matrix times v, summed left to right (FP64).
+__device__ __forceinline__ double rot_row(const double* m, int k, const double v[3]) {
+  return (m[3 * k] * v[0] + m[3 * k + 1] * v[1]) + m[3 * k + 2] * v[2];
+}
+
+// Column k of a row-major 3x3 matrix times v (the transpose's row k).
+__device__ __forceinline__ double rot_col(const double* m, int k, const double v[3]) {
+  return (m[k] * v[0] + m[3 + k] * v[1]) + m[6 + k] * v[2];
 }
 
 // Light-cone crossing of a straight worldline.  A segment at P0 when the
@@ -131,11 +146,29 @@ __device__ __forceinline__ SegGeom seg_geom(const DevBox& bx, const char* raw, i
   const int dt = bx.dtype;
   const int64_t n = bx.n;
   SegGeom g;
+  if (bx.rotated) {
+    // A box placed in a healpix cone: its arrays are in box coordinates and
+    // the box is turned onto the sky by rot (Sec. II.C).
+    double x[3], v[3], t[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    g.P[k] = bx.origin[k] + raw_at(raw, dt, 3 * i + k);
-    g.V[k] = raw_at(raw, dt, 3 * n + 3 * i + k);
-    g.T[k] = raw_at(raw, dt, 6 * n + 3 * i + k);
+    for (int k = 0; k < 3; ++k) {
+      x[k] = raw_at(raw, dt, 3 * i + k);
+      v[k] = raw_at(raw, dt, 3 * n + 3 * i + k);
+      t[k] = raw_at(raw, dt, 6 * n + 3 * i + k);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      g.P[k] = bx.origin[k] + rot_row(bx.rot, k, x);
+      g.V[k] = rot_row(bx.rot, k, v);
+      g.T[k] = rot_row(bx.rot, k, t);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      g.P[k] = bx.origin[k] + raw_at(raw, dt, 3 * i + k);
+      g.V[k] = raw_at(raw, dt, 3 * n + 3 * i + k);
+      g.T[k] = raw_at(raw, dt, 6 * n + 3 * i + k);
+    }
   }
   g.ds = raw_at(raw, dt, 9 * n + i);
   const double tt = (g.T[0] * g.T[0] + g.T[1] * g.T[1]) + g.T[2] * g.T[2];
@@ -156,6 +189,9 @@ __device__ __forceinline__ SegGeom seg_geom(const DevBox& bx, const char* raw, i
     const double eta = eta0 - g.R;
     g.keep = (g.R > 0.0) && (eta >= bx.eta_lo) && (eta < bx.eta_hi);
   }
+  // Stacking: only the strings inside the box's healpix cone are kept.
+  if (bx.cone_nside > 0 && g.keep)
+    g.keep = ang2pix_ring(bx.cone_nside, g.P[0], g.P[1], g.P[2]) == bx.cone_pix;
   g.eps = sqrt(tt / (1.0 - vv));
   return g;
 }
@@ -362,6 +398,12 @@ __global__ void k_dir_table(int64_t nside, int64_t npix, double* x, double* y, d
   x[i] = a;
   y[i] = b;
   z[i] = c;
+}
+
+__global__ void k_ang2pix(int64_t nside, int64_t n, const double* xyz, int64_t* pix) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  pix[i] = ang2pix_ring(nside, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
 }
 
 __global__ void k_pix2vec(int64_t nside, int64_t first, int64_t count, double* xyz) {
@@ -1132,6 +1174,14 @@ __global__ void k_adj_finalize(const DevBox* boxes, const DevBoxCount* counts, i
     V[k] = raw_at(raw, dt, 3 * n + 3 * i + k);
     T[k] = raw_at(raw, dt, 6 * n + 3 * i + k);
   }
+  if (bx.rotated) {
+    const double v[3] = {V[0], V[1], V[2]}, t[3] = {T[0], T[1], T[2]};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      V[k] = rot_row(bx.rot, k, v);
+      T[k] = rot_row(bx.rot, k, t);
+    }
+  }
   const double ds = raw_at(raw, dt, 9 * n + i);
   const double Ph[3] = {phat64[4 * rec + 0], phat64[4 * rec + 1], phat64[4 * rec + 2]};
   const double R = phat64[4 * rec + 3];
@@ -1142,11 +1192,20 @@ __global__ void k_adj_finalize(const DevBox* boxes, const DevBoxCount* counts, i
   for (int k = 0; k < 3; ++k) G[k] = V[k] * S[0] - T[k] * S[1] - S[5 + k];
   const double pg = (Ph[0] * G[0] + Ph[1] * G[1]) + Ph[2] * G[2];
   const double SF = S[2];
+  double gx[3], gv[3], gt[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    if (out.x) out.x[3 * i + k] = -(G[k] - Ph[k] * pg) / R - SF * Ph[k] / R;
-    if (out.xd) out.xd[3 * i + k] = S[8 + k] + Ph[k] * S[3] + SF * V[k] / (1.0 - vv);
-    if (out.xp) out.xp[3 * i + k] = -S[11 + k] - Ph[k] * S[4] + SF * T[k] / tt;
+    gx[k] = -(G[k] - Ph[k] * pg) / R - SF * Ph[k] / R;
+    gv[k] = S[8 + k] + Ph[k] * S[3] + SF * V[k] / (1.0 - vv);
+    gt[k] = -S[11 + k] - Ph[k] * S[4] + SF * T[k] / tt;
+  }
+  // A rotated box: sky = rot * box, so d/d(box) = rot^T d/d(sky).
+  const bool rot = bx.rotated != 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (out.x) out.x[3 * i + k] = rot ? rot_col(bx.rot, k, gx) : gx[k];
+    if (out.xd) out.xd[3 * i + k] = rot ? rot_col(bx.rot, k, gv) : gv[k];
+    if (out.xp) out.xp[3 * i + k] = rot ? rot_col(bx.rot, k, gt) : gt[k];
   }
   if (out.ds) out.ds[i] = SF / ds;
 }
@@ -1180,6 +1239,13 @@ hipError_t launch_zero_counters(unsigned long long* c, int n, uint32_t* work, hi
 hipError_t launch_dir_table(int64_t nside, int64_t npix, double* x, double* y, double* z,
                            hipStream_t st) {
   k_dir_table<<<dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, st>>>(nside, npix, x, y, z);
+  return hipGetLastError();
+}
+
+hipError_t launch_ang2pix(int64_t nside, int64_t n, const double* xyz, int64_t* pix,
+                          hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  k_ang2pix<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(nside, n, xyz, pix);
   return hipGetLastError();
 }
 

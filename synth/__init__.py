@@ -215,3 +215,60 @@ def config4_weights(npix: int) -> np.ndarray:
     """Gaussian pixel weights w_p of the loss L = sum_p w_p Theta_p^2 (seed 209)."""
     rng = np.random.Generator(np.random.PCG64(209))
     return rng.standard_normal(npix)
+
+
+# ----------------------------------------------------------------------------
+# Healpix-cone stacking (Sec. II.C, Fig. 1).  The paper's cosmology (Eq. (3)
+# parameters) is not given, so the shell radii are fixed here with
+# eta0 = 16 Gpc and eta(z) = eta0 / sqrt(1 + z) (matter era), rounded:
+# z = 1089 -> r = 15.5, z = 36 -> r = 13.4, z = 0.2 -> r = 1.4 Gpc.  Box
+# sides are round values for which the paper's grids are the coarsest that
+# fit: Nside 16 for the high-redshift shell with 2.4 Gpc boxes, Nside 1 for
+# the low-redshift shell with 16 Gpc boxes.
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class StackPlan:
+    """Which simulation run fills which healpix cone, and how."""
+    name: str
+    nside_c: int            # stacking grid
+    r_in: float             # shell radii (observer-relative, Gpc)
+    r_out: float
+    side: float             # box side (Gpc)
+    eta0: float
+    seg_per_run: int
+    run_seed0: int
+    uses: list              # (cone pixel, run index, box axis facing the observer)
+
+    @property
+    def eta_lo(self) -> float:
+        return self.eta0 - self.r_out
+
+    @property
+    def eta_hi(self) -> float:
+        return self.eta0 - self.r_in
+
+    @property
+    def nruns(self) -> int:
+        return 1 + max(u[1] for u in self.uses)
+
+    def run(self, r: int, dtype=np.float32):
+        """Segments of run r in box coordinates, inside [0, side)^3."""
+        return segments(self.seg_per_run, self.run_seed0 + r, dtype, self.side)
+
+
+def stack_highz(seg_per_run: int = 200_000) -> StackPlan:
+    """3072 cones of the Nside 16 grid between z = 1089 and z = 36, filled by
+    1024 runs used three times each (cone c: run c // 3, axis c % 3), FP32
+    segments, run seeds 1000-2023."""
+    uses = [(c, c // 3, c % 3) for c in range(12 * 16 * 16)]
+    return StackPlan("high-z cones: Nside_c=16, 1024 runs x 3 axes", 16, 13.4, 15.5, 2.4, 16.0,
+                     seg_per_run, 1000, uses)
+
+
+def stack_lowz(seg_per_run: int = 200_000) -> StackPlan:
+    """12 cones of the Nside 1 grid between z = 36 and z = 0.2, one run each
+    (axis 2), FP32 segments, run seeds 3000-3011."""
+    uses = [(c, c, 2) for c in range(12)]
+    return StackPlan("low-z cones: Nside_c=1, 12 runs", 1, 1.4, 13.4, 16.0, 16.0, seg_per_run,
+                     3000, uses)
