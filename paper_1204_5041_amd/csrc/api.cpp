@@ -98,6 +98,8 @@ struct HostBox {
   int rotated = 0;  // 1: box-frame arrays turned onto the sky by rot (csmap_add_cone_box)
   int64_t cone_nside = 0, cone_pix = 0;
   double rot[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  double cone_dir[3] = {0, 0, 1};
+  double cone_cos_out = -2.0, cone_cos_in = 2.0;
   int dtype;
   int64_t n;
   int64_t raw_byte_off;
@@ -138,7 +140,7 @@ struct csmap_sky {
   int planned_rings = -1;
   Tiling plan;
   DevBuf d_rows;     // ring-block row table (empty for strips)
-  DevBuf d_boxes, d_blk_box, d_blk_count, d_blk_prefix, d_box_count, d_raw_off;
+  DevBuf d_boxes, d_blk_box, d_blk_count, d_blk_prefix, d_box_count, d_raw_off, d_blk_mask;
   DevBuf d_rec32, d_phat64, d_rec64, d_orig;
   DevBuf d_tile_ptr, d_tile_boxes, d_items, d_box_items;
   std::vector<int64_t> box_items_off;  // per box offset into d_box_items (+ end)
@@ -245,6 +247,9 @@ csmap_status prepare(csmap_sky* s) {
     d.cone_nside = (int32_t)h.cone_nside;
     d.cone_pix = h.cone_pix;
     for (int k = 0; k < 9; ++k) d.rot[k] = h.rot[k];
+    for (int k = 0; k < 3; ++k) d.cone_dir[k] = h.cone_dir[k];
+    d.cone_cos_out = h.cone_cos_out;
+    d.cone_cos_in = h.cone_cos_in;
     d.n = h.n;
     d.raw_off = 0;
     d.rec_off = rec;
@@ -260,6 +265,8 @@ csmap_status prepare(csmap_sky* s) {
   HIPCHK(s, s->d_blk_box.ensure(sizeof(int32_t) * std::max<int64_t>(s->nblk, 1)), "alloc blocks");
   HIPCHK(s, s->d_blk_count.ensure(sizeof(int32_t) * std::max<int64_t>(s->nblk, 1)), "alloc blocks");
   HIPCHK(s, s->d_blk_prefix.ensure(sizeof(int64_t) * std::max<int64_t>(s->nblk, 1)), "alloc blocks");
+  HIPCHK(s, s->d_blk_mask.ensure(sizeof(uint64_t) * kPreWords *
+                                 std::max<int64_t>(s->nblk, 1)), "alloc blocks");
   HIPCHK(s, s->d_box_count.ensure(sizeof(DevBoxCount) * std::max<int64_t>(nbox, 1)), "alloc counts");
   HIPCHK(s, s->d_raw_off.ensure(sizeof(int64_t) * std::max<int64_t>(nbox, 1)), "alloc offsets");
   HIPCHK(s, s->d_orig.ensure(sizeof(int32_t) * nrec), "alloc records");
@@ -374,6 +381,7 @@ PreArgs pre_args(csmap_sky* s) {
   A.eta0 = s->eta0;
   A.blk_count = s->d_blk_count.as<int32_t>();
   A.blk_prefix = s->d_blk_prefix.as<int64_t>();
+  A.blk_mask = s->d_blk_mask.as<uint64_t>();
   A.box_count = s->d_box_count.as<DevBoxCount>();
   if (s->form == CSMAP_FORM_FP32C) {
     A.rec32 = s->d_rec32.as<float>();
@@ -555,6 +563,7 @@ csmap_status csmap_destroy_sky(csmap_sky* s) {
     if (e) (void)hipEventDestroy(e);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   DevBuf* bufs[] = {&s->raw, &s->d_boxes, &s->d_blk_box, &s->d_blk_count, &s->d_blk_prefix,
+                    &s->d_blk_mask,
                     &s->d_box_count, &s->d_raw_off, &s->d_rec32, &s->d_phat64, &s->d_rec64,
                     &s->d_orig, &s->d_tile_ptr, &s->d_tile_boxes, &s->d_items,
                     &s->d_box_items, &s->d_counters, &s->d_pixtab32, &s->d_pix64,
@@ -658,6 +667,8 @@ static csmap_status add_box_impl(csmap_sky* s, const csmap_box* box, int snapsho
     h.cone_nside = cone->nside;
     h.cone_pix = cone->pix;
     for (int k = 0; k < 9; ++k) h.rot[k] = cone->rot[k];
+    if (cone->nside > 0)
+      cone_caps(cone->nside, cone->pix, h.cone_dir, h.cone_cos_out, h.cone_cos_in);
   }
   for (int k = 0; k < 3; ++k) {
     h.geom.origin[k] = box->origin[k];

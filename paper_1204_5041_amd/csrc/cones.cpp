@@ -121,6 +121,19 @@ double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * 
 
 constexpr int kEdgeSamples = 256;  // intervals per edge
 
+// Point k (0 .. kEdgeSamples) of edge e (0 .. 3) of cell c.
+void edge_point(const Cell& c, int e, int k, double d[3]) {
+  const double tau = (double)k / kEdgeSamples;
+  double x, y;
+  switch (e) {
+    case 0: x = c.a; y = c.b + tau; break;
+    case 1: x = c.a + 1.0; y = c.b + tau; break;
+    case 2: x = c.a + tau; y = c.b; break;
+    default: x = c.a + tau; y = c.b + 1.0; break;
+  }
+  cell_dir(c, x, y, d);
+}
+
 }  // namespace
 
 void cone_place(int64_t nside, int64_t pix, int axis, double r_in, double r_out, double side,
@@ -150,23 +163,35 @@ void cone_place(int64_t nside, int64_t pix, int axis, double r_in, double r_out,
   // only stationary points of a linear function on the sphere are +-its
   // axis, which the pixel does not contain).
   double lat = 0.0, ncos = 1.0;
-  for (int edge = 0; edge < 4; ++edge) {
+  for (int edge = 0; edge < 4; ++edge)
     for (int k = 0; k <= kEdgeSamples; ++k) {
-      const double tau = (double)k / kEdgeSamples;
-      double x, y;
-      switch (edge) {
-        case 0: x = c.a; y = c.b + tau; break;
-        case 1: x = c.a + 1.0; y = c.b + tau; break;
-        case 2: x = c.a + tau; y = c.b; break;
-        default: x = c.a + tau; y = c.b + 1.0; break;
-      }
       double d[3];
-      cell_dir(c, x, y, d);
+      edge_point(c, edge, k, d);
       lat = std::max(lat, std::max(fabs(dot3(e1, d)), fabs(dot3(e2, d))));
       ncos = std::min(ncos, dot3(n, d));
     }
-  }
   out.slack = std::min(0.5 * side - r_out * lat, r_in * ncos - (r_out - side));
+}
+
+void cone_caps(int64_t nside, int64_t pix, double dir[3], double& cos_out, double& cos_in) {
+  const Cell c = cell_of(nside, pix);
+  double n[3];
+  cell_dir(c, c.a + 0.5, c.b + 0.5, n);
+  double lo = 1.0, hi = -1.0;
+  for (int edge = 0; edge < 4; ++edge)
+    for (int k = 0; k <= kEdgeSamples; ++k) {
+      double d[3];
+      edge_point(c, edge, k, d);
+      const double cd = dot3(n, d);
+      lo = std::min(lo, cd);
+      hi = std::max(hi, cd);
+    }
+  const double a_out = acos(std::max(-1.0, std::min(1.0, lo)));
+  const double a_in = acos(std::max(-1.0, std::min(1.0, hi)));
+  for (int k = 0; k < 3; ++k) dir[k] = n[k];
+  cos_out = cos(std::min(kPi, 1.02 * a_out + 1e-7));
+  const double inner = 0.98 * a_in - 1e-7;
+  cos_in = inner > 0.0 ? cos(inner) : 2.0;
 }
 
 double cone_grid_slack(int64_t nside, double r_in, double r_out, double side) {

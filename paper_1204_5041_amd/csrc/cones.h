@@ -35,6 +35,12 @@ struct ConePlacement {
 void cone_place(int64_t nside, int64_t pix, int axis, double r_in, double r_out, double side,
                 ConePlacement& out);
 
+// Caps around the pixel centre dir that bracket the pixel: every direction
+// whose cosine to dir is below cos_out lies outside the pixel, every one above
+// cos_in inside (cos_in > 1 when no such cap is certain), both with a margin
+// of 2% of the cap radius plus 1e-7 rad beyond the sampled boundary.
+void cone_caps(int64_t nside, int64_t pix, double dir[3], double& cos_out, double& cos_in);
+
 // Smallest slack over every cone of the grid (the same for every axis).
 double cone_grid_slack(int64_t nside, double r_in, double r_out, double side);
 

@@ -28,6 +28,11 @@ struct DevBox {
   int32_t cone_nside;  // > 0: keep only events whose direction lies in cone_pix
   int32_t pad;
   double rot[9];     // row-major box-to-sky rotation (rotated == 1)
+  // cone_nside > 0: caps around the cone axis that bracket the pixel with a
+  // wide margin: cos(angle to cone_dir) < cone_cos_out is certainly outside,
+  // > cone_cos_in certainly inside; only directions in between need ang2pix.
+  double cone_dir[3];
+  double cone_cos_out, cone_cos_in;
 };
 
 // Per-box result of the light-cone compaction, written on the device.
@@ -54,7 +59,9 @@ constexpr int kRec32 = 16;
 //   [12..14] P/R - hi (lo), [15] unused
 constexpr int kRec64 = 16;
 
-constexpr int kPreBlock = 256;  // segments per precompute workgroup
+constexpr int kPreThreads = 256;   // threads per precompute workgroup
+constexpr int kPreBlock = 1024;    // segments per precompute workgroup (4 per thread)
+constexpr int kPreWords = kPreBlock / 64;  // 64-bit keep-flag words per block
 
 struct PreArgs {
   const DevBox* boxes;
@@ -64,6 +71,7 @@ struct PreArgs {
   const int64_t* raw_byte_off; // byte offset of each box's raw arrays
   double eta0;
   int32_t* blk_count;          // kept segments per block
+  uint64_t* blk_mask;          // keep flags of each block's segments (kPreBlock bits)
   int64_t* blk_prefix;         // exclusive prefix within the box
   DevBoxCount* box_count;
   float* rec32;                // FP32C records (or null)

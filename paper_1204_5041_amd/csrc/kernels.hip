@@ -140,6 +140,8 @@ __device__ __forceinline__ bool snapshot_event(const double P0[3], const double 
   return D >= 0.0 && D < eta_hi - eta_lo;
 }
 
+// Geometry of segment i and whether it lies in its box's slab (the cone test
+// of a stacked box is separate: cone_state).
 __device__ __forceinline__ SegGeom seg_geom(const DevBox& bx, const char* raw, int64_t i,
                                             double eta0) {
   // Raw layout of a box: x_rel (n x 3), xdot (n x 3), xprime (n x 3), dsigma (n).
@@ -189,11 +191,42 @@ __device__ __forceinline__ SegGeom seg_geom(const DevBox& bx, const char* raw, i
     const double eta = eta0 - g.R;
     g.keep = (g.R > 0.0) && (eta >= bx.eta_lo) && (eta < bx.eta_hi);
   }
-  // Stacking: only the strings inside the box's healpix cone are kept.
-  if (bx.cone_nside > 0 && g.keep)
-    g.keep = ang2pix_ring(bx.cone_nside, g.P[0], g.P[1], g.P[2]) == bx.cone_pix;
   g.eps = sqrt(tt / (1.0 - vv));
   return g;
+}
+
+// Position, distance and slab test of segment i of a box of on-cone events:
+// the same operations as seg_geom, without the velocity and tangent (the
+// count pass of such boxes needs nothing else).
+__device__ __forceinline__ SegGeom seg_pos(const DevBox& bx, const char* raw, int64_t i,
+                                           double eta0) {
+  const int dt = bx.dtype;
+  SegGeom g;
+  double x[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) x[k] = raw_at(raw, dt, 3 * i + k);
+  if (bx.rotated) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) g.P[k] = bx.origin[k] + rot_row(bx.rot, k, x);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) g.P[k] = bx.origin[k] + x[k];
+  }
+  g.R = sqrt((g.P[0] * g.P[0] + g.P[1] * g.P[1]) + g.P[2] * g.P[2]);
+  const double eta = eta0 - g.R;
+  g.keep = (g.R > 0.0) && (eta >= bx.eta_lo) && (eta < bx.eta_hi);
+  return g;
+}
+
+// Stacking: only the strings inside the box's healpix cone are kept.  The
+// caps that bracket the pixel with a wide margin settle most directions
+// (0 outside, 1 inside); the rest (2) need the pixel test.  Comparing the
+// unnormalised cosine with the caps' cosines times R keeps a division out.
+__device__ __forceinline__ int cone_state(const DevBox& bx, const SegGeom& g) {
+  const double c = (bx.cone_dir[0] * g.P[0] + bx.cone_dir[1] * g.P[1]) + bx.cone_dir[2] * g.P[2];
+  if (c < bx.cone_cos_out * g.R) return 0;
+  if (c > bx.cone_cos_in * g.R) return 1;
+  return 2;
 }
 
 // Pixel visibility of a box (decided in FP64 with a fixed operation order).
@@ -229,18 +262,81 @@ __device__ __forceinline__ bool sees_box(double nx, double ny, double nz, const 
 // ---------------------------------------------------------------------------
 // Precompute: count kept segments per block, scan per box, emit records.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kPreBlock) k_pre_count(PreArgs A) {
+// Thread t of a block handles segments base + t + kPreThreads j, j < 4, so
+// that every pass of the wavefront reads consecutive segments; the four
+// segments' loads are in flight together.
+constexpr int kPrePer = kPreBlock / kPreThreads;
+
+// The pixel tests a block still needs are queued in LDS and run with every
+// lane busy, rather than by the few lanes of each wavefront that need them.
+__global__ void __launch_bounds__(kPreThreads) k_pre_count(PreArgs A) {
   const int64_t blk = blockIdx.x;
-  const int b = A.blk_box[blk];
-  const DevBox bx = A.boxes[b];
-  const int64_t i = (blk - bx.blk_off) * kPreBlock + threadIdx.x;
-  bool keep = false;
-  if (i < bx.n) {
-    const char* raw = (const char*)A.raw + A.raw_byte_off[b];
-    keep = seg_geom(bx, raw, i, A.eta0).keep;
+  const int b = ((ci32p)A.blk_box)[blk];
+  const DevBox bx = load_box(A.boxes, b);
+  const int64_t base = (blk - bx.blk_off) * kPreBlock;
+  const char* raw = (const char*)A.raw + A.raw_byte_off[b];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ unsigned long long flags[kPreWords];
+  __shared__ double qp[3][kPreBlock];
+  __shared__ int qpos[kPreBlock];
+  __shared__ int nq;
+  if (threadIdx.x == 0) nq = 0;
+  __syncthreads();
+  const bool cone = bx.cone_nside > 0;
+#pragma unroll
+  for (int j = 0; j < kPrePer; ++j) {
+    const int pos = threadIdx.x + kPreThreads * j;
+    const int64_t i = base + pos;
+    bool keep = false;
+    if (i < bx.n) {
+      const SegGeom g = bx.snapshot ? seg_geom(bx, raw, i, A.eta0) : seg_pos(bx, raw, i, A.eta0);
+      keep = g.keep;
+      if (keep && cone) {
+        const int st = cone_state(bx, g);
+        keep = st == 1;
+        if (st == 2) {
+          const int q = atomicAdd(&nq, 1);
+          qp[0][q] = g.P[0];
+          qp[1][q] = g.P[1];
+          qp[2][q] = g.P[2];
+          qpos[q] = pos;
+        }
+      }
+    }
+    // Keep flags, one 64-bit word per 64 consecutive segments.
+    const unsigned long long bal = __ballot(keep);
+    if (lane == 0) flags[(kPreThreads / 64) * j + wave] = bal;
   }
-  const int cnt = __syncthreads_count(keep);
-  if (threadIdx.x == 0) A.blk_count[blk] = cnt;
+  __syncthreads();
+  for (int q = threadIdx.x; q < nq; q += kPreThreads) {
+    if (ang2pix_ring(bx.cone_nside, qp[0][q], qp[1][q], qp[2][q]) == bx.cone_pix)
+      atomicOr(&flags[qpos[q] >> 6], 1ull << (qpos[q] & 63));
+  }
+  __syncthreads();
+  if (threadIdx.x < kPreWords) {
+    const unsigned long long w = flags[threadIdx.x];
+    A.blk_mask[blk * kPreWords + threadIdx.x] = w;
+    int c = __popcll(w);
+#pragma unroll
+    for (int off = 1; off < kPreWords; off <<= 1) c += __shfl_xor(c, off);
+    if (threadIdx.x == 0) A.blk_count[blk] = c;
+  }
+}
+
+// Position of the set bit of rank r (0-based) in a 64-bit word holding more
+// than r set bits.
+__device__ __forceinline__ int select_bit(uint64_t w, int r) {
+  int pos = 0;
+#pragma unroll
+  for (int width = 32; width >= 1; width >>= 1) {
+    const int c = __popcll(w & ((1ull << width) - 1ull));
+    if (r >= c) {
+      r -= c;
+      w >>= width;
+      pos += width;
+    }
+  }
+  return pos;
 }
 
 // One workgroup per box: exclusive prefix of the block counts of the box.
@@ -273,28 +369,52 @@ __global__ void __launch_bounds__(256) k_pre_scan(PreArgs A, int64_t nbox) {
   }
 }
 
-__global__ void __launch_bounds__(kPreBlock) k_pre_emit(PreArgs A) {
+// Records by rank: record li of box b (li < kept) is the kept segment of
+// rank li among the box's segments in index order.  Its block k is the last
+// with exclusive prefix <= li; its rank inside the block selects a set bit of
+// the block's keep flags.  A thread writes records base + t + kPreThreads j,
+// j < 4, so consecutive threads write consecutive records.
+__device__ __forceinline__ void emit_record(const PreArgs& A, const DevBox& bx, const char* raw,
+                                            int64_t li);
+
+__global__ void __launch_bounds__(kPreThreads) k_pre_emit(PreArgs A) {
   const int64_t blk = blockIdx.x;
-  const int b = A.blk_box[blk];
-  const DevBox bx = A.boxes[b];
-  const int64_t i = (blk - bx.blk_off) * kPreBlock + threadIdx.x;
-  SegGeom g;
-  g.keep = false;
-  if (i < bx.n) {
-    const char* raw = (const char*)A.raw + A.raw_byte_off[b];
-    g = seg_geom(bx, raw, i, A.eta0);
+  const int b = ((ci32p)A.blk_box)[blk];
+  const DevBox bx = load_box(A.boxes, b);
+  const int64_t kept = load_kept(A.box_count, b);
+  const int64_t base = (blk - bx.blk_off) * kPreBlock;
+  if (base >= kept) return;
+  const char* raw = (const char*)A.raw + A.raw_byte_off[b];
+#pragma unroll
+  for (int j = 0; j < kPrePer; ++j) {
+    const int64_t li = base + threadIdx.x + kPreThreads * j;
+    if (li < kept) emit_record(A, bx, raw, li);
   }
-  // Rank of this segment among the kept ones of the block (order preserved).
-  __shared__ int wave_tot[kPreBlock / 64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const unsigned long long bal = __ballot(g.keep);
-  const int in_wave = __popcll(bal & ((1ull << lane) - 1ull));
-  if (lane == 0) wave_tot[wave] = __popcll(bal);
-  __syncthreads();
-  int before = 0;
-  for (int w = 0; w < wave; ++w) before += wave_tot[w];
-  if (!g.keep) return;
-  const int64_t r = bx.rec_off + A.blk_prefix[blk] + before + in_wave;
+}
+
+__device__ __forceinline__ void emit_record(const PreArgs& A, const DevBox& bx, const char* raw,
+                                            int64_t li) {
+  const int64_t nb = (bx.n + kPreBlock - 1) / kPreBlock;
+  const int64_t* pre = A.blk_prefix + bx.blk_off;
+  int64_t k0 = 0, k1 = nb - 1;   // pre[k0] <= li holds throughout (pre[0] = 0)
+  while (k0 < k1) {
+    const int64_t mid = (k0 + k1 + 1) >> 1;
+    if (pre[mid] <= li) k0 = mid;
+    else k1 = mid - 1;
+  }
+  int rank = (int)(li - pre[k0]);
+  const uint64_t* mask = A.blk_mask + (bx.blk_off + k0) * kPreWords;
+  int word = 0;
+  for (int w = 0; w < kPreWords - 1; ++w) {
+    const int c = __popcll(mask[word]);
+    if (rank < c) break;
+    rank -= c;
+    ++word;
+  }
+  const int64_t i = k0 * kPreBlock + word * 64 + select_bit(mask[word], rank);
+  if (i >= bx.n) return;   // unreachable when the counts and flags agree
+  const SegGeom g = seg_geom(bx, raw, i, A.eta0);
+  const int64_t r = bx.rec_off + li;
   double Ph[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) Ph[k] = g.P[k] / g.R;
@@ -1217,9 +1337,9 @@ hipError_t launch_precompute(const PreArgs& A, int64_t nbox, hipStream_t st) {
   if (nbox == 0) return hipSuccess;
   // The scan runs for every box, also when no box has segments, so that every
   // kept count the pair kernels read has been written.
-  if (A.nblk) k_pre_count<<<dim3((unsigned)A.nblk), dim3(kPreBlock), 0, st>>>(A);
+  if (A.nblk) k_pre_count<<<dim3((unsigned)A.nblk), dim3(kPreThreads), 0, st>>>(A);
   k_pre_scan<<<dim3((unsigned)nbox), dim3(256), 0, st>>>(A, nbox);
-  if (A.nblk) k_pre_emit<<<dim3((unsigned)A.nblk), dim3(kPreBlock), 0, st>>>(A);
+  if (A.nblk) k_pre_emit<<<dim3((unsigned)A.nblk), dim3(kPreThreads), 0, st>>>(A);
   return hipGetLastError();
 }
 
