@@ -63,6 +63,9 @@ def lib() -> ctypes.CDLL:
         _lib.oracle_map2alm_m.argtypes = [i64, i64, i64, f64p, f64p, f64p]
         _lib.oracle_alm2cl.argtypes = [i64, f64p, f64p, f64p]
         _lib.oracle_ang2pix_many.argtypes = [i64, i64, f64p, i64p]
+        _lib.oracle_flat_theta.argtypes = [i64, i64, ctypes.c_double, f64p, ctypes.c_double,
+                                           ctypes.c_double, i64, f64p, i64p, f64p, f64p, f64p,
+                                           f64p, f64p]
         _lib.oracle_cone_events.argtypes = [i64, f64p, f64p, f64p, ctypes.c_double,
                                             ctypes.c_double, ctypes.c_double, f64p, f64p, u8p]
         _lib.oracle_theta_dirs.argtypes = [i64, f64p, ctypes.c_double, i64, f64p, i64p,
@@ -355,3 +358,17 @@ def cone_frame(nside_c: int, cone: int, axis: int, r_out: float, side: float):
     R[:, (axis + 2) % 3] = e2
     origin = (r_out - side) * n - 0.5 * side * (e1 + e2)
     return R, origin
+
+
+def flat_theta(nx: int, ny: int, h: float, frame, accept_cos: float, eta0: float,
+               boxes: Sequence) -> np.ndarray:
+    """Flat-sky small-angle Theta/GU on an ny x nx patch (row-major, index
+    j nx + i) of pixel size h (radians) around frame = (c, e1, e2) (rows of a
+    3x3 array): the 2-D form of Eq. (1) with every photon path parallel to c
+    (Sec. II.A, Fig. 3)."""
+    fr = _f64(frame).reshape(3, 3)
+    out = np.empty(ny * nx, dtype=np.float64)
+    pk = _Packed(boxes)
+    lib().oracle_flat_theta(nx, ny, float(h), _p(fr, ctypes.c_double), float(accept_cos),
+                            float(eta0), *pk.args(), _p(out, ctypes.c_double))
+    return out.reshape(ny, nx)

@@ -732,3 +732,74 @@ void oracle_ang2pix_many(int64_t nside, int64_t n, const double *v, int64_t *pix
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) pix[i] = oracle_ang2pix(nside, v + 3 * i);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Flat-sky, small-angle form of Eq. (1) (Sec. II.A: the limit X n -> X,    */
+/* with every photon path parallel to a fixed axis c; Sec. III.B, Fig. 3:   */
+/* the flat-sky maps the paper compares with a gnomonic projection of its   */
+/* full-sky map).  For a patch around c with orthonormal axes e1, e2:       */
+/*   a segment at P (depth D = c.P) is seen at the plane position            */
+/*   s = (e1.P, e2.P) / D (gnomonic), and in u the line of sight n is        */
+/*   replaced by c: u = Xdot - (c.X')/(1 + c.Xdot) X' ;                     */
+/*   pixel (i, j) (index j nx + i) is at t = ((i + 1/2 - nx/2) h,            */
+/*   (j + 1/2 - ny/2) h), and the term of the segment is                     */
+/*   -4 eps dsigma (u_perp . (t - s)) / (D |t - s|^2),                        */
+/*   u_perp = (e1.u, e2.u), the transverse separation D (t - s) standing for */
+/*   X n - X.                                                               */
+/* A segment enters when it is in its box's slab (as for Eq. (1)), in front */
+/* of the observer (D > 0, where the gnomonic position exists) and          */
+/* c.P > accept_cos |P|; a pixel at t = s exactly receives 0.               */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double s[2];    /* plane position */
+    double a[2];    /* -4 eps dsigma u_perp / D */
+} flat_seg_t;
+
+void oracle_flat_theta(int64_t nx, int64_t ny, double h, const double *frame,
+                       double accept_cos, double eta0, int64_t nbox, const double *boxes,
+                       const int64_t *seg_off, const double *x_rel, const double *xdot,
+                       const double *xprime, const double *dsigma, double *out)
+{
+    const double *c = frame, *e1 = frame + 3, *e2 = frame + 6;
+    const int64_t nseg = seg_off[nbox];
+    flat_seg_t *fs = (flat_seg_t *)malloc(sizeof(flat_seg_t) * (size_t)(nseg > 0 ? nseg : 1));
+    int64_t nf = 0;
+    for (int64_t b = 0; b < nbox; ++b) {
+        const double *box = boxes + BOX_STRIDE * b;
+        for (int64_t i = seg_off[b]; i < seg_off[b + 1]; ++i) {
+            seg_t sg;
+            if (!load_segment(box, eta0, x_rel + 3 * i, xdot + 3 * i, xprime + 3 * i,
+                              dsigma[i], &sg))
+                continue;
+            const double D = dot3(c, sg.P);
+            if (!(D > 0.0) || !(D > accept_cos * sg.R)) continue;
+            const double a = dot3(c, sg.T);
+            const double bb = 1.0 + dot3(c, sg.V);
+            double u[3];
+            for (int k = 0; k < 3; ++k) u[k] = sg.V[k] - (a / bb) * sg.T[k];
+            const double kap = -4.0 * sg.eps * sg.w / D;
+            fs[nf].s[0] = dot3(e1, sg.P) / D;
+            fs[nf].s[1] = dot3(e2, sg.P) / D;
+            fs[nf].a[0] = kap * dot3(e1, u);
+            fs[nf].a[1] = kap * dot3(e2, u);
+            ++nf;
+        }
+    }
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t j = 0; j < ny; ++j) {
+        const double ty = ((double)j + 0.5 - 0.5 * (double)ny) * h;
+        for (int64_t i = 0; i < nx; ++i) {
+            const double tx = ((double)i + 0.5 - 0.5 * (double)nx) * h;
+            csum_t acc = {0.0, 0.0};
+            for (int64_t k = 0; k < nf; ++k) {
+                const double dx = tx - fs[k].s[0];
+                const double dy = ty - fs[k].s[1];
+                const double q = dx * dx + dy * dy;
+                if (q == 0.0) continue;
+                cadd(&acc, (fs[k].a[0] * dx + fs[k].a[1] * dy) / q);
+            }
+            out[j * nx + i] = acc.sum + acc.comp;
+        }
+    }
+    free(fs);
+}
