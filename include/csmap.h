@@ -296,6 +296,32 @@ csmap_status csmap_cone_min_nside(double r_in, double r_out, double side, int64_
  * sky and options. */
 csmap_status csmap_render(csmap_sky *sky, double *map);
 
+/* A square-pixel patch of the sky in gnomonic projection (Sec. III.B,
+ * Fig. 3). */
+typedef struct {
+    double center[3];       /* patch axis c, a unit vector */
+    double e1[3], e2[3];    /* plane axes: unit vectors, orthogonal to c and each other */
+    int64_t nx, ny;         /* pixels along e1 and e2, each >= 1, nx * ny <= 2^31 */
+    double pix;             /* pixel size in radians (> 0) */
+    double accept_cos;      /* a segment enters only if c.P > accept_cos |P|, in [-1, 1] */
+} csmap_patch;
+
+/* Flat-sky, small-angle map of the sky's boxes on a patch (Sec. II.A: the
+ * limit X n -> X with every photon path parallel to c; the paper compares
+ * such maps with its full-sky map in Fig. 3).  A kept segment at P in front
+ * of the observer (D = c.P > 0, D > accept_cos |P|) is seen at the plane
+ * position s = (e1.P, e2.P)/D; pixel (i, j) is at
+ * t = ((i + 1/2 - nx/2) pix, (j + 1/2 - ny/2) pix) and receives, from each
+ * segment, -4 eps dsigma (u_perp . (t - s)) / (D |t - s|^2) with
+ * u = Xdot - (c.X')/(1 + c.Xdot) X' and u_perp = (e1.u, e2.u); a pixel at
+ * t = s receives 0.  Writes map (device, ny x nx doubles, index j nx + i).
+ * Segment geometry (slab, cone boxes, snapshot crossings) is that of render,
+ * in FP64; the pair sum is FP32 with compensated accumulation, whatever the
+ * sky's form.  stats report the light-cone stage and the record pass as
+ * ms_precompute and the pair kernel as ms_forward.  Enqueued on the sky's
+ * stream. */
+csmap_status csmap_render_flat(csmap_sky *sky, const csmap_patch *patch, double *map);
+
 /* Adjoint of render: given dmap = dL/d(Theta_p/GU) (device, npix doubles),
  * write dL/d(x_rel, xdot, xprime, dsigma) of every segment of box b into
  * grads[b] for b = 0 .. nbox-1 (nbox must equal the number of boxes).

@@ -66,6 +66,8 @@ def lib() -> ctypes.CDLL:
         _lib.oracle_flat_theta.argtypes = [i64, i64, ctypes.c_double, f64p, ctypes.c_double,
                                            ctypes.c_double, i64, f64p, i64p, f64p, f64p, f64p,
                                            f64p, f64p]
+        _lib.oracle_flat_points.argtypes = [i64, f64p, f64p, ctypes.c_double, ctypes.c_double,
+                                            i64, f64p, i64p, f64p, f64p, f64p, f64p, f64p]
         _lib.oracle_cone_events.argtypes = [i64, f64p, f64p, f64p, ctypes.c_double,
                                             ctypes.c_double, ctypes.c_double, f64p, f64p, u8p]
         _lib.oracle_theta_dirs.argtypes = [i64, f64p, ctypes.c_double, i64, f64p, i64p,
@@ -372,3 +374,14 @@ def flat_theta(nx: int, ny: int, h: float, frame, accept_cos: float, eta0: float
     lib().oracle_flat_theta(nx, ny, float(h), _p(fr, ctypes.c_double), float(accept_cos),
                             float(eta0), *pk.args(), _p(out, ctypes.c_double))
     return out.reshape(ny, nx)
+
+
+def flat_points(t, frame, accept_cos: float, eta0: float, boxes: Sequence) -> np.ndarray:
+    """The flat-sky map of flat_theta at plane positions t (n, 2) in radians."""
+    tt = _f64(t).reshape(-1, 2)
+    fr = _f64(frame).reshape(3, 3)
+    out = np.empty(tt.shape[0], dtype=np.float64)
+    pk = _Packed(boxes)
+    lib().oracle_flat_points(tt.shape[0], _p(tt, ctypes.c_double), _p(fr, ctypes.c_double),
+                             float(accept_cos), float(eta0), *pk.args(), _p(out, ctypes.c_double))
+    return out

@@ -755,10 +755,12 @@ typedef struct {
     double a[2];    /* -4 eps dsigma u_perp / D */
 } flat_seg_t;
 
-void oracle_flat_theta(int64_t nx, int64_t ny, double h, const double *frame,
-                       double accept_cos, double eta0, int64_t nbox, const double *boxes,
-                       const int64_t *seg_off, const double *x_rel, const double *xdot,
-                       const double *xprime, const double *dsigma, double *out)
+/* The segments that enter a flat patch, with their plane positions and
+ * weights; returns their number (*out is malloc'ed, caller frees). */
+static int64_t flat_segments(const double *frame, double accept_cos, double eta0, int64_t nbox,
+                             const double *boxes, const int64_t *seg_off, const double *x_rel,
+                             const double *xdot, const double *xprime, const double *dsigma,
+                             flat_seg_t **out)
 {
     const double *c = frame, *e1 = frame + 3, *e2 = frame + 6;
     const int64_t nseg = seg_off[nbox];
@@ -785,20 +787,52 @@ void oracle_flat_theta(int64_t nx, int64_t ny, double h, const double *frame,
             ++nf;
         }
     }
+    *out = fs;
+    return nf;
+}
+
+static double flat_sum(double tx, double ty, const flat_seg_t *fs, int64_t nf)
+{
+    csum_t acc = {0.0, 0.0};
+    for (int64_t k = 0; k < nf; ++k) {
+        const double dx = tx - fs[k].s[0];
+        const double dy = ty - fs[k].s[1];
+        const double q = dx * dx + dy * dy;
+        if (q == 0.0) continue;
+        cadd(&acc, (fs[k].a[0] * dx + fs[k].a[1] * dy) / q);
+    }
+    return acc.sum + acc.comp;
+}
+
+/* The flat map at npts plane positions t[2 k], t[2 k + 1] (radians). */
+void oracle_flat_points(int64_t npts, const double *t, const double *frame, double accept_cos,
+                        double eta0, int64_t nbox, const double *boxes, const int64_t *seg_off,
+                        const double *x_rel, const double *xdot, const double *xprime,
+                        const double *dsigma, double *out)
+{
+    flat_seg_t *fs;
+    const int64_t nf = flat_segments(frame, accept_cos, eta0, nbox, boxes, seg_off, x_rel, xdot,
+                                     xprime, dsigma, &fs);
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < npts; ++k) out[k] = flat_sum(t[2 * k], t[2 * k + 1], fs, nf);
+    free(fs);
+}
+
+/* The flat map on the nx x ny grid of pixel size h. */
+void oracle_flat_theta(int64_t nx, int64_t ny, double h, const double *frame,
+                       double accept_cos, double eta0, int64_t nbox, const double *boxes,
+                       const int64_t *seg_off, const double *x_rel, const double *xdot,
+                       const double *xprime, const double *dsigma, double *out)
+{
+    flat_seg_t *fs;
+    const int64_t nf = flat_segments(frame, accept_cos, eta0, nbox, boxes, seg_off, x_rel, xdot,
+                                     xprime, dsigma, &fs);
     #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t j = 0; j < ny; ++j) {
         const double ty = ((double)j + 0.5 - 0.5 * (double)ny) * h;
         for (int64_t i = 0; i < nx; ++i) {
             const double tx = ((double)i + 0.5 - 0.5 * (double)nx) * h;
-            csum_t acc = {0.0, 0.0};
-            for (int64_t k = 0; k < nf; ++k) {
-                const double dx = tx - fs[k].s[0];
-                const double dy = ty - fs[k].s[1];
-                const double q = dx * dx + dy * dy;
-                if (q == 0.0) continue;
-                cadd(&acc, (fs[k].a[0] * dx + fs[k].a[1] * dy) / q);
-            }
-            out[j * nx + i] = acc.sum + acc.comp;
+            out[j * nx + i] = flat_sum(tx, ty, fs, nf);
         }
     }
     free(fs);

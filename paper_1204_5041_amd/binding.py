@@ -35,7 +35,8 @@ EXPORTED = ["csmap_npix", "csmap_create_sky", "csmap_add_box", "csmap_add_snapsh
             "csmap_destroy_sky", "csmap_last_error", "csmap_pix2vec_ring", "csmap_set_option",
             "csmap_get_stats", "csmap_autotune", "csmap_cap_tiles", "csmap_ring_block_rows",
             "csmap_cap_block_tiles", "csmap_add_cone_box", "csmap_precompute",
-            "csmap_ang2pix_ring", "csmap_cone_place", "csmap_cone_min_nside"]
+            "csmap_ang2pix_ring", "csmap_cone_place", "csmap_cone_min_nside",
+            "csmap_render_flat"]
 
 
 class csmap_box(ctypes.Structure):
@@ -49,6 +50,12 @@ class csmap_box(ctypes.Structure):
 
 class csmap_cone(ctypes.Structure):
     _fields_ = [("nside", ctypes.c_int64), ("pix", ctypes.c_int64), ("rot", ctypes.c_double * 9)]
+
+
+class csmap_patch(ctypes.Structure):
+    _fields_ = [("center", ctypes.c_double * 3), ("e1", ctypes.c_double * 3),
+                ("e2", ctypes.c_double * 3), ("nx", ctypes.c_int64), ("ny", ctypes.c_int64),
+                ("pix", ctypes.c_double), ("accept_cos", ctypes.c_double)]
 
 
 class csmap_grad(ctypes.Structure):
@@ -112,6 +119,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.csmap_cone_place.argtypes = [i64, i64, i32, dbl, dbl, dbl, ctypes.POINTER(csmap_cone),
                                      ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
     lib.csmap_cone_min_nside.argtypes = [dbl, dbl, dbl, ctypes.POINTER(i64)]
+    lib.csmap_render_flat.argtypes = [vp, ctypes.POINTER(csmap_patch), vp]
     for name in EXPORTED:
         if name not in ("csmap_npix", "csmap_last_error"):
             getattr(lib, name).restype = i32
@@ -361,6 +369,23 @@ class Sky:
                                    for t in g]))
         csmap_backward(self.handle, _dev_ptr(dmap.contiguous()), gs)
         return grads
+
+    def render_flat(self, center, e1, e2, nx: int, ny: int, pix: float,
+                    accept_cos: float = -1.0, out=None):
+        """Flat-sky small-angle map on a gnomonic patch (csmap_render_flat):
+        a float64 CUDA tensor of shape (ny, nx)."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty((ny, nx), dtype=torch.float64, device="cuda")
+        if out.dtype != torch.float64 or out.numel() != nx * ny:
+            raise ValueError("map must be a float64 tensor of nx * ny elements")
+        p = csmap_patch()
+        p.center = (ctypes.c_double * 3)(*[float(v) for v in center])
+        p.e1 = (ctypes.c_double * 3)(*[float(v) for v in e1])
+        p.e2 = (ctypes.c_double * 3)(*[float(v) for v in e2])
+        p.nx, p.ny, p.pix, p.accept_cos = int(nx), int(ny), float(pix), float(accept_cos)
+        _check(lib().csmap_render_flat(self.handle, ctypes.byref(p), _dev_ptr(out)))
+        return out
 
     def precompute(self):
         """Run the light-cone stage alone (csmap_precompute)."""

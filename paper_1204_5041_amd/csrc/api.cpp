@@ -29,6 +29,8 @@ hipError_t launch_pix2vec(int64_t nside, int64_t first, int64_t count, double* x
                           hipStream_t st);
 hipError_t launch_ang2pix(int64_t nside, int64_t n, const double* xyz, int64_t* pix,
                           hipStream_t st);
+hipError_t launch_flat(const FlatArgs& A, hipStream_t st);
+hipError_t launch_flat_pairs(const FlatArgs& A, hipStream_t st);
 hipError_t launch_dir_table(int64_t nside, int64_t npix, double* x, double* y, double* z,
                             hipStream_t st);
 hipError_t launch_cone_events(int64_t n, int dtype, const void* x_rel, const void* xdot,
@@ -141,6 +143,7 @@ struct csmap_sky {
   Tiling plan;
   DevBuf d_rows;     // ring-block row table (empty for strips)
   DevBuf d_boxes, d_blk_box, d_blk_count, d_blk_prefix, d_box_count, d_raw_off, d_blk_mask;
+  DevBuf d_flat_off, d_flat_rec;
   DevBuf d_rec32, d_phat64, d_rec64, d_orig;
   DevBuf d_tile_ptr, d_tile_boxes, d_items, d_box_items;
   std::vector<int64_t> box_items_off;  // per box offset into d_box_items (+ end)
@@ -563,7 +566,7 @@ csmap_status csmap_destroy_sky(csmap_sky* s) {
     if (e) (void)hipEventDestroy(e);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   DevBuf* bufs[] = {&s->raw, &s->d_boxes, &s->d_blk_box, &s->d_blk_count, &s->d_blk_prefix,
-                    &s->d_blk_mask,
+                    &s->d_blk_mask, &s->d_flat_off, &s->d_flat_rec,
                     &s->d_box_count, &s->d_raw_off, &s->d_rec32, &s->d_phat64, &s->d_rec64,
                     &s->d_orig, &s->d_tile_ptr, &s->d_tile_boxes, &s->d_items,
                     &s->d_box_items, &s->d_counters, &s->d_pixtab32, &s->d_pix64,
@@ -938,6 +941,77 @@ csmap_status csmap_render(csmap_sky* s, double* map) {
     if (cs != CSMAP_OK) return cs;
     s->timed_graph = false;
   }
+  s->have_fwd_time = true;
+  return CSMAP_OK;
+}
+
+static bool unit3(const double* v) {
+  for (int k = 0; k < 3; ++k)
+    if (!isfinite(v[k])) return false;
+  return fabs(v[0] * v[0] + v[1] * v[1] + v[2] * v[2] - 1.0) < 1e-9;
+}
+
+static double dot3h(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+csmap_status csmap_render_flat(csmap_sky* s, const csmap_patch* patch, double* map) {
+  g_err.clear();
+  csmap_status cs = check_sky(s);
+  if (cs != CSMAP_OK) return cs;
+  if (!patch || !map) return fail(CSMAP_E_INVALID, "patch or map is NULL");
+  const csmap_patch& P = *patch;
+  if (!unit3(P.center) || !unit3(P.e1) || !unit3(P.e2))
+    return fail(CSMAP_E_INVALID, "center, e1 and e2 must be unit vectors");
+  if (fabs(dot3h(P.center, P.e1)) > 1e-9 || fabs(dot3h(P.center, P.e2)) > 1e-9 ||
+      fabs(dot3h(P.e1, P.e2)) > 1e-9)
+    return fail(CSMAP_E_INVALID, "center, e1 and e2 must be orthogonal");
+  if (P.nx < 1 || P.ny < 1 || P.nx > (int64_t)1 << 31 || P.ny > (int64_t)1 << 31 ||
+      P.nx * P.ny > (int64_t)1 << 31)
+    return fail(CSMAP_E_INVALID, "need nx, ny >= 1 and nx * ny <= 2^31");
+  if (!isfinite(P.pix) || !(P.pix > 0.0)) return fail(CSMAP_E_INVALID, "pix must be > 0");
+  if (!(P.accept_cos >= -1.0 && P.accept_cos <= 1.0))
+    return fail(CSMAP_E_INVALID, "accept_cos must be in [-1, 1]");
+  cs = prepare(s);
+  if (cs != CSMAP_OK) return cs;
+  const int64_t nbox = (int64_t)s->boxes.size();
+  hipStream_t st = s->stream;
+  HIPCHK(s, s->d_flat_off.ensure(sizeof(int64_t) * (nbox + 1)), "alloc flat offsets");
+  HIPCHK(s, s->d_flat_rec.ensure(sizeof(float) * kFlatRec * (size_t)(s->total_seg + 2)),
+         "alloc flat records");
+  PreArgs pa = pre_args(s);
+  pa.flat_on = 1;
+  for (int k = 0; k < 3; ++k) pa.flat_dir[k] = P.center[k];
+  pa.flat_cos = P.accept_cos;
+  FlatArgs A;
+  memset(&A, 0, sizeof(A));
+  A.boxes = s->d_boxes.as<DevBox>();
+  A.box_count = s->d_box_count.as<DevBoxCount>();
+  A.blk_box = s->d_blk_box.as<int32_t>();
+  A.nblk = s->nblk;
+  A.nbox = nbox;
+  A.raw = s->raw.p;
+  A.raw_byte_off = s->d_raw_off.as<int64_t>();
+  A.orig_index = s->d_orig.as<int32_t>();
+  A.eta0 = s->eta0;
+  for (int k = 0; k < 3; ++k) {
+    A.c[k] = P.center[k];
+    A.e1[k] = P.e1[k];
+    A.e2[k] = P.e2[k];
+  }
+  A.inv_h = 1.0 / P.pix;
+  A.off_x = 0.5 * (double)P.nx - 0.5;
+  A.off_y = 0.5 * (double)P.ny - 0.5;
+  A.nx = P.nx;
+  A.ny = P.ny;
+  A.flat_off = s->d_flat_off.as<int64_t>();
+  A.rec = s->d_flat_rec.as<float>();
+  A.map = map;
+  HIPCHK(s, hipEventRecord(s->ev[0], st), "event");
+  HIPCHK(s, launch_precompute(pa, nbox, st), "precompute launch");
+  HIPCHK(s, launch_flat(A, st), "flat record launch");
+  HIPCHK(s, hipEventRecord(s->ev[1], st), "event");
+  HIPCHK(s, launch_flat_pairs(A, st), "flat pair launch");
+  HIPCHK(s, hipEventRecord(s->ev[2], st), "event");
+  s->timed_graph = false;
   s->have_fwd_time = true;
   return CSMAP_OK;
 }

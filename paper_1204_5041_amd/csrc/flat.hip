@@ -1,0 +1,165 @@
+// flat.hip -- flat-sky small-angle maps on a gnomonic patch.
+//
+// The small-angle, flat-sky form of Eq. (1) (Sec. II.A: X n -> X, every
+// photon path parallel to the patch axis c; Sec. III.B, Fig. 3 compares such
+// maps with a gnomonic projection of the full-sky map).  A segment at P, at
+// depth D = c.P, is seen at the plane position s = (e1.P, e2.P)/D; with u
+// built from c instead of n, u = Xdot - (c.X')/(1 + c.Xdot) X', pixel t
+// receives -4 eps dsigma (u_perp . (t - s)) / (D |t - s|^2).
+//
+//   records : per kept segment (the light-cone stage, with the patch's
+//             acceptance cone, has compacted them), the plane position in
+//             pixel units as an FP32 pair hi + lo and the two weights
+//             a = -4 eps dsigma u_perp / (D h), from FP64 geometry;
+//   pairs   : one wavefront owns 64 x 8 pixels of one row (8 consecutive
+//             pixels per lane, sharing their row offset), records stream
+//             through scalar registers two at a time, and the two terms of
+//             a pixel are folded into one fraction before the division.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.h"
+#include "segment_dev.h"
+
+namespace csmap {
+
+constexpr int kFlatK = 8;            // pixels per lane
+constexpr int kFlatChunk = 32;       // records per FP32 partial sum
+constexpr float kFlatTiny = 1e-18f;  // floor of |t - s|^2 (pixel units): an exact hit gives 0
+
+// Exclusive prefix over boxes of their kept counts; the total is padded to
+// an even count with one zero-weight record.
+__global__ void __launch_bounds__(256) k_flat_scan(FlatArgs A) {
+  __shared__ int64_t sh[256];
+  int64_t running = 0;
+  for (int64_t c0 = 0; c0 < A.nbox; c0 += 256) {
+    const int64_t b = c0 + threadIdx.x;
+    const int64_t v = (b < A.nbox) ? A.box_count[b].kept : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const int64_t add = (threadIdx.x >= (unsigned)off) ? sh[threadIdx.x - off] : 0;
+      __syncthreads();
+      sh[threadIdx.x] += add;
+      __syncthreads();
+    }
+    if (b < A.nbox) A.flat_off[b] = running + sh[threadIdx.x] - v;
+    const int64_t tot = sh[255];
+    __syncthreads();
+    running += tot;
+  }
+  if (threadIdx.x == 0) {
+    if (running & 1) {
+      float* z = A.rec + (size_t)running * kFlatRec;
+      for (int k = 0; k < kFlatRec; ++k) z[k] = 0.f;
+      ++running;
+    }
+    A.flat_off[A.nbox] = running;
+  }
+}
+
+// One thread per kept record (four per thread, as the emit pass).
+__global__ void __launch_bounds__(kPreThreads) k_flat_rec(FlatArgs A) {
+  const int64_t blk = blockIdx.x;
+  const int b = ((ci32p)A.blk_box)[blk];
+  const DevBox bx = load_box(A.boxes, b);
+  const int64_t kept = load_kept(A.box_count, b);
+  const int64_t base = (blk - bx.blk_off) * kPreBlock;
+  if (base >= kept) return;
+  const char* raw = (const char*)A.raw + A.raw_byte_off[b];
+  const int64_t out0 = A.flat_off[b];
+  for (int j = 0; j < kPreBlock / kPreThreads; ++j) {
+    const int64_t li = base + threadIdx.x + kPreThreads * j;
+    if (li >= kept) break;
+    const int64_t i = A.orig_index[bx.rec_off + li];
+    const SegGeom g = seg_geom(bx, raw, i, A.eta0);
+    const double D = (A.c[0] * g.P[0] + A.c[1] * g.P[1]) + A.c[2] * g.P[2];
+    const double ca = (A.c[0] * g.T[0] + A.c[1] * g.T[1]) + A.c[2] * g.T[2];
+    const double cb = 1.0 + ((A.c[0] * g.V[0] + A.c[1] * g.V[1]) + A.c[2] * g.V[2]);
+    double u[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) u[k] = g.V[k] - (ca / cb) * g.T[k];
+    const double kap = -4.0 * g.eps * g.ds / D * A.inv_h;
+    const double sx = ((A.e1[0] * g.P[0] + A.e1[1] * g.P[1]) + A.e1[2] * g.P[2]) / D * A.inv_h +
+                      A.off_x;
+    const double sy = ((A.e2[0] * g.P[0] + A.e2[1] * g.P[1]) + A.e2[2] * g.P[2]) / D * A.inv_h +
+                      A.off_y;
+    const float sxh = (float)sx, syh = (float)sy;
+    const float ax = (float)(kap * ((A.e1[0] * u[0] + A.e1[1] * u[1]) + A.e1[2] * u[2]));
+    const float ay = (float)(kap * ((A.e2[0] * u[0] + A.e2[1] * u[1]) + A.e2[2] * u[2]));
+    float4* o = (float4*)(A.rec + (size_t)(out0 + li) * kFlatRec);
+    o[0] = make_float4(sxh, (float)(sx - (double)sxh), syh, (float)(sy - (double)syh));
+    o[1] = make_float4(ax, ay, 0.f, 0.f);
+  }
+}
+
+// Pair kernel: wavefront w of a workgroup owns tile 4 blockIdx.x + w, i.e.
+// row y and columns 512 c .. 512 c + 511 (lane l: 8 c... + 8 l + j).
+__global__ void __launch_bounds__(256) k_flat32(FlatArgs A, int64_t ntiles, int64_t tpr) {
+  const int lane = threadIdx.x & 63;
+  const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (tile >= ntiles) return;
+  const int64_t y = tile / tpr;
+  const int64_t x0 = (tile - y * tpr) * (64 * kFlatK) + (int64_t)lane * kFlatK;
+  const float fy = (float)y, fx = (float)x0;
+  const int64_t nrec = ((const int64_t __attribute__((address_space(4)))*)A.flat_off)[A.nbox];
+  const cf4p recs = (cf4p)A.rec;
+  float acc[kFlatK], cmp[kFlatK], part[kFlatK];
+#pragma unroll
+  for (int j = 0; j < kFlatK; ++j) {
+    acc[j] = 0.f;
+    cmp[j] = 0.f;
+    part[j] = 0.f;
+  }
+  int in_chunk = 0;
+  for (int64_t r = 0; r < nrec; r += 2) {
+    const v4f pa = recs[2 * r], wa = recs[2 * r + 1];
+    const v4f pb = recs[2 * r + 2], wb = recs[2 * r + 3];
+    // x - s = ((x0 - s_hi) + j) - s_lo: the first two steps are exact for
+    // a pixel near the segment, so s_lo is subtracted at the scale of the
+    // pixel's own offset (subtracting it before adding j would round at the
+    // scale of x0 - s and cost nearly-coincident pairs their accuracy).
+    const float hxa = fx - pa.x, dya = (fy - pa.z) - pa.w;
+    const float hxb = fx - pb.x, dyb = (fy - pb.z) - pb.w;
+    const float ya2 = fmaf(dya, dya, kFlatTiny), yb2 = fmaf(dyb, dyb, kFlatTiny);
+    const float aya = wa.y * dya, ayb = wb.y * dyb;
+#pragma unroll
+    for (int j = 0; j < kFlatK; ++j) {
+      const float xa = (hxa + (float)j) - pa.y, xb = (hxb + (float)j) - pb.y;
+      const float qa = fmaf(xa, xa, ya2), qb = fmaf(xb, xb, yb2);
+      const float na = fmaf(wa.x, xa, aya), nb = fmaf(wb.x, xb, ayb);
+      const float num = fmaf(na, qb, nb * qa);
+      part[j] = fmaf(num, __builtin_amdgcn_rcpf(qa * qb), part[j]);
+    }
+    in_chunk += 2;
+    if (in_chunk == kFlatChunk) {
+#pragma unroll
+      for (int j = 0; j < kFlatK; ++j) {
+        kahan_add(acc[j], cmp[j], part[j]);
+        part[j] = 0.f;
+      }
+      in_chunk = 0;
+    }
+  }
+  double* out = A.map + y * A.nx;
+#pragma unroll
+  for (int j = 0; j < kFlatK; ++j) {
+    kahan_add(acc[j], cmp[j], part[j]);
+    if (x0 + j < A.nx) out[x0 + j] = (double)acc[j] - (double)cmp[j];
+  }
+}
+
+hipError_t launch_flat(const FlatArgs& A, hipStream_t st) {
+  k_flat_scan<<<1, 256, 0, st>>>(A);
+  if (A.nblk) k_flat_rec<<<dim3((unsigned)A.nblk), dim3(kPreThreads), 0, st>>>(A);
+  return hipGetLastError();
+}
+
+hipError_t launch_flat_pairs(const FlatArgs& A, hipStream_t st) {
+  const int64_t tpr = (A.nx + 64 * kFlatK - 1) / (64 * kFlatK);
+  const int64_t ntiles = tpr * A.ny;
+  k_flat32<<<dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, st>>>(A, ntiles, tpr);
+  return hipGetLastError();
+}
+
+}  // namespace csmap

@@ -78,7 +78,32 @@ struct PreArgs {
   double* phat64;              // FP32C: P/R in FP64, 4 doubles per record
   double* rec64;               // FP64 records (or null)
   int32_t* orig_index;         // record -> index of the segment in its box
+  // Flat-sky patch (csmap_render_flat): when flat_on, a segment is kept only
+  // if D = flat_dir.P > 0 and D > flat_cos R.
+  double flat_dir[3];
+  double flat_cos;
+  int32_t flat_on;
 };
+
+// Arguments of the flat-sky kernels.
+struct FlatArgs {
+  const DevBox* boxes;
+  const DevBoxCount* box_count;
+  const int32_t* blk_box;
+  int64_t nblk, nbox;
+  const void* raw;
+  const int64_t* raw_byte_off;
+  const int32_t* orig_index;
+  double eta0;
+  double c[3], e1[3], e2[3];   // patch axis and plane axes
+  double inv_h;                // 1 / pixel size (radians)
+  double off_x, off_y;         // pixel coordinate of the axis: n/2 - 1/2
+  int64_t nx, ny;
+  int64_t* flat_off;           // [nbox + 1]: first flat record of each box; [nbox]: total (even)
+  float* rec;                  // kFlatRec floats per flat record
+  double* map;                 // ny x nx, row-major
+};
+constexpr int kFlatRec = 8;
 
 // Arguments of the forward pair kernels.
 struct FwdArgs {

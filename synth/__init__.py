@@ -272,3 +272,50 @@ def stack_lowz(seg_per_run: int = 200_000) -> StackPlan:
     uses = [(c, c, 2) for c in range(12)]
     return StackPlan("low-z cones: Nside_c=1, 12 runs", 1, 1.4, 13.4, 16.0, 16.0, seg_per_run,
                      3000, uses)
+
+
+# ----------------------------------------------------------------------------
+# Flat-sky patch (Sec. III.B, Fig. 3: a 7.2 degree patch at the north pole).
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class FlatPatch:
+    center: np.ndarray
+    e1: np.ndarray
+    e2: np.ndarray
+    nx: int
+    ny: int
+    pix: float              # radians
+    accept_cos: float
+    eta0: float
+    boxes: list
+
+    @property
+    def frame(self) -> np.ndarray:
+        return np.stack([self.center, self.e1, self.e2])
+
+
+def flat_pencil(nseg: int = 2_000_000, npix: int = 1024, seed: int = 800,
+                dtype=np.float32) -> FlatPatch:
+    """A 7.2 x 7.2 degree patch at the north pole (axes x, y), npix x npix
+    pixels, and one box of nseg segments whose directions are uniform in the
+    cap of radius 6 degrees around the pole (the patch's corners are 5.1
+    degrees out) and whose radii are uniform in volume between 1.4 and
+    15.5 Gpc (the stacked shells); eta0 = 16 Gpc, slab [0.5, 14.6).
+    Velocities, tangents and dsigma follow the module recipe (seed), the
+    positions are drawn with seed + 1."""
+    x, xd, xp, ds = segments(nseg, seed, np.float64)
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    rho = math.radians(6.0)
+    cz = rng.uniform(math.cos(rho), 1.0, nseg)
+    ph = rng.uniform(0.0, 2 * math.pi, nseg)
+    r = np.cbrt(rng.uniform(1.4 ** 3, 15.5 ** 3, nseg))
+    st = np.sqrt(1.0 - cz * cz)
+    P = np.stack([st * np.cos(ph), st * np.sin(ph), cz], 1) * r[:, None]
+    cast = lambda a: np.ascontiguousarray(a.astype(dtype))
+    box = Box(origin=np.zeros(3), ext=np.full(3, 32.0), eta_lo=0.5, eta_hi=14.6, x_rel=cast(P),
+              xdot=cast(xd), xprime=cast(xp), dsigma=cast(ds), seed=seed)
+    return FlatPatch(center=np.array([0.0, 0.0, 1.0]), e1=np.array([1.0, 0.0, 0.0]),
+                     e2=np.array([0.0, 1.0, 0.0]), nx=npix, ny=npix,
+                     pix=math.radians(7.2) / npix, accept_cos=math.cos(rho), eta0=16.0,
+                     boxes=[box])

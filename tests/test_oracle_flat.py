@@ -152,3 +152,14 @@ def test_selection_and_linearity():
     behind = box_of(P * np.array([1.0, 1.0, -1.0]), xd, xp, ds)
     np.testing.assert_array_equal(oracle.flat_theta(12, 10, 2e-2, fr, -1.0, 100.0, [a, behind]),
                                   ma)
+
+
+def test_points_agree_with_the_grid():
+    x, xd, xp, ds = synth.segments(300, 12, np.float64, side=0.5)
+    bx = box_of(x + np.array([-0.25, -0.25, 4.0]), xd, xp, ds)
+    nx, ny, h = 9, 7, 0.01
+    g = oracle.flat_theta(nx, ny, h, frame_z(), -1.0, 100.0, [bx])
+    jj, ii = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    t = np.stack([(ii.ravel() + 0.5 - nx / 2) * h, (jj.ravel() + 0.5 - ny / 2) * h], 1)
+    p = oracle.flat_points(t, frame_z(), -1.0, 100.0, [bx]).reshape(ny, nx)
+    np.testing.assert_array_equal(p, g)
