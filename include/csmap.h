@@ -296,6 +296,16 @@ csmap_status csmap_cone_min_nside(double r_in, double r_out, double side, int64_
  * sky and options. */
 csmap_status csmap_render(csmap_sky *sky, double *map);
 
+/* Theta/GU (Eq. (1)) at n arbitrary directions: xyz is a device array of
+ * n x 3 doubles (vectors of any positive, finite length; each is normalised
+ * on the device), out a device array of n doubles, 0 <= n <= 2^31.  The same
+ * light-cone stage and pair kernels as render, in the sky's form, with the
+ * directions cut into strips in the caller's order; every box is walked for
+ * every strip and its visibility rule applied per direction.  Used, e.g., to
+ * evaluate the full-sky sum at the pixel directions of a gnomonic patch.
+ * stats report the stages as for render.  Enqueued on the sky's stream. */
+csmap_status csmap_render_dirs(csmap_sky *sky, int64_t n, const double *xyz, double *out);
+
 /* A square-pixel patch of the sky in gnomonic projection (Sec. III.B,
  * Fig. 3). */
 typedef struct {

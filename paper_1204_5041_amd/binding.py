@@ -36,7 +36,7 @@ EXPORTED = ["csmap_npix", "csmap_create_sky", "csmap_add_box", "csmap_add_snapsh
             "csmap_get_stats", "csmap_autotune", "csmap_cap_tiles", "csmap_ring_block_rows",
             "csmap_cap_block_tiles", "csmap_add_cone_box", "csmap_precompute",
             "csmap_ang2pix_ring", "csmap_cone_place", "csmap_cone_min_nside",
-            "csmap_render_flat"]
+            "csmap_render_flat", "csmap_render_dirs"]
 
 
 class csmap_box(ctypes.Structure):
@@ -120,6 +120,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                      ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
     lib.csmap_cone_min_nside.argtypes = [dbl, dbl, dbl, ctypes.POINTER(i64)]
     lib.csmap_render_flat.argtypes = [vp, ctypes.POINTER(csmap_patch), vp]
+    lib.csmap_render_dirs.argtypes = [vp, i64, vp, vp]
     for name in EXPORTED:
         if name not in ("csmap_npix", "csmap_last_error"):
             getattr(lib, name).restype = i32
@@ -385,6 +386,22 @@ class Sky:
         p.e2 = (ctypes.c_double * 3)(*[float(v) for v in e2])
         p.nx, p.ny, p.pix, p.accept_cos = int(nx), int(ny), float(pix), float(accept_cos)
         _check(lib().csmap_render_flat(self.handle, ctypes.byref(p), _dev_ptr(out)))
+        return out
+
+    def render_dirs(self, xyz, out=None):
+        """Theta/GU at arbitrary directions (csmap_render_dirs): xyz is an
+        (n, 3) float64 CUDA tensor; returns an (n,) float64 tensor."""
+        torch = _torch()
+        if xyz.dtype != torch.float64 or xyz.dim() != 2 or xyz.shape[1] != 3:
+            raise ValueError("xyz must be a float64 tensor of shape (n, 3)")
+        xyz = xyz.contiguous()
+        n = int(xyz.shape[0])
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device="cuda")
+        if out.dtype != torch.float64 or out.numel() != n:
+            raise ValueError("out must be a float64 tensor of n elements")
+        _check(lib().csmap_render_dirs(self.handle, n, _dev_ptr(xyz) if n else None,
+                                       _dev_ptr(out) if n else None))
         return out
 
     def precompute(self):

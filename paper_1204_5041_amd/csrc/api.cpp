@@ -30,6 +30,8 @@ hipError_t launch_pix2vec(int64_t nside, int64_t first, int64_t count, double* x
 hipError_t launch_ang2pix(int64_t nside, int64_t n, const double* xyz, int64_t* pix,
                           hipStream_t st);
 hipError_t launch_flat(const FlatArgs& A, hipStream_t st);
+hipError_t launch_dirs_soa(int64_t n, const double* xyz, double* x, double* y, double* z,
+                           hipStream_t st);
 hipError_t launch_flat_pairs(const FlatArgs& A, hipStream_t st);
 hipError_t launch_dir_table(int64_t nside, int64_t npix, double* x, double* y, double* z,
                             hipStream_t st);
@@ -144,6 +146,7 @@ struct csmap_sky {
   DevBuf d_rows;     // ring-block row table (empty for strips)
   DevBuf d_boxes, d_blk_box, d_blk_count, d_blk_prefix, d_box_count, d_raw_off, d_blk_mask;
   DevBuf d_flat_off, d_flat_rec;
+  DevBuf d_udir;      // caller directions of csmap_render_dirs, x | y | z
   DevBuf d_rec32, d_phat64, d_rec64, d_orig;
   DevBuf d_tile_ptr, d_tile_boxes, d_items, d_box_items;
   std::vector<int64_t> box_items_off;  // per box offset into d_box_items (+ end)
@@ -566,7 +569,7 @@ csmap_status csmap_destroy_sky(csmap_sky* s) {
     if (e) (void)hipEventDestroy(e);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   DevBuf* bufs[] = {&s->raw, &s->d_boxes, &s->d_blk_box, &s->d_blk_count, &s->d_blk_prefix,
-                    &s->d_blk_mask, &s->d_flat_off, &s->d_flat_rec,
+                    &s->d_blk_mask, &s->d_flat_off, &s->d_flat_rec, &s->d_udir,
                     &s->d_box_count, &s->d_raw_off, &s->d_rec32, &s->d_phat64, &s->d_rec64,
                     &s->d_orig, &s->d_tile_ptr, &s->d_tile_boxes, &s->d_items,
                     &s->d_box_items, &s->d_counters, &s->d_pixtab32, &s->d_pix64,
@@ -1010,6 +1013,55 @@ csmap_status csmap_render_flat(csmap_sky* s, const csmap_patch* patch, double* m
   HIPCHK(s, launch_flat(A, st), "flat record launch");
   HIPCHK(s, hipEventRecord(s->ev[1], st), "event");
   HIPCHK(s, launch_flat_pairs(A, st), "flat pair launch");
+  HIPCHK(s, hipEventRecord(s->ev[2], st), "event");
+  s->timed_graph = false;
+  s->have_fwd_time = true;
+  return CSMAP_OK;
+}
+
+csmap_status csmap_render_dirs(csmap_sky* s, int64_t n, const double* xyz, double* out) {
+  g_err.clear();
+  csmap_status cs = check_sky(s);
+  if (cs != CSMAP_OK) return cs;
+  if (n < 0 || n > ((int64_t)1 << 31)) return fail(CSMAP_E_INVALID, "n must be in [0, 2^31]");
+  if (n > 0 && (!xyz || !out)) return fail(CSMAP_E_INVALID, "xyz or out is NULL");
+  cs = prepare(s);
+  if (cs != CSMAP_OK) return cs;
+  hipStream_t st = s->stream;
+  HIPCHK(s, s->d_udir.ensure(sizeof(double) * 3 * (size_t)std::max<int64_t>(n, 1)),
+         "alloc direction table");
+  double* d = s->d_udir.as<double>();
+  const PreArgs P = pre_args(s);
+  FwdArgs A = fwd_args(s, out);
+  // Strips of 64 K directions in the caller's order; every tile walks every
+  // box, and the per-pixel visibility test of the kernels applies each
+  // box's rule to each direction.
+  const int64_t tile_px = 64 * (int64_t)s->K;
+  const int64_t ntiles = (n + tile_px - 1) / tile_px;
+  A.all_boxes = 1;
+  A.rows = nullptr;
+  A.ring_g = 1;
+  A.ring_shift = 6;
+  A.items = nullptr;
+  A.nitems = ntiles;
+  A.nside = 0;
+  A.npix = n;
+  A.dirx = d;
+  A.diry = d + n;
+  A.dirz = d + 2 * n;
+  HIPCHK(s, launch_dirs_soa(n, xyz, d, d + n, d + 2 * n, st), "direction launch");
+  HIPCHK(s, hipEventRecord(s->ev[0], st), "event");
+  HIPCHK(s, launch_precompute(P, (int64_t)s->boxes.size(), st), "precompute launch");
+  HIPCHK(s, launch_zero_counters(s->d_counters.as<unsigned long long>(), 5,
+                                 (uint32_t*)(s->d_counters.as<unsigned long long>() + 2), st),
+         "counter reset");
+  HIPCHK(s, hipEventRecord(s->ev[1], st), "event");
+  if (ntiles > 0) {
+    const unsigned block = 64u * (unsigned)s->waves;
+    const unsigned grid = (unsigned)((ntiles + s->waves - 1) / s->waves);
+    HIPCHK(s, launch_forward(s->form == CSMAP_FORM_FP64, s->K, false, A, grid, block, st),
+           "forward launch");
+  }
   HIPCHK(s, hipEventRecord(s->ev[2], st), "event");
   s->timed_graph = false;
   s->have_fwd_time = true;

@@ -149,6 +149,25 @@ __global__ void __launch_bounds__(256) k_flat32(FlatArgs A, int64_t ntiles, int6
   }
 }
 
+// Caller directions (n x 3, any positive length) as unit vectors in three
+// arrays, the layout the forward kernels read pixel directions from.
+__global__ void k_dirs_soa(int64_t n, const double* xyz, double* x, double* y, double* z) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a = xyz[3 * i], b = xyz[3 * i + 1], c = xyz[3 * i + 2];
+  const double r = sqrt((a * a + b * b) + c * c);
+  x[i] = a / r;
+  y[i] = b / r;
+  z[i] = c / r;
+}
+
+hipError_t launch_dirs_soa(int64_t n, const double* xyz, double* x, double* y, double* z,
+                           hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  k_dirs_soa<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(n, xyz, x, y, z);
+  return hipGetLastError();
+}
+
 hipError_t launch_flat(const FlatArgs& A, hipStream_t st) {
   k_flat_scan<<<1, 256, 0, st>>>(A);
   if (A.nblk) k_flat_rec<<<dim3((unsigned)A.nblk), dim3(kPreThreads), 0, st>>>(A);

@@ -319,3 +319,38 @@ def flat_pencil(nseg: int = 2_000_000, npix: int = 1024, seed: int = 800,
                      e2=np.array([0.0, 1.0, 0.0]), nx=npix, ny=npix,
                      pix=math.radians(7.2) / npix, accept_cos=math.cos(rho), eta0=16.0,
                      boxes=[box])
+
+
+def straight_strings(nstr: int = 40, seg_per: int = 3000, seed: int = 880,
+                     cap_deg: float = 4.0, arc_deg: float = 12.0, dtype=np.float64) -> Box:
+    """Long straight moving strings seen near the north pole, for comparing
+    flat-sky and full-sky maps on coherent structures (Sec. III.B, Fig. 3):
+    string k has its centre at a direction uniform in the cap of radius
+    cap_deg and a distance uniform in [3, 15] Gpc, a tangent s uniform on
+    S^2, a velocity direction uniform in s_perp and a speed U(0.2, 0.8); its
+    seg_per segments (X' = s/gamma, Xdot = v v_hat, equal dsigma) span
+    arc_deg of arc at that distance.  One box at the observer, slab
+    [-100, 100) (every segment kept); values stored as `dtype`."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    P, V, T, DS = [], [], [], []
+    for _ in range(nstr):
+        th = math.radians(cap_deg) * math.sqrt(rng.uniform())
+        ph = rng.uniform(0.0, 2 * math.pi)
+        c = np.array([math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)])
+        dist = rng.uniform(3.0, 15.0)
+        sh = rng.standard_normal(3)
+        sh /= np.linalg.norm(sh)
+        g = rng.standard_normal(3)
+        g -= (g @ sh) * sh
+        vh = g / np.linalg.norm(g)
+        v = rng.uniform(0.2, 0.8)
+        gam = 1.0 / math.sqrt(1.0 - v * v)
+        ds = dist * math.radians(arc_deg) * gam / seg_per
+        sig = (np.arange(seg_per) + 0.5 - seg_per / 2) * ds
+        P.append(dist * c[None, :] + (sig / gam)[:, None] * sh[None, :])
+        V.append(np.tile(v * vh, (seg_per, 1)))
+        T.append(np.tile(sh / gam, (seg_per, 1)))
+        DS.append(np.full(seg_per, ds))
+    cast = lambda a: np.ascontiguousarray(np.concatenate(a).astype(dtype))
+    return Box(origin=np.zeros(3), ext=np.full(3, 32.0), eta_lo=-100.0, eta_hi=100.0,
+               x_rel=cast(P), xdot=cast(V), xprime=cast(T), dsigma=cast(DS), seed=seed)

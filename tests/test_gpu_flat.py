@@ -143,3 +143,85 @@ def test_flat_full_patch_sampled(B):
     e = err_metrics(got[jj, ii], ref)
     say(f"  sampled {len(ii)} pixels: {e}")
     assert e["rel_rms"] <= 1e-5 and e["rel_max"] <= 1e-4, e
+
+
+def unit_dirs(n, seed):
+    v = np.random.default_rng(seed).standard_normal((n, 3))
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32c"])
+def test_render_dirs_matches_oracle(B, form):
+    """Eq. (1) at caller directions (csmap_render_dirs): random directions,
+    directions next to segments (close pairs) and a ragged count, over boxes
+    with every visibility rule."""
+    dtype = np.float64 if form == "fp64" else np.float32
+    boxes = [synth.make_box(3000, 860, origin=(-0.5, -0.5, -0.5), eta_lo=0.0, eta_hi=1.0,
+                            dtype=dtype),
+             synth.make_box(2000, 861, origin=(0.6, -0.3, 0.2), eta_lo=0.0, eta_hi=3.0,
+                            dtype=dtype, vis=synth.VIS_BOX),
+             synth.make_box(2500, 862, origin=(-1.4, 0.9, 0.3), eta_lo=0.0, eta_hi=3.0,
+                            dtype=dtype, vis=synth.VIS_CAP, cap_dir=np.array([-0.8, 0.6, 0.0]),
+                            cap_cos=math.cos(0.5))]
+    eta0 = 3.0
+    P = boxes[0].origin + boxes[0].x_rel[:200].astype(np.float64)
+    near = P / np.linalg.norm(P, axis=1, keepdims=True) + 1e-4 * unit_dirs(200, 3)
+    raw = np.concatenate([3.0 * unit_dirs(5001, 2), 0.5 * near])
+    # the directions the device forms from them: v / sqrt((x^2 + y^2) + z^2)
+    r = np.sqrt((raw[:, 0] * raw[:, 0] + raw[:, 1] * raw[:, 1]) + raw[:, 2] * raw[:, 2])
+    dirs = raw / r[:, None]
+    ref = oracle.theta_dirs(dirs, eta0, boxes, use_vis=True)
+    f = B.CSMAP_FORM_FP64 if form == "fp64" else B.CSMAP_FORM_FP32C
+    sky = B.Sky(8, eta0, f)
+    for bx in boxes:
+        t = [torch.from_numpy(a).cuda() for a in (bx.x_rel, bx.xdot, bx.xprime, bx.dsigma)]
+        kw = {}
+        if bx.cap_dir is not None:
+            kw = dict(cap_dir=tuple(bx.cap_dir), cap_cos=bx.cap_cos)
+        sky.add_box(*t, origin=tuple(bx.origin), eta_lo=bx.eta_lo, eta_hi=bx.eta_hi, vis=bx.vis,
+                    ext=tuple(bx.ext), **kw)
+    got = sky.render_dirs(torch.from_numpy(raw).cuda()).cpu().numpy()
+    e = err_metrics(got, ref)
+    say(f"render_dirs form={form}: {e}")
+    if form == "fp64":
+        assert e["rel_rms"] <= 1e-12 and e["rel_max"] <= 1e-12, e
+    else:
+        assert e["rel_rms"] <= 1e-5 and e["rel_max"] <= 1e-4, e
+    # the pixel centres of the sky's own map give the map
+    pc = B.pix2vec_ring(8)
+    m = sky.render().cpu().numpy()
+    g2 = sky.render_dirs(pc).cpu().numpy()
+    tol = 1e-10 if form == "fp64" else 1e-5
+    assert np.max(np.abs(g2 - m)) <= tol * np.max(np.abs(m))
+    assert sky.render_dirs(torch.zeros((0, 3), dtype=torch.float64, device="cuda")).numel() == 0
+    sky.close()
+
+
+def test_flat_and_full_sky_on_straight_strings(B):
+    """Fig. 3-style: the flat map and the full-sky sum at the same gnomonic
+    directions, for long straight strings near the pole; the GPU profile of
+    their difference (per annulus) equals the oracle's."""
+    box = synth.straight_strings(12, 1500, seed=881)
+    nx = 64
+    pix = math.radians(7.2) / nx
+    c, e1, e2 = np.array([0.0, 0.0, 1.0]), np.array([1.0, 0.0, 0.0]), np.array([0.0, 1.0, 0.0])
+    acc = math.cos(math.radians(20.0))
+    t = (np.arange(nx) + 0.5 - nx / 2) * pix
+    tx, ty = np.meshgrid(t, t)
+    dirs = c[None, :] + tx.ravel()[:, None] * e1[None, :] + ty.ravel()[:, None] * e2[None, :]
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    sky = B.Sky(8, 16.0, B.CSMAP_FORM_FP64)
+    tt = [torch.from_numpy(a).cuda() for a in (box.x_rel, box.xdot, box.xprime, box.dsigma)]
+    sky.add_box(*tt, origin=(0.0, 0.0, 0.0), eta_lo=box.eta_lo, eta_hi=box.eta_hi)
+    full = sky.render_dirs(torch.from_numpy(dirs).cuda()).cpu().numpy().reshape(nx, nx)
+    flat = sky.render_flat(c, e1, e2, nx, nx, pix, acc).cpu().numpy()
+    sky.close()
+    rfull = oracle.theta_dirs(dirs, 16.0, [box]).reshape(nx, nx)
+    rflat = oracle.flat_theta(nx, nx, pix, np.stack([c, e1, e2]), acc, 16.0, [box])
+    rad = np.degrees(np.hypot(tx, ty))
+    for lo, hi in ((0.0, 1.2), (1.2, 2.4), (2.4, 6.0)):
+        m = (rad >= lo) & (rad < hi)
+        g = np.sqrt(np.mean((full - flat)[m] ** 2) / np.mean(full[m] ** 2))
+        r = np.sqrt(np.mean((rfull - rflat)[m] ** 2) / np.mean(rfull[m] ** 2))
+        say(f"  annulus {lo}-{hi} deg: flat vs full rel rms {g:.4f} (oracle {r:.4f})")
+        assert abs(g - r) <= 1e-3 * r + 1e-6
