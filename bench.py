@@ -575,9 +575,7 @@ def bench_alm(args, B, torch):
     """Angular power spectrum of a string map: the FP32C map of one 400,000-
     segment box at Nside=2048 (rendered first, not timed), then a_lm up to
     lmax = 4096 = 2 Nside and C_l, timed over the whole call (scratch
-    allocation included).  Algorithmic work: 4 FLOP per (pixel, m) for the
-    ring Fourier sums and 8 FLOP per (l, m, ring pair) for the Legendre sums,
-    in FP64."""
+    allocation included), in FP64."""
     nside, lmax = NSIDE, 2 * NSIDE
     sky, _ = make_sky(B, torch, 0, B.CSMAP_FORM_FP32C, args.nseg, nside)
     hmap = sky.render()
@@ -591,9 +589,17 @@ def bench_alm(args, B, torch):
         cl = B.alm2cl(alm, lmax)
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / K
-    npix = 12 * nside * nside
     size = (lmax + 1) * (lmax + 2) // 2
-    flop = 4.0 * npix * (lmax + 1) + 8.0 * (2 * nside) * size
+    # Work of the path taken at this Nside (a power of two <= 2048): direct
+    # Fourier sums on the cap rings (4 FLOP per (pixel, m)), one FFT per belt
+    # ring (5 H log2 H for the half-length complex FFT, H = 2 Nside, and
+    # 10 per output m for the unpacking and the half-pixel phase), and the
+    # Legendre sums (8 FLOP per (l, m, ring pair)).
+    cap_pix = 4 * nside * (nside - 1)
+    H = 2 * nside
+    flop = (4.0 * cap_pix * (lmax + 1) +
+            (2 * nside + 1) * (5.0 * H * math.log2(H) + 10.0 * (lmax + 1)) +
+            8.0 * (2 * nside) * size)
     tf = flop / el / 1e12
     c = cl.cpu().numpy()
     res = {"metric": "map2alm + alm2cl at Nside=2048, lmax=4096 (s per call)", "value": el,

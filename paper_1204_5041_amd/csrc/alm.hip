@@ -79,8 +79,9 @@ __device__ __forceinline__ void twiddle(int64_t t, int64_t L, double& c, double&
 // imaginary parts for m mod 4), so one complex twiddle serves four pixels.
 // Each lane advances e^{-i m 2 pi j / L} by one complex multiplication per
 // step and recomputes it exactly every kAnchor steps.
+// Rings skip_lo .. skip_hi are left to the FFT kernel.
 __global__ void __launch_bounds__(256) k_ring_dft(int64_t nside, int64_t mmax, const double* map,
-                                                 double* F) {
+                                                 double* F, int64_t skip_lo, int64_t skip_hi) {
   const int lane = threadIdx.x & 63;
   const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) +
                        __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -88,6 +89,7 @@ __global__ void __launch_bounds__(256) k_ring_dft(int64_t nside, int64_t mmax, c
   const int64_t nring = 4 * nside - 1;
   if (wave >= nring * mblocks) return;
   const int64_t i = 1 + wave / mblocks;
+  if (i >= skip_lo && i <= skip_hi) return;
   const int64_t m = (wave % mblocks) * 64 + lane;
   const Ring r = ring_of(nside, i);
   const int64_t L = r.len;
@@ -135,6 +137,84 @@ __global__ void __launch_bounds__(256) k_ring_dft(int64_t nside, int64_t mmax, c
     double* o = F + 2 * ((i - 1) * (mmax + 1) + m);
     o[0] = acc_re;
     o[1] = acc_im;
+  }
+}
+
+// Step 1 for the 2N + 1 belt rings when Nside is a power of two: every belt
+// ring has L = 4N pixels, so its Fourier sums are one length-L DFT of real
+// data.  It is taken as a complex FFT of half length H = L/2 on
+// z_n = x_{2n} + i x_{2n+1} (radix 2, decimation in time from a bit-reversed
+// load, in LDS), then unpacked: with E_k = (Z_k + conj Z_{H-k})/2 and
+// O_k = (Z_k - conj Z_{H-k})/(2i), X_k = E_k + e^{-2 pi i k/L} O_k for
+// 0 <= k <= H and X_k = conj X_{L-k} above.  F_m = X_{m mod L}, times
+// e^{-i pi m/L} on rings with the half-pixel offset.  tab[k] = e^{-i pi k/L},
+// k = 0 .. L, holds every twiddle (e^{-2 pi i j/H} is entry 4j).  One
+// workgroup per ring.
+constexpr int kFftThreads = 512;
+constexpr int64_t kFftMaxH = 4096;   // 64 KB of LDS: H <= 4096, Nside <= 2048
+
+__global__ void k_fft_table(int64_t L, double* tab) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > L) return;
+  double sp, cp;
+  sincospi((double)k / (double)L, &sp, &cp);
+  tab[2 * k] = cp;
+  tab[2 * k + 1] = -sp;
+}
+
+__global__ void __launch_bounds__(kFftThreads) k_ring_fft(int64_t nside, int64_t mmax,
+                                                          const double* map, const double* tab,
+                                                          double* F) {
+  extern __shared__ double zs[];   // H complex values, (re, im) interleaved
+  const int64_t i = nside + blockIdx.x;
+  const Ring r = ring_of(nside, i);
+  const int64_t L = r.len, H = L / 2;
+  const int bits = __builtin_ctzll((unsigned long long)H);
+  const double* x = map + r.first;
+  for (int64_t n = threadIdx.x; n < H; n += blockDim.x) {
+    const int64_t d = bits ? (int64_t)(__brev((unsigned)n) >> (32 - bits)) : 0;
+    zs[2 * d] = x[2 * n];
+    zs[2 * d + 1] = x[2 * n + 1];
+  }
+  __syncthreads();
+  for (int64_t half = 1; half < H; half <<= 1) {
+    const int64_t tstride = 4 * (H / (2 * half));
+    for (int64_t b = threadIdx.x; b < H / 2; b += blockDim.x) {
+      const int64_t pos = b & (half - 1);
+      const int64_t i0 = 2 * (b - pos) + pos, i1 = i0 + half;
+      const double wc = tab[2 * pos * tstride], ws = tab[2 * pos * tstride + 1];
+      const double br = zs[2 * i1], bi = zs[2 * i1 + 1];
+      const double tr = fma(br, wc, -(bi * ws)), ti = fma(br, ws, bi * wc);
+      const double ar = zs[2 * i0], ai = zs[2 * i0 + 1];
+      zs[2 * i0] = ar + tr;
+      zs[2 * i0 + 1] = ai + ti;
+      zs[2 * i1] = ar - tr;
+      zs[2 * i1 + 1] = ai - ti;
+    }
+    __syncthreads();
+  }
+  double* out = F + 2 * (i - 1) * (mmax + 1);
+  for (int64_t m = threadIdx.x; m <= mmax; m += blockDim.x) {
+    int64_t k = m % L;
+    const bool upper = k > H;
+    if (upper) k = L - k;
+    const int64_t ka = (k == H) ? 0 : k, kb = (H - k) % H;
+    const double zr = zs[2 * ka], zi = zs[2 * ka + 1];
+    const double cr = zs[2 * kb], ci = -zs[2 * kb + 1];        // conj Z_{H-k}
+    const double er = 0.5 * (zr + cr), ei = 0.5 * (zi + ci);
+    const double orr = 0.5 * (zi - ci), oi = -0.5 * (zr - cr);  // (Z - conj)/(2i)
+    const double wc = tab[4 * k], ws = tab[4 * k + 1];          // e^{-2 pi i k/L}
+    double xr = er + fma(wc, orr, -(ws * oi));
+    double xi = ei + fma(wc, oi, ws * orr);
+    if (upper) xi = -xi;
+    if (r.half) {
+      const double hc = tab[2 * m], hs = tab[2 * m + 1];        // e^{-i pi m/L}
+      const double yr = fma(xr, hc, -(xi * hs)), yi = fma(xr, hs, xi * hc);
+      xr = yr;
+      xi = yi;
+    }
+    out[2 * m] = xr;
+    out[2 * m + 1] = xi;
   }
 }
 
@@ -338,7 +418,7 @@ size_t map2alm_scratch_bytes(int64_t nside, int64_t lmax) {
   return sizeof(double) * (size_t)(2 * nring * M) + sizeof(double) * (size_t)(M * npair) +
          sizeof(int32_t) * (size_t)(M * npair) + sizeof(double) * (size_t)npair +
          sizeof(double) * (size_t)(2 * size) + sizeof(double) * (size_t)(2 * nblk * size) +
-         6 * 256;
+         sizeof(double) * (size_t)(2 * (4 * nside + 1)) + 7 * 256;
 }
 
 // All of map2alm on `st`; `scratch` holds map2alm_scratch_bytes(nside, lmax).
@@ -361,9 +441,21 @@ hipError_t launch_map2alm(int64_t nside, int64_t lmax, const double* map, double
   double* coef = (double*)p;
   p += align(sizeof(double) * (size_t)(2 * size));
   double* part = (double*)p;
+  p += align(sizeof(double) * (size_t)(2 * nblk * size));
+  double* tab = (double*)p;
   const int64_t mblocks = (lmax + 64) / 64;
   const int64_t dft_waves = nring * mblocks;
-  k_ring_dft<<<dim3((unsigned)((dft_waves + 3) / 4)), dim3(256), 0, st>>>(nside, lmax, map, F);
+  // Belt rings by FFT when their length 4N is a power of two whose half
+  // fits the LDS buffer; every other ring by direct sums.
+  const bool fft = (nside & (nside - 1)) == 0 && 2 * nside <= kFftMaxH;
+  if (fft) {
+    const int64_t L = 4 * nside;
+    k_fft_table<<<dim3((unsigned)((L + 256) / 256)), dim3(256), 0, st>>>(L, tab);
+    k_ring_fft<<<dim3((unsigned)(2 * nside + 1)), dim3(kFftThreads),
+                 sizeof(double) * 2 * (size_t)(2 * nside), st>>>(nside, lmax, map, tab, F);
+  }
+  k_ring_dft<<<dim3((unsigned)((dft_waves + 3) / 4)), dim3(256), 0, st>>>(
+      nside, lmax, map, F, fft ? nside : 0, fft ? 3 * nside : -1);
   k_lambda_mm<<<dim3((unsigned)((npair + 255) / 256)), dim3(256), 0, st>>>(nside, lmax, lam_v,
                                                                           lam_e, ring_z);
   k_leg_coef<<<dim3((unsigned)((M + 63) / 64)), dim3(64), 0, st>>>(lmax, coef);

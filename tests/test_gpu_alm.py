@@ -33,7 +33,9 @@ def gpu_alm(B, hmap, lmax):
     return B.map2alm(torch.from_numpy(np.ascontiguousarray(hmap)).cuda(), lmax).cpu().numpy()
 
 
-@pytest.mark.parametrize("nside,lmax", [(1, 4), (4, 12), (8, 16), (16, 64), (32, 64), (64, 128)])
+# Powers of two take the FFT of the belt rings, other Nside the direct sums.
+@pytest.mark.parametrize("nside,lmax", [(1, 4), (4, 12), (8, 16), (16, 64), (32, 64), (64, 128),
+                                        (12, 48), (48, 96), (64, 256)])
 def test_map2alm_matches_oracle(B, nside, lmax):
     rng = np.random.default_rng(100 + nside)
     hmap = rng.standard_normal(12 * nside * nside) + 0.3
