@@ -273,6 +273,32 @@ __device__ __forceinline__ double wave_sum(double x) {
   return x;
 }
 
+// x moved across lanes by a DPP pattern, as two 32-bit moves; lanes outside
+// the row mask receive 0.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, kCtrl, kRowMask, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), kCtrl, kRowMask, 0xf,
+                                             false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                          (unsigned)lo));
+}
+
+// Sum over the wavefront's 64 lanes, complete in lane 63, with register
+// moves only: lane pairs and quad halves (quad_perm), 8- and 16-lane groups
+// (row half mirror, row mirror), then rows 0+1 and 2+3 (row broadcast 15)
+// and all four (row broadcast 31).
+__device__ __forceinline__ double wave_sum_to_last(double x) {
+  x += dpp_f64<0xB1, 0xf>(x);    // quad_perm [1,0,3,2]
+  x += dpp_f64<0x4E, 0xf>(x);    // quad_perm [2,3,0,1]
+  x += dpp_f64<0x141, 0xf>(x);   // row_half_mirror
+  x += dpp_f64<0x140, 0xf>(x);   // row_mirror
+  x += dpp_f64<0x142, 0xa>(x);   // row_bcast:15 into rows 1 and 3
+  x += dpp_f64<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
 // Step 2b: partial a_lm of one block of 64 * kRingsPerLane ring pairs, for
 // one m: part[blk * S + idx(l, m)] = sum over the block's pairs of
 // lambda_lm(z) (F_north +- F_south), the sign (-1)^(l+m).
@@ -343,9 +369,9 @@ __global__ void __launch_bounds__(256) k_legendre(int64_t nside, int64_t lmax, i
       sr = fma(lam, even ? er[k] : orr[k], sr);
       si = fma(lam, even ? ei[k] : oi[k], si);
     }
-    sr = wave_sum(sr);
-    si = wave_sum(si);
-    if (lane == 0) {
+    sr = wave_sum_to_last(sr);
+    si = wave_sum_to_last(si);
+    if (lane == 63) {
       const int64_t idx = alm_idx(lmax, l, m);
       out[2 * idx] = sr;
       out[2 * idx + 1] = si;
