@@ -287,3 +287,33 @@ def test_full_stacking_grid(B):
     e = err_metrics(m[pix], ref)
     say(f"  stacked map vs oracle on {len(pix)} pixels: {e}")
     assert e["rel_rms"] <= 1e-5 and e["rel_max"] <= 1e-4, e
+
+
+def test_rotation_only_and_empty_cone_boxes(B):
+    """nside = 0 turns a box onto the sky without a cone test; an empty cone
+    box contributes nothing; both in the FP64 form against the oracle."""
+    eta0, lo, hi = 3.0, 1.0, 2.0
+    rng = np.random.default_rng(41)
+    q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    if np.linalg.det(q) < 0:
+        q[:, 0] = -q[:, 0]
+    x, xd, xp, ds = synth.segments(4000, 890, np.float64, 2.0)
+    origin = np.array([-0.4, 0.7, 0.2])
+    P, V, T = oracle.place_segments(x, xd, xp, q, origin)
+    ref_box = synth.Box(origin=np.zeros(3), ext=np.ones(3), eta_lo=lo, eta_hi=hi, x_rel=P,
+                        xdot=V, xprime=T, dsigma=ds)
+    nside = 16
+    ref = oracle.theta_pixels(nside, np.arange(12 * nside * nside), eta0, [ref_box])
+    sky = B.Sky(nside, eta0, B.CSMAP_FORM_FP64)
+    t = [torch.from_numpy(a).cuda() for a in (x, xd, xp, ds)]
+    sky.add_box(*t, origin=tuple(origin), eta_lo=lo, eta_hi=hi, cone=B.make_cone(0, 0, q))
+    e = [torch.zeros((0, 3), dtype=torch.float64, device="cuda") for _ in range(3)]
+    sky.add_box(*e, torch.zeros(0, dtype=torch.float64, device="cuda"), origin=(1.0, 2.0, 3.0),
+                eta_lo=lo, eta_hi=hi, cone=B.make_cone(4, 7, np.eye(3)))
+    got = sky.render().cpu().numpy()
+    st = sky.stats()
+    sky.close()
+    err = err_metrics(got, ref)
+    say(f"rotation-only cone box: kept {st['kept']}, {err}")
+    assert st["kept"] == int(oracle.kept(eta0, ref_box).sum())
+    assert err["rel_rms"] <= 1e-12 and err["rel_max"] <= 1e-12, err
