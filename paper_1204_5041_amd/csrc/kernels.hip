@@ -270,12 +270,12 @@ __device__ __forceinline__ void emit_record(const PreArgs& A, const DevBox& bx, 
 // ---------------------------------------------------------------------------
 // Light-cone events of a snapshot box, on their own (the same crossing as the
 // render path): per segment the observer-relative event position, D, and
-// whether the event falls inside the slab.  Coalesced: thread i reads
-// segment i's position and velocity and writes its outputs.
+// whether the event falls inside the slab.
 // ---------------------------------------------------------------------------
-__global__ void k_cone_events(int64_t n, int dtype, const void* x_rel, const void* xdot,
-                              double o0, double o1, double o2, double eta0, double eta_lo,
-                              double eta_hi, double* pos, double* delta, uint8_t* keep) {
+// One segment per thread: any alignment of the caller's arrays.
+__global__ void k_cone_events_1(int64_t n, int dtype, const void* x_rel, const void* xdot,
+                                double o0, double o1, double o2, double eta0, double eta_lo,
+                                double eta_hi, double* pos, double* delta, uint8_t* keep) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const char* xr = (const char*)x_rel;
@@ -297,13 +297,96 @@ __global__ void k_cone_events(int64_t n, int dtype, const void* x_rel, const voi
   keep[i] = in ? 1 : 0;
 }
 
+// Thread t handles segments 2t and 2t + 1: their six coordinates are
+// contiguous, so loads and stores move 8- and 16-byte vectors (positions
+// 48 bytes, D 16 bytes, keep flags 2 bytes per thread).
+template <typename Tin, typename Tin2>
+__global__ void k_cone_events(int64_t n, const Tin* x_rel, const Tin* xdot, double o0, double o1,
+                              double o2, double eta0, double eta_lo, double eta_hi, double* pos,
+                              double* delta, uint8_t* keep) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i0 = 2 * t;
+  if (i0 >= n) return;
+  const bool pair = i0 + 1 < n;
+  double x[6], v[6];
+  if (pair) {
+    const Tin2* xr = (const Tin2*)(x_rel + 3 * i0);
+    const Tin2* xd = (const Tin2*)(xdot + 3 * i0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const Tin2 a = xr[k], c = xd[k];
+      x[2 * k] = (double)a.x;
+      x[2 * k + 1] = (double)a.y;
+      v[2 * k] = (double)c.x;
+      v[2 * k + 1] = (double)c.y;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      x[k] = (double)x_rel[3 * i0 + k];
+      v[k] = (double)xdot[3 * i0 + k];
+      x[3 + k] = 0.0;
+      v[3 + k] = 0.0;
+    }
+  }
+  const double o[3] = {o0, o1, o2};
+  const double nan = __builtin_nan("");
+  double p[6], d[2];
+  bool in[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    double P0[3], V[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      P0[k] = o[k] + x[3 * s + k];
+      V[k] = v[3 * s + k];
+    }
+    const double vv = (V[0] * V[0] + V[1] * V[1]) + V[2] * V[2];
+    double D;
+    in[s] = snapshot_event(P0, V, eta0, eta_lo, eta_hi, vv, D);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) p[3 * s + k] = in[s] ? P0[k] + V[k] * D : nan;
+    d[s] = in[s] ? D : nan;
+  }
+  if (pair) {
+    double2* po = (double2*)(pos + 3 * i0);
+    po[0] = make_double2(p[0], p[1]);
+    po[1] = make_double2(p[2], p[3]);
+    po[2] = make_double2(p[4], p[5]);
+    *(double2*)(delta + i0) = make_double2(d[0], d[1]);
+    *(uint16_t*)(keep + i0) = (uint16_t)((in[0] ? 1u : 0u) | (in[1] ? 0x100u : 0u));
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) pos[3 * i0 + k] = p[k];
+    delta[i0] = d[0];
+    keep[i0] = in[0] ? 1 : 0;
+  }
+}
+
 hipError_t launch_cone_events(int64_t n, int dtype, const void* x_rel, const void* xdot,
                               const double origin[3], double eta0, double eta_lo, double eta_hi,
                               double* pos, double* delta, uint8_t* keep, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  k_cone_events<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(
-      n, dtype, x_rel, xdot, origin[0], origin[1], origin[2], eta0, eta_lo, eta_hi, pos, delta,
-      keep);
+  const size_t es = dtype == 0 ? 4 : 8;
+  const bool aligned = ((uintptr_t)x_rel % (2 * es)) == 0 && ((uintptr_t)xdot % (2 * es)) == 0 &&
+                       ((uintptr_t)pos % 16) == 0 && ((uintptr_t)delta % 16) == 0 &&
+                       ((uintptr_t)keep % 2) == 0;
+  if (!aligned) {
+    k_cone_events_1<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(
+        n, dtype, x_rel, xdot, origin[0], origin[1], origin[2], eta0, eta_lo, eta_hi, pos, delta,
+        keep);
+    return hipGetLastError();
+  }
+  const dim3 grid((unsigned)(((n + 1) / 2 + 255) / 256)), block(256);
+  if (dtype == 0)
+    k_cone_events<float, float2><<<grid, block, 0, st>>>(n, (const float*)x_rel,
+                                                         (const float*)xdot, origin[0], origin[1],
+                                                         origin[2], eta0, eta_lo, eta_hi, pos,
+                                                         delta, keep);
+  else
+    k_cone_events<double, double2><<<grid, block, 0, st>>>(
+        n, (const double*)x_rel, (const double*)xdot, origin[0], origin[1], origin[2], eta0,
+        eta_lo, eta_hi, pos, delta, keep);
   return hipGetLastError();
 }
 

@@ -160,3 +160,30 @@ def test_snapshot_box_rejects_the_ray_box_rule(B):
         sky.add_box(*t, ds, origin=(1.0, 1.0, 1.0), eta_lo=0.0, eta_hi=1.0, vis=B.CSMAP_VIS_BOX,
                     snapshot=True)
     sky.close()
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_cone_events_odd_count_and_unaligned_arrays(B, dtype):
+    """An odd segment count (the last thread holds one segment) and arrays
+    offset by one element (the one-segment-per-thread path)."""
+    n = 20_001
+    x, xd, _, _ = snapshot_segments(n, 311, dtype)
+    origin = np.array([1.2, -0.4, 2.1])
+    eta0, eta_lo, eta_hi = 16.0, 12.0, 12.5
+    rpos, rd, rkeep = oracle.cone_events(x, xd, origin, eta0, eta_lo, eta_hi)
+    tdt = torch.float32 if dtype == np.float32 else torch.float64
+    for off in (0, 1):
+        bx = torch.zeros(3 * n + 1, dtype=tdt, device="cuda")
+        bv = torch.zeros(3 * n + 1, dtype=tdt, device="cuda")
+        bx[off:off + 3 * n] = torch.from_numpy(x.ravel()).cuda()
+        bv[off:off + 3 * n] = torch.from_numpy(xd.ravel()).cuda()
+        xt, vt = bx[off:off + 3 * n].view(n, 3), bv[off:off + 3 * n].view(n, 3)
+        say(f"cone events n={n} dtype={np.dtype(dtype).name} offset={off}")
+        pos, d, keep = B.cone_events(xt, vt, origin, eta0, eta_lo, eta_hi)
+        pos, d, keep = pos.cpu().numpy(), d.cpu().numpy(), keep.cpu().numpy()
+        assert np.array_equal(keep, rkeep)
+        R0 = eta0 - eta_lo
+        speed = np.linalg.norm(xd.astype(np.float64), axis=1)
+        assert np.all(np.abs(d[keep] - rd[keep]) <= 64 * EPS * R0 / (1.0 - speed[keep]))
+        assert np.max(np.abs(pos[keep] - rpos[keep])) <= 64 * EPS * R0
+        assert np.isnan(d[~keep]).all()
