@@ -32,7 +32,8 @@ hipError_t launch_ang2pix(int64_t nside, int64_t n, const double* xyz, int64_t* 
 hipError_t launch_flat(const FlatArgs& A, hipStream_t st);
 hipError_t launch_dirs_soa(int64_t n, const double* xyz, double* x, double* y, double* z,
                            hipStream_t st);
-hipError_t launch_flat_pairs(const FlatArgs& A, hipStream_t st);
+hipError_t launch_flat_pairs(const FlatArgs& A, int64_t nsplit, double* part, hipStream_t st);
+int64_t flat_splits(int64_t nx, int64_t ny);
 hipError_t launch_dir_table(int64_t nside, int64_t npix, double* x, double* y, double* z,
                             hipStream_t st);
 hipError_t launch_cone_events(int64_t n, int dtype, const void* x_rel, const void* xdot,
@@ -145,7 +146,7 @@ struct csmap_sky {
   Tiling plan;
   DevBuf d_rows;     // ring-block row table (empty for strips)
   DevBuf d_boxes, d_blk_box, d_blk_count, d_blk_prefix, d_box_count, d_raw_off, d_blk_mask;
-  DevBuf d_flat_off, d_flat_rec;
+  DevBuf d_flat_off, d_flat_rec, d_flat_part;
   DevBuf d_udir;      // caller directions of csmap_render_dirs, x | y | z
   DevBuf d_rec32, d_phat64, d_rec64, d_orig;
   DevBuf d_tile_ptr, d_tile_boxes, d_items, d_box_items;
@@ -569,7 +570,7 @@ csmap_status csmap_destroy_sky(csmap_sky* s) {
     if (e) (void)hipEventDestroy(e);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   DevBuf* bufs[] = {&s->raw, &s->d_boxes, &s->d_blk_box, &s->d_blk_count, &s->d_blk_prefix,
-                    &s->d_blk_mask, &s->d_flat_off, &s->d_flat_rec, &s->d_udir,
+                    &s->d_blk_mask, &s->d_flat_off, &s->d_flat_rec, &s->d_udir, &s->d_flat_part,
                     &s->d_box_count, &s->d_raw_off, &s->d_rec32, &s->d_phat64, &s->d_rec64,
                     &s->d_orig, &s->d_tile_ptr, &s->d_tile_boxes, &s->d_items,
                     &s->d_box_items, &s->d_counters, &s->d_pixtab32, &s->d_pix64,
@@ -1012,7 +1013,11 @@ csmap_status csmap_render_flat(csmap_sky* s, const csmap_patch* patch, double* m
   HIPCHK(s, launch_precompute(pa, nbox, st), "precompute launch");
   HIPCHK(s, launch_flat(A, st), "flat record launch");
   HIPCHK(s, hipEventRecord(s->ev[1], st), "event");
-  HIPCHK(s, launch_flat_pairs(A, st), "flat pair launch");
+  const int64_t nsplit = flat_splits(P.nx, P.ny);
+  if (nsplit > 1)
+    HIPCHK(s, s->d_flat_part.ensure(sizeof(double) * (size_t)nsplit * (size_t)(P.nx * P.ny)),
+           "alloc flat partial maps");
+  HIPCHK(s, launch_flat_pairs(A, nsplit, s->d_flat_part.as<double>(), st), "flat pair launch");
   HIPCHK(s, hipEventRecord(s->ev[2], st), "event");
   s->timed_graph = false;
   s->have_fwd_time = true;

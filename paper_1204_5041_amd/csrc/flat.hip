@@ -13,8 +13,9 @@
 //             a = -4 eps dsigma u_perp / (D h), from FP64 geometry;
 //   pairs   : one wavefront owns 64 x 8 pixels of one row (8 consecutive
 //             pixels per lane, sharing their row offset), records stream
-//             through scalar registers two at a time, and the two terms of
-//             a pixel are folded into one fraction before the division.
+//             through scalar registers two at a time (the next pair
+//             requested before the current one is used), and the two terms
+//             of a pixel are folded into one fraction before the division.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -93,17 +94,24 @@ __global__ void __launch_bounds__(kPreThreads) k_flat_rec(FlatArgs A) {
   }
 }
 
-// Pair kernel: wavefront w of a workgroup owns tile 4 blockIdx.x + w, i.e.
-// row y and columns 512 c .. 512 c + 511 (lane l: 8 c... + 8 l + j).
-__global__ void __launch_bounds__(256) k_flat32(FlatArgs A, int64_t ntiles, int64_t tpr) {
+// Pair kernel: work item w = 4 blockIdx.x + (wavefront) is tile w mod ntiles
+// (row y, columns 512 c .. 512 c + 511; lane l holds 512 c + 8 l + j) and
+// record range s = w / ntiles of nsplit equal ranges (even bounds).  With one
+// range the sums go to the map, else to parts[s][pixel] for k_flat_combine.
+__global__ void __launch_bounds__(256) k_flat32(FlatArgs A, int64_t ntiles, int64_t tpr,
+                                               int64_t nsplit, double* parts) {
   const int lane = threadIdx.x & 63;
-  const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (tile >= ntiles) return;
+  const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (item >= ntiles * nsplit) return;
+  const int64_t split = item / ntiles, tile = item - split * ntiles;
   const int64_t y = tile / tpr;
   const int64_t x0 = (tile - y * tpr) * (64 * kFlatK) + (int64_t)lane * kFlatK;
   const float fy = (float)y, fx = (float)x0;
-  const int64_t nrec = ((const int64_t __attribute__((address_space(4)))*)A.flat_off)[A.nbox];
-  const cf4p recs = (cf4p)A.rec;
+  const int64_t nrec_all = ((const int64_t __attribute__((address_space(4)))*)A.flat_off)[A.nbox];
+  const int64_t half = nrec_all / 2;
+  const int64_t rbeg = 2 * (half * split / nsplit), rend = 2 * (half * (split + 1) / nsplit);
+  const int64_t nrec = rend - rbeg;
+  const cf4p recs = (cf4p)A.rec + 2 * rbeg;
   float acc[kFlatK], cmp[kFlatK], part[kFlatK];
 #pragma unroll
   for (int j = 0; j < kFlatK; ++j) {
@@ -112,9 +120,14 @@ __global__ void __launch_bounds__(256) k_flat32(FlatArgs A, int64_t ntiles, int6
     part[j] = 0.f;
   }
   int in_chunk = 0;
+  // The next window's records are requested before this window's arithmetic
+  // (an empty range reads the first window and uses none of it).
+  const cf4p rec0 = nrec > 0 ? recs : (cf4p)A.rec;
+  v4f pa = rec0[0], wa = rec0[1], pb = rec0[2], wb = rec0[3];
   for (int64_t r = 0; r < nrec; r += 2) {
-    const v4f pa = recs[2 * r], wa = recs[2 * r + 1];
-    const v4f pb = recs[2 * r + 2], wb = recs[2 * r + 3];
+    const int64_t rn = (r + 2 < nrec) ? r + 2 : r;
+    const v4f npa = recs[2 * rn], nwa = recs[2 * rn + 1];
+    const v4f npb = recs[2 * rn + 2], nwb = recs[2 * rn + 3];
     // x - s = ((x0 - s_hi) + j) - s_lo: the first two steps are exact for
     // a pixel near the segment, so s_lo is subtracted at the scale of the
     // pixel's own offset (subtracting it before adding j would round at the
@@ -131,6 +144,10 @@ __global__ void __launch_bounds__(256) k_flat32(FlatArgs A, int64_t ntiles, int6
       const float num = fmaf(na, qb, nb * qa);
       part[j] = fmaf(num, __builtin_amdgcn_rcpf(qa * qb), part[j]);
     }
+    pa = npa;
+    wa = nwa;
+    pb = npb;
+    wb = nwb;
     in_chunk += 2;
     if (in_chunk == kFlatChunk) {
 #pragma unroll
@@ -141,12 +158,21 @@ __global__ void __launch_bounds__(256) k_flat32(FlatArgs A, int64_t ntiles, int6
       in_chunk = 0;
     }
   }
-  double* out = A.map + y * A.nx;
+  double* out = (nsplit == 1 ? A.map : parts + split * (A.nx * A.ny)) + y * A.nx;
 #pragma unroll
   for (int j = 0; j < kFlatK; ++j) {
     kahan_add(acc[j], cmp[j], part[j]);
     if (x0 + j < A.nx) out[x0 + j] = (double)acc[j] - (double)cmp[j];
   }
+}
+
+// map[p] = sum over record ranges of part[s][p], in range order.
+__global__ void k_flat_combine(int64_t npix, int64_t nsplit, const double* part, double* map) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npix) return;
+  double v = part[p];
+  for (int64_t s = 1; s < nsplit; ++s) v += part[s * npix + p];
+  map[p] = v;
 }
 
 // Caller directions (n x 3, any positive length) as unit vectors in three
@@ -174,10 +200,28 @@ hipError_t launch_flat(const FlatArgs& A, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_flat_pairs(const FlatArgs& A, hipStream_t st) {
+// Record ranges per tile: one when the tiles alone give a launch about 2048
+// wavefronts (two per SIMD), else enough ranges to get there, at most 16
+// (small patches).  More ranges on large patches measured slower: the
+// wavefronts' record streams then compete for the scalar cache.  With more
+// than one range, part holds that many maps of nx ny doubles.
+int64_t flat_splits(int64_t nx, int64_t ny) {
+  const int64_t tpr = (nx + 64 * kFlatK - 1) / (64 * kFlatK);
+  const int64_t ntiles = tpr * ny;
+  int64_t ns = (2048 + ntiles - 1) / ntiles;
+  return ns < 1 ? 1 : (ns > 16 ? 16 : ns);
+}
+
+hipError_t launch_flat_pairs(const FlatArgs& A, int64_t nsplit, double* part, hipStream_t st) {
   const int64_t tpr = (A.nx + 64 * kFlatK - 1) / (64 * kFlatK);
   const int64_t ntiles = tpr * A.ny;
-  k_flat32<<<dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, st>>>(A, ntiles, tpr);
+  k_flat32<<<dim3((unsigned)((ntiles * nsplit + 3) / 4)), dim3(256), 0, st>>>(A, ntiles, tpr,
+                                                                             nsplit, part);
+  if (nsplit > 1) {
+    const int64_t npix = A.nx * A.ny;
+    k_flat_combine<<<dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, st>>>(npix, nsplit,
+                                                                               part, A.map);
+  }
   return hipGetLastError();
 }
 
