@@ -294,7 +294,8 @@ def bench_config3(args, B, torch):
            "autotune_s": tune_s}
     res["achieved_tflops"] = FLOP_PER_PAIR * res["value"] / 1e12
     res["frac_fp32_peak"] = res["achieved_tflops"] / FP32_PEAK_TFLOPS
-    res["accuracy_vs_oracle"] = _sampled_accuracy(torch, w, out, 4000, seed=397)
+    res["accuracy_vs_oracle"], dt = _sampled_accuracy(torch, w, out, 4000, seed=397)
+    res["cpu_baseline"] = _sampled_cpu_baseline(w, st["pairs"], 4000, dt)
     _log(f"bench config3: batched render {el * 1e3:.0f} ms; per-box launches next")
     sky.set_option(B.CSMAP_OPT_GRAPH, 0)
     sky.set_option(B.CSMAP_OPT_SCHEDULE, 2)
@@ -315,10 +316,25 @@ def _sampled_accuracy(torch, w, gpu_map, count, seed):
     pix = synth.sample_pixels(w.npix, count, seed=seed)
     got = gpu_map[torch.from_numpy(pix).cuda()].cpu().numpy()
     _log(f"bench: oracle on {count} sampled pixels")
+    t0 = time.perf_counter()
     ref = oracle.theta_pixels(w.nside, pix, w.eta0, w.boxes)
+    dt = time.perf_counter() - t0
     acc = {"pixels": int(count), "unit": "Theta/GU"}
     acc.update(err_metrics(got, ref))
-    return acc
+    return acc, dt
+
+
+def _sampled_cpu_baseline(w, pairs, count, dt):
+    """The oracle's rate on the same map, from its time on `count` pixels
+    drawn uniformly from the map (so that the time scales to the whole map in
+    expectation, boxes seen by part of the sky included)."""
+    import oracle
+    full_s = dt * w.npix / count
+    return {"value": pairs / full_s, "unit": "pairs/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{count} random pixels of the Nside={w.nside} map, all {len(w.boxes)} boxes "
+                      f"({sum(b.n for b in w.boxes):,} segments): {dt:.1f} s, scaled to the "
+                      f"{w.npix:,}-pixel map ({full_s:.3e} s)"}
 
 
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
@@ -375,15 +391,28 @@ def bench_events(args, B, torch):
            "ms_per_launch": kern * 1e3, "wall_ms_per_launch": wall * 1e3,
            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": gbs / HBM_PEAK_GBS, "bytes_per_segment": EVENT_BYTES}}
-    # Agreement with the oracle on a sample of 200,000 segments.
-    sel = synth.sample_pixels(n, 200_000, seed=512)
-    rp, rd, rk = oracle.cone_events(x[sel], xd[sel], np.array(origin), eta0, eta_lo, eta_hi)
+    # Agreement with the oracle: on all segments when the oracle is timed
+    # (a few seconds on the host's cores), else on a sample of 200,000.
+    if args.no_cpu:
+        sel = synth.sample_pixels(n, 200_000, seed=512)
+        xs, vs = x[sel], xd[sel]
+    else:
+        sel = slice(None)
+        xs, vs = x, xd
+    _log("bench events: oracle")
+    t0 = time.perf_counter()
+    rp, rd, rk = oracle.cone_events(xs, vs, np.array(origin), eta0, eta_lo, eta_hi)
+    dt = time.perf_counter() - t0
     k = keep.cpu().numpy()[sel]
     dd = d.cpu().numpy()[sel]
     both = k & rk
-    res["accuracy_vs_oracle"] = {"segments": int(sel.size),
+    res["accuracy_vs_oracle"] = {"segments": int(len(rk)),
                                  "keep_mismatches": int(np.sum(k != rk)),
                                  "max_abs_delta_error": float(np.max(np.abs(dd[both] - rd[both])))}
+    if not args.no_cpu:
+        res["cpu_baseline"] = {"value": n / dt, "unit": "segments/s", "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"the whole workload ({n:,} segments) in {dt:.2f} s"}
     print(json.dumps(res), flush=True)
 
 
@@ -618,6 +647,23 @@ def bench_alm(args, B, torch):
            "roofline": {"bound": "alu", "achieved": tf, "peak": FP64_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": tf / FP64_PEAK_TFLOPS, "flop": flop},
            "cl_sample": {str(l): float(c[l]) for l in (2, 10, 100, 1000, 4000)}}
+    if not args.no_cpu:
+        # The oracle's direct sum costs npix * lmax^2 / 2 terms, so at
+        # lmax = 2 Nside its time grows as Nside^4: it is timed on the same
+        # call at Nside = 128 and scaled.
+        import oracle
+        ns = 128
+        small = np.random.default_rng(515).standard_normal(12 * ns * ns)
+        _log(f"bench alm: oracle at Nside={ns}")
+        t0 = time.perf_counter()
+        oracle.alm2cl(2 * ns, oracle.map2alm(ns, 2 * ns, small))
+        dt = time.perf_counter() - t0
+        est = dt * (nside / ns) ** 4
+        res["cpu_baseline"] = {"value": est, "unit": "s", "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"map2alm + alm2cl at Nside={ns}, lmax={2 * ns} in {dt:.1f} s, "
+                                         f"scaled by (Nside ratio)^4 = {(nside / ns) ** 4:.0f} to "
+                                         f"Nside={nside}"}
     print(json.dumps(res), flush=True)
 
 
@@ -644,8 +690,9 @@ def bench_config4(args, B, torch):
     pairs = st["pairs"]
     res = {"metric": "config4 forward + adjoint pairs/s", "forward_pairs_per_s": pairs / tf,
            "adjoint_pairs_per_s": pairs / tb, "pairs": pairs, "forward_ms": tf * 1e3,
-           "adjoint_ms": tb * 1e3, "adjoint_kernel_ms": st["ms_backward"],
-           "forward_accuracy_vs_oracle": _sampled_accuracy(torch, w, m, 4000, seed=213)}
+           "adjoint_ms": tb * 1e3, "adjoint_kernel_ms": st["ms_backward"]}
+    res["forward_accuracy_vs_oracle"], dt = _sampled_accuracy(torch, w, m, 4000, seed=213)
+    res["cpu_baseline"] = _sampled_cpu_baseline(w, pairs, 4000, dt)
     print(json.dumps(res), flush=True)
 
 
