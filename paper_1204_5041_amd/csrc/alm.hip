@@ -248,11 +248,15 @@ __global__ void k_lambda_mm(int64_t nside, int64_t mmax, double* lam_v, int32_t*
 
 // Step 2a': the recursion coefficients of every (l, m), l > m, at a_lm's
 // position: coef[2 i] = A_lm, coef[2 i + 1] = B_lm (B = 0 and A = sqrt(2m+3)
-// at l = m + 1); one thread per m.
+// at l = m + 1), and A = 1, B = -1 at l = m, so that one step from
+// (lambda_{m-1,m}, lambda_{m-2,m}) = (0, lambda_mm) gives lambda_mm exactly;
+// one thread per m.
 __global__ void k_leg_coef(int64_t lmax, double* coef) {
   const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (m > lmax) return;
   const double mmd = (double)m;
+  coef[2 * alm_idx(lmax, m, m)] = 1.0;
+  coef[2 * alm_idx(lmax, m, m) + 1] = -1.0;
   for (int64_t l = m + 1; l <= lmax; ++l) {
     const int64_t i = alm_idx(lmax, l, m);
     if (l == m + 1) {
@@ -285,27 +289,85 @@ __device__ __forceinline__ double dpp_f64(double x) {
                                           (unsigned)lo));
 }
 
-// Sum over the wavefront's 64 lanes, complete in lane 63, with register
-// moves only: lane pairs and quad halves (quad_perm), 8- and 16-lane groups
-// (row half mirror, row mirror), then rows 0+1 and 2+3 (row broadcast 15)
-// and all four (row broadcast 31).
-__device__ __forceinline__ double wave_sum_to_last(double x) {
-  x += dpp_f64<0xB1, 0xf>(x);    // quad_perm [1,0,3,2]
-  x += dpp_f64<0x4E, 0xf>(x);    // quad_perm [2,3,0,1]
-  x += dpp_f64<0x141, 0xf>(x);   // row_half_mirror
-  x += dpp_f64<0x140, 0xf>(x);   // row_mirror
-  x += dpp_f64<0x142, 0xa>(x);   // row_bcast:15 into rows 1 and 3
-  x += dpp_f64<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3
-  return x;
+// The sum over the wavefront of x (lanes with bit b of the lane index clear)
+// and of y (bit b set) as one register: the halves are exchanged across
+// lanes x <-> x + 2^b and added.  b = 5 and 4 use the gfx950 half and row
+// swaps; b = 3 and 2 use a row mirror and a half-row mirror written into
+// the lanes that keep x (banks kLoBanks) and those that keep y (kHiBanks).
+__device__ __forceinline__ double sum_swap32(double x, double y) {
+  const unsigned long long ux = (unsigned long long)__double_as_longlong(x);
+  const unsigned long long uy = (unsigned long long)__double_as_longlong(y);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ux, (unsigned)uy, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(ux >> 32), (unsigned)(uy >> 32),
+                                                   false, false);
+  const double a = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+  const double b = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+  return a + b;
+}
+
+__device__ __forceinline__ double sum_swap16(double x, double y) {
+  const unsigned long long ux = (unsigned long long)__double_as_longlong(x);
+  const unsigned long long uy = (unsigned long long)__double_as_longlong(y);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ux, (unsigned)uy, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(ux >> 32), (unsigned)(uy >> 32),
+                                                   false, false);
+  const double a = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+  const double b = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+  return a + b;
+}
+
+// old, with the lanes of kBanks replaced by src moved by DPP pattern kCtrl.
+template <int kCtrl, int kBanks>
+__device__ __forceinline__ double dpp_into(double old, double src) {
+  const unsigned long long uo = (unsigned long long)__double_as_longlong(old);
+  const unsigned long long us = (unsigned long long)__double_as_longlong(src);
+  const int lo = __builtin_amdgcn_update_dpp((int)(unsigned)uo, (int)(unsigned)us, kCtrl, 0xf,
+                                             kBanks, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(uo >> 32), (int)(unsigned)(us >> 32),
+                                             kCtrl, 0xf, kBanks, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                          (unsigned)lo));
+}
+
+template <int kCtrl, int kLoBanks, int kHiBanks>
+__device__ __forceinline__ double sum_mirror(double x, double y) {
+  return dpp_into<kCtrl, kLoBanks>(y, x) + dpp_into<kCtrl, kHiBanks>(x, y);
+}
+
+// Sixteen values per lane summed over the wavefront: afterwards every lane
+// of quad (lane >> 2) holds the total of value (lane >> 2).  Each of the
+// four halving steps pairs each lane with one whose partial sums cover a
+// disjoint set of lanes, so a lane's total covers all 64 at the end.
+__device__ __forceinline__ double wave_sum16(const double v[16]) {
+  double r8[8], r4[4], r2[2];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) r8[k] = sum_swap32(v[k], v[k + 8]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r4[k] = sum_swap16(r8[k], r8[k + 4]);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) r2[k] = sum_mirror<0x140, 0x3, 0xc>(r4[k], r4[k + 2]);  // row_mirror
+  double r = sum_mirror<0x141, 0x5, 0xa>(r2[0], r2[1]);                               // row_half_mirror
+  r += dpp_f64<0x4E, 0xf>(r);   // quad_perm [2,3,0,1]
+  r += dpp_f64<0xB1, 0xf>(r);   // quad_perm [1,0,3,2]
+  return r;
 }
 
 // Step 2b: partial a_lm of one block of 64 * kRingsPerLane ring pairs, for
 // one m: part[blk * S + idx(l, m)] = sum over the block's pairs of
-// lambda_lm(z) (F_north +- F_south), the sign (-1)^(l+m).
+// lambda_lm(z) (F_north +- F_south), the sign (-1)^(l+m).  Degrees are taken
+// eight at a time: each lane keeps the eight partial sums (real and
+// imaginary) and the wavefront sums all sixteen at once.  The 2^(600 e)
+// scale of a ring's lambda is carried by its two Fourier factors instead
+// (exact while they stay normal; a ring whose lambda is below 2^-177 gives
+// products far below any a_lm and may lose them), so that a step is the
+// recursion and two multiply-adds.
 __global__ void __launch_bounds__(256) k_legendre(int64_t nside, int64_t lmax, int64_t mmax,
-                                                 const double* F, const double* lam_v,
-                                                 const int32_t* lam_e, const double* ring_z,
-                                                 const double* coef, int64_t nblk, double* part) {
+                                                 const double* __restrict__ F,
+                                                 const double* __restrict__ lam_v,
+                                                 const int32_t* __restrict__ lam_e,
+                                                 const double* __restrict__ ring_z,
+                                                 const double* __restrict__ coef, int64_t nblk,
+                                                 double* __restrict__ part) {
   const int lane = threadIdx.x & 63;
   const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) +
                        __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -318,14 +380,10 @@ __global__ void __launch_bounds__(256) k_legendre(int64_t nside, int64_t lmax, i
   double z[kRingsPerLane], cur[kRingsPerLane], prev[kRingsPerLane];
   double er[kRingsPerLane], ei[kRingsPerLane], orr[kRingsPerLane], oi[kRingsPerLane];
   int32_t sc[kRingsPerLane];
-#pragma unroll
-  for (int k = 0; k < kRingsPerLane; ++k) {
-    const int64_t q = (blk * kRingsPerLane + k) * 64 + lane;   // pair index, 0-based
-    z[k] = 0.0;
-    cur[k] = 0.0;
-    prev[k] = 0.0;
+  // Fourier factors of pair k scaled by 2^(600 sc[k]).
+  auto factors = [&](int k) {
+    const int64_t q = (blk * kRingsPerLane + k) * 64 + lane;
     er[k] = ei[k] = orr[k] = oi[k] = 0.0;
-    sc[k] = 0;
     if (q < npair) {
       const int64_t north = q + 1;
       const int64_t south = nring + 1 - north;   // equal to north for the equator ring
@@ -336,68 +394,91 @@ __global__ void __launch_bounds__(256) k_legendre(int64_t nside, int64_t lmax, i
         sr = fs[0];
         si = fs[1];
       }
-      er[k] = fn[0] + sr;
-      ei[k] = fn[1] + si;
-      orr[k] = fn[0] - sr;
-      oi[k] = fn[1] - si;
+      const int e = kLegScale * sc[k];
+      er[k] = ldexp(fn[0] + sr, e);
+      ei[k] = ldexp(fn[1] + si, e);
+      orr[k] = ldexp(fn[0] - sr, e);
+      oi[k] = ldexp(fn[1] - si, e);
+    }
+  };
+#pragma unroll
+  for (int k = 0; k < kRingsPerLane; ++k) {
+    const int64_t q = (blk * kRingsPerLane + k) * 64 + lane;   // pair index, 0-based
+    z[k] = 0.0;
+    cur[k] = 0.0;
+    prev[k] = 0.0;
+    sc[k] = 0;
+    if (q < npair) {
       z[k] = ring_z[q];
-      cur[k] = lam_v[m * npair + q];
+      prev[k] = lam_v[m * npair + q];   // the step at l = m moves it to cur
       sc[k] = lam_e[m * npair + q];
     }
+    factors(k);
   }
   const double big = ldexp(1.0, kLegScale);
   double* out = part + 2 * blk * ((lmax + 1) * (lmax + 2) / 2);
   cdp cf = (cdp)coef;
-  // lambda_{l,m} from lambda_{l-1,m} (cur) and lambda_{l-2,m} (prev).
-  auto step = [&](int64_t l) {
-    const int64_t i = alm_idx(lmax, l, m);
-    const double A = cf[2 * i], Bc = cf[2 * i + 1];
+  // Recursion coefficients of degrees l0 .. l0 + 7, the next group's
+  // requested one group ahead.  Degrees past lmax take lmax's: their steps
+  // run (every group is eight steps) but their sums are not written.
+  const int64_t row = alm_idx(lmax, m, m) - m;   // idx(l, m) = row + l
+  double cA[8], cB[8];
 #pragma unroll
-    for (int k = 0; k < kRingsPerLane; ++k) {
-      const double nx = A * (z[k] * cur[k] - Bc * prev[k]);
-      prev[k] = cur[k];
-      cur[k] = nx;
-    }
-  };
-  // a_lm's partial for this block: (F_north + F_south) for even l + m,
-  // (F_north - F_south) for odd.
-  auto emit = [&](int64_t l, bool even) {
-    double sr = 0.0, si = 0.0;
+  for (int g = 0; g < 8; ++g) {
+    const int64_t i = row + (m + g < lmax ? m + g : lmax);
+    cA[g] = cf[2 * i];
+    cB[g] = cf[2 * i + 1];
+  }
+  // The ring data loaded above has arrived: without this wait the loop's
+  // first use of it waits on every vector memory operation in flight, the
+  // previous group's store included, in every iteration.
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+  for (int64_t l0 = m; l0 <= lmax; l0 += 8) {
+    double nA[8], nB[8];
 #pragma unroll
-    for (int k = 0; k < kRingsPerLane; ++k) {
-      const double lam = ldexp(cur[k], kLegScale * sc[k]);
-      sr = fma(lam, even ? er[k] : orr[k], sr);
-      si = fma(lam, even ? ei[k] : oi[k], si);
+    for (int g = 0; g < 8; ++g) {
+      const int64_t i = row + (l0 + 8 + g < lmax ? l0 + 8 + g : lmax);
+      nA[g] = cf[2 * i];
+      nB[g] = cf[2 * i + 1];
     }
-    sr = wave_sum_to_last(sr);
-    si = wave_sum_to_last(si);
-    if (lane == 63) {
-      const int64_t idx = alm_idx(lmax, l, m);
-      out[2 * idx] = sr;
-      out[2 * idx + 1] = si;
-    }
-  };
-  emit(m, true);
-  // Two degrees per iteration, so the parity of l + m is fixed at compile
-  // time in each half.
-  for (int64_t l = m + 1; l <= lmax; l += 2) {
-    // Bring scaled values back once they have grown (growth over 16 steps
+    __builtin_amdgcn_sched_barrier(0);    // issue the requests before the arithmetic
+    // Bring scaled values back once they have grown (growth over 8 steps
     // stays far below the 2^423 headroom above 2^600).
-    if (((l - m - 1) & 15) == 0) {
 #pragma unroll
-      for (int k = 0; k < kRingsPerLane; ++k) {
-        if (sc[k] < 0 && fabs(cur[k]) > big) {
-          cur[k] = ldexp(cur[k], -kLegScale);
-          prev[k] = ldexp(prev[k], -kLegScale);
-          sc[k] += 1;
-        }
+    for (int k = 0; k < kRingsPerLane; ++k) {
+      if (sc[k] < 0 && fmax(fabs(cur[k]), fabs(prev[k])) > big) {
+        cur[k] = ldexp(cur[k], -kLegScale);
+        prev[k] = ldexp(prev[k], -kLegScale);
+        sc[k] += 1;
+        factors(k);
       }
     }
-    step(l);
-    emit(l, false);
-    if (l + 1 <= lmax) {
-      step(l + 1);
-      emit(l + 1, true);
+    double acc[16];
+#pragma unroll
+    for (int g = 0; g < 16; ++g) acc[g] = 0.0;
+    // Degree l0 + g: l + m has the parity of g, so even g takes
+    // F_north + F_south and odd g F_north - F_south.
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+#pragma unroll
+      for (int k = 0; k < kRingsPerLane; ++k) {
+        const double nx = cA[g] * fma(z[k], cur[k], -(cB[g] * prev[k]));
+        prev[k] = cur[k];
+        cur[k] = nx;
+      }
+#pragma unroll
+      for (int k = 0; k < kRingsPerLane; ++k) {
+        acc[2 * g] = fma(cur[k], (g & 1) ? orr[k] : er[k], acc[2 * g]);
+        acc[2 * g + 1] = fma(cur[k], (g & 1) ? oi[k] : ei[k], acc[2 * g + 1]);
+      }
+    }
+    const double tot = wave_sum16(acc);
+    const int v = lane >> 2;   // value held: real (even) or imaginary (odd) part of degree l0 + v/2
+    if ((lane & 3) == 0 && l0 + (v >> 1) <= lmax) out[2 * (row + l0) + v] = tot;
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+      cA[g] = nA[g];
+      cB[g] = nB[g];
     }
   }
 }

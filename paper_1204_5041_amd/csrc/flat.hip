@@ -101,7 +101,10 @@ __global__ void __launch_bounds__(kPreThreads) k_flat_rec(FlatArgs A) {
 __global__ void __launch_bounds__(256) k_flat32(FlatArgs A, int64_t ntiles, int64_t tpr,
                                                int64_t nsplit, double* parts) {
   const int lane = threadIdx.x & 63;
-  const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  // The wavefront's index through readfirstlane: everything derived from it
+  // (tile, record range, record addresses) then lives in scalar registers and
+  // the records arrive by scalar loads.
+  const int64_t item = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (item >= ntiles * nsplit) return;
   const int64_t split = item / ntiles, tile = item - split * ntiles;
   const int64_t y = tile / tpr;
@@ -126,8 +129,10 @@ __global__ void __launch_bounds__(256) k_flat32(FlatArgs A, int64_t ntiles, int6
   v4f pa = rec0[0], wa = rec0[1], pb = rec0[2], wb = rec0[3];
   for (int64_t r = 0; r < nrec; r += 2) {
     const int64_t rn = (r + 2 < nrec) ? r + 2 : r;
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): this window's records have arrived
     const v4f npa = recs[2 * rn], nwa = recs[2 * rn + 1];
     const v4f npb = recs[2 * rn + 2], nwb = recs[2 * rn + 3];
+    __builtin_amdgcn_sched_barrier(0);    // issue the requests before the arithmetic
     // x - s = ((x0 - s_hi) + j) - s_lo: the first two steps are exact for
     // a pixel near the segment, so s_lo is subtracted at the scale of the
     // pixel's own offset (subtracting it before adding j would round at the
@@ -136,13 +141,28 @@ __global__ void __launch_bounds__(256) k_flat32(FlatArgs A, int64_t ntiles, int6
     const float hxb = fx - pb.x, dyb = (fy - pb.z) - pb.w;
     const float ya2 = fmaf(dya, dya, kFlatTiny), yb2 = fmaf(dyb, dyb, kFlatTiny);
     const float aya = wa.y * dya, ayb = wb.y * dyb;
+    const float sla = to_vgpr(pa.y), slb = to_vgpr(pb.y);
+    const float uxa = to_vgpr(wa.x), uxb = to_vgpr(wb.x);
+    // Each stage runs over the lane's K pixels before the next starts, so
+    // that K independent operations separate dependent ones.
+    float xa[kFlatK], xb[kFlatK], qa[kFlatK], qb[kFlatK], rq[kFlatK];
 #pragma unroll
     for (int j = 0; j < kFlatK; ++j) {
-      const float xa = (hxa + (float)j) - pa.y, xb = (hxb + (float)j) - pb.y;
-      const float qa = fmaf(xa, xa, ya2), qb = fmaf(xb, xb, yb2);
-      const float na = fmaf(wa.x, xa, aya), nb = fmaf(wb.x, xb, ayb);
-      const float num = fmaf(na, qb, nb * qa);
-      part[j] = fmaf(num, __builtin_amdgcn_rcpf(qa * qb), part[j]);
+      xa[j] = (hxa + (float)j) - sla;
+      xb[j] = (hxb + (float)j) - slb;
+    }
+#pragma unroll
+    for (int j = 0; j < kFlatK; ++j) {
+      qa[j] = fmaf(xa[j], xa[j], ya2);
+      qb[j] = fmaf(xb[j], xb[j], yb2);
+    }
+#pragma unroll
+    for (int j = 0; j < kFlatK; ++j) rq[j] = __builtin_amdgcn_rcpf(qa[j] * qb[j]);
+#pragma unroll
+    for (int j = 0; j < kFlatK; ++j) {
+      const float na = fmaf(uxa, xa[j], aya), nb = fmaf(uxb, xb[j], ayb);
+      const float num = fmaf(na, qb[j], nb * qa[j]);
+      part[j] = fmaf(num, rq[j], part[j]);
     }
     pa = npa;
     wa = nwa;

@@ -505,13 +505,6 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t x) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// Copy a wave-uniform value into a vector register.
-__device__ __forceinline__ float to_vgpr(float x) {
-  float y;
-  asm("v_mov_b32 %0, %1" : "=v"(y) : "s"(x));
-  return y;
-}
-
 // Terms of one segment for close pairs: the direction difference n - P/R
 // is taken in FP64 (n from this wavefront's LDS slice, P/R from the FP64
 // record) and the rest in FP32.  An exact coincidence gives m = 0 and a

@@ -204,6 +204,15 @@ __device__ __forceinline__ int cone_state(const DevBox& bx, const SegGeom& g) {
   return 2;
 }
 
+// Copy a wave-uniform value into a vector register: an FP32 operation whose
+// operands are all vector registers issues at twice the rate of one that
+// reads a scalar register.
+__device__ __forceinline__ float to_vgpr(float x) {
+  float y;
+  asm("v_mov_b32 %0, %1" : "=v"(y) : "s"(x));
+  return y;
+}
+
 // Kahan update of (s, c) by x: s - c carries the sum.
 __device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
   const float y = x - c;
