@@ -630,15 +630,20 @@ def bench_alm(args, B, torch):
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / K
     size = (lmax + 1) * (lmax + 2) // 2
-    # Work of the path taken at this Nside (a power of two <= 2048): direct
-    # Fourier sums on the cap rings (4 FLOP per (pixel, m)), one FFT per belt
-    # ring (5 H log2 H for the half-length complex FFT, H = 2 Nside, and
-    # 10 per output m for the unpacking and the half-pixel phase), and the
+    # Work of the path taken at this Nside (a power of two <= 2048): per
+    # pair of cap rings of 4i pixels, nine power-of-two transforms of
+    # P = 2^ceil(log2(2i - 1)) points (5 P log2 P each: the chirp filter and
+    # two per quarter-length DFT), four pointwise products (6 P each) and
+    # 20 per output m for the radix-4 step, the unpacking and the
+    # half-pixel phase; one FFT per belt ring (5 H log2 H for the
+    # half-length complex FFT, H = 2 Nside, and 10 per output m); and the
     # Legendre sums (8 FLOP per (l, m, ring pair)).
-    cap_pix = 4 * nside * (nside - 1)
+    cap = 0.0
+    for i in range(1, nside):
+        P = 1 << max(0, (2 * i - 2).bit_length())
+        cap += 9 * 5.0 * P * math.log2(P) + 24.0 * P + 20.0 * (lmax + 1)
     H = 2 * nside
-    flop = (4.0 * cap_pix * (lmax + 1) +
-            (2 * nside + 1) * (5.0 * H * math.log2(H) + 10.0 * (lmax + 1)) +
+    flop = (cap + (2 * nside + 1) * (5.0 * H * math.log2(H) + 10.0 * (lmax + 1)) +
             8.0 * (2 * nside) * size)
     tf = flop / el / 1e12
     c = cl.cpu().numpy()

@@ -27,7 +27,7 @@ namespace csmap {
 namespace {
 
 constexpr int kLegScale = 600;   // values are v * 2^(600 e)
-constexpr int kRingsPerLane = 8; // ring pairs summed by one lane of the Legendre kernel
+constexpr int kRingsPerLane = 4; // ring pairs summed by one lane of the Legendre kernel
 constexpr int kAnchor = 32;      // Fourier twiddles are recomputed exactly every 32 pixels
 
 typedef const double __attribute__((address_space(4)))* cdp;
@@ -79,17 +79,15 @@ __device__ __forceinline__ void twiddle(int64_t t, int64_t L, double& c, double&
 // imaginary parts for m mod 4), so one complex twiddle serves four pixels.
 // Each lane advances e^{-i m 2 pi j / L} by one complex multiplication per
 // step and recomputes it exactly every kAnchor steps.
-// Rings skip_lo .. skip_hi are left to the FFT kernel.
+// Only rings ring_lo .. ring_hi; the others are left to the FFT kernels.
 __global__ void __launch_bounds__(256) k_ring_dft(int64_t nside, int64_t mmax, const double* map,
-                                                 double* F, int64_t skip_lo, int64_t skip_hi) {
+                                                 double* F, int64_t ring_lo, int64_t ring_hi) {
   const int lane = threadIdx.x & 63;
   const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) +
                        __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t mblocks = (mmax + 64) / 64;
-  const int64_t nring = 4 * nside - 1;
-  if (wave >= nring * mblocks) return;
-  const int64_t i = 1 + wave / mblocks;
-  if (i >= skip_lo && i <= skip_hi) return;
+  if (wave >= (ring_hi - ring_lo + 1) * mblocks) return;
+  const int64_t i = ring_lo + wave / mblocks;
   const int64_t m = (wave % mblocks) * 64 + lane;
   const Ring r = ring_of(nside, i);
   const int64_t L = r.len;
@@ -215,6 +213,211 @@ __global__ void __launch_bounds__(kFftThreads) k_ring_fft(int64_t nside, int64_t
     }
     out[2 * m] = xr;
     out[2 * m + 1] = xi;
+  }
+}
+
+// Step 1 for the polar-cap rings (Nside <= 2048).  North ring i and south
+// ring 4N - i both have L = 4i pixels at azimuths 2 pi (j + 1/2)/L; they are
+// taken together as z_j = x^N_j + i x^S_j, whose DFT Z gives both:
+// X^N_k = (Z_k + conj Z_{L-k})/2, X^S_k = (Z_k - conj Z_{L-k})/(2i), and
+// F_m = e^{-i pi m/L} X_{m mod L}.  L = 4i is split by four (j = 4n + r):
+// Z_{kappa + s i} = sum_r (-i)^{rs} e^{-2 pi i r kappa/L} D_r(kappa), D_r the
+// length-i DFT of z_{4n+r}.  i is arbitrary, so each D_r is taken by
+// Bluestein's chirp transform: with w_n = e^{-i pi n^2/i} (from n^2 mod 2i,
+// exact), D(kappa) = w_kappa sum_n (y_n w_n) conj(w_{kappa-n}), a linear
+// convolution computed as a cyclic one of power-of-two length P >= 2i - 1.
+// The convolution's transforms run in LDS: forward by decimation in
+// frequency (natural order in, bit-reversed out), the product with the
+// chirp filter's transform in that order, inverse by decimation in time
+// (bit-reversed in, natural out), so no reordering pass is needed.  The
+// filter's transform stays in registers over the four D_r, and D_r stays
+// in registers until the radix-4 step; Z goes through a global slot of 4i
+// values before the unpacking, which pairs k with L - k.  One workgroup
+// per ring pair; ctab[k] = e^{-2 pi i k/kCapMaxP}, k < kCapMaxP/2.
+constexpr int kCapThreads = 512;
+constexpr int64_t kCapMaxP = 4096;                     // 64 KB of LDS: i <= 2048, Nside <= 2049
+constexpr int kCapPer = (int)(kCapMaxP / kCapThreads);  // transform positions per thread
+constexpr int kCapKappa = kCapPer / 2;                  // D_r values per thread (i <= kCapMaxP / 2)
+
+__global__ void k_cap_table(double* ctab) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= kCapMaxP / 2) return;
+  double sp, cp;
+  sincospi((double)(2 * k) / (double)kCapMaxP, &sp, &cp);
+  ctab[2 * k] = cp;
+  ctab[2 * k + 1] = -sp;
+}
+
+__device__ __forceinline__ int64_t pow2_at_least(int64_t v) {
+  int64_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// w_n = e^{-i pi n^2 / len}.
+__device__ __forceinline__ void chirp(int64_t n, int64_t len, double& c, double& s) {
+  double sp, cp;
+  sincospi((double)((n * n) % (2 * len)) / (double)len, &sp, &cp);
+  c = cp;
+  s = -sp;
+}
+
+// Forward transform of P (a power of two <= kCapMaxP) values in LDS, natural
+// order in, bit-reversed order out.
+__device__ void fft_dif(double* x, int64_t P, const double* ctab) {
+  for (int64_t h = P >> 1; h >= 1; h >>= 1) {
+    const int64_t ts = kCapMaxP / (2 * h);
+    for (int64_t b = threadIdx.x; b < P / 2; b += kCapThreads) {
+      const int64_t pos = b & (h - 1);
+      const int64_t i0 = 2 * (b - pos) + pos, i1 = i0 + h;
+      const double wc = ctab[2 * pos * ts], ws = ctab[2 * pos * ts + 1];
+      const double ur = x[2 * i0], ui = x[2 * i0 + 1], vr = x[2 * i1], vi = x[2 * i1 + 1];
+      const double dr = ur - vr, di = ui - vi;
+      x[2 * i0] = ur + vr;
+      x[2 * i0 + 1] = ui + vi;
+      x[2 * i1] = fma(dr, wc, -(di * ws));
+      x[2 * i1 + 1] = fma(dr, ws, di * wc);
+    }
+    __syncthreads();
+  }
+}
+
+// Inverse transform (conjugate twiddles, no 1/P), bit-reversed order in,
+// natural order out.
+__device__ void fft_dit_inv(double* x, int64_t P, const double* ctab) {
+  for (int64_t h = 1; h < P; h <<= 1) {
+    const int64_t ts = kCapMaxP / (2 * h);
+    for (int64_t b = threadIdx.x; b < P / 2; b += kCapThreads) {
+      const int64_t pos = b & (h - 1);
+      const int64_t i0 = 2 * (b - pos) + pos, i1 = i0 + h;
+      const double wc = ctab[2 * pos * ts], ws = -ctab[2 * pos * ts + 1];
+      const double br = x[2 * i1], bi = x[2 * i1 + 1];
+      const double tr = fma(br, wc, -(bi * ws)), ti = fma(br, ws, bi * wc);
+      const double ar = x[2 * i0], ai = x[2 * i0 + 1];
+      x[2 * i0] = ar + tr;
+      x[2 * i0 + 1] = ai + ti;
+      x[2 * i1] = ar - tr;
+      x[2 * i1 + 1] = ai - ti;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kCapThreads) k_cap_bluestein(int64_t nside, int64_t mmax,
+                                                               const double* map,
+                                                               const double* ctab, double* zslot,
+                                                               double* F) {
+  extern __shared__ double xs[];   // P complex values, (re, im) interleaved
+  const int t = threadIdx.x;
+  const int64_t N = nside, i = 1 + blockIdx.x, L = 4 * i;
+  const int64_t P = pow2_at_least(2 * i - 1);
+  const double inv_p = 1.0 / (double)P;   // exact: P is a power of two
+  const double* xn = map + 2 * i * (i - 1);
+  const double* xsth = map + 12 * N * N - 2 * i * (i + 1);
+  // Chirp filter b_m = conj(w_m) at m mod P for |m| < i, then its transform.
+  for (int64_t p = t; p < P; p += kCapThreads) {
+    const int64_t n = p < i ? p : (p > P - i ? P - p : -1);
+    double br = 0.0, bi = 0.0;
+    if (n >= 0) {
+      double c, s;
+      chirp(n, i, c, s);
+      br = c;
+      bi = -s;
+    }
+    xs[2 * p] = br;
+    xs[2 * p + 1] = bi;
+  }
+  __syncthreads();
+  fft_dif(xs, P, ctab);
+  double Br[kCapPer], Bi[kCapPer];
+#pragma unroll
+  for (int j = 0; j < kCapPer; ++j) {
+    const int64_t p = t + (int64_t)j * kCapThreads;
+    Br[j] = p < P ? xs[2 * p] : 0.0;
+    Bi[j] = p < P ? xs[2 * p + 1] : 0.0;
+  }
+  __syncthreads();
+  // E_r(kappa) = e^{-2 pi i r kappa / L} D_r(kappa).
+  double Er[4][kCapKappa], Ei[4][kCapKappa];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    for (int64_t p = t; p < P; p += kCapThreads) {
+      double ar = 0.0, ai = 0.0;
+      if (p < i) {
+        const double yr = xn[4 * p + r], yi = xsth[4 * p + r];
+        double c, s;
+        chirp(p, i, c, s);
+        ar = fma(yr, c, -(yi * s));
+        ai = fma(yr, s, yi * c);
+      }
+      xs[2 * p] = ar;
+      xs[2 * p + 1] = ai;
+    }
+    __syncthreads();
+    fft_dif(xs, P, ctab);
+#pragma unroll
+    for (int j = 0; j < kCapPer; ++j) {
+      const int64_t p = t + (int64_t)j * kCapThreads;
+      if (p < P) {
+        const double ar = xs[2 * p], ai = xs[2 * p + 1];
+        xs[2 * p] = fma(ar, Br[j], -(ai * Bi[j]));
+        xs[2 * p + 1] = fma(ar, Bi[j], ai * Br[j]);
+      }
+    }
+    __syncthreads();
+    fft_dit_inv(xs, P, ctab);
+#pragma unroll
+    for (int j = 0; j < kCapKappa; ++j) {
+      const int64_t kap = t + (int64_t)j * kCapThreads;
+      Er[r][j] = 0.0;
+      Ei[r][j] = 0.0;
+      if (kap < i) {
+        double c, s;
+        chirp(kap, i, c, s);
+        const double cr = xs[2 * kap] * inv_p, ci = xs[2 * kap + 1] * inv_p;
+        const double dr = fma(cr, c, -(ci * s)), di = fma(cr, s, ci * c);
+        double sp, cp;
+        sincospi((double)(2 * r * kap) / (double)L, &sp, &cp);
+        Er[r][j] = fma(dr, cp, di * sp);      // times e^{-i pi 2 r kappa / L}
+        Ei[r][j] = fma(di, cp, -(dr * sp));
+      }
+    }
+    __syncthreads();
+  }
+  // Radix-4 step: Z_{kappa + s i} = sum_r (-i)^{rs} E_r(kappa).
+  double* Z = zslot + 2 * (2 * i * (i - 1));
+#pragma unroll
+  for (int j = 0; j < kCapKappa; ++j) {
+    const int64_t kap = t + (int64_t)j * kCapThreads;
+    if (kap < i) {
+      const double s0r = Er[0][j] + Er[2][j], s0i = Ei[0][j] + Ei[2][j];
+      const double d0r = Er[0][j] - Er[2][j], d0i = Ei[0][j] - Ei[2][j];
+      const double s1r = Er[1][j] + Er[3][j], s1i = Ei[1][j] + Ei[3][j];
+      const double d1r = Er[1][j] - Er[3][j], d1i = Ei[1][j] - Ei[3][j];
+      Z[2 * kap] = s0r + s1r;                 // s = 0
+      Z[2 * kap + 1] = s0i + s1i;
+      Z[2 * (kap + i)] = d0r + d1i;           // s = 1: E0 - i E1 - E2 + i E3
+      Z[2 * (kap + i) + 1] = d0i - d1r;
+      Z[2 * (kap + 2 * i)] = s0r - s1r;       // s = 2
+      Z[2 * (kap + 2 * i) + 1] = s0i - s1i;
+      Z[2 * (kap + 3 * i)] = d0r - d1i;       // s = 3: E0 + i E1 - E2 - i E3
+      Z[2 * (kap + 3 * i) + 1] = d0i + d1r;
+    }
+  }
+  __syncthreads();
+  double* fn = F + 2 * (i - 1) * (mmax + 1);
+  double* fs = F + 2 * (4 * N - i - 1) * (mmax + 1);
+  for (int64_t m = t; m <= mmax; m += kCapThreads) {
+    const int64_t k = m % L, k2 = (L - k) % L;
+    const double zr = Z[2 * k], zi = Z[2 * k + 1], yr = Z[2 * k2], yi = Z[2 * k2 + 1];
+    const double nr = 0.5 * (zr + yr), ni = 0.5 * (zi - yi);    // (Z_k + conj Z_{L-k}) / 2
+    const double sr = 0.5 * (zi + yi), si = -0.5 * (zr - yr);   // (Z_k - conj Z_{L-k}) / (2i)
+    double sp, cp;
+    sincospi((double)(m % (2 * L)) / (double)L, &sp, &cp);      // e^{-i pi m / L} = cp - i sp
+    fn[2 * m] = fma(nr, cp, ni * sp);
+    fn[2 * m + 1] = fma(ni, cp, -(nr * sp));
+    fs[2 * m] = fma(sr, cp, si * sp);
+    fs[2 * m + 1] = fma(si, cp, -(sr * sp));
   }
 }
 
@@ -460,11 +663,18 @@ __global__ void __launch_bounds__(256) k_legendre(int64_t nside, int64_t lmax, i
     // F_north + F_south and odd g F_north - F_south.
 #pragma unroll
     for (int g = 0; g < 8; ++g) {
+      // The three operations of a step run over the lane's ring pairs one
+      // after the other, so that a dependent operation comes
+      // kRingsPerLane instructions after the one it waits for.
+      double t[kRingsPerLane];
+#pragma unroll
+      for (int k = 0; k < kRingsPerLane; ++k) t[k] = cB[g] * prev[k];
+#pragma unroll
+      for (int k = 0; k < kRingsPerLane; ++k) t[k] = fma(z[k], cur[k], -t[k]);
 #pragma unroll
       for (int k = 0; k < kRingsPerLane; ++k) {
-        const double nx = cA[g] * fma(z[k], cur[k], -(cB[g] * prev[k]));
         prev[k] = cur[k];
-        cur[k] = nx;
+        cur[k] = cA[g] * t[k];
       }
 #pragma unroll
       for (int k = 0; k < kRingsPerLane; ++k) {
@@ -517,15 +727,25 @@ __global__ void __launch_bounds__(256) k_alm2cl(int64_t lmax, const double* alm,
 
 // Scratch needs of map2alm at (nside, lmax): bytes of the Fourier table,
 // the lambda_mm tables and the block partials.
+// Doubles of the region that holds the Legendre partial sums; the cap
+// rings' Z slots (2 N (N - 1) complex values) use it first.
+static int64_t part_doubles(int64_t nside, int64_t lmax) {
+  const int64_t npair = 2 * nside;
+  const int64_t nblk = (npair + 64 * kRingsPerLane - 1) / (64 * kRingsPerLane);
+  const int64_t size = (lmax + 1) * (lmax + 2) / 2;
+  const int64_t zs = 4 * nside * (nside - 1);
+  return 2 * nblk * size > zs ? 2 * nblk * size : zs;
+}
+
 size_t map2alm_scratch_bytes(int64_t nside, int64_t lmax) {
   const int64_t M = lmax + 1;
   const int64_t nring = 4 * nside - 1, npair = 2 * nside;
-  const int64_t nblk = (npair + 64 * kRingsPerLane - 1) / (64 * kRingsPerLane);
   const int64_t size = (lmax + 1) * (lmax + 2) / 2;
   return sizeof(double) * (size_t)(2 * nring * M) + sizeof(double) * (size_t)(M * npair) +
          sizeof(int32_t) * (size_t)(M * npair) + sizeof(double) * (size_t)npair +
-         sizeof(double) * (size_t)(2 * size) + sizeof(double) * (size_t)(2 * nblk * size) +
-         sizeof(double) * (size_t)(2 * (4 * nside + 1)) + 7 * 256;
+         sizeof(double) * (size_t)(2 * size) + sizeof(double) * (size_t)part_doubles(nside, lmax) +
+         sizeof(double) * (size_t)(2 * (4 * nside + 1)) + sizeof(double) * (size_t)kCapMaxP +
+         8 * 256;
 }
 
 // All of map2alm on `st`; `scratch` holds map2alm_scratch_bytes(nside, lmax).
@@ -548,21 +768,39 @@ hipError_t launch_map2alm(int64_t nside, int64_t lmax, const double* map, double
   double* coef = (double*)p;
   p += align(sizeof(double) * (size_t)(2 * size));
   double* part = (double*)p;
-  p += align(sizeof(double) * (size_t)(2 * nblk * size));
+  p += align(sizeof(double) * (size_t)part_doubles(nside, lmax));
   double* tab = (double*)p;
+  p += align(sizeof(double) * (size_t)(2 * (4 * nside + 1)));
+  double* ctab = (double*)p;
   const int64_t mblocks = (lmax + 64) / 64;
-  const int64_t dft_waves = nring * mblocks;
   // Belt rings by FFT when their length 4N is a power of two whose half
-  // fits the LDS buffer; every other ring by direct sums.
+  // fits the LDS buffer; cap rings by the chirp transform when their
+  // convolutions fit it; every other ring by direct sums.
   const bool fft = (nside & (nside - 1)) == 0 && 2 * nside <= kFftMaxH;
+  const bool caps = nside >= 2 && nside - 1 <= kCapMaxP / 2;
   if (fft) {
     const int64_t L = 4 * nside;
     k_fft_table<<<dim3((unsigned)((L + 256) / 256)), dim3(256), 0, st>>>(L, tab);
     k_ring_fft<<<dim3((unsigned)(2 * nside + 1)), dim3(kFftThreads),
                  sizeof(double) * 2 * (size_t)(2 * nside), st>>>(nside, lmax, map, tab, F);
   }
-  k_ring_dft<<<dim3((unsigned)((dft_waves + 3) / 4)), dim3(256), 0, st>>>(
-      nside, lmax, map, F, fft ? nside : 0, fft ? 3 * nside : -1);
+  if (caps) {
+    int64_t P = 1;
+    while (P < 2 * (nside - 1) - 1) P <<= 1;
+    k_cap_table<<<dim3((unsigned)((kCapMaxP / 2 + 255) / 256)), dim3(256), 0, st>>>(ctab);
+    k_cap_bluestein<<<dim3((unsigned)(nside - 1)), dim3(kCapThreads),
+                      sizeof(double) * 2 * (size_t)P, st>>>(nside, lmax, map, ctab, part, F);
+  }
+  // Rings left for the direct sums: none, the belt, or all (Nside 1 has no
+  // cap rings; a belt done by FFT implies Nside <= 2048, where the caps
+  // take the chirp transform).
+  const bool caps_done = caps || nside == 1;
+  if (!(fft && caps_done)) {
+    const int64_t lo = caps_done ? nside : 1, hi = caps_done ? 3 * nside : 4 * nside - 1;
+    const int64_t dft_waves = (hi - lo + 1) * mblocks;
+    k_ring_dft<<<dim3((unsigned)((dft_waves + 3) / 4)), dim3(256), 0, st>>>(nside, lmax, map, F,
+                                                                           lo, hi);
+  }
   k_lambda_mm<<<dim3((unsigned)((npair + 255) / 256)), dim3(256), 0, st>>>(nside, lmax, lam_v,
                                                                           lam_e, ring_z);
   k_leg_coef<<<dim3((unsigned)((M + 63) / 64)), dim3(64), 0, st>>>(lmax, coef);
