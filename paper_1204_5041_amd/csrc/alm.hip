@@ -453,25 +453,26 @@ __global__ void k_lambda_mm(int64_t nside, int64_t mmax, double* lam_v, int32_t*
 // position: coef[2 i] = A_lm, coef[2 i + 1] = B_lm (B = 0 and A = sqrt(2m+3)
 // at l = m + 1), and A = 1, B = -1 at l = m, so that one step from
 // (lambda_{m-1,m}, lambda_{m-2,m}) = (0, lambda_mm) gives lambda_mm exactly;
-// one thread per m.
+// one thread per (l, m): blockIdx.y is m, l runs over x.
 __global__ void k_leg_coef(int64_t lmax, double* coef) {
-  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m > lmax) return;
-  const double mmd = (double)m;
-  coef[2 * alm_idx(lmax, m, m)] = 1.0;
-  coef[2 * alm_idx(lmax, m, m) + 1] = -1.0;
-  for (int64_t l = m + 1; l <= lmax; ++l) {
-    const int64_t i = alm_idx(lmax, l, m);
-    if (l == m + 1) {
-      coef[2 * i] = sqrt(2.0 * mmd + 3.0);
-      coef[2 * i + 1] = 0.0;
-    } else {
-      const double ll = (double)l;
-      coef[2 * i] = sqrt((4.0 * ll * ll - 1.0) / (ll * ll - mmd * mmd));
-      coef[2 * i + 1] = sqrt(((ll - 1.0) * (ll - 1.0) - mmd * mmd) /
-                             (4.0 * (ll - 1.0) * (ll - 1.0) - 1.0));
-    }
+  const int64_t m = blockIdx.y;
+  const int64_t l = m + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l > lmax) return;
+  const int64_t i = alm_idx(lmax, l, m);
+  const double mmd = (double)m, ll = (double)l;
+  double A, B;
+  if (l == m) {
+    A = 1.0;
+    B = -1.0;
+  } else if (l == m + 1) {
+    A = sqrt(2.0 * mmd + 3.0);
+    B = 0.0;
+  } else {
+    A = sqrt((4.0 * ll * ll - 1.0) / (ll * ll - mmd * mmd));
+    B = sqrt(((ll - 1.0) * (ll - 1.0) - mmd * mmd) / (4.0 * (ll - 1.0) * (ll - 1.0) - 1.0));
   }
+  coef[2 * i] = A;
+  coef[2 * i + 1] = B;
 }
 
 __device__ __forceinline__ double wave_sum(double x) {
@@ -803,7 +804,7 @@ hipError_t launch_map2alm(int64_t nside, int64_t lmax, const double* map, double
   }
   k_lambda_mm<<<dim3((unsigned)((npair + 255) / 256)), dim3(256), 0, st>>>(nside, lmax, lam_v,
                                                                           lam_e, ring_z);
-  k_leg_coef<<<dim3((unsigned)((M + 63) / 64)), dim3(64), 0, st>>>(lmax, coef);
+  k_leg_coef<<<dim3((unsigned)((M + 255) / 256), (unsigned)M), dim3(256), 0, st>>>(lmax, coef);
   const int64_t leg_waves = M * nblk;
   k_legendre<<<dim3((unsigned)((leg_waves + 3) / 4)), dim3(256), 0, st>>>(
       nside, lmax, lmax, F, lam_v, lam_e, ring_z, coef, nblk, part);
