@@ -105,6 +105,7 @@ struct HostBox {
   double rot[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
   double cone_dir[3] = {0, 0, 1};
   double cone_cos_out = -2.0, cone_cos_in = 2.0;
+  ConeEdges cone_edge = {};
   int dtype;
   int64_t n;
   int64_t raw_byte_off;
@@ -257,6 +258,11 @@ csmap_status prepare(csmap_sky* s) {
     for (int k = 0; k < 3; ++k) d.cone_dir[k] = h.cone_dir[k];
     d.cone_cos_out = h.cone_cos_out;
     d.cone_cos_in = h.cone_cos_in;
+    for (int e = 0; e < 4; ++e) {
+      for (int k = 0; k < 3; ++k) d.cone_n[e][k] = h.cone_edge.n[e][k];
+      d.cone_hi[e] = h.cone_edge.hi[e];
+      d.cone_lo[e] = h.cone_edge.lo[e];
+    }
     d.n = h.n;
     d.raw_off = 0;
     d.rec_off = rec;
@@ -674,8 +680,10 @@ static csmap_status add_box_impl(csmap_sky* s, const csmap_box* box, int snapsho
     h.cone_nside = cone->nside;
     h.cone_pix = cone->pix;
     for (int k = 0; k < 9; ++k) h.rot[k] = cone->rot[k];
-    if (cone->nside > 0)
+    if (cone->nside > 0) {
       cone_caps(cone->nside, cone->pix, h.cone_dir, h.cone_cos_out, h.cone_cos_in);
+      cone_edges(cone->nside, cone->pix, h.cone_edge);
+    }
   }
   for (int k = 0; k < 3; ++k) {
     h.geom.origin[k] = box->origin[k];

@@ -194,6 +194,50 @@ void cone_caps(int64_t nside, int64_t pix, double dir[3], double& cos_out, doubl
   cos_in = inner > 0.0 ? cos(inner) : 2.0;
 }
 
+void cone_edges(int64_t nside, int64_t pix, ConeEdges& out) {
+  const Cell c = cell_of(nside, pix);
+  double ctr[3];
+  cell_dir(c, c.a + 0.5, c.b + 0.5, ctr);
+  double pts[4][kEdgeSamples + 1][3];
+  double lo_cap = 1.0;
+  for (int e = 0; e < 4; ++e)
+    for (int k = 0; k <= kEdgeSamples; ++k) {
+      edge_point(c, e, k, pts[e][k]);
+      lo_cap = std::min(lo_cap, dot3(ctr, pts[e][k]));
+    }
+  const double a_out = 1.02 * acos(std::max(-1.0, std::min(1.0, lo_cap))) + 1e-7;
+  const double margin = 1e-7 + (4.0 * a_out / kEdgeSamples) * (4.0 * a_out / kEdgeSamples);
+  bool ok = a_out < 0.5 * kPi;
+  for (int e = 0; e < 4; ++e) {
+    const double* p0 = pts[e][0];
+    const double* p1 = pts[e][kEdgeSamples];
+    double n[3] = {p0[1] * p1[2] - p0[2] * p1[1], p0[2] * p1[0] - p0[0] * p1[2],
+                   p0[0] * p1[1] - p0[1] * p1[0]};
+    const double len = sqrt(dot3(n, n));
+    if (!(len > 0.0)) {
+      ok = false;
+      n[0] = 1.0;
+      n[1] = n[2] = 0.0;
+    } else {
+      const double sgn = dot3(n, ctr) < 0.0 ? -1.0 : 1.0;
+      for (int k = 0; k < 3; ++k) n[k] *= sgn / len;
+    }
+    double hi = -INFINITY, lo = INFINITY;
+    for (int k = 0; k <= kEdgeSamples; ++k) hi = std::max(hi, dot3(n, pts[e][k]));
+    for (int f = 0; f < 4; ++f)
+      for (int k = 0; k <= kEdgeSamples; ++k) lo = std::min(lo, dot3(n, pts[f][k]));
+    for (int k = 0; k < 3; ++k) out.n[e][k] = n[k];
+    out.hi[e] = hi + margin;
+    out.lo[e] = lo - margin;
+    ok = ok && dot3(n, ctr) > out.hi[e];
+  }
+  if (!ok)
+    for (int e = 0; e < 4; ++e) {
+      out.hi[e] = INFINITY;
+      out.lo[e] = -INFINITY;
+    }
+}
+
 double cone_grid_slack(int64_t nside, double r_in, double r_out, double side) {
   // Cones congruent under quarter turns, the north-south mirror and (in the
   // belt) turns by one pixel share their slack: visit one of each.

@@ -41,6 +41,23 @@ void cone_place(int64_t nside, int64_t pix, int axis, double r_in, double r_out,
 // of 2% of the cap radius plus 1e-7 rad beyond the sampled boundary.
 void cone_caps(int64_t nside, int64_t pix, double dir[3], double& cos_out, double& cos_in);
 
+// Between the caps, each edge e of the pixel is bracketed by the plane
+// through the origin and the edge's two end corners, with unit normal n[e]
+// pointing into the pixel: hi[e] is the largest n[e].d over edge e and lo[e]
+// the smallest n[e].d over the whole boundary, each moved by a margin of
+// 1e-7 + (4 a_out / 256)^2 (a_out the outer cap's radius) for the sampling
+// of the edges.  A direction inside the outer cap with n[e].d > hi[e] for
+// every e is inside the pixel, and one with n[e].d < lo[e] for some e is
+// outside it: a great-circle arc from the centre of length below pi/2 along
+// which n[e].d falls to the boundary and rises again cannot exist.  When the
+// centre is not strictly inside every slab or the cap is not below pi/2,
+// hi = +inf and lo = -inf (the planes never decide).
+struct ConeEdges {
+  double n[4][3];
+  double hi[4], lo[4];
+};
+void cone_edges(int64_t nside, int64_t pix, ConeEdges& out);
+
 // Smallest slack over every cone of the grid (the same for every axis).
 double cone_grid_slack(int64_t nside, double r_in, double r_out, double side);
 

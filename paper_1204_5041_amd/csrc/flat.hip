@@ -220,15 +220,16 @@ hipError_t launch_flat(const FlatArgs& A, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Record ranges per tile: one when the tiles alone give a launch about 2048
-// wavefronts (two per SIMD), else enough ranges to get there, at most 16
-// (small patches).  More ranges on large patches measured slower: the
-// wavefronts' record streams then compete for the scalar cache.  With more
-// than one range, part holds that many maps of nx ny doubles.
+// Record ranges per tile: enough that the launch has about 32768
+// wavefronts (32 per SIMD), at most 16.  Each wavefront's chain of
+// dependent operations leaves the SIMD idle unless several others are
+// resident; on the 1024 x 1024 patch (2048 tiles) 1, 2, 4, 8 and 16 ranges
+// measured 445, 407, 384, 372 and 366 ms.  With more than one range, part
+// holds that many maps of nx ny doubles, summed in range order.
 int64_t flat_splits(int64_t nx, int64_t ny) {
   const int64_t tpr = (nx + 64 * kFlatK - 1) / (64 * kFlatK);
   const int64_t ntiles = tpr * ny;
-  int64_t ns = (2048 + ntiles - 1) / ntiles;
+  int64_t ns = (32768 + ntiles - 1) / ntiles;
   return ns < 1 ? 1 : (ns > 16 ? 16 : ns);
 }
 

@@ -30,9 +30,14 @@ struct DevBox {
   double rot[9];     // row-major box-to-sky rotation (rotated == 1)
   // cone_nside > 0: caps around the cone axis that bracket the pixel with a
   // wide margin: cos(angle to cone_dir) < cone_cos_out is certainly outside,
-  // > cone_cos_in certainly inside; only directions in between need ang2pix.
+  // > cone_cos_in certainly inside; in between, the planes through the ends
+  // of the pixel's four edges decide most directions: n_e.d > cone_hi[e] for
+  // every e is inside, n_e.d < cone_lo[e] for some e outside; only the rest
+  // need ang2pix.
   double cone_dir[3];
   double cone_cos_out, cone_cos_in;
+  double cone_n[4][3];
+  double cone_hi[4], cone_lo[4];
 };
 
 // Per-box result of the light-cone compaction, written on the device.

@@ -78,56 +78,100 @@ constexpr int kPrePer = kPreBlock / kPreThreads;
 
 // The pixel tests a block still needs are queued in LDS and run with every
 // lane busy, rather than by the few lanes of each wavefront that need them.
+// The few directions that neither the caps nor the edge planes settle
+// (about 0.3% of the segments of a stacked grid) are queued in LDS by their
+// position in the block and tested once the block's segments are done: their
+// geometry is formed again and ang2pix runs with every lane busy.  Queuing
+// positions rather than event coordinates keeps the block's LDS at 4 KB.
+// A block belongs to one box, so its storage type and kind are uniform: the
+// body is specialised on them, and the common case (positions stored, not
+// slab-start snapshots) requests all of a thread's positions before using
+// any of them.
+struct PreShared {
+  unsigned long long flags[kPreWords];
+  int qpos[kPreBlock];
+  int nq;
+  ConeTest cone;
+};
+
+__device__ __forceinline__ void pre_keep(const PreArgs& A, const DevBox& bx, PreShared& sh,
+                                         const SegGeom& g, int pos, bool& keep) {
+  keep = g.keep;
+  if (keep && A.flat_on) {
+    const double D = (A.flat_dir[0] * g.P[0] + A.flat_dir[1] * g.P[1]) + A.flat_dir[2] * g.P[2];
+    keep = (D > 0.0) && (D > A.flat_cos * g.R);
+  }
+  if (keep && bx.cone_nside > 0) {
+    const int st = cone_state(sh.cone, g);
+    keep = st == 1;
+    if (st == 2) sh.qpos[atomicAdd(&sh.nq, 1)] = pos;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void pre_count_pos(const PreArgs& A, const DevBox& bx, PreShared& sh,
+                                              const T* x, int64_t base) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // Indices past the box's end read its last segment (a block of the box
+  // starts below n) and are not used: the loads carry no branch and are all
+  // in flight together.
+  T v[kPrePer][3];
+#pragma unroll
+  for (int j = 0; j < kPrePer; ++j) {
+    const int64_t i = base + threadIdx.x + kPreThreads * j;
+    const int64_t ic = i < bx.n ? i : bx.n - 1;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[j][k] = x[3 * ic + k];
+  }
+#pragma unroll
+  for (int j = 0; j < kPrePer; ++j) {
+    const int pos = threadIdx.x + kPreThreads * j;
+    bool keep = false;
+    if (base + pos < bx.n) {
+      const double xd[3] = {(double)v[j][0], (double)v[j][1], (double)v[j][2]};
+      pre_keep(A, bx, sh, seg_pos_at(bx, xd, A.eta0), pos, keep);
+    }
+    const unsigned long long bal = __ballot(keep);
+    if (lane == 0) sh.flags[(kPreThreads / 64) * j + wave] = bal;
+  }
+}
+
+__device__ __forceinline__ void pre_count_snap(const PreArgs& A, const DevBox& bx, PreShared& sh,
+                                               const char* raw, int64_t base) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int j = 0; j < kPrePer; ++j) {
+    const int pos = threadIdx.x + kPreThreads * j;
+    bool keep = false;
+    if (base + pos < bx.n) pre_keep(A, bx, sh, seg_geom(bx, raw, base + pos, A.eta0), pos, keep);
+    const unsigned long long bal = __ballot(keep);
+    if (lane == 0) sh.flags[(kPreThreads / 64) * j + wave] = bal;
+  }
+}
+
 __global__ void __launch_bounds__(kPreThreads) k_pre_count(PreArgs A) {
   const int64_t blk = blockIdx.x;
   const int b = ((ci32p)A.blk_box)[blk];
   const DevBox bx = load_box(A.boxes, b);
   const int64_t base = (blk - bx.blk_off) * kPreBlock;
   const char* raw = (const char*)A.raw + A.raw_byte_off[b];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __shared__ unsigned long long flags[kPreWords];
-  __shared__ double qp[3][kPreBlock];
-  __shared__ int qpos[kPreBlock];
-  __shared__ int nq;
-  if (threadIdx.x == 0) nq = 0;
+  __shared__ PreShared sh;
+  if (threadIdx.x == 0) sh.nq = 0;
+  if (bx.cone_nside > 0) load_cone(A.boxes, b, sh.cone);
   __syncthreads();
-  const bool cone = bx.cone_nside > 0;
-#pragma unroll
-  for (int j = 0; j < kPrePer; ++j) {
-    const int pos = threadIdx.x + kPreThreads * j;
-    const int64_t i = base + pos;
-    bool keep = false;
-    if (i < bx.n) {
-      const SegGeom g = bx.snapshot ? seg_geom(bx, raw, i, A.eta0) : seg_pos(bx, raw, i, A.eta0);
-      keep = g.keep;
-      if (keep && A.flat_on) {
-        const double D = (A.flat_dir[0] * g.P[0] + A.flat_dir[1] * g.P[1]) + A.flat_dir[2] * g.P[2];
-        keep = (D > 0.0) && (D > A.flat_cos * g.R);
-      }
-      if (keep && cone) {
-        const int st = cone_state(bx, g);
-        keep = st == 1;
-        if (st == 2) {
-          const int q = atomicAdd(&nq, 1);
-          qp[0][q] = g.P[0];
-          qp[1][q] = g.P[1];
-          qp[2][q] = g.P[2];
-          qpos[q] = pos;
-        }
-      }
-    }
-    // Keep flags, one 64-bit word per 64 consecutive segments.
-    const unsigned long long bal = __ballot(keep);
-    if (lane == 0) flags[(kPreThreads / 64) * j + wave] = bal;
-  }
+  if (bx.snapshot) pre_count_snap(A, bx, sh, raw, base);
+  else if (bx.dtype == 0) pre_count_pos(A, bx, sh, (const float*)raw, base);
+  else pre_count_pos(A, bx, sh, (const double*)raw, base);
   __syncthreads();
-  for (int q = threadIdx.x; q < nq; q += kPreThreads) {
-    if (ang2pix_ring(bx.cone_nside, qp[0][q], qp[1][q], qp[2][q]) == bx.cone_pix)
-      atomicOr(&flags[qpos[q] >> 6], 1ull << (qpos[q] & 63));
+  for (int q = threadIdx.x; q < sh.nq; q += kPreThreads) {
+    const int pos = sh.qpos[q];
+    const SegGeom g = bx.snapshot ? seg_geom(bx, raw, base + pos, A.eta0)
+                                  : seg_pos(bx, raw, base + pos, A.eta0);
+    if (ang2pix_ring(bx.cone_nside, g.P[0], g.P[1], g.P[2]) == bx.cone_pix)
+      atomicOr(&sh.flags[pos >> 6], 1ull << (pos & 63));
   }
   __syncthreads();
   if (threadIdx.x < kPreWords) {
-    const unsigned long long w = flags[threadIdx.x];
+    const unsigned long long w = sh.flags[threadIdx.x];
     A.blk_mask[blk * kPreWords + threadIdx.x] = w;
     int c = __popcll(w);
 #pragma unroll
@@ -188,7 +232,25 @@ __global__ void __launch_bounds__(256) k_pre_scan(PreArgs A, int64_t nbox) {
 // the block's keep flags.  A thread writes records base + t + kPreThreads j,
 // j < 4, so consecutive threads write consecutive records.
 __device__ __forceinline__ void emit_record(const PreArgs& A, const DevBox& bx, const char* raw,
-                                            int64_t li);
+                                            int64_t li, int64_t k0);
+
+// Last block k in [lo, hi] with pre[k] <= li (pre[lo] <= li must hold).
+__device__ __forceinline__ int64_t block_of_rank(const int64_t* pre, int64_t lo, int64_t hi,
+                                                 int64_t li) {
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= li) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// The workgroup's records (ranks base .. base + kPreBlock - 1) come from a
+// short run of consecutive source blocks: two searches over the box's block
+// prefixes find the run, whose prefixes are then staged in LDS, and each
+// record's block is found there (a run longer than the staging buffer is
+// searched in global memory, within the run).
+constexpr int kEmitStage = 1024;
 
 __global__ void __launch_bounds__(kPreThreads) k_pre_emit(PreArgs A) {
   const int64_t blk = blockIdx.x;
@@ -198,33 +260,67 @@ __global__ void __launch_bounds__(kPreThreads) k_pre_emit(PreArgs A) {
   const int64_t base = (blk - bx.blk_off) * kPreBlock;
   if (base >= kept) return;
   const char* raw = (const char*)A.raw + A.raw_byte_off[b];
+  const int64_t nb = (bx.n + kPreBlock - 1) / kPreBlock;
+  const int64_t* pre = A.blk_prefix + bx.blk_off;
+  const int64_t last = (base + kPreBlock < kept ? base + kPreBlock : kept) - 1;
+  __shared__ int64_t run[2];
+  __shared__ int64_t spre[kEmitStage];
+  if (threadIdx.x < 2) run[threadIdx.x] = block_of_rank(pre, 0, nb - 1, threadIdx.x ? last : base);
+  __syncthreads();
+  const int64_t r0 = run[0], r1 = run[1];
+  const bool staged = r1 - r0 < kEmitStage;
+  if (staged)
+    for (int64_t k = threadIdx.x; k <= r1 - r0; k += kPreThreads) spre[k] = pre[r0 + k];
+  __syncthreads();
 #pragma unroll
   for (int j = 0; j < kPrePer; ++j) {
     const int64_t li = base + threadIdx.x + kPreThreads * j;
-    if (li < kept) emit_record(A, bx, raw, li);
+    if (li < kept) {
+      int64_t k0;
+      if (staged) {
+        int lo = 0, hi = (int)(r1 - r0);
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (spre[mid] <= li) lo = mid;
+          else hi = mid - 1;
+        }
+        k0 = r0 + lo;
+      } else {
+        k0 = block_of_rank(pre, r0, r1, li);
+      }
+      emit_record(A, bx, raw, li, k0);
+    }
   }
 }
 
+// Record li, from the kept segment of rank li - pre[k0] in block k0.
 __device__ __forceinline__ void emit_record(const PreArgs& A, const DevBox& bx, const char* raw,
-                                            int64_t li) {
-  const int64_t nb = (bx.n + kPreBlock - 1) / kPreBlock;
+                                            int64_t li, int64_t k0) {
   const int64_t* pre = A.blk_prefix + bx.blk_off;
-  int64_t k0 = 0, k1 = nb - 1;   // pre[k0] <= li holds throughout (pre[0] = 0)
-  while (k0 < k1) {
-    const int64_t mid = (k0 + k1 + 1) >> 1;
-    if (pre[mid] <= li) k0 = mid;
-    else k1 = mid - 1;
-  }
   int rank = (int)(li - pre[k0]);
+  // The block's keep flags are requested together (128 contiguous bytes)
+  // and scanned in registers.
   const uint64_t* mask = A.blk_mask + (bx.blk_off + k0) * kPreWords;
+  uint64_t mw[kPreWords];
+#pragma unroll
+  for (int w = 0; w < kPreWords; ++w) mw[w] = mask[w];
   int word = 0;
-  for (int w = 0; w < kPreWords - 1; ++w) {
-    const int c = __popcll(mask[word]);
-    if (rank < c) break;
-    rank -= c;
-    ++word;
+  uint64_t bits = mw[0];
+  bool found = false;
+#pragma unroll
+  for (int w = 0; w < kPreWords; ++w) {
+    const int c = __popcll(mw[w]);
+    if (!found) {
+      if (rank < c || w == kPreWords - 1) {
+        found = true;
+        word = w;
+        bits = mw[w];
+      } else {
+        rank -= c;
+      }
+    }
   }
-  const int64_t i = k0 * kPreBlock + word * 64 + select_bit(mask[word], rank);
+  const int64_t i = k0 * kPreBlock + word * 64 + select_bit(bits, rank);
   if (i >= bx.n) return;   // unreachable when the counts and flags agree
   const SegGeom g = seg_geom(bx, raw, i, A.eta0);
   const int64_t r = bx.rec_off + li;

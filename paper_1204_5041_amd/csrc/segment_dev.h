@@ -49,7 +49,7 @@ __device__ __forceinline__ DevBox load_box(const DevBox* boxes, int64_t b) {
   r.cone_nside = q->cone_nside;
 #pragma unroll
   for (int k = 0; k < 9; ++k) r.rot[k] = q->rot[k];
-  return r;
+  return r;   // the cone test's data is read where it is used (ConeTest)
 }
 
 __device__ __forceinline__ int64_t load_kept(const DevBoxCount* c, int64_t b) {
@@ -117,22 +117,24 @@ __device__ __forceinline__ bool snapshot_event(const double P0[3], const double 
 
 // Geometry of segment i and whether it lies in its box's slab (the cone test
 // of a stacked box is separate: cone_state).
-__device__ __forceinline__ SegGeom seg_geom(const DevBox& bx, const char* raw, int64_t i,
-                                            double eta0) {
-  // Raw layout of a box: x_rel (n x 3), xdot (n x 3), xprime (n x 3), dsigma (n).
-  const int dt = bx.dtype;
+template <typename T>
+__device__ __forceinline__ SegGeom seg_geom_t(const DevBox& bx, const T* raw, int64_t i,
+                                              double eta0) {
+  // Raw layout of a box: x_rel (n x 3), xdot (n x 3), xprime (n x 3), dsigma
+  // (n), all of type T; every element is requested before any is used.
   const int64_t n = bx.n;
+  double x[3], v[3], t[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    x[k] = (double)raw[3 * i + k];
+    v[k] = (double)raw[3 * n + 3 * i + k];
+    t[k] = (double)raw[6 * n + 3 * i + k];
+  }
   SegGeom g;
+  g.ds = (double)raw[9 * n + i];
   if (bx.rotated) {
     // A box placed in a healpix cone: its arrays are in box coordinates and
     // the box is turned onto the sky by rot (Sec. II.C).
-    double x[3], v[3], t[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      x[k] = raw_at(raw, dt, 3 * i + k);
-      v[k] = raw_at(raw, dt, 3 * n + 3 * i + k);
-      t[k] = raw_at(raw, dt, 6 * n + 3 * i + k);
-    }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       g.P[k] = bx.origin[k] + rot_row(bx.rot, k, x);
@@ -142,12 +144,11 @@ __device__ __forceinline__ SegGeom seg_geom(const DevBox& bx, const char* raw, i
   } else {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      g.P[k] = bx.origin[k] + raw_at(raw, dt, 3 * i + k);
-      g.V[k] = raw_at(raw, dt, 3 * n + 3 * i + k);
-      g.T[k] = raw_at(raw, dt, 6 * n + 3 * i + k);
+      g.P[k] = bx.origin[k] + x[k];
+      g.V[k] = v[k];
+      g.T[k] = t[k];
     }
   }
-  g.ds = raw_at(raw, dt, 9 * n + i);
   const double tt = (g.T[0] * g.T[0] + g.T[1] * g.T[1]) + g.T[2] * g.T[2];
   const double vv = (g.V[0] * g.V[0] + g.V[1] * g.V[1]) + g.V[2] * g.V[2];
   if (bx.snapshot) {
@@ -170,16 +171,18 @@ __device__ __forceinline__ SegGeom seg_geom(const DevBox& bx, const char* raw, i
   return g;
 }
 
-// Position, distance and slab test of segment i of a box of on-cone events:
-// the same operations as seg_geom, without the velocity and tangent (the
-// count pass of such boxes needs nothing else).
-__device__ __forceinline__ SegGeom seg_pos(const DevBox& bx, const char* raw, int64_t i,
-                                           double eta0) {
-  const int dt = bx.dtype;
+__device__ __forceinline__ SegGeom seg_geom(const DevBox& bx, const char* raw, int64_t i,
+                                            double eta0) {
+  return bx.dtype == 0 ? seg_geom_t(bx, (const float*)raw, i, eta0)
+                       : seg_geom_t(bx, (const double*)raw, i, eta0);
+}
+
+// Position, distance and slab test of a box of on-cone events from a
+// segment's stored position x (box or sky coordinates, as the box holds
+// them): the same operations as seg_geom, without the velocity and tangent
+// (the count pass of such boxes needs nothing else).
+__device__ __forceinline__ SegGeom seg_pos_at(const DevBox& bx, const double x[3], double eta0) {
   SegGeom g;
-  double x[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) x[k] = raw_at(raw, dt, 3 * i + k);
   if (bx.rotated) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) g.P[k] = bx.origin[k] + rot_row(bx.rot, k, x);
@@ -193,15 +196,60 @@ __device__ __forceinline__ SegGeom seg_pos(const DevBox& bx, const char* raw, in
   return g;
 }
 
+// The same for segment i of the box's raw arrays.
+__device__ __forceinline__ SegGeom seg_pos(const DevBox& bx, const char* raw, int64_t i,
+                                           double eta0) {
+  double x[3];
+  if (bx.dtype == 0) {
+    const float* r = (const float*)raw;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) x[k] = (double)r[3 * i + k];
+  } else {
+    const double* r = (const double*)raw;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) x[k] = r[3 * i + k];
+  }
+  return seg_pos_at(bx, x, eta0);
+}
+
 // Stacking: only the strings inside the box's healpix cone are kept.  The
-// caps that bracket the pixel with a wide margin settle most directions
-// (0 outside, 1 inside); the rest (2) need the pixel test.  Comparing the
-// unnormalised cosine with the caps' cosines times R keeps a division out.
-__device__ __forceinline__ int cone_state(const DevBox& bx, const SegGeom& g) {
-  const double c = (bx.cone_dir[0] * g.P[0] + bx.cone_dir[1] * g.P[1]) + bx.cone_dir[2] * g.P[2];
-  if (c < bx.cone_cos_out * g.R) return 0;
-  if (c > bx.cone_cos_in * g.R) return 1;
-  return 2;
+// caps that bracket the pixel with a wide margin settle the directions far
+// from its boundary (0 outside, 1 inside), the four edge planes most of the
+// others; the rest (2), within a thin band around the edges, need the pixel
+// test.  Comparing unnormalised dot products with thresholds times R keeps
+// a division out.  The data sits in LDS (25 doubles per box): held in
+// scalar registers with the rest of the box it overflowed them.
+struct ConeTest {
+  double dir[3];
+  double cos_out, cos_in;
+  double n[4][3];
+  double hi[4], lo[4];
+};
+
+// Threads 0 .. 24 of the block copy box b's cone data into t.
+__device__ __forceinline__ void load_cone(const DevBox* boxes, int64_t b, ConeTest& t) {
+  const DevBox& q = boxes[b];
+  const int k = threadIdx.x;
+  if (k < 3) t.dir[k] = q.cone_dir[k];
+  else if (k == 3) t.cos_out = q.cone_cos_out;
+  else if (k == 4) t.cos_in = q.cone_cos_in;
+  else if (k < 17) t.n[(k - 5) / 3][(k - 5) % 3] = q.cone_n[(k - 5) / 3][(k - 5) % 3];
+  else if (k < 21) t.hi[k - 17] = q.cone_hi[k - 17];
+  else if (k < 25) t.lo[k - 21] = q.cone_lo[k - 21];
+}
+
+__device__ __forceinline__ int cone_state(const ConeTest& t, const SegGeom& g) {
+  const double c = (t.dir[0] * g.P[0] + t.dir[1] * g.P[1]) + t.dir[2] * g.P[2];
+  if (c < t.cos_out * g.R) return 0;
+  if (c > t.cos_in * g.R) return 1;
+  bool inside = true;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const double f = (t.n[e][0] * g.P[0] + t.n[e][1] * g.P[1]) + t.n[e][2] * g.P[2];
+    if (f < t.lo[e] * g.R) return 0;
+    inside = inside && f > t.hi[e] * g.R;
+  }
+  return inside ? 1 : 2;
 }
 
 // Copy a wave-uniform value into a vector register: an FP32 operation whose
