@@ -163,18 +163,20 @@ def test_snapshot_box_rejects_the_ray_box_rule(B):
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
-def test_cone_events_odd_count_and_unaligned_arrays(B, dtype):
-    """An odd segment count (the last thread holds one segment) and arrays
-    offset by one element (the one-segment-per-thread path)."""
-    n = 20_001
+@pytest.mark.parametrize("n", [20_001, 20_002, 20_003])
+def test_cone_events_odd_count_and_unaligned_arrays(B, dtype, n):
+    """Odd and even counts (an odd one leaves the last thread of the
+    two-segments-per-thread kernel one segment), and arrays offset by 0, 1
+    or 2 elements: aligned for two segments per thread (0 and 2) or not
+    (1: one segment per thread)."""
     x, xd, _, _ = snapshot_segments(n, 311, dtype)
     origin = np.array([1.2, -0.4, 2.1])
     eta0, eta_lo, eta_hi = 16.0, 12.0, 12.5
     rpos, rd, rkeep = oracle.cone_events(x, xd, origin, eta0, eta_lo, eta_hi)
     tdt = torch.float32 if dtype == np.float32 else torch.float64
-    for off in (0, 1):
-        bx = torch.zeros(3 * n + 1, dtype=tdt, device="cuda")
-        bv = torch.zeros(3 * n + 1, dtype=tdt, device="cuda")
+    for off in (0, 1, 2):
+        bx = torch.zeros(3 * n + 2, dtype=tdt, device="cuda")
+        bv = torch.zeros(3 * n + 2, dtype=tdt, device="cuda")
         bx[off:off + 3 * n] = torch.from_numpy(x.ravel()).cuda()
         bv[off:off + 3 * n] = torch.from_numpy(xd.ravel()).cuda()
         xt, vt = bx[off:off + 3 * n].view(n, 3), bv[off:off + 3 * n].view(n, 3)
