@@ -123,6 +123,16 @@ def main():
     import torch
     from paper_1204_5041_amd import binding as B
     assert torch.cuda.is_available(), "no GPU visible"
+    if args.copy_calib_mib > 0:
+        # One device copy of known size, before any workload, so that traffic
+        # counters can be scaled by what they read for it.
+        n = args.copy_calib_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.workload == "config3":
         return bench_config3(args, B, torch)
     if args.workload == "config4":
@@ -135,15 +145,6 @@ def main():
         return bench_stack(args, B, torch)
     if args.workload == "flat":
         return bench_flat(args, B, torch)
-
-    if args.copy_calib_mib > 0:
-        n = args.copy_calib_mib * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
 
     W, K = args.warmup, args.steps
     _log(f"bench: generating {W + K} boxes of {args.nseg:,} segments")
