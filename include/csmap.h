@@ -56,7 +56,7 @@ typedef enum {
     CSMAP_E_NOMEM = -2,        /* device or host allocation failed */
     CSMAP_E_DEVICE = -3,       /* a HIP call failed; the sky is now unusable */
     CSMAP_E_STATE = -4,        /* call not valid in the sky's current state */
-    CSMAP_E_UNSUPPORTED = -5   /* valid request this build does not provide */
+    CSMAP_E_UNSUPPORTED = -5   /* valid request the library does not provide */
 } csmap_status;
 
 /* Arithmetic form of the pair evaluation.

@@ -108,7 +108,7 @@ def sample_pixels(npix: int, count: int, seed: int) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------------
-# The five benchmark workloads.  Geometry the task description leaves open is
+# The five benchmark workloads.  Geometry the paper leaves open is
 # fixed here once (box placement, slabs, eta0) so every consumer agrees.
 # ----------------------------------------------------------------------------
 
