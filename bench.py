@@ -50,18 +50,22 @@ def make_sky(B, torch, b, form, nseg, nside):
     return sky, box
 
 
-def measured_traffic():
-    """HBM bytes per launch of the forward kernel from the committed
-    rocprofv3 counter runs, if they were taken on the current kernel source."""
+def measured_traffic(kernel):
+    """HBM bytes (per launch, or per step for the stacking stage) of a kernel
+    from the committed rocprofv3 counter runs, if they were taken on the
+    current device sources (the record holds their SHA-256)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_fwd32_traffic.json")
+    path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = os.path.join(ROOT, "paper_1204_5041_amd", "csrc", "kernels.hip")
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("kernels_hip_sha256"):
+    h = hashlib.sha256()
+    for src in rec.get("sources", []):
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    k = rec.get("kernels", {}).get(kernel)
+    if k is None or h.hexdigest() != rec.get("sources_sha256"):
         return None
-    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    return k["fetch_bytes"] + k["write_bytes"]
 
 
 def cpu_baseline(box, b, nside, pix):
@@ -205,7 +209,7 @@ def main():
                    "pairs_per_step": pairs_per_step, "tile": cfg},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
-                     "traffic": measured_traffic() if args.nseg == NSEG and args.nside == NSIDE
+                     "traffic": measured_traffic("k_fwd32") if args.nseg == NSEG and args.nside == NSIDE
                      else None,
                      "kernel": "k_fwd32", "kernel_ms": kern_s * 1e3,
                      "flop_per_pair": FLOP_PER_PAIR},
@@ -391,7 +395,8 @@ def bench_events(args, B, torch):
            "unit": "segments/s", "segments": n, "kept": int(keep.sum().item()),
            "ms_per_launch": kern * 1e3, "wall_ms_per_launch": wall * 1e3,
            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": gbs / HBM_PEAK_GBS, "bytes_per_segment": EVENT_BYTES}}
+                        "frac": gbs / HBM_PEAK_GBS, "bytes_per_segment": EVENT_BYTES,
+                        "traffic": measured_traffic("k_cone_events")}}
     # Agreement with the oracle: on all segments when the oracle is timed
     # (a few seconds on the host's cores), else on a sample of 200,000.
     if args.no_cpu:
@@ -484,7 +489,9 @@ def bench_stack(args, B, torch):
                       "segments_per_run": args.stack_seg, "placed_segments": nseg,
                       "kept": kept, "kept_expected_high_z_share": share},
            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                        "frac": gbs / HBM_PEAK_GBS,
+                        "traffic": (measured_traffic("k_pre_count+k_pre_emit")
+                                    if args.stack_seg == 200_000 else None),
                         "bytes": f"{STACK_RAW_BYTES} per placed + {STACK_REC_BYTES} per kept"}}
     if not args.no_cpu:
         # The oracle's placement and cone test on the first uses of the
