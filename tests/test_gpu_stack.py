@@ -317,3 +317,71 @@ def test_rotation_only_and_empty_cone_boxes(B):
     say(f"rotation-only cone box: kept {st['kept']}, {err}")
     assert st["kept"] == int(oracle.kept(eta0, ref_box).sum())
     assert err["rel_rms"] <= 1e-12 and err["rel_max"] <= 1e-12, err
+
+
+def edge_points(nside_c, cone, center, rng, count):
+    """Directions within 1e-9 .. 1e-3 rad of the boundary of pixel `cone`,
+    on both sides: boundary points found by bisection with the oracle's
+    ang2pix along great circles from the pixel centre, then moved along
+    the circle by the offsets."""
+    out = []
+    size = 1.02 / nside_c
+    nb = count // 8   # boundary points, eight offsets each
+    while len(out) < count:
+        u = rng.standard_normal((4 * count, 3))
+        u -= (u @ center)[:, None] * center
+        u /= np.linalg.norm(u, axis=1, keepdims=True)
+        far = np.cos(1.5 * size) * center + np.sin(1.5 * size) * u
+        far_out = oracle.ang2pix(nside_c, far) != cone
+        a = np.zeros(len(u))
+        b = np.full(len(u), 1.5 * size)
+        u, a, b = u[far_out][:nb], a[far_out][:nb], b[far_out][:nb]
+        for _ in range(60):
+            mid = 0.5 * (a + b)
+            d = np.cos(mid)[:, None] * center + np.sin(mid)[:, None] * u
+            inside = oracle.ang2pix(nside_c, d) == cone
+            a = np.where(inside, mid, a)
+            b = np.where(inside, b, mid)
+        for off in (1e-9, 1e-7, 1e-5, 1e-3):
+            for sgn in (-1.0, 1.0):
+                ang = 0.5 * (a + b) + sgn * off
+                out.extend(np.cos(ang)[:, None] * center + np.sin(ang)[:, None] * u)
+    return np.array(out[:count])
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("nside_c,cones,axes", [(1, [0, 4, 9], [0, 1, 2]),
+                                                (2, [0, 19, 44], [2, 0, 1]),
+                                                (16, [0, 1000, 1536, 3071], [1, 2, 0, 2])])
+def test_cone_membership_near_pixel_edges(B, dtype, nside_c, cones, axes):
+    """Segments placed within 1e-9 .. 1e-3 rad of their cone pixel's
+    boundary, on both sides: the GPU keeps exactly the segments the oracle
+    keeps (the bounding caps and edge planes only decide where the decision
+    is certain, the rest go to the pixel test), and renders the same map."""
+    rng = np.random.default_rng(4100 + nside_c)
+    r_in, r_out, eta0, side = 1.0, 2.0, 3.0, 3.0
+    uses = []
+    for k, (cone, axis) in enumerate(zip(cones, axes)):
+        R, origin = oracle.cone_frame(nside_c, cone, axis, r_out, side)
+        center = R[:, axis]
+        d = edge_points(nside_c, cone, center, rng, 800)
+        P = d * rng.uniform(1.1, 1.9, (len(d), 1))
+        x = ((P - origin) @ R).astype(dtype)          # box coordinates: R^T (P - origin)
+        _, xd, xp, ds = synth.segments(len(d), 4200 + k, dtype, side)
+        uses.append(dict(cone=cone, axis=axis, R=R, origin=origin, x=x, xd=xd, xp=xp, ds=ds))
+    lo, hi = eta0 - r_out, eta0 - r_in
+    boxes, idx = oracle_cone_boxes(eta0, lo, hi, nside_c, uses, False)
+    kept = sum(len(i) for i in idx)
+    total = sum(len(u["ds"]) for u in uses)
+    say(f"edge cones nside_c={nside_c} dtype={np.dtype(dtype).name}: kept {kept} of {total}")
+    assert 0.3 * total < kept < 0.7 * total
+    nside = 32
+    sky = gpu_cone_sky(B, nside, eta0, lo, hi, nside_c, uses, B.CSMAP_FORM_FP64, False)
+    m = sky.render().cpu().numpy()
+    st = sky.stats()
+    sky.close()
+    assert st["kept"] == kept
+    ref = oracle.theta_pixels(nside, np.arange(12 * nside * nside), eta0, boxes)
+    e = err_metrics(m, ref)
+    say(f"  {e}")
+    assert e["rel_rms"] <= 1e-12 and e["rel_max"] <= 1e-12, e
