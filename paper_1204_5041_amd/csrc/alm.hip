@@ -423,8 +423,16 @@ __global__ void __launch_bounds__(kCapThreads) k_cap_bluestein(int64_t nside, in
 
 // Step 2a: lambda_mm of the north ring of every ring pair q = 1 .. 2N (its
 // z >= 0), for m = 0 .. mmax, as v * 2^(600 e); one thread per ring.
-__global__ void k_lambda_mm(int64_t nside, int64_t mmax, double* lam_v, int32_t* lam_e,
-                            double* ring_z) {
+// fac[m] = -sqrt((2m+1)/(2m)), m = 1 .. mmax: the ring-independent factor of
+// the lambda_mm recursion, formed once rather than in every ring's thread.
+__global__ void k_mm_factor(int64_t mmax, double* fac) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < 1 || m > mmax) return;
+  fac[m] = -sqrt((2.0 * m + 1.0) / (2.0 * m));
+}
+
+__global__ void k_lambda_mm(int64_t nside, int64_t mmax, const double* mm_fac, double* lam_v,
+                            int32_t* lam_e, double* ring_z) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t npair = 2 * nside;
   if (q >= npair) return;
@@ -436,9 +444,10 @@ __global__ void k_lambda_mm(int64_t nside, int64_t mmax, double* lam_v, int32_t*
   double v = 1.0 / sqrt(4.0 * 3.14159265358979323846);
   int32_t e = 0;
   const double tiny = ldexp(1.0, -kLegScale);
+  cdp fac = (cdp)mm_fac;
   for (int64_t m = 0; m <= mmax; ++m) {
     if (m > 0) {
-      v = -sqrt((2.0 * m + 1.0) / (2.0 * m)) * s * v;
+      v = fac[m] * s * v;
       if (fabs(v) < tiny) {
         v = ldexp(v, kLegScale);
         e -= 1;
@@ -746,7 +755,7 @@ size_t map2alm_scratch_bytes(int64_t nside, int64_t lmax) {
          sizeof(int32_t) * (size_t)(M * npair) + sizeof(double) * (size_t)npair +
          sizeof(double) * (size_t)(2 * size) + sizeof(double) * (size_t)part_doubles(nside, lmax) +
          sizeof(double) * (size_t)(2 * (4 * nside + 1)) + sizeof(double) * (size_t)kCapMaxP +
-         8 * 256;
+         sizeof(double) * (size_t)M + 9 * 256;
 }
 
 // All of map2alm on `st`; `scratch` holds map2alm_scratch_bytes(nside, lmax).
@@ -773,6 +782,8 @@ hipError_t launch_map2alm(int64_t nside, int64_t lmax, const double* map, double
   double* tab = (double*)p;
   p += align(sizeof(double) * (size_t)(2 * (4 * nside + 1)));
   double* ctab = (double*)p;
+  p += align(sizeof(double) * (size_t)kCapMaxP);
+  double* mm_fac = (double*)p;
   const int64_t mblocks = (lmax + 64) / 64;
   // Belt rings by FFT when their length 4N is a power of two whose half
   // fits the LDS buffer; cap rings by the chirp transform when their
@@ -802,8 +813,9 @@ hipError_t launch_map2alm(int64_t nside, int64_t lmax, const double* map, double
     k_ring_dft<<<dim3((unsigned)((dft_waves + 3) / 4)), dim3(256), 0, st>>>(nside, lmax, map, F,
                                                                            lo, hi);
   }
-  k_lambda_mm<<<dim3((unsigned)((npair + 255) / 256)), dim3(256), 0, st>>>(nside, lmax, lam_v,
-                                                                          lam_e, ring_z);
+  k_mm_factor<<<dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st>>>(lmax, mm_fac);
+  k_lambda_mm<<<dim3((unsigned)((npair + 255) / 256)), dim3(256), 0, st>>>(nside, lmax, mm_fac,
+                                                                          lam_v, lam_e, ring_z);
   k_leg_coef<<<dim3((unsigned)((M + 255) / 256), (unsigned)M), dim3(256), 0, st>>>(lmax, coef);
   const int64_t leg_waves = M * nblk;
   k_legendre<<<dim3((unsigned)((leg_waves + 3) / 4)), dim3(256), 0, st>>>(
