@@ -273,6 +273,34 @@ def test_exact_coincidence_is_zero(B):
         sky.close()
 
 
+def test_sparse_keep_records_span_many_blocks(B):
+    """2,000,000 segments of which every 1,700th lies in the slab: the first
+    workgroup of the records pass finds its records spread over more source
+    blocks than it stages in LDS, and searches the block prefixes in global
+    memory.  The kept count and the map equal the oracle's."""
+    n = 2_000_000
+    _, xd, xp, ds = synth.segments(n, 61, np.float64)
+    r = np.full(n, 5.0)
+    r[::1700] = 2.0
+    P = synth.uniform_directions(n, 62) * r[:, None]
+    bx = synth.Box(origin=np.zeros(3), ext=np.ones(3), eta_lo=0.5, eta_hi=1.5, x_rel=P,
+                   xdot=xd, xprime=xp, dsigma=ds)
+    w = synth.Workload("sparse", 8, 3.0, [bx])
+    kept = int(oracle.kept(3.0, bx).sum())
+    assert kept == len(r[::1700])
+    ref = oracle.theta_pixels(w.nside, np.arange(w.npix), w.eta0, w.boxes)
+    for form, tol in ((B.CSMAP_FORM_FP64, (FP64_TOL, FP64_TOL)),
+                      (B.CSMAP_FORM_FP32C, (FP32_RMS, FP32_MAX))):
+        sky = sky_from_workload(w, form)
+        m = sky.render().cpu().numpy()
+        st = sky.stats()
+        sky.close()
+        e = err_metrics(m, ref)
+        say(f"sparse keep form={form}: kept {st['kept']} of {n} {e}")
+        assert st["kept"] == kept
+        assert e["rel_rms"] <= tol[0] and e["rel_max"] <= tol[1], e
+
+
 # ----------------------------------------------------------------------------
 # The benchmark workloads
 # ----------------------------------------------------------------------------
