@@ -384,8 +384,9 @@ csmap_status csmap_autotune(csmap_sky *sky, const char *cache_path);
  * real and imaginary parts at positions 2 i and 2 i + 1 with
  * i = m (2 lmax + 1 - m) / 2 + l.  0 <= lmax <= 4 Nside.  Allocates device
  * scratch for the duration of the call (about 16 (4 Nside)(lmax + 1) +
- * 12 (2 Nside)(lmax + 1) + 16 (ceil(Nside / 256) + 1)(lmax + 1)(lmax + 2)/2
- * bytes) and synchronises hip_stream before returning. */
+ * 12 (2 Nside)(lmax + 1) + 16 (ceil(Nside / 128) + 1)(lmax + 1)(lmax + 2)/2
+ * bytes: 3.0 GB at Nside 2048, lmax 4096) and synchronises hip_stream
+ * before returning. */
 csmap_status csmap_map2alm(int64_t nside, int64_t lmax, const double *map, double *alm,
                            void *hip_stream);
 
