@@ -28,22 +28,22 @@ constexpr int kFlatK = 8;            // pixels per lane
 constexpr int kFlatChunk = 32;       // records per FP32 partial sum
 constexpr float kFlatTiny = 1e-18f;  // floor of |t - s|^2 (pixel units): an exact hit gives 0
 
-// 1/x for x in [2^-126, 2^126] on the ordinary FP32 pipeline: the hardware
+// 1/x for x in [2^-125, 2^125] on the ordinary FP32 pipeline: the hardware
 // reciprocal is a transcendental instruction that costs the pair loop about
 // ten ordinary ones.  Subtracting the bits of x = 2^E (1 + f) from those of
-// 2^127 negates the exponent and maps the mantissa to 2 - f, so the seed is
-// y0 = 2^(-E-1) (2 - f) and x y0 = 1 + (f - f^2)/2 lies in [1, 1.125].  Each
-// Newton step of third order, y <- y + y (e + e^2) with e = 1 - x y, cubes
-// the relative error (1.25e-1, 2.0e-3, 7.5e-9), which leaves the result
-// within 0.6 ulp of 1/x (the hardware reciprocal is within 1 ulp).
+// 2^127 would negate the exponent and map the mantissa to 2 - f, a seed y0
+// with x y0 in [1, 1.125]; the constant used, 0x7EF311C2, is that one less
+// 847422, the shift that minimises max |1 - x y0| over all mantissas (5.05e-2).
+// A Newton step of third order, y <- y + y (e + e^2) with e = 1 - x y, cubes
+// the relative error (to 1.3e-4), one of second order, y <- y + y e, squares
+// it (to 1.7e-8), which leaves the result within 0.8 ulp of 1/x (the hardware
+// reciprocal is within 1 ulp).
 __device__ __forceinline__ float recip_newton(float x) {
-  float y = __uint_as_float(0x7F000000u - __float_as_uint(x));
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const float e = fmaf(-x, y, 1.0f);
-    y = fmaf(y, fmaf(e, e, e), y);
-  }
-  return y;
+  float y = __uint_as_float(0x7EF311C2u - __float_as_uint(x));
+  float e = fmaf(-x, y, 1.0f);
+  y = fmaf(y, fmaf(e, e, e), y);
+  e = fmaf(-x, y, 1.0f);
+  return fmaf(y, e, y);
 }
 
 // Exclusive prefix over boxes of their kept counts; the total is padded to
@@ -175,7 +175,7 @@ __global__ void __launch_bounds__(256) k_flat32(FlatArgs A, int64_t ntiles, int6
       qb[j] = fmaf(xb[j], xb[j], yb2);
     }
 #pragma unroll
-    // qa qb >= kFlatTiny^2 = 1e-36 > 2^-126, and far below 2^126 for any
+    // qa qb >= kFlatTiny^2 = 1e-36 > 2^-125, and far below 2^125 for any
     // patch: inside recip_newton's range.
     for (int j = 0; j < kFlatK; ++j) rq[j] = recip_newton(qa[j] * qb[j]);
 #pragma unroll
