@@ -244,8 +244,10 @@ hipError_t launch_flat(const FlatArgs& A, hipStream_t st) {
 // wavefronts (32 per SIMD), at most 16.  Each wavefront's chain of
 // dependent operations leaves the SIMD idle unless several others are
 // resident; on the 1024 x 1024 patch (2048 tiles) 1, 2, 4, 8 and 16 ranges
-// measured 445, 407, 384, 372 and 366 ms.  With more than one range, part
-// holds that many maps of nx ny doubles, summed in range order.
+// measured 445, 407, 384, 372 and 366 ms with the hardware reciprocal, and
+// 8, 16 and 32 ranges 317, 311 and 308 ms with recip_newton (32 would double
+// the partial maps for 1%).  With more than one range, part holds that many
+// maps of nx ny doubles, summed in range order.
 int64_t flat_splits(int64_t nx, int64_t ny) {
   const int64_t tpr = (nx + 64 * kFlatK - 1) / (64 * kFlatK);
   const int64_t ntiles = tpr * ny;
