@@ -388,7 +388,7 @@ void oracle_kept_many(int64_t nseg, const double *box, double eta0, const double
  *            (d depends on P through R n - P, and dR/dP = Phat)
  *   df/dV  = (C/q) [ d + (a (T.d)/b^2) n ] + f V/(1 - V^2)
  *   df/dT  = -(C/(b q)) [ (T.d) n + a d ] + f T/T^2
- *   df/dw  = f / w
+ *   df/dw  = -4 eps N / q   (f is linear in w; finite at w = 0)
  * where the last terms come from eps = sqrt(T^2/(1 - V^2)).
  */
 void oracle_grad(int64_t nside, int64_t nlist, const int64_t *pix, const double *g,
@@ -452,7 +452,9 @@ void oracle_grad(int64_t nside, int64_t nlist, const int64_t *pix, const double 
                     cadd(&loc[3 + k], gp * dV);
                     cadd(&loc[6 + k], gp * dT);
                 }
-                cadd(&loc[9], gp * (f / s.w));
+                /* Eq. (1) is linear in dsigma: its derivative is the summand
+                 * without the dsigma factor, finite at dsigma = 0. */
+                cadd(&loc[9], gp * (-4.0 * s.eps * N / q));
             }
         }
         for (int c = 0; c < 10; ++c) {
