@@ -30,6 +30,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "pixel-segment pairs/s (FP32 vs FP64, Nside=2048) + % of VALU peak"
 FLOP_PER_PAIR = 36          # algorithmic count of one Eq. (1) term
+# Algorithmic count of one pair's contribution to the adjoint's 14 sums (far
+# form, FMA = 2): w, a, b (17), n - P/R (3), kappa-weighted dot products t1,
+# t2 (4), m and the term f (4), the reciprocal of b w (2), the coefficients
+# and updates of the 14 sums (37).
+ADJ_FLOP_PER_PAIR = 67
 FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector peak
 FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector peak
 NSIDE = 2048
@@ -99,9 +104,13 @@ def main():
     ap.add_argument("--nside", type=int, default=NSIDE)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="config2: leave out the batched 256-box Nside=4096 measurement that "
+                         "follows the headline steps")
     ap.add_argument("--cpu-pixels", type=int, default=40000)
     ap.add_argument("--workload", default="config2",
-                    choices=["config2", "config3", "config4", "events", "alm", "stack", "flat"],
+                    choices=["config2", "config3", "config4", "events", "alm", "stack", "flat",
+                             "counters"],
                     help="config2: the headline Nside=2048 line (default); config3: the "
                          "batched uneven 256-box Nside=4096 sky; config4: forward + adjoint at "
                          "Nside=1024; events: light-cone event recording from slab-start "
@@ -110,7 +119,9 @@ def main():
                          "stacking of 1024 runs x 3 axes into the 3072 Nside_c=16 cones plus "
                          "12 Nside_c=1 cones (light-cone stage of 3084 placed boxes); flat: "
                          "flat-sky small-angle map of a 7.2 degree 1024^2 patch from 2M "
-                         "segments")
+                         "segments; counters: one launch each of a known-FMA probe (FP32, "
+                         "FP64), the bench step's k_fwd32 and k_fwd64, the config4 adjoint "
+                         "and map2alm, for hardware counter runs")
     ap.add_argument("--stack-seg", type=int, default=200_000,
                     help="stack: segments per simulation run")
     ap.add_argument("--count-scale", type=float, default=1.0,
@@ -149,6 +160,8 @@ def main():
         return bench_stack(args, B, torch)
     if args.workload == "flat":
         return bench_flat(args, B, torch)
+    if args.workload == "counters":
+        return bench_counters(args, B, torch)
 
     W, K = args.warmup, args.steps
     _log(f"bench: generating {W + K} boxes of {args.nseg:,} segments")
@@ -246,6 +259,17 @@ def main():
             acc["fp64"] = err_metrics(got64, ref)
         out["accuracy_vs_oracle"] = acc
 
+    if not args.no_batched:
+        # The batched uneven workload (256 boxes, Nside 4096, cap visibility),
+        # in the form the batched path is meant to run: autotuned, one
+        # persistent launch captured in a graph and replayed once.
+        bt = batched_config3(B, torch, steps=1, per_box=False, cpu=False)
+        out["batched_config3"] = {k: bt[k] for k in (
+            "value", "unit", "ms_per_step", "kernel_ms", "pairs", "segments", "achieved_tflops",
+            "frac_fp32_peak", "tile", "autotune_s", "accuracy_vs_oracle")}
+        out["batched_config3"]["workload"] = ("Nside=4096, 256 boxes, lognormal counts "
+                                              "(22.1M FP32 segments), caps of 0.1%-5% of the sky")
+
     print(json.dumps(out), flush=True)
 
 
@@ -262,14 +286,15 @@ def _sky_from(B, torch, w, form):
     return sky
 
 
-def bench_config3(args, B, torch):
+def batched_config3(B, torch, steps=1, count_scale=1.0, per_box=True, cpu=True):
     """256 boxes of lognormal size, each seen by a cap of 0.1%-5% of an
-    Nside=4096 sky: one persistent launch over per-tile box lists, captured
-    in a graph, launch shape from the autotuner; compared with one launch
-    per box."""
+    Nside=4096 sky: autotuned launch shape, then one persistent launch over
+    per-tile box lists captured in a graph (the first render captures it,
+    `steps` replays are timed); accuracy against the oracle on 4,000 pixels
+    drawn inside the caps; optionally compared with one launch per box."""
     import synth
     _log("bench config3: generating 256 boxes")
-    w = synth.config3(count_scale=args.count_scale)
+    w = synth.config3(count_scale=count_scale)
     _log(f"bench config3: {sum(b.n for b in w.boxes):,} segments; uploading")
     sky = _sky_from(B, torch, w, B.CSMAP_FORM_FP32C)
     out = torch.empty(w.npix, dtype=torch.float64, device="cuda")
@@ -284,7 +309,7 @@ def bench_config3(args, B, torch):
     sky.render(out)                               # capture + warm-up
     torch.cuda.synchronize()
     _log(f"bench config3: warm-up render done ({sky.stats()['ms_forward']:.0f} ms)")
-    K = max(1, args.steps)
+    K = max(1, steps)
     t0 = time.perf_counter()
     for _ in range(K):
         sky.render(out)
@@ -292,33 +317,68 @@ def bench_config3(args, B, torch):
     el = (time.perf_counter() - t0) / K
     st = sky.stats()
     res = {"metric": "config3 batched pairs/s", "value": st["pairs"] / el, "unit": "pairs/s",
-           "ms_per_step": el * 1e3, "pairs": st["pairs"], "kept": st["kept"],
-           "segments": st["segments"], "tile": {k: st[k] for k in ("pix_per_lane", "waves",
-                                                                   "schedule", "graph", "tiling")},
+           "ms_per_step": el * 1e3, "kernel_ms": st["ms_forward"], "pairs": st["pairs"],
+           "kept": st["kept"], "segments": st["segments"],
+           "tile": {k: st[k] for k in ("pix_per_lane", "waves", "schedule", "graph", "tiling",
+                                       "near_w", "far_w")},
            "fp64_steps": st["near_steps"], "mid_steps": st["mid_steps"], "steps": st["steps"],
            "autotune_s": tune_s}
     res["achieved_tflops"] = FLOP_PER_PAIR * res["value"] / 1e12
     res["frac_fp32_peak"] = res["achieved_tflops"] / FP32_PEAK_TFLOPS
-    res["accuracy_vs_oracle"], dt = _sampled_accuracy(torch, w, out, 4000, seed=397)
-    res["cpu_baseline"] = _sampled_cpu_baseline(w, st["pairs"], 4000, dt)
-    _log(f"bench config3: batched render {el * 1e3:.0f} ms; per-box launches next")
-    sky.set_option(B.CSMAP_OPT_GRAPH, 0)
-    sky.set_option(B.CSMAP_OPT_SCHEDULE, 2)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sky.render(out)
-    torch.cuda.synchronize()
-    el2 = time.perf_counter() - t0
-    res["per_box_launches_pairs_per_s"] = sky.stats()["pairs"] / el2
-    res["speedup_batched_over_per_box"] = el2 / el
-    print(json.dumps(res), flush=True)
+    pix = _cap_pixels(w, 4000, seed=396)
+    res["accuracy_vs_oracle"], dt = _sampled_accuracy(torch, w, out, len(pix), seed=397, pix=pix)
+    res["accuracy_vs_oracle"]["pixels_drawn"] = "inside the boxes' caps"
+    if cpu:
+        res["cpu_baseline"] = _sampled_cpu_baseline(w, st["pairs"], 4000, None)
+    if per_box:
+        _log(f"bench config3: batched render {el * 1e3:.0f} ms; per-box launches next")
+        sky.set_option(B.CSMAP_OPT_GRAPH, 0)
+        sky.set_option(B.CSMAP_OPT_SCHEDULE, 2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sky.render(out)
+        torch.cuda.synchronize()
+        el2 = time.perf_counter() - t0
+        res["per_box_launches_pairs_per_s"] = sky.stats()["pairs"] / el2
+        res["speedup_batched_over_per_box"] = el2 / el
+    sky.close()
+    return res
 
 
-def _sampled_accuracy(torch, w, gpu_map, count, seed):
-    """Errors of a rendered map against the oracle on `count` random pixels."""
+def _cap_pixels(w, count, seed):
+    """Pixels drawn inside the boxes' caps (a box chosen with probability
+    proportional to its cap's area, a direction uniform in that cap, its
+    RING pixel by the oracle's ang2pix), so that each sees at least one box
+    unless it sits on a cap's edge."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    area = np.array([1.0 - b.cap_cos for b in w.boxes])
+    pick = rng.choice(len(w.boxes), size=count, p=area / area.sum())
+    dirs = np.empty((count, 3))
+    for i, b in enumerate(pick):
+        bx = w.boxes[b]
+        c = bx.cap_dir / np.linalg.norm(bx.cap_dir)
+        a = np.cross(c, [1.0, 0.0, 0.0] if abs(c[0]) < 0.9 else [0.0, 1.0, 0.0])
+        a /= np.linalg.norm(a)
+        bb = np.cross(c, a)
+        ct = rng.uniform(bx.cap_cos, 1.0)
+        st = math.sqrt(max(0.0, 1.0 - ct * ct))
+        ph = rng.uniform(0.0, 2.0 * math.pi)
+        dirs[i] = ct * c + st * (math.cos(ph) * a + math.sin(ph) * bb)
+    return np.unique(oracle.ang2pix(w.nside, dirs))
+
+
+def bench_config3(args, B, torch):
+    print(json.dumps(batched_config3(B, torch, args.steps, args.count_scale)), flush=True)
+
+
+def _sampled_accuracy(torch, w, gpu_map, count, seed, pix=None):
+    """Errors of a rendered map against the oracle on `count` random pixels
+    (or on the given pixels)."""
     import oracle
     import synth
-    pix = synth.sample_pixels(w.npix, count, seed=seed)
+    if pix is None:
+        pix = synth.sample_pixels(w.npix, count, seed=seed)
     got = gpu_map[torch.from_numpy(pix).cuda()].cpu().numpy()
     _log(f"bench: oracle on {count} sampled pixels")
     t0 = time.perf_counter()
@@ -332,8 +392,15 @@ def _sampled_accuracy(torch, w, gpu_map, count, seed):
 def _sampled_cpu_baseline(w, pairs, count, dt):
     """The oracle's rate on the same map, from its time on `count` pixels
     drawn uniformly from the map (so that the time scales to the whole map in
-    expectation, boxes seen by part of the sky included)."""
+    expectation, boxes seen by part of the sky included); timed here when dt
+    is None."""
     import oracle
+    import synth
+    if dt is None:
+        pix = synth.sample_pixels(w.npix, count, seed=397)
+        t0 = time.perf_counter()
+        oracle.theta_pixels(w.nside, pix, w.eta0, w.boxes)
+        dt = time.perf_counter() - t0
     full_s = dt * w.npix / count
     return {"value": pairs / full_s, "unit": "pairs/s", "cores": oracle.num_threads(),
             "kind": "oracle",
@@ -704,8 +771,99 @@ def bench_config4(args, B, torch):
     res = {"metric": "config4 forward + adjoint pairs/s", "forward_pairs_per_s": pairs / tf,
            "adjoint_pairs_per_s": pairs / tb, "pairs": pairs, "forward_ms": tf * 1e3,
            "adjoint_ms": tb * 1e3, "adjoint_kernel_ms": st["ms_backward"]}
+    adj_tf = ADJ_FLOP_PER_PAIR * pairs / (st["ms_backward"] / 1e3) / 1e12
+    res["adjoint_roofline"] = {"bound": "alu", "kernel": "k_adj32", "flop_per_pair":
+                               ADJ_FLOP_PER_PAIR, "achieved": adj_tf, "peak": FP32_PEAK_TFLOPS,
+                               "unit": "TFLOP/s", "frac": adj_tf / FP32_PEAK_TFLOPS,
+                               "hw": measured_valu("k_adj32", st["ms_backward"])}
     res["forward_accuracy_vs_oracle"], dt = _sampled_accuracy(torch, w, m, 4000, seed=213)
     res["cpu_baseline"] = _sampled_cpu_baseline(w, pairs, 4000, dt)
+    # The adjoint's gradient on 64 sampled segments against the oracle's
+    # (each over all pixels; the cotangent is 2 w Theta of the GPU map).
+    import oracle
+    grads = sky.backward(2.0 * wts * m)
+    got = np.concatenate([np.concatenate([a.cpu().numpy(), b.cpu().numpy(), c.cpu().numpy(),
+                                          d.cpu().numpy()[:, None]], 1)
+                          for a, b, c, d in grads])
+    sel = synth.sample_pixels(sum(bx.n for bx in w.boxes), 64, seed=210)
+    _log("bench config4: oracle gradient on 64 segments")
+    gref = oracle.grad(w.nside, np.arange(w.npix), (2.0 * wts * m).cpu().numpy(), w.eta0,
+                       w.boxes, sel)
+    acc = {"segments": 64}
+    for name, sl in (("x_rel", slice(0, 3)), ("xdot", slice(3, 6)), ("xprime", slice(6, 9)),
+                     ("dsigma", slice(9, 10))):
+        d = got[sel][:, sl] - gref[:, sl]
+        acc[name + "_rel_l2"] = float(np.linalg.norm(d) / np.linalg.norm(gref[:, sl]))
+    res["adjoint_accuracy_vs_oracle"] = acc
+    print(json.dumps(res), flush=True)
+
+
+def measured_valu(kernel, kernel_ms):
+    """Hardware-counted vector FLOP of a kernel launch from the committed
+    rocprofv3 counter runs (if taken on the current device sources), as FLOP
+    per launch and the rate over a launch of kernel_ms."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "valu_counters.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for src in rec.get("sources", []):
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    k = rec.get("kernels", {}).get(kernel)
+    if k is None or h.hexdigest() != rec.get("sources_sha256"):
+        return None
+    out = {"fp32_flop": k["fp32_flop"], "fp64_flop": k["fp64_flop"],
+           "valu_insts": k["valu_insts"], "summary": rec.get("summary")}
+    if kernel_ms:
+        out["fp32_tflops"] = k["fp32_flop"] / (kernel_ms / 1e3) / 1e12
+        out["fp64_tflops"] = k["fp64_flop"] / (kernel_ms / 1e3) / 1e12
+    return out
+
+
+def bench_counters(args, B, torch):
+    """One launch of each kernel that the hardware counter summaries cover,
+    each preceded by a log line naming it: the FMA probe in FP32 and in
+    FP64 (known instruction counts), the default step's k_fwd32 (config2 box
+    0, FP32C), k_fwd64 (same box, FP64 form), the config4 adjoint (k_adj32)
+    and map2alm of the FP32C map at lmax 4096 (k_legendre)."""
+    import synth
+    res = {"metric": "counter-run launches"}
+    blocks = 2048
+    for kind, name, iters in ((0, "fp32", 200_000), (1, "fp64", 100_000),
+                              (2, "fp32_scalar_operand", 100_000)):
+        _log(f"counters: probe {name}")
+        ms, insts = B.valu_probe(kind, blocks, iters)
+        lanes = insts * 64 / (ms / 1e3) / (256 * 2.4e9)
+        res[f"probe_{name}"] = {"blocks": blocks, "iters": iters, "ms": ms, "fma_insts": insts,
+                                "fma_lanes_per_clk_per_cu": lanes}
+    _log("counters: k_fwd32 (config2 box 0)")
+    sky, box = make_sky(B, torch, 0, B.CSMAP_FORM_FP32C, NSEG, NSIDE)
+    m = sky.render()
+    st = sky.stats()
+    res["k_fwd32"] = {"pairs": st["pairs"], "ms": st["ms_forward"]}
+    sky.close()
+    _log("counters: k_fwd64 (config2 box 0)")
+    sky, _ = make_sky(B, torch, 0, B.CSMAP_FORM_FP64, NSEG, NSIDE)
+    sky.render()
+    st = sky.stats()
+    res["k_fwd64"] = {"pairs": st["pairs"], "ms": st["ms_forward"]}
+    sky.close()
+    _log("counters: k_adj32 (config4)")
+    w = synth.config4()
+    sky = _sky_from(B, torch, w, B.CSMAP_FORM_FP32C)
+    wts = torch.from_numpy(synth.config4_weights(w.npix)).cuda()
+    m4 = sky.render()
+    sky.backward(2.0 * wts * m4)
+    st = sky.stats()
+    res["k_adj32"] = {"pairs": st["pairs"], "ms": st["ms_backward"]}
+    sky.close()
+    _log("counters: map2alm (k_legendre), Nside 2048, lmax 4096")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.map2alm(m, 4096)
+    torch.cuda.synchronize()
+    res["map2alm"] = {"nside": NSIDE, "lmax": 4096, "ms": (time.perf_counter() - t0) * 1e3}
     print(json.dumps(res), flush=True)
 
 

@@ -313,7 +313,8 @@ typedef struct {
     double e1[3], e2[3];    /* plane axes: unit vectors, orthogonal to c and each other */
     int64_t nx, ny;         /* pixels along e1 and e2, each >= 1, nx * ny <= 2^31 */
     double pix;             /* pixel size in radians (> 0) */
-    double accept_cos;      /* a segment enters only if c.P > accept_cos |P|, in [-1, 1] */
+    double accept_cos;      /* a segment enters only if c.P > accept_cos |P|; in (0, 1]
+                             * with tan(acos(accept_cos))/pix + max(nx, ny) <= 2^30 */
 } csmap_patch;
 
 /* Flat-sky, small-angle map of the sky's boxes on a patch (Sec. II.A: the
@@ -329,7 +330,10 @@ typedef struct {
  * in FP64; the pair sum is FP32 with compensated accumulation, whatever the
  * sky's form.  stats report the light-cone stage and the record pass as
  * ms_precompute and the pair kernel as ms_forward.  Enqueued on the sky's
- * stream. */
+ * stream.  CSMAP_E_INVALID for accept_cos outside (0, 1] or an acceptance
+ * cone so wide that tan(acos(accept_cos))/pix + max(nx, ny) > 2^30 (the
+ * bound on plane offsets in pixel units that keeps the FP32 pair arithmetic
+ * in range). */
 csmap_status csmap_render_flat(csmap_sky *sky, const csmap_patch *patch, double *map);
 
 /* Adjoint of render: given dmap = dL/d(Theta_p/GU) (device, npix doubles),
@@ -426,6 +430,21 @@ csmap_status csmap_ring_block_rows(int64_t nside, int64_t rings, int64_t width, 
 csmap_status csmap_cap_block_tiles(int64_t nside, int64_t rings, int64_t width, double cx,
                                    double cy, double cz, double rho, int64_t *ranges,
                                    int64_t max_ranges, int64_t *n_ranges);
+
+/* Measurement helper, outside the map path: a kernel of known vector-ALU
+ * work against which hardware instruction counters and the achievable issue
+ * rate are read.  kind 0 runs FP32 fused multiply-adds with vector-register
+ * operands, kind 1 FP64 ones, kind 2 FP32 ones whose multiplier is read
+ * from a scalar register: `blocks` workgroups of 256 threads, each lane
+ * `iters` iterations of 16 independent FMAs, then one value per lane written
+ * to out (device, blocks * 256 floats, or doubles for kind 1).  Synchronises
+ * hip_stream; *ms (may be NULL) receives the kernel's time from HIP events
+ * around it, *fma_insts (may be NULL) the FMA instructions issued, counted
+ * per wavefront (blocks * 4 * iters * 16; each is 64 lanes x 2 FLOP).
+ * CSMAP_E_INVALID for kind outside {0, 1, 2}, blocks outside [1, 2^24],
+ * iters outside [1, 2^30] or a NULL out. */
+csmap_status csmap_valu_probe(int kind, int64_t blocks, int64_t iters, void *out,
+                              void *hip_stream, double *ms, double *fma_insts);
 
 #ifdef __cplusplus
 }

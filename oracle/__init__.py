@@ -63,6 +63,7 @@ def lib() -> ctypes.CDLL:
         _lib.oracle_map2alm_m.argtypes = [i64, i64, i64, f64p, f64p, f64p]
         _lib.oracle_alm2cl.argtypes = [i64, f64p, f64p, f64p]
         _lib.oracle_ang2pix_many.argtypes = [i64, i64, f64p, i64p]
+        _lib.oracle_quarter_turns_many.argtypes = [i64, f64p, f64p]
         _lib.oracle_flat_theta.argtypes = [i64, i64, ctypes.c_double, f64p, ctypes.c_double,
                                            ctypes.c_double, i64, f64p, i64p, f64p, f64p, f64p,
                                            f64p, f64p]
@@ -79,6 +80,7 @@ def lib() -> ctypes.CDLL:
                                           u8p]
         _lib.oracle_grad.argtypes = [i64, i64, i64p, f64p, ctypes.c_double, i64, f64p, i64p,
                                      f64p, f64p, f64p, f64p, i64, i64p, f64p]
+        _lib.oracle_grad_abs.argtypes = _lib.oracle_grad.argtypes
         _lib.oracle_num_threads.restype = ctypes.c_int
     return _lib
 
@@ -209,12 +211,15 @@ def kept(eta0: float, box) -> np.ndarray:
     return out.astype(bool)
 
 
-def grad(nside: int, pix, cotangent, eta0: float, boxes: Sequence, sel) -> np.ndarray:
+def grad(nside: int, pix, cotangent, eta0: float, boxes: Sequence, sel,
+         absolute: bool = False) -> np.ndarray:
     """Gradient of sum_p g_p Theta_p/GU over the listed pixels with respect to
     (x_rel[3], xdot[3], xprime[3], dsigma) of the selected segments.
 
     ``sel`` holds global segment indices (box-major concatenation order).
-    Returns an array (len(sel), 10)."""
+    Returns an array (len(sel), 10).  With absolute=True, every pixel's
+    contribution enters in absolute value: sum_p |g_p df_p/dtheta|, the scale
+    of each component before its terms cancel."""
     p = _i64(pix).ravel()
     g = _f64(cotangent).ravel()
     if g.size != p.size:
@@ -224,9 +229,9 @@ def grad(nside: int, pix, cotangent, eta0: float, boxes: Sequence, sel) -> np.nd
     if s.size and (s.min() < 0 or s.max() >= pk.seg_off[-1]):
         raise ValueError("segment index out of range")
     out = np.empty((s.size, 10), dtype=np.float64)
-    lib().oracle_grad(nside, p.size, _p(p, ctypes.c_int64), _p(g, ctypes.c_double),
-                      float(eta0), *pk.args(), s.size, _p(s, ctypes.c_int64),
-                      _p(out, ctypes.c_double))
+    fn = lib().oracle_grad_abs if absolute else lib().oracle_grad
+    fn(nside, p.size, _p(p, ctypes.c_int64), _p(g, ctypes.c_double), float(eta0), *pk.args(),
+       s.size, _p(s, ctypes.c_int64), _p(out, ctypes.c_double))
     return out
 
 
@@ -308,6 +313,15 @@ def ang2pix(nside: int, vecs) -> np.ndarray:
     v = _f64(vecs).reshape(-1, 3)
     out = np.empty(v.shape[0], dtype=np.int64)
     lib().oracle_ang2pix_many(nside, v.shape[0], _p(v, ctypes.c_double), _p(out, ctypes.c_int64))
+    return out
+
+
+def quarter_turns(xy) -> np.ndarray:
+    """Azimuth phi / (pi/2) in [0, 4) of directions (n, 2) by the fixed
+    arctangent recipe that ang2pix uses."""
+    v = _f64(xy).reshape(-1, 2)
+    out = np.empty(v.shape[0], dtype=np.float64)
+    lib().oracle_quarter_turns_many(v.shape[0], _p(v, ctypes.c_double), _p(out, ctypes.c_double))
     return out
 
 

@@ -391,10 +391,41 @@ void oracle_kept_many(int64_t nseg, const double *box, double eta0, const double
  *   df/dw  = -4 eps N / q   (f is linear in w; finite at w = 0)
  * where the last terms come from eps = sqrt(T^2/(1 - V^2)).
  */
+static void grad_sums(int64_t nside, int64_t nlist, const int64_t *pix, const double *g,
+                      double eta0, int64_t nbox, const double *boxes, const int64_t *seg_off,
+                      const double *x_rel, const double *xdot, const double *xprime,
+                      const double *dsigma, int64_t nsel, const int64_t *sel, int absolute,
+                      double *out);
+
 void oracle_grad(int64_t nside, int64_t nlist, const int64_t *pix, const double *g,
                  double eta0, int64_t nbox, const double *boxes, const int64_t *seg_off,
                  const double *x_rel, const double *xdot, const double *xprime,
                  const double *dsigma, int64_t nsel, const int64_t *sel, double *out)
+{
+    grad_sums(nside, nlist, pix, g, eta0, nbox, boxes, seg_off, x_rel, xdot, xprime, dsigma,
+              nsel, sel, 0, out);
+}
+
+/*
+ * The same sums with every pixel's contribution taken in absolute value,
+ * sum_p |g_p df_p/dtheta| per component: the scale of each gradient
+ * component before its terms cancel (the bound on the error of a sum whose
+ * terms each carry a relative error e is e times this).
+ */
+void oracle_grad_abs(int64_t nside, int64_t nlist, const int64_t *pix, const double *g,
+                     double eta0, int64_t nbox, const double *boxes, const int64_t *seg_off,
+                     const double *x_rel, const double *xdot, const double *xprime,
+                     const double *dsigma, int64_t nsel, const int64_t *sel, double *out)
+{
+    grad_sums(nside, nlist, pix, g, eta0, nbox, boxes, seg_off, x_rel, xdot, xprime, dsigma,
+              nsel, sel, 1, out);
+}
+
+static void grad_sums(int64_t nside, int64_t nlist, const int64_t *pix, const double *g,
+                      double eta0, int64_t nbox, const double *boxes, const int64_t *seg_off,
+                      const double *x_rel, const double *xdot, const double *xprime,
+                      const double *dsigma, int64_t nsel, const int64_t *sel, int absolute,
+                      double *out)
 {
     double *dirs = (double *)malloc(sizeof(double) * 3 * (size_t)(nlist > 0 ? nlist : 1));
     #pragma omp parallel for schedule(static)
@@ -448,13 +479,14 @@ void oracle_grad(int64_t nside, int64_t nlist, const int64_t *pix, const double 
                     const double dV = (C / q) * (d[k] + (a * td / (bb * bb)) * n[k])
                                       + f * s.V[k] / (1.0 - vv);
                     const double dT = -(C / (bb * q)) * (td * n[k] + a * d[k]) + f * s.T[k] / tt;
-                    cadd(&loc[k], gp * dP);
-                    cadd(&loc[3 + k], gp * dV);
-                    cadd(&loc[6 + k], gp * dT);
+                    cadd(&loc[k], absolute ? fabs(gp * dP) : gp * dP);
+                    cadd(&loc[3 + k], absolute ? fabs(gp * dV) : gp * dV);
+                    cadd(&loc[6 + k], absolute ? fabs(gp * dT) : gp * dT);
                 }
                 /* Eq. (1) is linear in dsigma: its derivative is the summand
                  * without the dsigma factor, finite at dsigma = 0. */
-                cadd(&loc[9], gp * (-4.0 * s.eps * N / q));
+                const double dw = gp * (-4.0 * s.eps * N / q);
+                cadd(&loc[9], absolute ? fabs(dw) : dw);
             }
         }
         for (int c = 0; c < 10; ++c) {
@@ -693,17 +725,72 @@ void oracle_alm2cl(int64_t lmax, const double *alm_re, const double *alm_im, dou
 /*               + 1 and the position floor(t ring) mod 4 ring.             */
 /* 1 - |z| is taken as (x^2 + y^2) / (r (r + |z_v|)) for a vector (x, y, z_v) */
 /* of length r, which keeps its accuracy near the poles.                     */
+/* The azimuth t comes from the fixed arctangent recipe below (IEEE          */
+/* operations only), so that two implementations of it agree bit for bit.   */
 /* ------------------------------------------------------------------------ */
+
+/* atan(u) / (pi/2) for |u| <= tan(pi/8): the Maclaurin series of atan,
+ *   atan(u) = u - u^3/3 + u^5/5 - ... ,
+ * cut after u^45 (|u|^46/47 < 2e-19 |u| there), summed in u^2 by
+ * fma-Horner from the highest term, with coefficients (-1)^k/(2k+1) as the
+ * doubles nearest them, then scaled by 2/pi (the double nearest). */
+static double atan_quarter(double u)
+{
+    static const double c[22] = {
+        -1.0 / 3.0,  1.0 / 5.0,  -1.0 / 7.0,  1.0 / 9.0,  -1.0 / 11.0, 1.0 / 13.0,
+        -1.0 / 15.0, 1.0 / 17.0, -1.0 / 19.0, 1.0 / 21.0, -1.0 / 23.0, 1.0 / 25.0,
+        -1.0 / 27.0, 1.0 / 29.0, -1.0 / 31.0, 1.0 / 33.0, -1.0 / 35.0, 1.0 / 37.0,
+        -1.0 / 39.0, 1.0 / 41.0, -1.0 / 43.0, 1.0 / 45.0};
+    const double v = u * u;
+    double p = c[21];
+    for (int k = 20; k >= 0; --k) p = fma(p, v, c[k]);
+    const double a = fma(u * v, p, u);
+    return a * 0.63661977236758134308;
+}
+
+/* phi / (pi/2) in [0, 4) for the direction (x, y) of azimuth phi in
+ * [0, 2 pi), (x, y) != (0, 0):
+ *   1. the quadrant q from the signs, and (a, b) the direction turned by
+ *      -q pi/2 into a >= 0, b >= 0 (exact swaps and negations);
+ *   2. r = min(a, b) / max(a, b) in [0, 1] (one division);
+ *   3. atan(r) / (pi/2): if r > tan(pi/8) (the double nearest), as
+ *      1/2 + atan_quarter((r - 1) / (r + 1)), else atan_quarter(r);
+ *   4. the angle from the a axis is that value when b <= a, else one minus
+ *      it; t = q + angle, and t = 4 wraps to 0. */
+double oracle_quarter_turns(double x, double y)
+{
+    int q;
+    double a, b;
+    if (y >= 0.0) {
+        if (x > 0.0) { q = 0; a = x; b = y; }
+        else { q = 1; a = y; b = -x; }
+    } else {
+        if (x < 0.0) { q = 2; a = -x; b = -y; }
+        else { q = 3; a = -y; b = x; }
+    }
+    const int swap = b > a;
+    const double r = swap ? a / b : b / a;
+    double f;
+    if (r > 0.41421356237309503) f = 0.5 + atan_quarter((r - 1.0) / (r + 1.0));
+    else f = atan_quarter(r);
+    const double ang = swap ? 1.0 - f : f;
+    double t = (double)q + ang;
+    if (t >= 4.0) t -= 4.0;
+    return t;
+}
+
+void oracle_quarter_turns_many(int64_t n, const double *xy, double *t)
+{
+    for (int64_t i = 0; i < n; ++i) t[i] = oracle_quarter_turns(xy[2 * i], xy[2 * i + 1]);
+}
+
 int64_t oracle_ang2pix(int64_t nside, const double v[3])
 {
     const int64_t N = nside;
     const double rho2 = v[0] * v[0] + v[1] * v[1];
     const double r = sqrt(rho2 + v[2] * v[2]);
     const double z = v[2] / r;
-    double phi = atan2(v[1], v[0]);
-    if (phi < 0.0) phi += 2.0 * ORACLE_PI;
-    double t = phi / (0.5 * ORACLE_PI);
-    if (t >= 4.0) t -= 4.0;
+    const double t = oracle_quarter_turns(v[0], v[1]);
     const double az = fabs(z);
     if (az <= 2.0 / 3.0) {
         const double t1 = (double)N * (0.5 + t);

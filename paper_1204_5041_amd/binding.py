@@ -36,7 +36,7 @@ EXPORTED = ["csmap_npix", "csmap_create_sky", "csmap_add_box", "csmap_add_snapsh
             "csmap_get_stats", "csmap_autotune", "csmap_cap_tiles", "csmap_ring_block_rows",
             "csmap_cap_block_tiles", "csmap_add_cone_box", "csmap_precompute",
             "csmap_ang2pix_ring", "csmap_cone_place", "csmap_cone_min_nside",
-            "csmap_render_flat", "csmap_render_dirs"]
+            "csmap_render_flat", "csmap_render_dirs", "csmap_valu_probe"]
 
 
 class csmap_box(ctypes.Structure):
@@ -96,6 +96,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.csmap_add_snapshot_box.argtypes = [vp, ctypes.POINTER(csmap_box), ctypes.POINTER(i64)]
     lib.csmap_cone_events.argtypes = [ctypes.POINTER(csmap_box), ctypes.c_double, vp, vp, vp, vp]
     lib.csmap_map2alm.argtypes = [i64, i64, vp, vp, vp]
+    lib.csmap_valu_probe.argtypes = [i32, i64, i64, vp, vp, ctypes.POINTER(dbl),
+                                     ctypes.POINTER(dbl)]
     lib.csmap_alm2cl.argtypes = [i64, vp, vp, vp]
     lib.csmap_render.argtypes = [vp, vp]
     lib.csmap_backward.argtypes = [vp, vp, ctypes.POINTER(csmap_grad), i64]
@@ -372,9 +374,10 @@ class Sky:
         return grads
 
     def render_flat(self, center, e1, e2, nx: int, ny: int, pix: float,
-                    accept_cos: float = -1.0, out=None):
+                    accept_cos: float, out=None):
         """Flat-sky small-angle map on a gnomonic patch (csmap_render_flat):
-        a float64 CUDA tensor of shape (ny, nx)."""
+        a float64 CUDA tensor of shape (ny, nx).  accept_cos is the cosine of
+        the acceptance cone around the patch axis, in (0, 1]."""
         torch = _torch()
         if out is None:
             out = torch.empty((ny, nx), dtype=torch.float64, device="cuda")
@@ -482,6 +485,20 @@ def map2alm(hmap, lmax: int, stream=None):
     _check(lib().csmap_map2alm(nside, lmax, _dev_ptr(hmap.contiguous()), _dev_ptr(alm),
                                st.cuda_stream))
     return torch.view_as_complex(alm.view(-1, 2))
+
+
+def valu_probe(kind: int, blocks: int, iters: int, stream=None):
+    """csmap_valu_probe: (kernel ms, FMA instructions per wavefront count) of
+    a launch of known FMA work: FP32 (kind 0), FP64 (kind 1), FP32 with a
+    scalar-register multiplier (kind 2)."""
+    torch = _torch()
+    out = torch.empty(int(blocks) * 256, dtype=torch.float64 if kind == 1 else torch.float32,
+                      device="cuda")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    ms, n = ctypes.c_double(), ctypes.c_double()
+    _check(lib().csmap_valu_probe(int(kind), int(blocks), int(iters), _dev_ptr(out),
+                                  st.cuda_stream, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
 
 
 def alm2cl(alm, lmax: int, stream=None):

@@ -20,7 +20,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcsmap.so")
 ROOT = os.path.dirname(HERE)
 
-HIP_SOURCES = ["kernels.hip", "alm.hip", "flat.hip", "api.cpp"]
+HIP_SOURCES = ["kernels.hip", "alm.hip", "flat.hip", "probe.hip", "api.cpp"]
 CXX_SOURCES = ["sched.cpp", "cones.cpp"]
 
 HIPCC_FLAGS = [

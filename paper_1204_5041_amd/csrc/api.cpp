@@ -40,6 +40,8 @@ hipError_t launch_cone_events(int64_t n, int dtype, const void* x_rel, const voi
                               const double origin[3], double eta0, double eta_lo, double eta_hi,
                               double* pos, double* delta, uint8_t* keep, hipStream_t st);
 size_t map2alm_scratch_bytes(int64_t nside, int64_t lmax);
+hipError_t launch_valu_probe(int kind, int64_t blocks, int64_t iters, void* out, hipStream_t st);
+int64_t valu_probe_chains();
 hipError_t launch_map2alm(int64_t nside, int64_t lmax, const double* map, double* alm,
                           void* scratch, hipStream_t st);
 hipError_t launch_alm2cl(int64_t lmax, const double* alm, double* cl, hipStream_t st);
@@ -162,7 +164,7 @@ struct csmap_sky {
   bool dir_ready = false;
 
   // adjoint scratch
-  DevBuf d_pixtab32, d_pix64, d_partial, d_adj_items;
+  DevBuf d_pixtab32, d_pix64, d_partial, d_adj_items, d_adjc;
 
   // graph
   hipStream_t cap_stream = nullptr;
@@ -580,7 +582,7 @@ csmap_status csmap_destroy_sky(csmap_sky* s) {
                     &s->d_box_count, &s->d_raw_off, &s->d_rec32, &s->d_phat64, &s->d_rec64,
                     &s->d_orig, &s->d_tile_ptr, &s->d_tile_boxes, &s->d_items,
                     &s->d_box_items, &s->d_counters, &s->d_pixtab32, &s->d_pix64,
-                    &s->d_partial, &s->d_adj_items, &s->d_dir};
+                    &s->d_partial, &s->d_adj_items, &s->d_adjc, &s->d_dir};
   for (DevBuf* b : bufs) b->release();
   delete s;
   return CSMAP_OK;
@@ -814,6 +816,31 @@ csmap_status csmap_map2alm(int64_t nside, int64_t lmax, const double* map, doubl
   return CSMAP_OK;
 }
 
+csmap_status csmap_valu_probe(int kind, int64_t blocks, int64_t iters, void* out,
+                              void* hip_stream, double* ms, double* fma_insts) {
+  g_err.clear();
+  if (kind < 0 || kind > 2) return fail(CSMAP_E_INVALID, "kind must be 0, 1 or 2");
+  if (blocks < 1 || blocks > (int64_t)1 << 24 || iters < 1 || iters > (int64_t)1 << 30)
+    return fail(CSMAP_E_INVALID, "need 1 <= blocks <= 2^24 and 1 <= iters <= 2^30");
+  if (!out) return fail(CSMAP_E_INVALID, "out is NULL");
+  hipStream_t st = (hipStream_t)hip_stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = hipEventRecord(e0, st);
+  if (e == hipSuccess) e = launch_valu_probe(kind, blocks, iters, out, st);
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return dev_fail(nullptr, e, "valu probe");
+  if (ms) *ms = t;
+  if (fma_insts) *fma_insts = (double)blocks * 4.0 * (double)iters * (double)valu_probe_chains();
+  return CSMAP_OK;
+}
+
 csmap_status csmap_alm2cl(int64_t lmax, const double* alm, double* cl, void* hip_stream) {
   g_err.clear();
   if (lmax < 0 || lmax > 4 * kMaxNside) return fail(CSMAP_E_INVALID, "lmax out of range");
@@ -980,8 +1007,22 @@ csmap_status csmap_render_flat(csmap_sky* s, const csmap_patch* patch, double* m
       P.nx * P.ny > (int64_t)1 << 31)
     return fail(CSMAP_E_INVALID, "need nx, ny >= 1 and nx * ny <= 2^31");
   if (!isfinite(P.pix) || !(P.pix > 0.0)) return fail(CSMAP_E_INVALID, "pix must be > 0");
-  if (!(P.accept_cos >= -1.0 && P.accept_cos <= 1.0))
-    return fail(CSMAP_E_INVALID, "accept_cos must be in [-1, 1]");
+  if (!(P.accept_cos > 0.0 && P.accept_cos <= 1.0))
+    return fail(CSMAP_E_INVALID, "accept_cos must be in (0, 1]");
+  // An accepted segment has |e.P|/D < tan(rho), so its plane position in
+  // pixel units is below tan(rho)/pix + n/2, every pixel-segment offset below
+  // tan(rho)/pix + n, and with that bound at 2^30 the pair kernel's product
+  // of two squared distances stays below 4 (2^30)^4 = 2^122, inside the range
+  // of its reciprocal ([2^-125, 2^125]).
+  {
+    const double c = P.accept_cos;
+    const double tan_rho = sqrt((1.0 - c) * (1.0 + c)) / c;
+    const double nmax = (double)std::max(P.nx, P.ny);
+    if (!(tan_rho / P.pix + nmax <= 1073741824.0))
+      return fail(CSMAP_E_INVALID,
+                  "acceptance cone too wide for the pixel size: need "
+                  "tan(acos(accept_cos))/pix + max(nx, ny) <= 2^30");
+  }
   cs = prepare(s);
   if (cs != CSMAP_OK) return cs;
   const int64_t nbox = (int64_t)s->boxes.size();
@@ -1099,7 +1140,10 @@ csmap_status csmap_backward(csmap_sky* s, const double* dmap, const csmap_grad* 
   if (cs != CSMAP_OK) return cs;
   hipStream_t st = s->stream;
   HIPCHK(s, hipEventRecord(s->ev[3], st), "event");
-  const PreArgs P = pre_args(s);
+  HIPCHK(s, s->d_adjc.ensure(sizeof(float) * 4 * (size_t)std::max<int64_t>(1, s->total_seg)),
+         "alloc adjoint constants");
+  PreArgs P = pre_args(s);
+  P.adjc = s->d_adjc.as<float>();
   HIPCHK(s, launch_precompute(P, nbox, st), "precompute launch");
   // Kept counts decide the work items.
   std::vector<DevBoxCount> kc(std::max<int64_t>(nbox, 1));
@@ -1156,6 +1200,7 @@ csmap_status csmap_backward(csmap_sky* s, const double* dmap, const csmap_grad* 
   A.pix64 = s->d_pix64.as<double>();
   A.rec32 = s->d_rec32.as<float>();
   A.phat64 = s->d_phat64.as<double>();
+  A.adjc = s->d_adjc.as<float>();
   A.items = s->d_adj_items.as<int32_t>();
   A.nitems = nitems;
   A.nsplit = nsplit;

@@ -175,8 +175,9 @@ __global__ void __launch_bounds__(256) k_flat32(FlatArgs A, int64_t ntiles, int6
       qb[j] = fmaf(xb[j], xb[j], yb2);
     }
 #pragma unroll
-    // qa qb >= kFlatTiny^2 = 1e-36 > 2^-125, and far below 2^125 for any
-    // patch: inside recip_newton's range.
+    // qa qb >= kFlatTiny^2 = 1e-36 > 2^-125, and below 2^122 because the
+    // entry point admits only patches whose pixel offsets stay below 2^30:
+    // inside recip_newton's range.
     for (int j = 0; j < kFlatK; ++j) rq[j] = recip_newton(qa[j] * qb[j]);
 #pragma unroll
     for (int j = 0; j < kFlatK; ++j) {

@@ -124,9 +124,61 @@ __device__ __forceinline__ void pix2vec_ring(int64_t nside, int64_t p, double* v
   *vz = z;
 }
 
+// Azimuth of (x, y) in quarter turns, phi / (pi/2) in [0, 4), from IEEE
+// operations only (so that any implementation of the same steps agrees bit
+// for bit; the device atan2 is not correctly rounded):
+//   * the quadrant q from the signs of x and y, and (a, b) the direction
+//     turned back by q quarter turns, a >= 0, b >= 0 (swaps and negations);
+//   * r = min(a, b) / max(a, b);
+//   * atan(r) in quarter turns: 1/2 + A((r - 1)/(r + 1)) above tan(pi/8)
+//     (the double nearest), else A(r), where A(u) is the Maclaurin series
+//     of atan through u^45 (|u| <= tan(pi/8), so the first omitted term is
+//     below 2e-19 |u|), fma-Horner in u^2 from the top, coefficients the
+//     doubles nearest (-1)^k/(2k+1), times the double nearest 2/pi;
+//   * the angle from the a axis is that value if b <= a, else 1 minus it;
+//     t = q + angle, wrapped from 4 to 0.
+// Within 2 ulp of the exact azimuth.
+__device__ __forceinline__ double atan_quarter_turns(double u) {
+  constexpr double kC[22] = {
+      -1.0 / 3.0,  1.0 / 5.0,  -1.0 / 7.0,  1.0 / 9.0,  -1.0 / 11.0, 1.0 / 13.0,
+      -1.0 / 15.0, 1.0 / 17.0, -1.0 / 19.0, 1.0 / 21.0, -1.0 / 23.0, 1.0 / 25.0,
+      -1.0 / 27.0, 1.0 / 29.0, -1.0 / 31.0, 1.0 / 33.0, -1.0 / 35.0, 1.0 / 37.0,
+      -1.0 / 39.0, 1.0 / 41.0, -1.0 / 43.0, 1.0 / 45.0};
+  const double v = u * u;
+  double p = kC[21];
+#pragma unroll
+  for (int k = 20; k >= 0; --k) p = fma(p, v, kC[k]);
+  return fma(u * v, p, u) * 0.63661977236758134308;
+}
+
+__device__ __forceinline__ double quarter_turns(double x, double y) {
+  int q;
+  double a, b;
+  if (y >= 0.0) {
+    if (x > 0.0) {
+      q = 0; a = x; b = y;
+    } else {
+      q = 1; a = y; b = -x;
+    }
+  } else {
+    if (x < 0.0) {
+      q = 2; a = -x; b = -y;
+    } else {
+      q = 3; a = -y; b = x;
+    }
+  }
+  const bool swap = b > a;
+  const double r = swap ? a / b : b / a;
+  const double f = (r > 0.41421356237309503) ? 0.5 + atan_quarter_turns((r - 1.0) / (r + 1.0))
+                                             : atan_quarter_turns(r);
+  double t = (double)q + (swap ? 1.0 - f : f);
+  if (t >= 4.0) t -= 4.0;
+  return t;
+}
+
 // RING pixel of the direction of (x, y, z), a vector of any positive length:
 // the inverse of pix2vec_ring (Gorski et al. 2005).  With c = cos(theta) and
-// t = phi / (pi/2) in [0, 4):
+// t = phi / (pi/2) in [0, 4) (quarter_turns):
 //   * |c| <= 2/3: the pixel edges are the lines N (1/2 + t) - (3N/4) c = k and
 //     N (1/2 + t) + (3N/4) c = k' for integers k, k'; the cell (k, k') is
 //     belt ring N + 1 + k - k' (of the 2N + 1 belt rings, from the north),
@@ -138,15 +190,11 @@ __device__ __forceinline__ void pix2vec_ring(int64_t nside, int64_t p, double* v
 // 1 - |c| is formed as (x^2 + y^2) / (r (r + |z|)), free of cancellation
 // near the poles.  Used to decide which strings lie inside a healpix cone.
 __device__ __forceinline__ int64_t ang2pix_ring(int64_t nside, double x, double y, double z) {
-  constexpr double kPiD = 3.141592653589793;
   const int64_t N = nside;
   const double rho2 = x * x + y * y;
   const double r = sqrt(rho2 + z * z);
   const double c = z / r;
-  double phi = atan2(y, x);
-  if (phi < 0.0) phi += 2.0 * kPiD;
-  double t = phi / (0.5 * kPiD);
-  if (t >= 4.0) t -= 4.0;
+  const double t = quarter_turns(x, y);
   const double ac = fabs(c);
   if (ac <= 2.0 / 3.0) {
     const double base = (double)N * (0.5 + t);

@@ -83,6 +83,9 @@ struct PreArgs {
   double* phat64;              // FP32C: P/R in FP64, 4 doubles per record
   double* rec64;               // FP64 records (or null)
   int32_t* orig_index;         // record -> index of the segment in its box
+  // Adjoint only (or null): per record the FP32C constants per unit dsigma,
+  // (k, k (1 + Ph.Xdot), k Ph.X', 0) with k = -2 eps / R.
+  float* adjc;
   // Flat-sky patch (csmap_render_flat): when flat_on, a segment is kept only
   // if D = flat_dir.P > 0 and D > flat_cos R.
   double flat_dir[3];
@@ -157,6 +160,7 @@ struct AdjArgs {
   const double* pix64;         // per pixel: n in FP64 (4 doubles)
   const float* rec32;
   const double* phat64;
+  const float* adjc;           // per record: constants per unit dsigma (see PreArgs)
   const int32_t* items;        // (box, segment group, pixel chunk) triples
   int64_t nitems;
   int32_t nsplit;              // pixel chunks per segment group

@@ -340,6 +340,13 @@ __device__ __forceinline__ void emit_record(const PreArgs& A, const DevBox& bx, 
     const double vv = (g.V[0] * g.V[0] + g.V[1] * g.V[1]) + g.V[2] * g.V[2];
     const float force_near = (1.0 - sqrt(vv) < 0.05) ? 1.0f : 0.0f;
     o[3] = make_float4(__int_as_float((int)i), force_near, 0.f, 0.f);
+    if (A.adjc) {
+      // The same constants without the dsigma factor: every adjoint sum is
+      // linear in them, and the dsigma derivative is the unit-dsigma sum.
+      const double ku = -2.0 * g.eps / g.R;
+      ((float4*)A.adjc)[r] = make_float4((float)ku, (float)(ku * (1.0 + pv)), (float)(ku * pt),
+                                         0.f);
+    }
     double2* h = (double2*)(A.phat64 + (size_t)r * 4);
     h[0] = make_double2(Ph[0], Ph[1]);
     h[1] = make_double2(Ph[2], g.R);
@@ -1154,7 +1161,10 @@ __global__ void __launch_bounds__(256) k_adj32(AdjArgs A) {
   const float px = q0.x, py = q0.y, pz = q0.z;
   const float tx = q0.w, ty = q1.x, tz = q1.y;
   const float vx = q1.z, vy = q1.w, vz = q2.x;
-  const float kap = active ? q2.y : 0.0f, c1v = q2.z, c2v = q2.w;
+  // Constants per unit dsigma: the sums come out per unit dsigma, and the
+  // finalize step multiplies by dsigma (finite at dsigma = 0).
+  const float4 ku = ((const float4*)A.adjc)[rec];
+  const float kap = active ? ku.x : 0.0f, c1v = ku.y, c2v = ku.z;
   const double2 h0 = ((const double2*)A.phat64)[2 * rec + 0];
   const double2 h1 = ((const double2*)A.phat64)[2 * rec + 1];
   // The pixel range is uniform; computing it through readfirstlane keeps it
@@ -1241,11 +1251,12 @@ struct GradPtrs {
 
 // Combine the pixel-chunk partials of each kept record (in chunk order) and
 // apply the per-segment chain rule, then scatter to the caller's arrays.
+// The partial sums are per unit dsigma (kappa without its dsigma factor):
 //   G_d   = V S1 - T S2 - D3                   (sum of s df/d(n - Ph))
-//   dL/dP = -(G_d - Ph (Ph.G_d))/R - SF Ph / R (Ph = P/R, dR/dP = Ph)
-//   dL/dV = DV + Ph C2 + SF V/(1 - V^2)        (the last term from eps)
-//   dL/dT = -DT - Ph C4 + SF T/T^2             (the last term from eps)
-//   dL/ddsigma = SF / dsigma
+//   dL/dP = dsigma [-(G_d - Ph (Ph.G_d))/R - SF Ph / R] (Ph = P/R, dR/dP = Ph)
+//   dL/dV = dsigma [DV + Ph C2 + SF V/(1 - V^2)]        (the last term from eps)
+//   dL/dT = dsigma [-DT - Ph C4 + SF T/T^2]             (the last term from eps)
+//   dL/ddsigma = SF                            (Eq. (1) is linear in dsigma)
 __global__ void k_adj_finalize(const DevBox* boxes, const DevBoxCount* counts, int32_t b,
                                const char* raw, const int32_t* orig_index,
                                const double* phat64, const double* partial, int32_t nsplit,
@@ -1292,9 +1303,9 @@ __global__ void k_adj_finalize(const DevBox* boxes, const DevBoxCount* counts, i
   double gx[3], gv[3], gt[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    gx[k] = -(G[k] - Ph[k] * pg) / R - SF * Ph[k] / R;
-    gv[k] = S[8 + k] + Ph[k] * S[3] + SF * V[k] / (1.0 - vv);
-    gt[k] = -S[11 + k] - Ph[k] * S[4] + SF * T[k] / tt;
+    gx[k] = ds * (-(G[k] - Ph[k] * pg) / R - SF * Ph[k] / R);
+    gv[k] = ds * (S[8 + k] + Ph[k] * S[3] + SF * V[k] / (1.0 - vv));
+    gt[k] = ds * (-S[11 + k] - Ph[k] * S[4] + SF * T[k] / tt);
   }
   // A rotated box: sky = rot * box, so d/d(box) = rot^T d/d(sky).
   const bool rot = bx.rotated != 0;
@@ -1304,7 +1315,7 @@ __global__ void k_adj_finalize(const DevBox* boxes, const DevBoxCount* counts, i
     if (out.xd) out.xd[3 * i + k] = rot ? rot_col(bx.rot, k, gv) : gv[k];
     if (out.xp) out.xp[3 * i + k] = rot ? rot_col(bx.rot, k, gt) : gt[k];
   }
-  if (out.ds) out.ds[i] = SF / ds;
+  if (out.ds) out.ds[i] = SF;
 }
 
 // ---------------------------------------------------------------------------

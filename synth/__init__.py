@@ -85,6 +85,30 @@ def segments(n: int, seed: int, dtype=np.float64, side: float = 1.0):
     return cast(x), cast(xdot), cast(xprime), cast(ds)
 
 
+def near_luminal_segments(n: int, seed: int, speeds, v_dirs=None, dtype=np.float32,
+                          side: float = 1.0):
+    """Segments moving close to the speed of light (cusps of Nambu-Goto
+    strings): the recipe above with the speed taken cyclically from
+    `speeds` and, when given, the velocity direction from the unit rows of
+    v_dirs (n, 3); the tangent is drawn uniformly in the plane normal to it,
+    so Xdot.X' = 0 and Xdot^2 + X'^2 = 1 still hold."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = rng.random((n, 3)) * side
+    if v_dirs is None:
+        v_hat = _unit_rows(rng.standard_normal((n, 3)))
+    else:
+        v_hat = _unit_rows(np.asarray(v_dirs, dtype=np.float64).reshape(n, 3))
+    g = rng.standard_normal((n, 3))
+    g = g - np.sum(g * v_hat, axis=1, keepdims=True) * v_hat
+    s_hat = _unit_rows(g)
+    v = np.resize(np.asarray(speeds, dtype=np.float64), n)
+    ds = rng.uniform(0.001, 0.01, n)
+    xdot = v[:, None] * v_hat
+    xprime = np.sqrt(1.0 - v * v)[:, None] * s_hat
+    cast = lambda a: np.ascontiguousarray(a.astype(dtype))
+    return cast(x), cast(xdot), cast(xprime), cast(ds)
+
+
 def make_box(n: int, seed: int, origin, eta_lo: float, eta_hi: float, dtype=np.float64,
              side: float = 1.0, vis: int = VIS_ALL, cap_dir=None, cap_cos=None) -> Box:
     x, xd, xp, ds = segments(n, seed, dtype, side)

@@ -36,3 +36,41 @@ def sky_from_workload(workload, form, options=None, boxes=None):
         sky.add_box(*t, origin=tuple(float(v) for v in bx.origin), eta_lo=bx.eta_lo,
                     eta_hi=bx.eta_hi, vis=bx.vis, ext=tuple(float(v) for v in bx.ext), **kw)
     return sky
+
+
+GRAD_GROUPS = (("x_rel", slice(0, 3)), ("xdot", slice(3, 6)), ("xprime", slice(6, 9)),
+               ("dsigma", slice(9, 10)))
+
+
+def grad_group_errors(got, ref):
+    """Relative L2 error of each parameter group (x_rel, xdot, xprime, dsigma)
+    over all checked segments (rows of 10 gradient components)."""
+    out = {}
+    for name, sl in GRAD_GROUPS:
+        d = got[:, sl] - ref[:, sl]
+        out[name] = float(np.linalg.norm(d) / max(np.linalg.norm(ref[:, sl]), 1e-300))
+    return out
+
+
+# Per-segment bar: |got_s - ref_s| <= 1e-4 |ref_s| + 2e-5 |abs_s| per group,
+# abs_s being the sum over pixels of each component's contributions in
+# absolute value (oracle.grad(..., absolute=True)).  A segment's gradient is a
+# sum over pixels whose terms can cancel to far below their size; the FP32
+# form's terms each carry a relative error up to about 1.2e-5 (its far pair
+# form rounds n.P/R against 1 - n.P/R >= 5e-3), so 2e-5 |abs_s| bounds what
+# rounding of the terms alone can leave in such a sum.
+SEG_REL, SEG_ABS = 1e-4, 2e-5
+
+
+def grad_segment_errors(got, ref, absref):
+    """Largest per-segment error of each parameter group in units of the
+    per-segment bar, |got_s - ref_s| / (|ref_s| + (SEG_ABS/SEG_REL) |abs_s|),
+    to be compared with SEG_REL."""
+    out = {}
+    k = SEG_ABS / SEG_REL
+    for name, sl in GRAD_GROUPS:
+        nref = np.linalg.norm(ref[:, sl], axis=1)
+        nabs = np.linalg.norm(absref[:, sl], axis=1)
+        nd = np.linalg.norm(got[:, sl] - ref[:, sl], axis=1)
+        out[name] = float(np.max(nd / np.maximum(nref + k * nabs, 1e-300))) if nd.size else 0.0
+    return out

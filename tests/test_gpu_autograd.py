@@ -2,8 +2,9 @@
 and its hand-written adjoint (backward), for the loss L = sum_p w_p Theta_p^2
 of the differentiation workload.  Checked against the oracle's FP64 gradient
 and against central FP64 finite differences (h = 1e-6) on sampled segments.
-Bar: relative L2 error <= 1e-4 per parameter group (x_rel, xdot, xprime,
-dsigma)."""
+Bars: relative L2 error <= 1e-4 per parameter group (x_rel, xdot, xprime,
+dsigma), and per checked segment and group |got - ref| <= 1e-4 |ref| +
+2e-5 |abs|, abs summing the pixels' contributions in absolute value."""
 import sys
 
 import numpy as np
@@ -11,13 +12,12 @@ import pytest
 
 import oracle
 import synth
+from helpers import SEG_REL, grad_group_errors, grad_segment_errors
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 GRAD_TOL = 1e-4
-GROUPS = (("x_rel", slice(0, 3)), ("xdot", slice(3, 6)), ("xprime", slice(6, 9)),
-          ("dsigma", slice(9, 10)))
 
 
 def say(*a):
@@ -25,12 +25,13 @@ def say(*a):
     sys.stdout.flush()
 
 
-def grad_errors(got, ref):
-    out = {}
-    for name, sl in GROUPS:
-        d = got[:, sl] - ref[:, sl]
-        out[name] = float(np.linalg.norm(d) / max(np.linalg.norm(ref[:, sl]), 1e-300))
-    return out
+def check_grads(got, ref, absref, what):
+    e = grad_group_errors(got, ref)
+    es = grad_segment_errors(got, ref, absref)
+    say(f"{what}: group L2 {e}; per segment (units of the bar) {es}")
+    assert np.all(np.isfinite(got))
+    assert max(e.values()) <= GRAD_TOL, e
+    assert max(es.values()) <= SEG_REL, es
 
 
 def box_dicts(w, requires_grad=True):
@@ -75,9 +76,10 @@ def test_autograd_quadratic_loss_matches_oracle():
     pix = np.arange(w.npix)
     th = oracle.theta_pixels(w.nside, pix, w.eta0, w.boxes)
     ref = oracle.grad(w.nside, pix, 2.0 * wts * th, w.eta0, w.boxes, np.arange(400))
-    e = grad_errors(got, ref)
-    say(f"autograd reduced config4 errors {e}")
-    assert max(e.values()) <= GRAD_TOL, e
+    absref = oracle.grad(w.nside, pix, 2.0 * wts * th, w.eta0, w.boxes, np.arange(400),
+                         absolute=True)
+    kept = np.concatenate([oracle.kept(w.eta0, b) for b in w.boxes])
+    check_grads(got[kept], ref[kept], absref[kept], "autograd reduced config4")
 
 
 def test_autograd_rejects_a_stale_graph():
@@ -145,6 +147,5 @@ def test_config4_gradient_against_finite_differences():
                 d = term(p) - t0
                 dl.append(float(a.dot(d) + ws.dot(d * d)))
             fd[r, k] = (dl[0] - dl[1]) / (2.0 * h)
-    e = grad_errors(got_all[sel], fd)
-    say(f"config4 autograd vs finite differences {e}")
-    assert max(e.values()) <= GRAD_TOL, e
+    absref = oracle.grad(w.nside, S, a, w.eta0, w.boxes, sel, absolute=True)
+    check_grads(got_all[sel], fd, absref, "config4 autograd vs finite differences")

@@ -117,11 +117,15 @@ def test_flat_leaves_render_unchanged_and_handles_empty(B):
     assert np.all(z == 0.0)
     sky.close()
     empty = B.Sky(8, 16.0, B.CSMAP_FORM_FP32C)
-    z = empty.render_flat(fp.center, fp.e1, fp.e2, 17, 5, fp.pix).cpu().numpy()
+    z = empty.render_flat(fp.center, fp.e1, fp.e2, 17, 5, fp.pix, fp.accept_cos).cpu().numpy()
     assert np.all(z == 0.0)
+    # Rejected: bad sizes and axes, accept_cos outside (0, 1], and cones so
+    # wide for the pixel size that plane offsets would exceed 2^30 pixels.
     for bad in (dict(nx=0), dict(pix=0.0), dict(accept_cos=2.0), dict(e1=(0.0, 0.0, 1.0)),
-                dict(center=(0.0, 0.0, 2.0))):
-        kw = dict(center=fp.center, e1=fp.e1, e2=fp.e2, nx=4, ny=4, pix=fp.pix, accept_cos=-1.0)
+                dict(center=(0.0, 0.0, 2.0)), dict(accept_cos=-1.0), dict(accept_cos=0.0),
+                dict(accept_cos=math.cos(math.radians(89.0)), pix=1e-11)):
+        kw = dict(center=fp.center, e1=fp.e1, e2=fp.e2, nx=4, ny=4, pix=fp.pix,
+                  accept_cos=fp.accept_cos)
         kw.update(bad)
         with pytest.raises(B.CsmapError):
             empty.render_flat(**kw)

@@ -15,6 +15,8 @@
   transposed rotation fails these.
 * Cap visibility: a pixel sees a cap box when its angle to the cap axis is
   at most the cap radius, decided against an independent angle formula.
+* Absolute gradient sums: the triangle inequality against the gradient,
+  equality for one pixel, additivity over pixels.
 """
 import math
 
@@ -259,3 +261,33 @@ def test_cap_visibility_is_the_angular_disc(frac):
     mc = oracle.theta_pixels(nside, pix, 1.0, [bb])
     ma = oracle.theta_pixels(nside, pix, 1.0, [ball])
     assert np.array_equal(mc, np.where(vis, ma, 0.0))
+
+
+# ---------------------------------------------------------------------------
+# Absolute gradient sums (the scale a gradient's terms have before cancelling)
+# ---------------------------------------------------------------------------
+
+def test_absolute_gradient_sums():
+    nside = 4
+    pix = np.arange(12 * nside * nside)
+    x, xd, xp, ds = _segments_eps_not_one(8, 51)
+    box = _box(x, xd, xp, ds, origin=(-0.5, -0.5, -0.5), eta_lo=0.0, eta_hi=2.0)
+    g = np.random.default_rng(8).standard_normal(len(pix))
+    sel = np.arange(8)
+    G = oracle.grad(nside, pix, g, 2.0, [box], sel)
+    A = oracle.grad(nside, pix, g, 2.0, [box], sel, absolute=True)
+    # triangle inequality, strict somewhere (terms of both signs cancel)
+    assert np.all(A >= np.abs(G) * (1 - 1e-14))
+    assert np.any(A > 1.5 * np.abs(G))
+    # invariant under the cotangent's sign, linear in its magnitude
+    assert np.allclose(oracle.grad(nside, pix, -2.0 * g, 2.0, [box], sel, absolute=True), 2 * A,
+                       rtol=1e-14, atol=0)
+    # one pixel: the absolute sum is the absolute gradient
+    for p in (0, 77, 191):
+        G1 = oracle.grad(nside, pix[p:p + 1], g[p:p + 1], 2.0, [box], sel)
+        A1 = oracle.grad(nside, pix[p:p + 1], g[p:p + 1], 2.0, [box], sel, absolute=True)
+        assert np.array_equal(A1, np.abs(G1))
+    # and the sum over pixels of those
+    A_parts = sum(oracle.grad(nside, pix[p:p + 1], g[p:p + 1], 2.0, [box], sel, absolute=True)
+                  for p in range(len(pix)))
+    assert np.allclose(A, A_parts, rtol=1e-13, atol=0)

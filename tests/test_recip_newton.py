@@ -7,8 +7,11 @@ is far below the bound).  Pinned against the exact 1/x in FP64: the seed's
 relative error is at most 5.05e-2 (the constant is the bits of 2^127 less
 the shift that minimises it), the third-order step cubes it (1.3e-4) and the
 second-order step squares it (1.7e-8 before rounding), so the result is
-within 0.8 ulp of 1/x over the operand range the kernel uses (products of
-two floored squared distances, [1e-36, 1e18))."""
+within 0.8 ulp of 1/x over [2^-125, 2^125].  The kernel's operands are
+products of two floored squared distances: at least 1e-36 > 2^-125 by the
+floor, and below 2^122 because csmap_render_flat rejects patches whose
+pixel-segment offsets could exceed 2^30 pixels (tan(rho)/pix + max(nx, ny)
+<= 2^30, so each squared distance is below 2 (2^30)^2)."""
 import os
 import re
 
@@ -58,11 +61,11 @@ def test_seed_minimises_the_seed_error():
 def test_newton_reciprocal_within_0p8_ulp():
     rng = np.random.default_rng(17)
     m = rng.uniform(1.0, 2.0, 1_000_000)
-    x = (m * 2.0 ** rng.integers(-119, 60, m.size)).astype(np.float32)
-    p2 = (2.0 ** np.arange(-119, 60)).astype(np.float32)
+    x = (m * 2.0 ** rng.integers(-125, 125, m.size)).astype(np.float32)
+    p2 = (2.0 ** np.arange(-125, 126)).astype(np.float32)
     x = np.concatenate([x, p2, np.nextafter(p2, np.float32(np.inf)),
                         np.nextafter(p2, np.float32(0))])
-    x = x[(x >= 1e-36) & (x < 1e18)]
+    x = x[(x >= 2.0 ** -125) & (x <= 2.0 ** 125)]
     y, y0 = _recip(x, _seed_constant())
     ref = 1.0 / x.astype(np.float64)
     # the seed's error, which the bound rests on
@@ -71,3 +74,15 @@ def test_newton_reciprocal_within_0p8_ulp():
     ulp = np.spacing(ref.astype(np.float32)).astype(np.float64)
     err = np.abs(y.astype(np.float64) - ref) / ulp
     assert err.max() <= 0.8, err.max()
+
+
+def test_operand_bound_of_the_flat_kernel():
+    """The entry point's patch bound keeps the kernel's operands in range,
+    and past 2^126 the seed wraps (why the bound is needed)."""
+    off = 2.0 ** 30                       # largest pixel-segment offset admitted
+    q_max = 2.0 * off * off               # squared distance, both axes at the bound
+    assert q_max * q_max <= 2.0 ** 122 < 2.0 ** 125
+    assert 1e-18 * 1e-18 >= 2.0 ** -125   # the floor of each squared distance
+    big = np.array([1.7e38, 3e38], dtype=np.float32)
+    y, _ = _recip(big, _seed_constant())
+    assert not np.all(np.isfinite(y) & (np.abs(y * big.astype(np.float64) - 1.0) < 1e-6))
