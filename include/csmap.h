@@ -394,6 +394,21 @@ csmap_status csmap_autotune(csmap_sky *sky, const char *cache_path);
 csmap_status csmap_map2alm(int64_t nside, int64_t lmax, const double *map, double *alm,
                            void *hip_stream);
 
+/* csmap_map2alm for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same result, with the scratch taken from a fixed
+ * 64 MiB device array of the library (one per GPU, held until the process
+ * ends) instead of an allocation.  Calls no hipMalloc, hipFree or allocating
+ * routine and does not synchronise: the work is enqueued on hip_stream, which
+ * must belong to the current device.  Arguments, layout and errors as
+ * csmap_map2alm, plus CSMAP_E_INVALID when (nside, lmax) needs more scratch
+ * than 64 MiB (Nside 512 with lmax 512 fits; Nside 512 with lmax 1024 does
+ * not).  Every call on one GPU shares its array and nothing in it needs to
+ * start at zero; calls that overlap on one GPU (different streams, or
+ * threads) race on it and must be serialised by the caller. */
+csmap_status csmap_map2alm_noalloc(int64_t nside, int64_t lmax, const double *map, double *alm,
+                                   void *hip_stream);
+
 /* C_l = (|a_l0|^2 + 2 sum_{m=1}^{l} |a_lm|^2) / (2l + 1) for l = 0 .. lmax of
  * a real map's a_lm (layout of csmap_map2alm); cl: device, lmax + 1
  * doubles.  Enqueued on hip_stream. */

@@ -36,7 +36,8 @@ EXPORTED = ["csmap_npix", "csmap_create_sky", "csmap_add_box", "csmap_add_snapsh
             "csmap_get_stats", "csmap_autotune", "csmap_cap_tiles", "csmap_ring_block_rows",
             "csmap_cap_block_tiles", "csmap_add_cone_box", "csmap_precompute",
             "csmap_ang2pix_ring", "csmap_cone_place", "csmap_cone_min_nside",
-            "csmap_render_flat", "csmap_render_dirs", "csmap_valu_probe"]
+            "csmap_render_flat", "csmap_render_dirs", "csmap_map2alm_noalloc",
+            "csmap_valu_probe"]
 
 
 class csmap_box(ctypes.Structure):
@@ -96,6 +97,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.csmap_add_snapshot_box.argtypes = [vp, ctypes.POINTER(csmap_box), ctypes.POINTER(i64)]
     lib.csmap_cone_events.argtypes = [ctypes.POINTER(csmap_box), ctypes.c_double, vp, vp, vp, vp]
     lib.csmap_map2alm.argtypes = [i64, i64, vp, vp, vp]
+    lib.csmap_map2alm_noalloc.argtypes = [i64, i64, vp, vp, vp]
     lib.csmap_valu_probe.argtypes = [i32, i64, i64, vp, vp, ctypes.POINTER(dbl),
                                      ctypes.POINTER(dbl)]
     lib.csmap_alm2cl.argtypes = [i64, vp, vp, vp]
@@ -485,6 +487,23 @@ def map2alm(hmap, lmax: int, stream=None):
     _check(lib().csmap_map2alm(nside, lmax, _dev_ptr(hmap.contiguous()), _dev_ptr(alm),
                                st.cuda_stream))
     return torch.view_as_complex(alm.view(-1, 2))
+
+
+def map2alm_noalloc(hmap, lmax: int, alm, stream=None):
+    """csmap_map2alm_noalloc into a caller-owned float64 CUDA tensor `alm` of
+    2 alm_size(lmax) entries (real and imaginary parts interleaved); the
+    library allocates nothing.  Enqueued on `stream` without synchronising."""
+    torch = _torch()
+    npix = int(hmap.numel())
+    nside = int(round((npix / 12) ** 0.5))
+    if 12 * nside * nside != npix or hmap.dtype != torch.float64 or not hmap.is_contiguous():
+        raise ValueError("map must be a contiguous float64 tensor of 12 Nside^2 pixels")
+    if alm.dtype != torch.float64 or alm.numel() != 2 * alm_size(lmax) or not alm.is_contiguous():
+        raise ValueError("alm must be a contiguous float64 tensor of 2 alm_size(lmax) entries")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().csmap_map2alm_noalloc(nside, lmax, _dev_ptr(hmap), _dev_ptr(alm),
+                                       st.cuda_stream))
+    return alm
 
 
 def valu_probe(kind: int, blocks: int, iters: int, stream=None):

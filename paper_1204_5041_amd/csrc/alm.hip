@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "healpix_dev.h"
 
 namespace csmap {
@@ -824,6 +826,35 @@ hipError_t launch_map2alm(int64_t nside, int64_t lmax, const double* map, double
   k_alm_sum<<<dim3((unsigned)((size + 255) / 256)), dim3(256), 0, st>>>(size, nblk, w, part,
                                                                         alm);
   return hipGetLastError();
+}
+
+// Scratch of the allocation-free map2alm: a fixed device array, one copy per
+// GPU, held until the process ends.  Host code reaches it only through the
+// address hipGetSymbolAddress returns on each device (the array's name is a
+// host-side stand-in there), looked up once per device and kept.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+size_t map2alm_noalloc_max_bytes() { return kNoAllocScratchBytes; }
+
+hipError_t map2alm_noalloc_scratch(void** ptr) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_alm2cl(int64_t lmax, const double* alm, double* cl, hipStream_t st) {

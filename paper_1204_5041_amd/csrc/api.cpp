@@ -40,6 +40,8 @@ hipError_t launch_cone_events(int64_t n, int dtype, const void* x_rel, const voi
                               const double origin[3], double eta0, double eta_lo, double eta_hi,
                               double* pos, double* delta, uint8_t* keep, hipStream_t st);
 size_t map2alm_scratch_bytes(int64_t nside, int64_t lmax);
+size_t map2alm_noalloc_max_bytes();
+hipError_t map2alm_noalloc_scratch(void** ptr);
 hipError_t launch_valu_probe(int kind, int64_t blocks, int64_t iters, void* out, hipStream_t st);
 int64_t valu_probe_chains();
 hipError_t launch_map2alm(int64_t nside, int64_t lmax, const double* map, double* alm,
@@ -813,6 +815,26 @@ csmap_status csmap_map2alm(int64_t nside, int64_t lmax, const double* map, doubl
   (void)hipFree(scratch);
   if (e != hipSuccess) return dev_fail(nullptr, e, "map2alm launch");
   if (e2 != hipSuccess) return dev_fail(nullptr, e2, "map2alm");
+  return CSMAP_OK;
+}
+
+csmap_status csmap_map2alm_noalloc(int64_t nside, int64_t lmax, const double* map, double* alm,
+                                   void* hip_stream) {
+  g_err.clear();
+  if (nside < 1 || nside > kMaxNside) return fail(CSMAP_E_INVALID, "nside must be in [1, 8192]");
+  if (lmax < 0 || lmax > 4 * nside) return fail(CSMAP_E_INVALID, "lmax must be in [0, 4 Nside]");
+  if (!map || !alm) return fail(CSMAP_E_INVALID, "map or alm is NULL");
+  const size_t need = map2alm_scratch_bytes(nside, lmax);
+  if (need > map2alm_noalloc_max_bytes())
+    return fail(CSMAP_E_INVALID, "map2alm_noalloc: Nside " + std::to_string(nside) + ", lmax " +
+                                     std::to_string(lmax) + " needs " + std::to_string(need) +
+                                     " bytes of scratch; the fixed scratch holds " +
+                                     std::to_string(map2alm_noalloc_max_bytes()));
+  void* scratch = nullptr;
+  hipError_t e = map2alm_noalloc_scratch(&scratch);
+  if (e != hipSuccess) return dev_fail(nullptr, e, "map2alm_noalloc scratch address");
+  e = launch_map2alm(nside, lmax, map, alm, scratch, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return dev_fail(nullptr, e, "map2alm_noalloc launch");
   return CSMAP_OK;
 }
 

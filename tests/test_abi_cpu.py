@@ -61,6 +61,15 @@ def test_invalid_arguments_rejected_on_host():
     assert L.csmap_cone_events(ctypes.byref(bx), 2.0, None, None, None, None) == B.CSMAP_E_INVALID
     bx.n = 0                                                          # nothing to do
     assert L.csmap_cone_events(ctypes.byref(bx), 2.0, None, None, None, None) == B.CSMAP_OK
+    # The allocation-free map2alm validates (and refuses scratch needs above
+    # its fixed array) before any device call.
+    fake = ctypes.c_void_p(0x1000)
+    assert L.csmap_map2alm_noalloc(0, 0, fake, fake, None) == B.CSMAP_E_INVALID
+    assert L.csmap_map2alm_noalloc(64, 257, fake, fake, None) == B.CSMAP_E_INVALID
+    assert L.csmap_map2alm_noalloc(64, 8, None, fake, None) == B.CSMAP_E_INVALID
+    assert L.csmap_map2alm_noalloc(512, 1024, fake, fake, None) == B.CSMAP_E_INVALID
+    assert "scratch" in B.csmap_last_error()
+    assert L.csmap_map2alm_noalloc(2048, 4096, fake, fake, None) == B.CSMAP_E_INVALID
 
 
 @pytest.mark.parametrize("nside,tile", [(16, 64), (64, 256), (128, 512), (37, 128)])
