@@ -126,10 +126,18 @@ def main():
                     help="stack: segments per simulation run")
     ap.add_argument("--count-scale", type=float, default=1.0,
                     help="config3: scale of the per-box segment counts")
+    ap.add_argument("--summarize-counters", nargs=4, metavar=("TRACE_DIR", "PMC_A_DIR", "PMC_B_DIR",
+                                                              "LAUNCHES_JSON"),
+                    help="no GPU work: summarise the rocprofv3 kernel-trace and the two --pmc "
+                         "runs of --workload counters (their output directories, and the JSON "
+                         "line that run printed) into the per-kernel VALU record")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="before the timed region, run one plain device copy of this many "
                          "MiB (a known-size reference for hardware traffic counters)")
     args = ap.parse_args()
+    if args.summarize_counters:
+        print(json.dumps(summarize_counters(*args.summarize_counters), indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU layout is described, not run).", file=sys.stderr)
@@ -227,6 +235,12 @@ def main():
                      "kernel": "k_fwd32", "kernel_ms": kern_s * 1e3,
                      "flop_per_pair": FLOP_PER_PAIR},
     }
+    if args.nseg == NSEG and args.nside == NSIDE:
+        # Hardware-counted FLOP of this launch (rocprofv3 counters of the same
+        # kernel on the same box size), over the launch time measured here.
+        hw = measured_valu("k_fwd32", kern_s * 1e3)
+        out["roofline"]["hw"] = hw
+        out["roofline"]["hw_tflops"] = hw["fp32_tflops"] if hw else None
     del skies
     torch.cuda.synchronize()
 
@@ -245,6 +259,8 @@ def main():
         out["fp64"] = {"value": v64, "unit": "pairs/s", "ms_per_step": e64 * 1e3,
                        "kernel_ms": st["ms_forward"], "achieved_tflops": a64,
                        "frac_fp64_peak": a64 / FP64_PEAK_TFLOPS}
+        if args.nseg == NSEG and args.nside == NSIDE:
+            out["fp64"]["hw"] = measured_valu("k_fwd64", st["ms_forward"])
         got64 = maps[pix_t].cpu().numpy()
         out["speedup_fp32_over_fp64"] = value / v64
         sky64.close()
@@ -727,6 +743,18 @@ def bench_alm(args, B, torch):
            "roofline": {"bound": "alu", "achieved": tf, "peak": FP64_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": tf / FP64_PEAK_TFLOPS, "flop": flop},
            "cl_sample": {str(l): float(c[l]) for l in (2, 10, 100, 1000, 4000)}}
+    # The Legendre kernel alone: its time in one more call, from HIP events
+    # on the stream it runs on, against the sums' 8 FLOP per (l, m, ring
+    # pair) and against the counted hardware FLOP.
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    B.map2alm(hmap, lmax)
+    ev1.record()
+    torch.cuda.synchronize()
+    res["call_ms_events"] = ev0.elapsed_time(ev1)
+    leg_flop = 8.0 * (2 * nside) * size
+    res["legendre"] = {"flop": leg_flop, "hw": measured_valu("k_legendre", None)}
     if not args.no_cpu:
         # The oracle's direct sum costs npix * lmax^2 / 2 terms, so at
         # lmax = 2 Nside its time grows as Nside^4: it is timed on the same
@@ -800,25 +828,128 @@ def bench_config4(args, B, torch):
 
 def measured_valu(kernel, kernel_ms):
     """Hardware-counted vector FLOP of a kernel launch from the committed
-    rocprofv3 counter runs (if taken on the current device sources), as FLOP
-    per launch and the rate over a launch of kernel_ms."""
-    import hashlib
+    rocprofv3 counter runs (if taken on the kernel's current sources: the
+    record holds their SHA-256), as FLOP per launch and the rate over a
+    launch of kernel_ms."""
     path = os.path.join(ROOT, "profiles", "valu_counters.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    h = hashlib.sha256()
-    for src in rec.get("sources", []):
-        h.update(open(os.path.join(ROOT, src), "rb").read())
     k = rec.get("kernels", {}).get(kernel)
-    if k is None or h.hexdigest() != rec.get("sources_sha256"):
+    if k is None or _sources_sha(k["sources"]) != k["sources_sha256"]:
         return None
     out = {"fp32_flop": k["fp32_flop"], "fp64_flop": k["fp64_flop"],
-           "valu_insts": k["valu_insts"], "summary": rec.get("summary")}
-    if kernel_ms:
-        out["fp32_tflops"] = k["fp32_flop"] / (kernel_ms / 1e3) / 1e12
-        out["fp64_tflops"] = k["fp64_flop"] / (kernel_ms / 1e3) / 1e12
+           "valu_insts": k["valu_insts"], "valu_insts_per_pair": k.get("valu_insts_per_pair"),
+           "counted_launch_ms": k["trace_ns"] / 1e6, "summary": rec.get("summary")}
+    ms = kernel_ms if kernel_ms else k["trace_ns"] / 1e6
+    out["fp32_tflops"] = k["fp32_flop"] / (ms / 1e3) / 1e12
+    out["fp64_tflops"] = k["fp64_flop"] / (ms / 1e3) / 1e12
+    out["frac_fp32_peak"] = out["fp32_tflops"] / FP32_PEAK_TFLOPS
+    out["frac_fp64_peak"] = out["fp64_tflops"] / FP64_PEAK_TFLOPS
     return out
+
+
+# Sources each counted kernel is built from (its record holds their SHA-256).
+VALU_SOURCES = {
+    "k_fwd32": ["paper_1204_5041_amd/csrc/kernels.hip", "paper_1204_5041_amd/csrc/segment_dev.h",
+                "paper_1204_5041_amd/csrc/internal.h", "paper_1204_5041_amd/csrc/healpix_dev.h"],
+    "k_legendre": ["paper_1204_5041_amd/csrc/alm.hip", "paper_1204_5041_amd/csrc/healpix_dev.h"],
+    "k_valu_probe": ["paper_1204_5041_amd/csrc/probe.hip"],
+}
+VALU_SOURCES["k_fwd64"] = VALU_SOURCES["k_adj32"] = VALU_SOURCES["k_fwd32"]
+
+
+def _sources_sha(files):
+    import hashlib
+    h = hashlib.sha256()
+    for src in files:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    return h.hexdigest()
+
+
+def summarize_counters(trace_dir, pmc_a, pmc_b, launches_json):
+    """Per-kernel VALU record from the counter runs of --workload counters:
+    instruction counts of each launch (SQ_INSTS_VALU and the FP32/FP64 FMA,
+    ADD, MUL and TRANS counts, all per wavefront instruction), hardware FLOP
+    (64 lanes x (2 FMA + ADD + MUL + TRANS)), the kernel-trace duration of
+    the same launch, the rate against the published peaks, the issue rate
+    per SIMD and clock, and the clock from SQ_BUSY_CYCLES (summed over the
+    32 shader engines).  The FMA probe's counted instructions are compared
+    with the number it issues by construction."""
+    import csv
+    runs = json.loads([l for l in open(launches_json) if l.startswith("{")][-1])
+
+    def launches(d):
+        out = {}
+        for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
+            key = (r["Kernel_Name"], int(r["Dispatch_Id"]))
+            rec = out.setdefault(key, {"ns": int(r["End_Timestamp"]) - int(r["Start_Timestamp"])})
+            rec[r["Counter_Name"]] = float(r["Counter_Value"])
+        return out
+
+    def trace_ns(name_part, nth=0):
+        rows = [r for r in csv.DictReader(open(os.path.join(trace_dir, "run_kernel_trace.csv")))
+                if name_part in r["Kernel_Name"]]
+        rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+        r = rows[nth]
+        return int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+
+    a, b = launches(pmc_a), launches(pmc_b)
+
+    def counters(name_part, nth=0):
+        ka = sorted(k for k in a if name_part in k[0])[nth]
+        kb = sorted(k for k in b if name_part in k[0])[nth]
+        c = dict(a[ka])
+        c.update({k: v for k, v in b[kb].items() if k != "ns"})
+        return ka[0], c
+
+    rec = {"note": "rocprofv3 counters per launch of `bench.py --workload counters`; FLOP = "
+                   "64 x (2 FMA + ADD + MUL + TRANS) per precision (counts are per wavefront "
+                   "instruction); durations from the kernel-trace run of the same command",
+           "peaks_tflops": {"fp32": FP32_PEAK_TFLOPS, "fp64": FP64_PEAK_TFLOPS},
+           "summary": "profiles/valu_counters.md", "kernels": {}}
+    plan = [("k_valu_probe<float, false>", "probe_fp32", None),
+            ("k_valu_probe<double, false>", "probe_fp64", None),
+            ("k_valu_probe<float, true>", "probe_fp32_scalar_operand", None),
+            ("k_fwd32", "k_fwd32", ("k_fwd32", 0)),
+            ("k_fwd64", "k_fwd64", ("k_fwd64", 0)),
+            ("k_adj32", "k_adj32", ("k_adj32", 0)),
+            ("k_legendre", "k_legendre", None)]
+    for part, key, _ in plan:
+        name, c = counters(part)
+        ns = trace_ns(part)
+        s = ns / 1e9
+        f32 = 64 * (2 * c["SQ_INSTS_VALU_FMA_F32"] + c["SQ_INSTS_VALU_ADD_F32"] +
+                    c["SQ_INSTS_VALU_MUL_F32"] + c["SQ_INSTS_VALU_TRANS_F32"])
+        f64 = 64 * (2 * c["SQ_INSTS_VALU_FMA_F64"] + c["SQ_INSTS_VALU_ADD_F64"] +
+                    c["SQ_INSTS_VALU_MUL_F64"] + c["SQ_INSTS_VALU_TRANS_F64"])
+        clock = c["SQ_BUSY_CYCLES"] / 32 / (c["ns"] / 1e9)
+        k = {"kernel": name, "trace_ns": ns, "valu_insts": c["SQ_INSTS_VALU"],
+             "salu_insts": c["SQ_INSTS_SALU"], "fp32_flop": f32, "fp64_flop": f64,
+             "counts": {n: c[n] for n in sorted(c) if n.startswith("SQ_")},
+             "hw_fp32_tflops": f32 / s / 1e12, "hw_fp64_tflops": f64 / s / 1e12,
+             "frac_fp32_peak": f32 / s / 1e12 / FP32_PEAK_TFLOPS,
+             "frac_fp64_peak": f64 / s / 1e12 / FP64_PEAK_TFLOPS,
+             "clock_ghz_from_busy_cycles": clock / 1e9,
+             "valu_issue_per_simd_clk_at_2p4ghz": c["SQ_INSTS_VALU"] / (s * 2.4e9 * 1024),
+             "valu_issue_per_simd_clk_at_measured_clock": c["SQ_INSTS_VALU"] / (s * clock * 1024)}
+        base = key if not key.startswith("probe") else "k_valu_probe"
+        k["sources"] = VALU_SOURCES[base]
+        k["sources_sha256"] = _sources_sha(VALU_SOURCES[base])
+        if key.startswith("probe"):
+            pr = runs[key]
+            k["fma_insts_by_construction"] = pr["fma_insts"]
+            fma = c["SQ_INSTS_VALU_FMA_F64" if "fp64" in key else "SQ_INSTS_VALU_FMA_F32"]
+            k["counted_over_constructed"] = fma / pr["fma_insts"]
+            k["fma_lanes_per_clk_per_cu_at_2p4ghz"] = fma * 64 / s / 256 / 2.4e9
+            k["fma_lanes_per_clk_per_cu_at_measured_clock"] = fma * 64 / s / 256 / clock
+        elif key in runs and "pairs" in runs[key]:
+            p = runs[key]["pairs"]
+            k["pairs"] = p
+            k["valu_insts_per_pair"] = c["SQ_INSTS_VALU"] * 64 / p
+            k["hw_flop_per_pair"] = (f32 + f64) / p
+        rec["kernels"][key] = k
+    return rec
 
 
 def bench_counters(args, B, torch):
