@@ -460,30 +460,72 @@ __global__ void k_lambda_mm(int64_t nside, int64_t mmax, const double* mm_fac, d
   }
 }
 
-// Step 2a': the recursion coefficients of every (l, m), l > m, at a_lm's
-// position: coef[2 i] = A_lm, coef[2 i + 1] = B_lm (B = 0 and A = sqrt(2m+3)
-// at l = m + 1), and A = 1, B = -1 at l = m, so that one step from
-// (lambda_{m-1,m}, lambda_{m-2,m}) = (0, lambda_mm) gives lambda_mm exactly;
-// one thread per (l, m): blockIdx.y is m, l runs over x.
+// Step 2a': the coefficients of the rescaled recursion.  With
+// lambda_lm = c_l mu_l, where c_m = c_{m+1} = 1 and c_l = -A_l B_l c_{l-2},
+// the three-term recursion lambda_l = A_l (z lambda_{l-1} - B_l lambda_{l-2})
+// becomes
+//   mu_l = (a_l z) mu_{l-1} + mu_{l-2},   a_l = A_l c_{l-1} / c_l,
+// two operations per step instead of three, and c_l multiplies the ring sum
+// once per (l, m).  At l = m + 1 (B = 0) the step is mu_{m+1} =
+// sqrt(2m+3) z mu_m; at l = m, a_m = 0 takes (mu_{m-1}, mu_{m-2}) =
+// (0, lambda_mm) to mu_m = lambda_mm.
+// First pass, one thread per (l, m) (blockIdx.y is m): coef[2 i] = A_l and
+// coef[2 i + 1] = -A_l B_l at a_lm's position i (A = 0 and 1 at l = m,
+// A = sqrt(2m+3) and 1 at l = m + 1, so that c_m = c_{m+1} = 1).
 __global__ void k_leg_coef(int64_t lmax, double* coef) {
   const int64_t m = blockIdx.y;
   const int64_t l = m + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (l > lmax) return;
   const int64_t i = alm_idx(lmax, l, m);
   const double mmd = (double)m, ll = (double)l;
-  double A, B;
+  double A, g;
   if (l == m) {
-    A = 1.0;
-    B = -1.0;
+    A = 0.0;
+    g = 1.0;
   } else if (l == m + 1) {
     A = sqrt(2.0 * mmd + 3.0);
-    B = 0.0;
+    g = 1.0;
   } else {
     A = sqrt((4.0 * ll * ll - 1.0) / (ll * ll - mmd * mmd));
-    B = sqrt(((ll - 1.0) * (ll - 1.0) - mmd * mmd) / (4.0 * (ll - 1.0) * (ll - 1.0) - 1.0));
+    const double B =
+        sqrt(((ll - 1.0) * (ll - 1.0) - mmd * mmd) / (4.0 * (ll - 1.0) * (ll - 1.0) - 1.0));
+    g = -(A * B);
   }
   coef[2 * i] = A;
-  coef[2 * i + 1] = B;
+  coef[2 * i + 1] = g;
+}
+
+// Second pass, one wavefront per m: c_l as the product of g over l, l - 2,
+// ..., and a_l = A_l c_{l-1} / c_l, in place (coef[2 i] = a_l,
+// coef[2 i + 1] = c_l).  64 consecutive degrees at a time: a product scan
+// over the lanes of equal parity (strides 2 .. 32), times the last c of
+// that parity from the previous 64.
+__global__ void __launch_bounds__(256) k_leg_scan(int64_t lmax, double* coef) {
+  const int lane = threadIdx.x & 63;
+  const int64_t m = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (m > lmax) return;
+  const int64_t row = alm_idx(lmax, m, m) - m;   // idx(l, m) = row + l
+  double carry0 = 1.0, carry1 = 1.0;             // c_{base-2}, c_{base-1}
+  for (int64_t base = m; base <= lmax; base += 64) {
+    const int64_t l = base + lane;
+    const bool in = l <= lmax;
+    const double A = in ? coef[2 * (row + l)] : 0.0;
+    double p = in ? coef[2 * (row + l) + 1] : 1.0;
+#pragma unroll
+    for (int s = 2; s < 64; s <<= 1) {
+      const double o = __shfl_up(p, s);
+      if (lane >= s) p *= o;
+    }
+    const double c = p * ((lane & 1) ? carry1 : carry0);
+    double cm1 = __shfl_up(c, 1);
+    if (lane == 0) cm1 = carry1;
+    if (in) {
+      coef[2 * (row + l)] = A * cm1 / c;
+      coef[2 * (row + l) + 1] = c;
+    }
+    carry0 = __shfl(c, 62);
+    carry1 = __shfl(c, 63);
+  }
 }
 
 __device__ __forceinline__ double wave_sum(double x) {
@@ -633,29 +675,21 @@ __global__ void __launch_bounds__(256) k_legendre(int64_t nside, int64_t lmax, i
   const double big = ldexp(1.0, kLegScale);
   double* out = part + 2 * blk * ((lmax + 1) * (lmax + 2) / 2);
   cdp cf = (cdp)coef;
-  // Recursion coefficients of degrees l0 .. l0 + 7, the next group's
+  // Recursion coefficients a_l of degrees l0 .. l0 + 7, the next group's
   // requested one group ahead.  Degrees past lmax take lmax's: their steps
   // run (every group is eight steps) but their sums are not written.
   const int64_t row = alm_idx(lmax, m, m) - m;   // idx(l, m) = row + l
-  double cA[8], cB[8];
+  double cA[8];
 #pragma unroll
-  for (int g = 0; g < 8; ++g) {
-    const int64_t i = row + (m + g < lmax ? m + g : lmax);
-    cA[g] = cf[2 * i];
-    cB[g] = cf[2 * i + 1];
-  }
+  for (int g = 0; g < 8; ++g) cA[g] = cf[2 * (row + (m + g < lmax ? m + g : lmax))];
   // The ring data loaded above has arrived: without this wait the loop's
   // first use of it waits on every vector memory operation in flight, the
   // previous group's store included, in every iteration.
   __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
   for (int64_t l0 = m; l0 <= lmax; l0 += 8) {
-    double nA[8], nB[8];
+    double nA[8];
 #pragma unroll
-    for (int g = 0; g < 8; ++g) {
-      const int64_t i = row + (l0 + 8 + g < lmax ? l0 + 8 + g : lmax);
-      nA[g] = cf[2 * i];
-      nB[g] = cf[2 * i + 1];
-    }
+    for (int g = 0; g < 8; ++g) nA[g] = cf[2 * (row + (l0 + 8 + g < lmax ? l0 + 8 + g : lmax))];
     __builtin_amdgcn_sched_barrier(0);    // issue the requests before the arithmetic
     // Bring scaled values back once they have grown (growth over 8 steps
     // stays far below the 2^423 headroom above 2^600).
@@ -675,18 +709,17 @@ __global__ void __launch_bounds__(256) k_legendre(int64_t nside, int64_t lmax, i
     // F_north + F_south and odd g F_north - F_south.
 #pragma unroll
     for (int g = 0; g < 8; ++g) {
-      // The three operations of a step run over the lane's ring pairs one
-      // after the other, so that a dependent operation comes
-      // kRingsPerLane instructions after the one it waits for.
+      // mu_l = (a_l z) mu_{l-1} + mu_{l-2}: the product a_l z does not wait
+      // on the recursion, so the dependent chain is one FMA per degree; the
+      // operations run over the lane's ring pairs one after the other.
       double t[kRingsPerLane];
 #pragma unroll
-      for (int k = 0; k < kRingsPerLane; ++k) t[k] = cB[g] * prev[k];
-#pragma unroll
-      for (int k = 0; k < kRingsPerLane; ++k) t[k] = fma(z[k], cur[k], -t[k]);
+      for (int k = 0; k < kRingsPerLane; ++k) t[k] = cA[g] * z[k];
 #pragma unroll
       for (int k = 0; k < kRingsPerLane; ++k) {
+        const double nu = fma(t[k], cur[k], prev[k]);
         prev[k] = cur[k];
-        cur[k] = cA[g] * t[k];
+        cur[k] = nu;
       }
 #pragma unroll
       for (int k = 0; k < kRingsPerLane; ++k) {
@@ -698,15 +731,14 @@ __global__ void __launch_bounds__(256) k_legendre(int64_t nside, int64_t lmax, i
     const int v = lane >> 2;   // value held: real (even) or imaginary (odd) part of degree l0 + v/2
     if ((lane & 3) == 0 && l0 + (v >> 1) <= lmax) out[2 * (row + l0) + v] = tot;
 #pragma unroll
-    for (int g = 0; g < 8; ++g) {
-      cA[g] = nA[g];
-      cB[g] = nB[g];
-    }
+    for (int g = 0; g < 8; ++g) cA[g] = nA[g];
   }
 }
 
-// Step 3: a_lm = (4 pi / Npix) sum over blocks, in block order.
-__global__ void k_alm_sum(int64_t size, int64_t nblk, double w, const double* part, double* alm) {
+// Step 3: a_lm = (4 pi / Npix) c_l sum over blocks, in block order (the
+// block sums are of the rescaled mu_l).
+__global__ void k_alm_sum(int64_t size, int64_t nblk, double w, const double* part,
+                          const double* coef, double* alm) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= size) return;
   double re = 0.0, im = 0.0;
@@ -714,8 +746,9 @@ __global__ void k_alm_sum(int64_t size, int64_t nblk, double w, const double* pa
     re += part[2 * (b * size + i)];
     im += part[2 * (b * size + i) + 1];
   }
-  alm[2 * i] = w * re;
-  alm[2 * i + 1] = w * im;
+  const double f = w * coef[2 * i + 1];
+  alm[2 * i] = f * re;
+  alm[2 * i + 1] = f * im;
 }
 
 // C_l: one wavefront per l, lanes stride over m, then a fixed-order
@@ -819,12 +852,13 @@ hipError_t launch_map2alm(int64_t nside, int64_t lmax, const double* map, double
   k_lambda_mm<<<dim3((unsigned)((npair + 255) / 256)), dim3(256), 0, st>>>(nside, lmax, mm_fac,
                                                                           lam_v, lam_e, ring_z);
   k_leg_coef<<<dim3((unsigned)((M + 255) / 256), (unsigned)M), dim3(256), 0, st>>>(lmax, coef);
+  k_leg_scan<<<dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st>>>(lmax, coef);
   const int64_t leg_waves = M * nblk;
   k_legendre<<<dim3((unsigned)((leg_waves + 3) / 4)), dim3(256), 0, st>>>(
       nside, lmax, lmax, F, lam_v, lam_e, ring_z, coef, nblk, part);
   const double w = 4.0 * 3.14159265358979323846 / (double)(12 * nside * nside);
   k_alm_sum<<<dim3((unsigned)((size + 255) / 256)), dim3(256), 0, st>>>(size, nblk, w, part,
-                                                                        alm);
+                                                                        coef, alm);
   return hipGetLastError();
 }
 
