@@ -58,17 +58,12 @@ def make_sky(B, torch, b, form, nseg, nside):
 def measured_traffic(kernel):
     """HBM bytes (per launch, or per step for the stacking stage) of a kernel
     from the committed rocprofv3 counter runs, if they were taken on the
-    current device sources (the record holds their SHA-256)."""
-    import hashlib
+    kernel's current sources (its record holds their SHA-256)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path))
-    h = hashlib.sha256()
-    for src in rec.get("sources", []):
-        h.update(open(os.path.join(ROOT, src), "rb").read())
-    k = rec.get("kernels", {}).get(kernel)
-    if k is None or h.hexdigest() != rec.get("sources_sha256"):
+    k = json.load(open(path)).get("kernels", {}).get(kernel)
+    if k is None or _sources_sha(k["sources"]) != k["sources_sha256"]:
         return None
     return k["fetch_bytes"] + k["write_bytes"]
 
