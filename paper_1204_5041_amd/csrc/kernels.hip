@@ -341,11 +341,9 @@ __device__ __forceinline__ void emit_record(const PreArgs& A, const DevBox& bx, 
     const float force_near = (1.0 - sqrt(vv) < 0.05) ? 1.0f : 0.0f;
     o[3] = make_float4(__int_as_float((int)i), force_near, 0.f, 0.f);
     if (A.adjc) {
-      // The same constants without the dsigma factor: every adjoint sum is
-      // linear in them, and the dsigma derivative is the unit-dsigma sum.
-      const double ku = -2.0 * g.eps / g.R;
-      ((float4*)A.adjc)[r] = make_float4((float)ku, (float)(ku * (1.0 + pv)), (float)(ku * pt),
-                                         0.f);
+      // The adjoint's constants, without kappa (every adjoint sum is linear
+      // in kappa, which the finalize step applies in FP64).
+      ((float4*)A.adjc)[r] = make_float4((float)(1.0 + pv), (float)pt, 0.f, 0.f);
     }
     double2* h = (double2*)(A.phat64 + (size_t)r * 4);
     h[0] = make_double2(Ph[0], Ph[1]);
@@ -1096,45 +1094,48 @@ __global__ void k_pixtab(int64_t nside, int64_t npix, const double* dmap, float*
   ((double2*)tab64)[2 * p + 1] = make_double2(z, dmap[p]);
 }
 
-// Accumulators of one segment (see the finalize kernel for their use), with
-// d = n - Ph the direction difference of the pair and r = 1/(b w):
-//   0 S1  = sum s kap/w                  1 S2 = sum s kap a r
-//   2 SF  = sum s f                      3 C2 = sum s a t2 r/b
-//   4 C4  = sum s t2 r                   5..7   D3 = sum (s f/w) d
-//   8..10 DV = sum (s kap/w + s a t2 r/b) d    11..13 DT = sum s r (t2 + kap a) d
+// Accumulators of one segment (see the finalize kernel for their use).  All
+// of them are linear in kappa' = -2 eps dsigma / R, which is left out here
+// and applied in FP64 by the finalize step.  With s the pixel's cotangent,
+// d = n - Ph the direction difference of the pair, w = 1 - n.Ph = |d|^2/2,
+// a = n.X', b = 1 + n.Xdot, v = Xdot.d, u = X'.d, r = 1/(b w) and
+// m = v b - a u (the Eq. (1) term is kappa' m r):
+//   0 S1  = sum s/w                      1 S2 = sum s a r
+//   2 SF  = sum s m r                    3 C2 = sum s a u r/b
+//   4 C4  = sum s u r                    5..7   D3 = sum (s m r/w) d
+//   8..10 DV = sum (s/w + s a u r/b) d   11..13 DT = sum s r (u + a) d
 // Every vector sum multiplies d rather than n: the n-weighted sums of the
 // close pixels are each of order 1/theta larger than the result and would
 // cancel against Ph times a scalar sum.
 constexpr int kAcc = 14;
 
 // Add one pair to the accumulators (see their list above): s the pixel's
-// cotangent, w = 1 - n.Ph, t1 = kap Xdot.d, t2 = kap X'.d, r = 1/(b w),
-// d = n - Ph.
-__device__ __forceinline__ void adj_accumulate(float (&pa)[kAcc], float s, float kap, float a,
-                                               float bb, float w, float t1, float t2, float r,
-                                               float dx, float dy, float dz) {
-  const float m = fmaf(-a, t2, t1 * bb);       // kap * m
-  const float f = m * r;                        // the Eq. (1) term
-  const float sr = s * r;
-  const float k1 = sr * kap;                    // s kap / (b w)
-  const float c1 = k1 * bb;                     // s kap / w
-  pa[0] += c1;
-  pa[1] = fmaf(k1, a, pa[1]);
-  const float sf = s * f;
-  pa[2] += sf;
-  const float c4 = sr * t2;                     // s kap Td / (b w)
-  pa[4] += c4;
-  const float c2 = (c4 * a) * (w * r);          // s kap a Td / (b^2 w)
+// cotangent, a, b, w, v = Xdot.d, u = X'.d, r = 1/(b w), d = n - Ph.
+// With g = s r: S1 += g b, S2 += g a, SF += g m, C4 += g u,
+// C2 += (g u) a (w r), D3 += (g m)(b r) d, DV += (g b + C2 term) d,
+// DT += (g a + g u) d: 28 instructions.
+__device__ __forceinline__ void adj_accumulate(float (&pa)[kAcc], float s, float a, float bb,
+                                               float w, float v, float u, float r, float dx,
+                                               float dy, float dz) {
+  const float g = s * r;
+  const float m = fmaf(-a, u, v * bb);
+  const float gm = g * m;                       // s m r
+  pa[2] += gm;
+  pa[0] = fmaf(g, bb, pa[0]);
+  pa[1] = fmaf(g, a, pa[1]);
+  const float gu = g * u;                       // s u r
+  pa[4] += gu;
+  const float c2 = (gu * a) * (w * r);          // s a u r / b
   pa[3] += c2;
-  const float d3 = sf * (bb * r);               // s f / w
+  const float d3 = gm * (bb * r);               // s m r / w
   pa[5] = fmaf(d3, dx, pa[5]);
   pa[6] = fmaf(d3, dy, pa[6]);
   pa[7] = fmaf(d3, dz, pa[7]);
-  const float dv = c1 + c2;
+  const float dv = fmaf(g, bb, c2);             // s/w + s a u r/b
   pa[8] = fmaf(dv, dx, pa[8]);
   pa[9] = fmaf(dv, dy, pa[9]);
   pa[10] = fmaf(dv, dz, pa[10]);
-  const float c3 = fmaf(k1, a, c4);             // s kap (Td + a) / (b w)
+  const float c3 = fmaf(g, a, gu);              // s r (u + a)
   pa[11] = fmaf(c3, dx, pa[11]);
   pa[12] = fmaf(c3, dy, pa[12]);
   pa[13] = fmaf(c3, dz, pa[13]);
@@ -1161,10 +1162,10 @@ __global__ void __launch_bounds__(256) k_adj32(AdjArgs A) {
   const float px = q0.x, py = q0.y, pz = q0.z;
   const float tx = q0.w, ty = q1.x, tz = q1.y;
   const float vx = q1.z, vy = q1.w, vz = q2.x;
-  // Constants per unit dsigma: the sums come out per unit dsigma, and the
-  // finalize step multiplies by dsigma (finite at dsigma = 0).
-  const float4 ku = ((const float4*)A.adjc)[rec];
-  const float kap = active ? ku.x : 0.0f, c1v = ku.y, c2v = ku.z;
+  // 1 + Ph.Xdot and Ph.X' (the sums leave out kappa' = -2 eps dsigma / R,
+  // which the finalize step applies, so they stay finite at dsigma = 0).
+  const float4 cu = ((const float4*)A.adjc)[rec];
+  const float c1 = cu.x, c2 = cu.y;
   const double2 h0 = ((const double2*)A.phat64)[2 * rec + 0];
   const double2 h1 = ((const double2*)A.phat64)[2 * rec + 1];
   // The pixel range is uniform; computing it through readfirstlane keeps it
@@ -1181,6 +1182,10 @@ __global__ void __launch_bounds__(256) k_adj32(AdjArgs A) {
 #pragma unroll
   for (int k = 0; k < kAcc; ++k) acc[k] = 0.0;
   const bool check_vis = bx.vis != 0;
+  // The pixels of a ring share z: the z parts of w, a, b and d are formed
+  // once per ring (whenever the z of the next pixel differs).
+  uint32_t zbits = 0x40000000u;   // the bits of 2.0f: no pixel has z = 2
+  float wz = 0.f, az = 0.f, bz = 0.f, dzr = 0.f;
   constexpr int J = 64;
   for (int64_t pc = p0; pc < p1; pc += J) {
     const int64_t pe = (pc + J < p1) ? pc + J : p1;
@@ -1204,15 +1209,26 @@ __global__ void __launch_bounds__(256) k_adj32(AdjArgs A) {
         const v2d e1 = tab64[2 * p + 1];
         if (!sees_box(e0.x, e0.y, e1.x, bx, A.eta0)) continue;
       }
-      const float nx = to_vgpr(pt.x), ny = to_vgpr(pt.y), nz = to_vgpr(pt.z);
+      // A new ring (compared as bits, so that the test stays in scalar
+      // registers).
+      if (__float_as_uint(pt.z) != zbits) {
+        zbits = __float_as_uint(pt.z);
+        const float z = to_vgpr(pt.z);
+        wz = fmaf(-z, pz, 1.0f);
+        az = z * tz;
+        bz = fmaf(z, vz, 1.0f);
+        dzr = z - pz;
+      }
+      const float nx = to_vgpr(pt.x), ny = to_vgpr(pt.y);
       float s = to_vgpr(pt.w);
-      float w = fmaf(-nz, pz, fmaf(-ny, py, fmaf(-nx, px, 1.0f)));
-      const float a = fmaf(nz, tz, fmaf(ny, ty, nx * tx));
-      const float bb = fmaf(nz, vz, fmaf(ny, vy, fmaf(nx, vx, 1.0f)));
-      // The far form's values; a close pixel (for some lane) overwrites them
-      // in place, which lets the far form run without register copies.
-      float dx = nx - px, dy = ny - py, dz = nz - pz;
-      float t1 = fmaf(kap, bb, -c1v), t2 = fmaf(kap, a, -c2v);
+      float w = fmaf(-ny, py, fmaf(-nx, px, wz));
+      const float a = fmaf(ny, ty, fmaf(nx, tx, az));
+      const float bb = fmaf(ny, vy, fmaf(nx, vx, bz));
+      // The far form's values: Xdot.d = b - (1 + Ph.Xdot), X'.d = a - Ph.X'.
+      // A close pixel (for some lane) overwrites them in place, which lets
+      // the far form run without register copies.
+      float dx = nx - px, dy = ny - py, dz = dzr;
+      float v = bb - c1, u = a - c2;
       if (force || __any(w < far_w)) {
         // Middle form: the direction difference in FP32 (see the forward
         // kernel); FP64 form: from the FP64 directions.
@@ -1224,13 +1240,13 @@ __global__ void __launch_bounds__(256) k_adj32(AdjArgs A) {
           dz = (float)(e1.x - h1.x);
         }
         const float q = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        t1 = kap * fmaf(vz, dz, fmaf(vy, dy, vx * dx));
-        t2 = kap * fmaf(tz, dz, fmaf(ty, dy, tx * dx));
+        v = fmaf(vz, dz, fmaf(vy, dy, vx * dx));
+        u = fmaf(tz, dz, fmaf(ty, dy, tx * dx));
         // An exact coincidence (q = 0) contributes nothing.
         w = (q > 0.0f) ? 0.5f * q : 1.0f;
         s = (q > 0.0f) ? s : 0.0f;
       }
-      adj_accumulate(pa, s, kap, a, bb, w, t1, t2, __builtin_amdgcn_rcpf(bb * w), dx, dy, dz);
+      adj_accumulate(pa, s, a, bb, w, v, u, __builtin_amdgcn_rcpf(bb * w), dx, dy, dz);
     }
 #pragma unroll
     for (int k = 0; k < kAcc; ++k) acc[k] += (double)pa[k];
@@ -1251,7 +1267,8 @@ struct GradPtrs {
 
 // Combine the pixel-chunk partials of each kept record (in chunk order) and
 // apply the per-segment chain rule, then scatter to the caller's arrays.
-// The partial sums are per unit dsigma (kappa without its dsigma factor):
+// The partial sums leave out kappa' = -2 eps dsigma / R; with S the sums
+// times k = -2 eps / R (kappa' per unit dsigma):
 //   G_d   = V S1 - T S2 - D3                   (sum of s df/d(n - Ph))
 //   dL/dP = dsigma [-(G_d - Ph (Ph.G_d))/R - SF Ph / R] (Ph = P/R, dR/dP = Ph)
 //   dL/dV = dsigma [DV + Ph C2 + SF V/(1 - V^2)]        (the last term from eps)
@@ -1295,6 +1312,9 @@ __global__ void k_adj_finalize(const DevBox* boxes, const DevBoxCount* counts, i
   const double R = phat64[4 * rec + 3];
   const double vv = (V[0] * V[0] + V[1] * V[1]) + V[2] * V[2];
   const double tt = (T[0] * T[0] + T[1] * T[1]) + T[2] * T[2];
+  const double kunit = -2.0 * sqrt(tt / (1.0 - vv)) / R;
+#pragma unroll
+  for (int k = 0; k < kAcc; ++k) S[k] *= kunit;
   double G[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) G[k] = V[k] * S[0] - T[k] * S[1] - S[5 + k];
