@@ -366,17 +366,24 @@ csmap_status csmap_set_option(csmap_sky *sky, csmap_option opt, double value);
 /* Counters and timings of the last render/backward; synchronises the stream. */
 csmap_status csmap_get_stats(csmap_sky *sky, csmap_stats *out);
 
-/* Time the forward kernel over a grid of launch shapes (pixels per lane,
- * wavefronts per workgroup, accumulation mode; persistent schedule) on this
- * sky's boxes, each candidate on a sample of its own tiles spread evenly
- * over the sky (about 25M pixels, each tile limited to the first 2,048
- * segments of every box it sees), and keep the one with the most pairs per
- * second.  If cache_path is not NULL the choice is first looked up in, and
- * afterwards appended to, that text file, keyed by device architecture,
- * form, Nside, box count, visibility rules and segment count (rounded to a
- * power of two).  Allocates a scratch map of 12 Nside^2 doubles for the
- * duration of the call; synchronises the stream; results of later renders
- * are unchanged up to rounding (the sum order within a pixel may change). */
+/* Time the forward kernel on this sky's boxes and keep the settings with the
+ * most pairs per second, each candidate measured on a sample of its own
+ * tiles spread evenly over the sky (about 25M pixels, each tile limited to
+ * the first 2,048 segments of every box it sees).  First the launch shape
+ * (pixels per lane, wavefronts per workgroup, accumulation mode; persistent
+ * schedule); then, from the best shape, one setting at a time: the tiling
+ * and rings per ring-block tile (skies with visibility rules), the FP32
+ * partial-sum length before each compensated update (16, 32 or 64; FP32C),
+ * and the pair-form thresholds among those at least as accurate as the
+ * defaults (CSMAP_OPT_FAR_W >= 5e-3, CSMAP_OPT_NEAR_W >= 5e-5), so tuning
+ * never trades accuracy for speed.  If cache_path is not NULL the choice is
+ * first looked up in, and afterwards appended to, that text file, keyed by
+ * device architecture, form, Nside, box count, the number of boxes under
+ * each visibility rule, the caps' summed sky fraction (two significant
+ * digits) and the segment count (rounded to a power of two).  Allocates a
+ * scratch map of 12 Nside^2 doubles for the duration of the call;
+ * synchronises the stream; results of later renders agree with the untuned
+ * ones to the form's accuracy (the sum order within a pixel may change). */
 csmap_status csmap_autotune(csmap_sky *sky, const char *cache_path);
 
 /* Spherical-harmonic analysis of a RING map (the angular power spectrum of

@@ -1385,30 +1385,53 @@ csmap_status csmap_autotune(csmap_sky* s, const char* cache_path) {
   HIPCHK(s, hipGetDevice(&dev), "device");
   hipDeviceProp_t prop;
   HIPCHK(s, hipGetDeviceProperties(&prop, dev), "device properties");
-  bool all = true;
-  for (auto& h : s->boxes)
-    if (h.geom.vis != 0) all = false;
-  // Workload key: device, form, Nside, box count, visibility rules, and the
-  // segment count rounded to a power of two.
+  // Workload key: device, form, Nside, box count, the number of boxes under
+  // each visibility rule, the caps' summed sky fraction (two significant
+  // digits), and the segment count rounded to a power of two.
+  int nrule[3] = {0, 0, 0};
+  double cap_frac = 0.0;
+  for (auto& h : s->boxes) {
+    nrule[std::min(std::max(h.geom.vis, 0), 2)]++;
+    if (h.geom.vis == CSMAP_VIS_CAP) cap_frac += 0.5 * (1.0 - h.geom.cap_cos);
+  }
+  const bool all = nrule[1] == 0 && nrule[2] == 0;
   int seg_log2 = 0;
   while (((int64_t)1 << seg_log2) < std::max<int64_t>(1, s->total_seg)) ++seg_log2;
+  char frac_txt[32];
+  snprintf(frac_txt, sizeof(frac_txt), "%.2g", cap_frac);
   std::ostringstream key;
   key << prop.gcnArchName << "|" << (fp64 ? "fp64" : "fp32c") << "|" << s->nside << "|" << nbox
-      << "|" << (all ? "all" : "subset") << "|" << seg_log2;
+      << "|vis" << nrule[0] << "," << nrule[1] << "," << nrule[2] << "|caps" << frac_txt << "|"
+      << seg_log2;
+  struct Cand {
+    int K, W, S, F, tiling, rings, chunk;
+    double near_w, far_w;
+  };
+  auto apply = [&](const Cand& c) {
+    s->K = c.K;
+    s->waves = c.W;
+    s->schedule = c.S;
+    s->frac = c.F;
+    s->tiling = c.tiling;
+    s->block_rings = c.rings;
+    s->chunk = c.chunk;
+    s->near_w = c.near_w;
+    s->far_w = c.far_w;
+    s->have_fwd_time = false;
+    s->version++;
+    drop_graph(s);
+  };
   if (cache_path) {
     std::ifstream in(cache_path);
     std::string line;
     while (std::getline(in, line)) {
       std::istringstream ls(line);
       std::string k;
-      int K, W, S, F;
-      if (ls >> k >> K >> W >> S >> F && k == key.str()) {
-        s->K = K;
-        s->waves = W;
-        s->schedule = S;
-        s->frac = F;
-        s->version++;
-        drop_graph(s);
+      Cand c;
+      if (ls >> k >> c.K >> c.W >> c.S >> c.F >> c.tiling >> c.rings >> c.chunk >> c.near_w >>
+          c.far_w &&
+          k == key.str()) {
+        apply(c);
         return CSMAP_OK;
       }
     }
@@ -1423,29 +1446,21 @@ csmap_status csmap_autotune(csmap_sky* s, const char* cache_path) {
   const int64_t sample_px = 49152 * 512;
   DevBuf scratch, items;
   HIPCHK(s, scratch.ensure(sizeof(double) * (size_t)s->npix), "alloc scratch map");
-  struct Cand { int K, W, S, F; };
-  std::vector<Cand> cands;
-  // The persistent schedule (tiles pulled most expensive first) is kept for
-  // every candidate: it was never slower than one-tile-per-wavefront launches
-  // on uniform skies and it bounds the tail on uneven ones.
-  for (int K : {1, 2, 4, 8})
-    for (int W : {1, 2, 4})
-      for (int F : {0, 1}) {
-        if (fp64 && F) continue;
-        if (!fp64 && K == 1) continue;
-        cands.push_back({K, W, 1, F});
-      }
-  const int saveK = s->K, saveW = s->waves, saveS = s->schedule, saveF = s->frac;
-  double best_rate = -1.0;
-  Cand best = {saveK, saveW, saveS, saveF};
+  const Cand saved = {s->K,     s->waves, s->schedule, s->frac,  s->tiling,
+                      s->block_rings, s->chunk, s->near_w, s->far_w};
   hipStream_t st = s->stream;
-  for (const Cand& c : cands) {
-    s->K = c.K;
-    s->waves = c.W;
-    s->schedule = c.S;
-    s->frac = c.F;
-    cs = prepare(s);
-    if (cs != CSMAP_OK) break;
+  const bool log = getenv("CSMAP_TUNE_LOG") != nullptr;
+  // Pairs per second of one candidate on the sample; -1 if the planner
+  // rejects its shape (the candidate is skipped, not an error).
+  auto measure = [&](const Cand& c, double* rate) -> csmap_status {
+    *rate = -1.0;
+    apply(c);
+    csmap_status r = prepare(s);
+    if (r == CSMAP_E_INVALID) {   // a shape the planner does not admit
+      g_err.clear();
+      return CSMAP_OK;
+    }
+    if (r != CSMAP_OK) return r;
     const int64_t nsample = std::max<int64_t>(
         1, std::min<int64_t>(s->ntiles, sample_px / (64 * (int64_t)c.K)));
     std::vector<int32_t> it(nsample);
@@ -1459,12 +1474,16 @@ csmap_status csmap_autotune(csmap_sky* s, const char* cache_path) {
     A.items = items.as<int32_t>();
     A.nitems = (int64_t)it.size();
     A.seg_cap = 2048;
-    cs = check_forward(s, A, c.K);
-    if (cs != CSMAP_OK) break;
+    r = check_forward(s, A, c.K);
+    if (r == CSMAP_E_INVALID) {
+      g_err.clear();
+      return CSMAP_OK;
+    }
+    if (r != CSMAP_OK) return r;
     const unsigned block = 64u * (unsigned)c.W;
     const unsigned grid = c.S ? persistent_grid(s) : (unsigned)((A.nitems + c.W - 1) / c.W);
     double ms_min = 1e300;
-    unsigned long long pairs = 0;
+    unsigned long long ctr[5] = {0, 0, 0, 0, 0};
     for (int rep = 0; rep < 3; ++rep) {
       HIPCHK(s, launch_zero_counters(s->d_counters.as<unsigned long long>(), 5, A.work_counter, st),
              "counter reset");
@@ -1476,32 +1495,115 @@ csmap_status csmap_autotune(csmap_sky* s, const char* cache_path) {
       HIPCHK(s, hipEventElapsedTime(&ms, s->ev[0], s->ev[1]), "elapsed");
       if (rep > 0) ms_min = std::min(ms_min, (double)ms);
     }
-    HIPCHK(s, hipMemcpy(&pairs, s->d_counters.p, sizeof(pairs), hipMemcpyDeviceToHost),
+    HIPCHK(s, hipMemcpy(ctr, s->d_counters.p, sizeof(ctr), hipMemcpyDeviceToHost),
            "read counters");
-    const double rate = (double)pairs / std::max(ms_min, 1e-6);
-    if (getenv("CSMAP_TUNE_LOG"))
+    *rate = (double)ctr[0] / std::max(ms_min, 1e-6) * 1e3;
+    if (log)
       fprintf(stderr,
-              "csmap_autotune: K=%d waves=%d schedule=%d accum=%d items=%lld %.3f ms "
-              "%.4g pairs/s\n",
-              c.K, c.W, c.S, c.F, (long long)it.size(), ms_min, rate * 1e3);
+              "csmap_autotune: K=%d waves=%d accum=%d tiling=%d rings=%d chunk=%d near_w=%g "
+              "far_w=%g items=%lld %.3f ms %.4g pairs/s (FP64 steps %llu, middle %llu of "
+              "%llu)\n",
+              c.K, c.W, c.F, c.tiling, c.rings, c.chunk, c.near_w, c.far_w, (long long)it.size(),
+              ms_min, *rate, ctr[1], ctr[3], ctr[4]);
+    return CSMAP_OK;
+  };
+  Cand best = saved;
+  best.S = 1;
+  if (best.tiling == 0) best.tiling = all ? 1 : 2;
+  double best_rate = -1.0;
+  auto consider = [&](const Cand& c) -> csmap_status {
+    double rate = -1.0;
+    csmap_status r = measure(c, &rate);
+    if (r != CSMAP_OK) return r;
     if (rate > best_rate) {
       best_rate = rate;
       best = c;
     }
+    return CSMAP_OK;
+  };
+  // Stage 1: launch shape (pixels per lane, wavefronts per workgroup,
+  // accumulation mode) with the persistent schedule, which was never slower
+  // than one-tile-per-wavefront launches on uniform skies and bounds the
+  // tail on uneven ones.
+  {
+    const Cand base = best;
+    for (int K : {1, 2, 4, 8})
+      for (int W : {1, 2, 4})
+        for (int F : {0, 1}) {
+          if (fp64 && F) continue;
+          if (!fp64 && K == 1) continue;
+          Cand c = base;
+          c.K = K;
+          c.W = W;
+          c.F = F;
+          c.rings = 0;
+          cs = consider(c);
+          if (cs != CSMAP_OK) break;
+        }
+  }
+  // Stage 2: from the best shape, one parameter at a time: the tiling and
+  // rings per ring-block tile (skies with visibility rules only; strips are
+  // best when every pixel sees every box), the FP32 partial-sum length
+  // before each compensated update (FP32C; at most 64 terms), and the pair
+  // form thresholds among those whose per-term error bound is no larger
+  // than the defaults' (far form 6e-8/far_w, middle form 1e-7/sqrt(2 near_w):
+  // far_w >= 5e-3, near_w >= 5e-5), so that tuning never trades accuracy.
+  if (cs == CSMAP_OK && !all) {
+    const Cand base = best;
+    std::vector<Cand> cands;
+    Cand c = base;
+    c.tiling = base.tiling == 1 ? 2 : 1;
+    c.rings = 0;
+    cands.push_back(c);
+    for (int g : {base.K, 4 * base.K, 8 * base.K})
+      if (g >= 1 && g <= 64 && g != 2 * base.K) {
+        c = base;
+        c.tiling = 2;
+        c.rings = g;
+        cands.push_back(c);
+      }
+    for (const Cand& cc : cands) {
+      cs = consider(cc);
+      if (cs != CSMAP_OK) break;
+    }
+  }
+  if (cs == CSMAP_OK && !fp64) {
+    const Cand base = best;
+    for (int ch : {16, 64}) {
+      Cand c = base;
+      c.chunk = ch;
+      cs = consider(c);
+      if (cs != CSMAP_OK) break;
+    }
+  }
+  if (cs == CSMAP_OK && !fp64) {
+    const Cand base = best;
+    for (double fw : {1e-2, 2e-2}) {
+      Cand c = base;
+      c.far_w = std::max(fw, base.far_w);
+      if (c.far_w != base.far_w) {
+        cs = consider(c);
+        if (cs != CSMAP_OK) break;
+      }
+    }
+    for (double nw : {1e-4, 2e-4}) {
+      if (cs != CSMAP_OK) break;
+      Cand c = best;
+      c.near_w = std::max(nw, best.near_w);
+      if (c.near_w != best.near_w) cs = consider(c);
+    }
   }
   scratch.release();
   items.release();
-  s->K = best.K;
-  s->waves = best.W;
-  s->schedule = best.S;
-  s->frac = best.F;
-  s->have_fwd_time = false;
-  s->version++;
-  drop_graph(s);
+  if (best_rate < 0.0) best = saved;
+  apply(best);
   if (cs != CSMAP_OK) return cs;
   if (cache_path) {
     std::ofstream out(cache_path, std::ios::app);
-    out << key.str() << " " << best.K << " " << best.W << " " << best.S << " " << best.F << "\n";
+    out.precision(17);
+    out << key.str() << " " << best.K << " " << best.W << " " << best.S << " " << best.F << " "
+        << best.tiling << " " << best.rings << " " << best.chunk << " " << best.near_w << " "
+        << best.far_w << "\n";
   }
   return CSMAP_OK;
 }

@@ -393,8 +393,10 @@ def test_autotune_keeps_parity_and_caches(B, mixed, tmp_path):
     sky2 = sky_from_workload(w, B.CSMAP_FORM_FP32C)
     sky2.autotune(cache)
     s2 = sky2.stats()
-    for k in ("pix_per_lane", "waves", "schedule"):
-        assert s2[k] == st0[k]
+    for k in ("pix_per_lane", "waves", "schedule", "tiling", "chunk", "near_w", "far_w"):
+        assert s2[k] == st0[k], k
+    # tuning never picks a less accurate pair form than the defaults
+    assert st0["far_w"] >= 5e-3 and st0["near_w"] >= 5e-5
     assert len(open(cache).read().strip().splitlines()) == 1
     sky.close()
     sky2.close()
