@@ -29,7 +29,12 @@ namespace csmap {
 namespace {
 
 constexpr int kLegScale = 600;   // values are v * 2^(600 e)
-constexpr int kRingsPerLane = 4; // ring pairs summed by one lane of the Legendre kernel
+// Ring pairs summed by one lane of the Legendre kernel.  The wavefront
+// reduction of each group of eight degrees is spread over more pairs as this
+// grows, at the cost of registers: at Nside 2048, lmax 4096, map2alm took
+// 12.3, 11.3, 10.9, 12.9 and 13.6 ms with 4, 5, 6, 7 and 8 (106, 142, 150,
+// 186 and 186 VGPRs: four, three, three, two and two wavefronts per SIMD).
+constexpr int kRingsPerLane = 6;
 constexpr int kAnchor = 32;      // Fourier twiddles are recomputed exactly every 32 pixels
 
 typedef const double __attribute__((address_space(4)))* cdp;

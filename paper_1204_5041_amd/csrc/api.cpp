@@ -1192,7 +1192,7 @@ csmap_status csmap_backward(csmap_sky* s, const double* dmap, const csmap_grad* 
         items.push_back(sp);
       }
   const int64_t nitems = (int64_t)items.size() / 3;
-  HIPCHK(s, s->d_pixtab32.ensure(sizeof(float) * 4 * s->npix), "alloc pixel table");
+  HIPCHK(s, s->d_pixtab32.ensure(sizeof(float) * 4 * (s->npix + 1)), "alloc pixel table");
   HIPCHK(s, s->d_pix64.ensure(sizeof(double) * 4 * s->npix), "alloc pixel table");
   HIPCHK(s, s->d_partial.ensure(sizeof(double) * 14 * (size_t)std::max<int64_t>(1, s->total_seg) *
                                 nsplit), "alloc partials");

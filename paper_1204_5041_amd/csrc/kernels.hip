@@ -1083,10 +1083,17 @@ __global__ void __launch_bounds__(256) k_fwd64(FwdArgs A) {
 // ---------------------------------------------------------------------------
 // Pixel table: direction (FP32) and cotangent (FP32) per pixel, plus the FP64
 // direction for close pairs and visibility decisions.
+// The adjoint's pixel table: per pixel n (FP32) and the cotangent, and n in
+// FP64 with the cotangent; one zero record past the last pixel lets the
+// pixel loop read one record ahead without a bound.
 __global__ void k_pixtab(int64_t nside, int64_t npix, const double* dmap, float* tab32,
                          double* tab64) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= npix) return;
+  if (p == npix) {
+    ((float4*)tab32)[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
+  if (p > npix) return;
   double x, y, z;
   pix2vec_ring(nside, p, &x, &y, &z);
   ((float4*)tab32)[p] = make_float4((float)x, (float)y, (float)z, (float)dmap[p]);
@@ -1141,6 +1148,94 @@ __device__ __forceinline__ void adj_accumulate(float (&pa)[kAcc], float s, float
   pa[13] = fmaf(c3, dz, pa[13]);
 }
 
+// Per-lane constants of the adjoint's segment (see k_adj32).
+struct AdjSeg {
+  float px, py, pz, tx, ty, tz, vx, vy, vz;
+  float c1, c2;   // 1 + Ph.Xdot, Ph.X'
+  double hx, hy, hz;   // Ph in FP64
+};
+
+// The adjoint's pixel loop over [p0, p1): pixel records stream through
+// scalar registers one step ahead (the table holds one padding record past
+// the last pixel, so the read ahead needs no bound); the values are copied
+// to vector registers so that the per-pair FMAs read vector operands only
+// (twice the issue rate of scalar operands).  kVis: the box has a
+// visibility rule, tested per pixel.
+template <bool kVis>
+__device__ __forceinline__ void adj_pixels(const AdjArgs& A, const DevBox& bx, const AdjSeg& g,
+                                           bool force, int64_t p0, int64_t p1,
+                                           double (&acc)[kAcc]) {
+  const float near_w = A.near_w, far_w = A.far_w;
+  cf4p tab = (cf4p)A.pixtab;
+  cd2p tab64 = (cd2p)A.pix64;
+  // The pixels of a ring share z: the z parts of w, a, b and d are formed
+  // once per ring (whenever the z of the next pixel differs).
+  uint32_t zbits = 0x40000000u;   // the bits of 2.0f: no pixel has z = 2
+  float wz = 0.f, az = 0.f, bz = 0.f, dzr = 0.f;
+  constexpr int J = 64;
+  v4f cur = tab[p0];
+  for (int64_t pc = p0; pc < p1; pc += J) {
+    const int64_t pe = (pc + J < p1) ? pc + J : p1;
+    float pa[kAcc];
+#pragma unroll
+    for (int k = 0; k < kAcc; ++k) pa[k] = 0.f;
+    // A 32-bit count keeps the loop test on the scalar unit (it has no
+    // 64-bit ordered compare).
+    const int32_t np = (int32_t)(pe - pc);   // at most J
+    for (int32_t i = 0; i < np; ++i) {
+      const int64_t p = pc + i;
+      __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): cur has arrived
+      const v4f pt = cur;
+      cur = tab[p + 1];
+      if (kVis) {
+        const v2d e0 = tab64[2 * p + 0];
+        const v2d e1 = tab64[2 * p + 1];
+        if (!sees_box(e0.x, e0.y, e1.x, bx, A.eta0)) continue;
+      }
+      // A new ring (compared as bits, so that the test stays in scalar
+      // registers).
+      if (__float_as_uint(pt.z) != zbits) {
+        zbits = __float_as_uint(pt.z);
+        const float z = to_vgpr(pt.z);
+        wz = fmaf(-z, g.pz, 1.0f);
+        az = z * g.tz;
+        bz = fmaf(z, g.vz, 1.0f);
+        dzr = z - g.pz;
+      }
+      const float nx = to_vgpr(pt.x), ny = to_vgpr(pt.y);
+      float s = to_vgpr(pt.w);
+      float w = fmaf(-ny, g.py, fmaf(-nx, g.px, wz));
+      const float a = fmaf(ny, g.ty, fmaf(nx, g.tx, az));
+      const float bb = fmaf(ny, g.vy, fmaf(nx, g.vx, bz));
+      // The far form's values: Xdot.d = b - (1 + Ph.Xdot), X'.d = a - Ph.X'.
+      // A close pixel (for some lane) overwrites them in place, which lets
+      // the far form run without register copies.
+      float dx = nx - g.px, dy = ny - g.py, dz = dzr;
+      float v = bb - g.c1, u = a - g.c2;
+      if (force || __any(w < far_w)) {
+        // Middle form: the direction difference in FP32 (see the forward
+        // kernel); FP64 form: from the FP64 directions.
+        if (force || __any(w < near_w)) {
+          const v2d e0 = tab64[2 * p + 0];
+          const v2d e1 = tab64[2 * p + 1];
+          dx = (float)(e0.x - g.hx);
+          dy = (float)(e0.y - g.hy);
+          dz = (float)(e1.x - g.hz);
+        }
+        const float q = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        v = fmaf(g.vz, dz, fmaf(g.vy, dy, g.vx * dx));
+        u = fmaf(g.tz, dz, fmaf(g.ty, dy, g.tx * dx));
+        // An exact coincidence (q = 0) contributes nothing.
+        w = (q > 0.0f) ? 0.5f * q : 1.0f;
+        s = (q > 0.0f) ? s : 0.0f;
+      }
+      adj_accumulate(pa, s, a, bb, w, v, u, __builtin_amdgcn_rcpf(bb * w), dx, dy, dz);
+    }
+#pragma unroll
+    for (int k = 0; k < kAcc; ++k) acc[k] += (double)pa[k];
+  }
+}
+
 // Work item: a group of 64 consecutive kept records of one box (one per
 // lane) and one of `nsplit` contiguous pixel ranges.
 __global__ void __launch_bounds__(256) k_adj32(AdjArgs A) {
@@ -1159,98 +1254,27 @@ __global__ void __launch_bounds__(256) k_adj32(AdjArgs A) {
   // Segment constants (per lane).
   const float4* R4 = (const float4*)(A.rec32 + (size_t)rec * kRec32);
   const float4 q0 = R4[0], q1 = R4[1], q2 = R4[2], q3 = R4[3];
-  const float px = q0.x, py = q0.y, pz = q0.z;
-  const float tx = q0.w, ty = q1.x, tz = q1.y;
-  const float vx = q1.z, vy = q1.w, vz = q2.x;
   // 1 + Ph.Xdot and Ph.X' (the sums leave out kappa' = -2 eps dsigma / R,
   // which the finalize step applies, so they stay finite at dsigma = 0).
   const float4 cu = ((const float4*)A.adjc)[rec];
-  const float c1 = cu.x, c2 = cu.y;
   const double2 h0 = ((const double2*)A.phat64)[2 * rec + 0];
   const double2 h1 = ((const double2*)A.phat64)[2 * rec + 1];
+  const AdjSeg g = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, q2.x,
+                    cu.x, cu.y, h0.x, h0.y, h1.x};
   // The pixel range is uniform; computing it through readfirstlane keeps it
   // (and the loop bound) in scalar registers.
   const int64_t p0 = uniform_i64(A.npix * split / A.nsplit);
   const int64_t p1 = uniform_i64(A.npix * (split + 1) / A.nsplit);
-  const float near_w = A.near_w, far_w = A.far_w;
   // A group holding a segment flagged at precompute takes the FP64 form
   // against every pixel.
   const bool force = __any(active && __float_as_int(q3.y) != 0);
-  cf4p tab = (cf4p)A.pixtab;
-  cd2p tab64 = (cd2p)A.pix64;
   double acc[kAcc];
 #pragma unroll
   for (int k = 0; k < kAcc; ++k) acc[k] = 0.0;
-  const bool check_vis = bx.vis != 0;
-  // The pixels of a ring share z: the z parts of w, a, b and d are formed
-  // once per ring (whenever the z of the next pixel differs).
-  uint32_t zbits = 0x40000000u;   // the bits of 2.0f: no pixel has z = 2
-  float wz = 0.f, az = 0.f, bz = 0.f, dzr = 0.f;
-  constexpr int J = 64;
-  for (int64_t pc = p0; pc < p1; pc += J) {
-    const int64_t pe = (pc + J < p1) ? pc + J : p1;
-    float pa[kAcc];
-#pragma unroll
-    for (int k = 0; k < kAcc; ++k) pa[k] = 0.f;
-    // Pixel records stream through scalar registers one step ahead; the
-    // values are then copied to vector registers so that the per-pair FMAs
-    // read vector operands only (twice the issue rate of scalar operands).
-    v4f cur = tab[pc];
-    const int32_t np = (int32_t)(pe - pc);   // at most J
-    for (int32_t i = 0; i < np; ++i) {
-      const int64_t p = pc + i;
-      __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): cur has arrived
-      const v4f pt = cur;
-      cur = tab[pc + ((i + 1 < np) ? i + 1 : i)];
-      // Pixels with a zero cotangent contribute nothing.
-      if ((__float_as_int(pt.w) & 0x7fffffff) == 0) continue;
-      if (check_vis) {
-        const v2d e0 = tab64[2 * p + 0];
-        const v2d e1 = tab64[2 * p + 1];
-        if (!sees_box(e0.x, e0.y, e1.x, bx, A.eta0)) continue;
-      }
-      // A new ring (compared as bits, so that the test stays in scalar
-      // registers).
-      if (__float_as_uint(pt.z) != zbits) {
-        zbits = __float_as_uint(pt.z);
-        const float z = to_vgpr(pt.z);
-        wz = fmaf(-z, pz, 1.0f);
-        az = z * tz;
-        bz = fmaf(z, vz, 1.0f);
-        dzr = z - pz;
-      }
-      const float nx = to_vgpr(pt.x), ny = to_vgpr(pt.y);
-      float s = to_vgpr(pt.w);
-      float w = fmaf(-ny, py, fmaf(-nx, px, wz));
-      const float a = fmaf(ny, ty, fmaf(nx, tx, az));
-      const float bb = fmaf(ny, vy, fmaf(nx, vx, bz));
-      // The far form's values: Xdot.d = b - (1 + Ph.Xdot), X'.d = a - Ph.X'.
-      // A close pixel (for some lane) overwrites them in place, which lets
-      // the far form run without register copies.
-      float dx = nx - px, dy = ny - py, dz = dzr;
-      float v = bb - c1, u = a - c2;
-      if (force || __any(w < far_w)) {
-        // Middle form: the direction difference in FP32 (see the forward
-        // kernel); FP64 form: from the FP64 directions.
-        if (force || __any(w < near_w)) {
-          const v2d e0 = tab64[2 * p + 0];
-          const v2d e1 = tab64[2 * p + 1];
-          dx = (float)(e0.x - h0.x);
-          dy = (float)(e0.y - h0.y);
-          dz = (float)(e1.x - h1.x);
-        }
-        const float q = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        v = fmaf(vz, dz, fmaf(vy, dy, vx * dx));
-        u = fmaf(tz, dz, fmaf(ty, dy, tx * dx));
-        // An exact coincidence (q = 0) contributes nothing.
-        w = (q > 0.0f) ? 0.5f * q : 1.0f;
-        s = (q > 0.0f) ? s : 0.0f;
-      }
-      adj_accumulate(pa, s, a, bb, w, v, u, __builtin_amdgcn_rcpf(bb * w), dx, dy, dz);
-    }
-#pragma unroll
-    for (int k = 0; k < kAcc; ++k) acc[k] += (double)pa[k];
-  }
+  if (bx.vis != 0)
+    adj_pixels<true>(A, bx, g, force, p0, p1, acc);
+  else
+    adj_pixels<false>(A, bx, g, force, p0, p1, acc);
   if (active) {
     double* o = A.partial + ((size_t)rec * A.nsplit + split) * kAcc;
 #pragma unroll
@@ -1444,7 +1468,7 @@ hipError_t launch_forward(bool fp64, int K, bool persistent, const FwdArgs& A, u
 
 hipError_t launch_pixtab(int64_t nside, int64_t npix, const double* dmap, float* tab32,
                          double* tab64, hipStream_t st) {
-  k_pixtab<<<dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, st>>>(nside, npix, dmap, tab32,
+  k_pixtab<<<dim3((unsigned)((npix + 256) / 256)), dim3(256), 0, st>>>(nside, npix, dmap, tab32,
                                                                         tab64);
   return hipGetLastError();
 }
