@@ -652,8 +652,10 @@ __device__ __forceinline__ void frac_box(const FwdArgs& A, cf4p recs, cd2p ph64,
                                          unsigned long long& near_steps,
                                          unsigned long long& mid_steps) {
   const float near_w = A.near_w, far_w = A.far_w;
-  const int64_t nseg = r1 - r0;
-  const int64_t nwin = (nseg + 3) >> 2;
+  // 32-bit counts (a box holds fewer than 2^31 records) keep the loop tests
+  // on the scalar unit, which has no 64-bit ordered compare.
+  const int32_t nseg = (int32_t)(r1 - r0);
+  const int32_t nwin = (nseg + 3) >> 2;
   const cf4p last = recs + 4 * (r1 - 1);
   cf4p rp = recs + 4 * r0;
   v4f q0 = rp[0], q1 = rp[1], q2 = rp[2], q3 = rp[3];
@@ -661,8 +663,8 @@ __device__ __forceinline__ void frac_box(const FwdArgs& A, cf4p recs, cd2p ph64,
 #pragma unroll
   for (int j = 0; j < K; ++j) { part[j] = 0.f; fp[j] = 0.f; fq[j] = 1.f; }
   int32_t left = A.chunk;   // segments until the next Kahan update (multiple of 4)
-  for (int64_t win = 0; win < nwin; ++win) {
-    const int32_t nslot = (win + 1 < nwin) ? 4 : (int32_t)(nseg - 4 * win);
+  for (int32_t win = 0; win < nwin; ++win) {
+    const int32_t nslot = (win + 1 < nwin) ? 4 : nseg - 4 * win;
 #pragma unroll
     for (int slot = 0; slot < 4; ++slot) {
       if (slot < nslot) {
