@@ -31,10 +31,11 @@ namespace {
 constexpr int kLegScale = 600;   // values are v * 2^(600 e)
 // Ring pairs summed by one lane of the Legendre kernel.  The wavefront
 // reduction of each group of eight degrees is spread over more pairs as this
-// grows, at the cost of registers: at Nside 2048, lmax 4096, map2alm took
-// 12.3, 11.3, 10.9, 12.9 and 13.6 ms with 4, 5, 6, 7 and 8 (106, 142, 150,
-// 186 and 186 VGPRs: four, three, three, two and two wavefronts per SIMD).
-constexpr int kRingsPerLane = 6;
+// grows, at the cost of registers.  With the Fourier-factor reload kept out
+// of the loop's live registers, 8 pairs take 162 VGPRs (three wavefronts per
+// SIMD); at Nside 2048, lmax 4096 the kernel took 7.7 ms with 6 pairs and
+// 6.4-6.7 ms with 8 (7 pairs: 140 VGPRs, slower than 8).
+constexpr int kRingsPerLane = 8;
 constexpr int kAnchor = 32;      // Fourier twiddles are recomputed exactly every 32 pixels
 
 typedef const double __attribute__((address_space(4)))* cdp;
@@ -642,9 +643,15 @@ __global__ void __launch_bounds__(256) k_legendre(int64_t nside, int64_t lmax, i
   double z[kRingsPerLane], cur[kRingsPerLane], prev[kRingsPerLane];
   double er[kRingsPerLane], ei[kRingsPerLane], orr[kRingsPerLane], oi[kRingsPerLane];
   int32_t sc[kRingsPerLane];
-  // Fourier factors of pair k scaled by 2^(600 sc[k]).
+  // Fourier factors of pair k scaled by 2^(600 sc[k]).  The lane index is
+  // re-read here through an opaque instruction so that the compiler cannot
+  // hoist the reload's addresses out of the degree loop, where they would
+  // hold 2 * kRingsPerLane 64-bit registers for a path taken a few times per
+  // wavefront.
   auto factors = [&](int k) {
-    const int64_t q = (blk * kRingsPerLane + k) * 64 + lane;
+    int ln;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(ln));
+    const int64_t q = (blk * kRingsPerLane + k) * 64 + ln;
     er[k] = ei[k] = orr[k] = oi[k] = 0.0;
     if (q < npair) {
       const int64_t north = q + 1;
@@ -683,28 +690,47 @@ __global__ void __launch_bounds__(256) k_legendre(int64_t nside, int64_t lmax, i
   // Recursion coefficients a_l of degrees l0 .. l0 + 7, the next group's
   // requested one group ahead.  Degrees past lmax take lmax's: their steps
   // run (every group is eight steps) but their sums are not written.
-  const int64_t row = alm_idx(lmax, m, m) - m;   // idx(l, m) = row + l
+  // Degree and table indices in 32 bits (2 (lmax + 1)(lmax + 2) / 2 < 2^31
+  // for lmax <= 32768), so that the loop's bounds and clamps stay on the
+  // scalar unit, which has no 64-bit ordered compare.
+  const int row = (int)(alm_idx(lmax, m, m) - m);   // idx(l, m) = row + l
+  const int L = (int)lmax;
   double cA[8];
 #pragma unroll
-  for (int g = 0; g < 8; ++g) cA[g] = cf[2 * (row + (m + g < lmax ? m + g : lmax))];
+  for (int g = 0; g < 8; ++g) cA[g] = cf[2 * (row + min((int)m + g, L))];
   // The ring data loaded above has arrived: without this wait the loop's
   // first use of it waits on every vector memory operation in flight, the
   // previous group's store included, in every iteration.
   __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
-  for (int64_t l0 = m; l0 <= lmax; l0 += 8) {
+  for (int l0 = (int)m; l0 <= L; l0 += 8) {
     double nA[8];
 #pragma unroll
-    for (int g = 0; g < 8; ++g) nA[g] = cf[2 * (row + (l0 + 8 + g < lmax ? l0 + 8 + g : lmax))];
+    for (int g = 0; g < 8; ++g) nA[g] = cf[2 * (row + min(l0 + 8 + g, L))];
     __builtin_amdgcn_sched_barrier(0);    // issue the requests before the arithmetic
-    // Bring scaled values back once they have grown (growth over 8 steps
-    // stays far below the 2^423 headroom above 2^600).
+    // Bring scaled values back once they have grown, every 32 degrees: with
+    // |z| <= 1, max(|mu_l|, |mu_{l-1}|) grows by at most |a_l| + 1 per step,
+    // which over any 32 consecutive degrees is below 2^200 for every
+    // m <= l <= 32768, far inside the 2^424 between the 2^600 threshold and
+    // the double range.  One wavefront-wide test skips the whole block when
+    // no lane needs it.
+    if (((l0 - (int)m) & 31) == 0) {
+      bool need[kRingsPerLane];
+      bool any = false;
 #pragma unroll
-    for (int k = 0; k < kRingsPerLane; ++k) {
-      if (sc[k] < 0 && fmax(fabs(cur[k]), fabs(prev[k])) > big) {
-        cur[k] = ldexp(cur[k], -kLegScale);
-        prev[k] = ldexp(prev[k], -kLegScale);
-        sc[k] += 1;
-        factors(k);
+      for (int k = 0; k < kRingsPerLane; ++k) {
+        need[k] = sc[k] < 0 && fmax(fabs(cur[k]), fabs(prev[k])) > big;
+        any |= need[k];
+      }
+      if (__builtin_amdgcn_ballot_w64(any)) {
+#pragma unroll
+        for (int k = 0; k < kRingsPerLane; ++k) {
+          if (need[k]) {
+            cur[k] = ldexp(cur[k], -kLegScale);
+            prev[k] = ldexp(prev[k], -kLegScale);
+            sc[k] += 1;
+            factors(k);
+          }
+        }
       }
     }
     double acc[16];
@@ -734,7 +760,7 @@ __global__ void __launch_bounds__(256) k_legendre(int64_t nside, int64_t lmax, i
     }
     const double tot = wave_sum16(acc);
     const int v = lane >> 2;   // value held: real (even) or imaginary (odd) part of degree l0 + v/2
-    if ((lane & 3) == 0 && l0 + (v >> 1) <= lmax) out[2 * (row + l0) + v] = tot;
+    if ((lane & 3) == 0 && l0 + (v >> 1) <= L) out[2 * (row + l0) + v] = tot;
 #pragma unroll
     for (int g = 0; g < 8; ++g) cA[g] = nA[g];
   }
