@@ -700,8 +700,9 @@ def bench_flat(args, B, torch):
 def bench_alm(args, B, torch):
     """Angular power spectrum of a string map: the FP32C map of one 400,000-
     segment box at Nside=2048 (rendered first, not timed), then a_lm up to
-    lmax = 4096 = 2 Nside and C_l, timed over the whole call (scratch
-    allocation included), in FP64."""
+    lmax = 4096 = 2 Nside and C_l, timed over back-to-back whole calls (each
+    takes its scratch from the library's stream-ordered pool and returns it),
+    in FP64."""
     nside, lmax = NSIDE, 2 * NSIDE
     sky, _ = make_sky(B, torch, 0, B.CSMAP_FORM_FP32C, args.nseg, nside)
     hmap = sky.render()

@@ -393,11 +393,15 @@ csmap_status csmap_autotune(csmap_sky *sky, const char *cache_path);
  * Condon-Shortley phase, n_p the pixel centres.  map: device, 12 Nside^2
  * doubles (RING order); alm: device, (lmax + 1)(lmax + 2) doubles, a_lm's
  * real and imaginary parts at positions 2 i and 2 i + 1 with
- * i = m (2 lmax + 1 - m) / 2 + l.  0 <= lmax <= 4 Nside.  Allocates device
- * scratch for the duration of the call (about 16 (4 Nside)(lmax + 1) +
- * 12 (2 Nside)(lmax + 1) + 16 (ceil(Nside / 128) + 1)(lmax + 1)(lmax + 2)/2
- * bytes: 3.0 GB at Nside 2048, lmax 4096) and synchronises hip_stream
- * before returning. */
+ * i = m (2 lmax + 1 - m) / 2 + l.  0 <= lmax <= 4 Nside.  Enqueued on
+ * hip_stream, which must belong to the current device; does not
+ * synchronise.  The work's device scratch (about 16 (4 Nside)(lmax + 1) +
+ * 12 (2 Nside)(lmax + 1) + 8 (ceil(Nside / 256) + 1)(lmax + 1)(lmax + 2)
+ * bytes: 2.0 GB at Nside 2048, lmax 4096) is taken in stream order from a
+ * memory pool that the library creates per device on first use and released
+ * to it when the work ends; the pool keeps the memory for later calls until
+ * the process ends.  CSMAP_E_NOMEM when the scratch cannot be had; errors of
+ * the device work itself surface at the caller's next synchronisation. */
 csmap_status csmap_map2alm(int64_t nside, int64_t lmax, const double *map, double *alm,
                            void *hip_stream);
 

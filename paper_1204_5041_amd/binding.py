@@ -476,7 +476,8 @@ def alm_size(lmax: int) -> int:
 
 def map2alm(hmap, lmax: int, stream=None):
     """a_lm of a RING map (csmap_map2alm) as a complex128 CUDA tensor of
-    alm_size(lmax) entries, a_lm at m (2 lmax + 1 - m) / 2 + l."""
+    alm_size(lmax) entries, a_lm at m (2 lmax + 1 - m) / 2 + l.  Enqueued on
+    `stream` (default: the current stream) without synchronising."""
     torch = _torch()
     npix = int(hmap.numel())
     nside = int(round((npix / 12) ** 0.5))
@@ -484,8 +485,12 @@ def map2alm(hmap, lmax: int, stream=None):
         raise ValueError("map must be a float64 tensor of 12 Nside^2 pixels")
     alm = torch.empty(2 * alm_size(lmax), dtype=torch.float64, device="cuda")
     st = stream if stream is not None else torch.cuda.current_stream()
-    _check(lib().csmap_map2alm(nside, lmax, _dev_ptr(hmap.contiguous()), _dev_ptr(alm),
-                               st.cuda_stream))
+    src = hmap.contiguous()
+    _check(lib().csmap_map2alm(nside, lmax, _dev_ptr(src), _dev_ptr(alm), st.cuda_stream))
+    # The work reads `src` and writes `alm` after this returns: tell torch's
+    # allocator that both are in use on `st`.
+    src.record_stream(st)
+    alm.record_stream(st)
     return torch.view_as_complex(alm.view(-1, 2))
 
 

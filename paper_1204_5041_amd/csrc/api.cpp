@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <chrono>
 #include <fstream>
+#include <mutex>
 #include <numeric>
 #include <sstream>
 #include <string>
@@ -800,6 +801,40 @@ csmap_status csmap_cone_min_nside(double r_in, double r_out, double side, int64_
   return CSMAP_OK;
 }
 
+// The current device's stream-ordered pool for map2alm's scratch, created on
+// first use.  Its release threshold is unbounded, so memory a call frees
+// (in stream order) stays in the pool and the next call of the same or a
+// smaller size takes it without a device allocation.
+static hipError_t map2alm_pool(hipMemPool_t* out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static hipMemPool_t pools[kMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!pools[dev]) {
+    hipMemPoolProps props;
+    memset(&props, 0, sizeof(props));
+    props.allocType = hipMemAllocationTypePinned;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    hipMemPool_t p = nullptr;
+    e = hipMemPoolCreate(&p, &props);
+    if (e != hipSuccess) return e;
+    uint64_t keep = UINT64_MAX;
+    e = hipMemPoolSetAttribute(p, hipMemPoolAttrReleaseThreshold, &keep);
+    if (e != hipSuccess) {
+      (void)hipMemPoolDestroy(p);
+      return e;
+    }
+    pools[dev] = p;
+  }
+  *out = pools[dev];
+  return hipSuccess;
+}
+
 csmap_status csmap_map2alm(int64_t nside, int64_t lmax, const double* map, double* alm,
                            void* hip_stream) {
   g_err.clear();
@@ -807,14 +842,17 @@ csmap_status csmap_map2alm(int64_t nside, int64_t lmax, const double* map, doubl
   if (lmax < 0 || lmax > 4 * nside) return fail(CSMAP_E_INVALID, "lmax must be in [0, 4 Nside]");
   if (!map || !alm) return fail(CSMAP_E_INVALID, "map or alm is NULL");
   hipStream_t st = (hipStream_t)hip_stream;
+  hipMemPool_t pool = nullptr;
+  hipError_t e = map2alm_pool(&pool);
+  if (e != hipSuccess) return dev_fail(nullptr, e, "map2alm scratch pool");
   void* scratch = nullptr;
-  hipError_t e = hipMalloc(&scratch, map2alm_scratch_bytes(nside, lmax));
-  if (e != hipSuccess) return fail(CSMAP_E_NOMEM, "device allocation of map2alm scratch failed");
+  e = hipMallocFromPoolAsync(&scratch, map2alm_scratch_bytes(nside, lmax), pool, st);
+  if (e != hipSuccess || !scratch)
+    return fail(CSMAP_E_NOMEM, "device allocation of map2alm scratch failed");
   e = launch_map2alm(nside, lmax, map, alm, scratch, st);
-  const hipError_t e2 = hipStreamSynchronize(st);
-  (void)hipFree(scratch);
+  const hipError_t e2 = hipFreeAsync(scratch, st);
   if (e != hipSuccess) return dev_fail(nullptr, e, "map2alm launch");
-  if (e2 != hipSuccess) return dev_fail(nullptr, e2, "map2alm");
+  if (e2 != hipSuccess) return dev_fail(nullptr, e2, "map2alm scratch release");
   return CSMAP_OK;
 }
 
