@@ -396,8 +396,8 @@ csmap_status csmap_autotune(csmap_sky *sky, const char *cache_path);
  * i = m (2 lmax + 1 - m) / 2 + l.  0 <= lmax <= 4 Nside.  Enqueued on
  * hip_stream, which must belong to the current device; does not
  * synchronise.  The work's device scratch (about 16 (4 Nside)(lmax + 1) +
- * 12 (2 Nside)(lmax + 1) + 8 (ceil(Nside / 256) + 1)(lmax + 1)(lmax + 2)
- * bytes: 2.0 GB at Nside 2048, lmax 4096) is taken in stream order from a
+ * 8 (ceil(Nside / 256) + 1)(lmax + 1)(lmax + 2) bytes: 1.7 GB at Nside
+ * 2048, lmax 4096) is taken in stream order from a
  * memory pool that the library creates per device on first use and released
  * to it when the work ends; the pool keeps the memory for later calls until
  * the process ends.  CSMAP_E_NOMEM when the scratch cannot be had; errors of
@@ -413,8 +413,8 @@ csmap_status csmap_map2alm(int64_t nside, int64_t lmax, const double *map, doubl
  * routine and does not synchronise: the work is enqueued on hip_stream, which
  * must belong to the current device.  Arguments, layout and errors as
  * csmap_map2alm, plus CSMAP_E_INVALID when (nside, lmax) needs more scratch
- * than 64 MiB (Nside 512 with lmax 512 fits; Nside 512 with lmax 1024 does
- * not).  Every call on one GPU shares its array and nothing in it needs to
+ * than 64 MiB (Nside 512 with lmax 1024 fits; Nside 1024 with lmax 1024
+ * does not).  Every call on one GPU shares its array and nothing in it needs to
  * start at zero; calls that overlap on one GPU (different streams, or
  * threads) race on it and must be serialised by the caller. */
 csmap_status csmap_map2alm_noalloc(int64_t nside, int64_t lmax, const double *map, double *alm,

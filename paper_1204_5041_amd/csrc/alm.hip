@@ -234,14 +234,17 @@ __global__ void __launch_bounds__(kFftThreads) k_ring_fft(int64_t nside, int64_t
 // Bluestein's chirp transform: with w_n = e^{-i pi n^2/i} (from n^2 mod 2i,
 // exact), D(kappa) = w_kappa sum_n (y_n w_n) conj(w_{kappa-n}), a linear
 // convolution computed as a cyclic one of power-of-two length P >= 2i - 1.
-// The convolution's transforms run in LDS: forward by decimation in
-// frequency (natural order in, bit-reversed out), the product with the
+// The convolution's transforms run in LDS in radix-8 passes (one radix-2
+// or radix-4 pass when log2 P is not a multiple of 3), each thread taking
+// one 8-point butterfly in registers per pass: forward by decimation in
+// frequency (natural order in, digit-reversed out), the product with the
 // chirp filter's transform in that order, inverse by decimation in time
-// (bit-reversed in, natural out), so no reordering pass is needed.  The
-// filter's transform stays in registers over the four D_r, and D_r stays
-// in registers until the radix-4 step; Z goes through a global slot of 4i
-// values before the unpacking, which pairs k with L - k.  One workgroup
-// per ring pair; ctab[k] = e^{-2 pi i k/kCapMaxP}, k < kCapMaxP/2.
+// with the passes reversed (digit-reversed in, natural out), so no
+// reordering pass is needed.  The filter's transform stays in registers
+// over the four D_r, and D_r stays in registers until the radix-4 step; Z
+// goes through a global slot of 4i values before the unpacking, which pairs
+// k with L - k.  One workgroup per ring pair; ctab[k] = e^{-2 pi i k/kCapMaxP},
+// k < kCapMaxP.
 constexpr int kCapThreads = 512;
 constexpr int64_t kCapMaxP = 4096;                     // 64 KB of LDS: i <= 2048, Nside <= 2049
 constexpr int kCapPer = (int)(kCapMaxP / kCapThreads);  // transform positions per thread
@@ -249,7 +252,7 @@ constexpr int kCapKappa = kCapPer / 2;                  // D_r values per thread
 
 __global__ void k_cap_table(double* ctab) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= kCapMaxP / 2) return;
+  if (k >= kCapMaxP) return;
   double sp, cp;
   sincospi((double)(2 * k) / (double)kCapMaxP, &sp, &cp);
   ctab[2 * k] = cp;
@@ -270,60 +273,136 @@ __device__ __forceinline__ void chirp(int64_t n, int64_t len, double& c, double&
   s = -sp;
 }
 
-// Forward transform of P (a power of two <= kCapMaxP) values in LDS, natural
-// order in, bit-reversed order out.
-__device__ void fft_dif(double* x, int64_t P, const double* ctab) {
-  for (int64_t h = P >> 1; h >= 1; h >>= 1) {
-    const int64_t ts = kCapMaxP / (2 * h);
-    for (int64_t b = threadIdx.x; b < P / 2; b += kCapThreads) {
-      const int64_t pos = b & (h - 1);
-      const int64_t i0 = 2 * (b - pos) + pos, i1 = i0 + h;
-      const double wc = ctab[2 * pos * ts], ws = ctab[2 * pos * ts + 1];
-      const double ur = x[2 * i0], ui = x[2 * i0 + 1], vr = x[2 * i1], vi = x[2 * i1 + 1];
-      const double dr = ur - vr, di = ui - vi;
-      x[2 * i0] = ur + vr;
-      x[2 * i0 + 1] = ui + vi;
-      x[2 * i1] = fma(dr, wc, -(di * ws));
-      x[2 * i1 + 1] = fma(dr, ws, di * wc);
+struct cplx {
+  double r, i;
+};
+
+__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return {a.r + b.r, a.i + b.i}; }
+__device__ __forceinline__ cplx csub(cplx a, cplx b) { return {a.r - b.r, a.i - b.i}; }
+__device__ __forceinline__ cplx cmul(cplx a, cplx w) {
+  return {fma(a.r, w.r, -(a.i * w.i)), fma(a.r, w.i, a.i * w.r)};
+}
+// a * (-i) for the forward direction (kInv false), a * i for the inverse.
+template <bool kInv>
+__device__ __forceinline__ cplx rot90(cplx a) {
+  return kInv ? cplx{-a.i, a.r} : cplx{a.i, -a.r};
+}
+
+// In-register DFT of R = 2, 4 or 8 points, natural order in and out:
+// y_q' = sum_q x_q e^{-+2 pi i q q'/R} (minus sign forward, plus inverse).
+template <int R, bool kInv>
+__device__ __forceinline__ void dft_small(cplx* x) {
+  if constexpr (R == 2) {
+    const cplx a = x[0], b = x[1];
+    x[0] = cadd(a, b);
+    x[1] = csub(a, b);
+  } else if constexpr (R == 4) {
+    const cplx s0 = cadd(x[0], x[2]), d0 = csub(x[0], x[2]);
+    const cplx s1 = cadd(x[1], x[3]), d1 = rot90<kInv>(csub(x[1], x[3]));
+    x[0] = cadd(s0, s1);
+    x[2] = csub(s0, s1);
+    x[1] = cadd(d0, d1);
+    x[3] = csub(d0, d1);
+  } else {
+    // Split by halves: a_k = x_k + x_{k+4} feeds the even outputs,
+    // b_k = (x_k - x_{k+4}) e^{-+2 pi i k/8} the odd ones.
+    constexpr double h = 0.70710678118654752440;   // 1/sqrt(2), rounded
+    cplx a[4], b[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      a[k] = cadd(x[k], x[k + 4]);
+      b[k] = csub(x[k], x[k + 4]);
     }
-    __syncthreads();
+    // e^{-+i pi/4} = (1 -+ i)/sqrt(2), e^{-+i pi/2} = -+i, e^{-+3 i pi/4} = (-1 -+ i)/sqrt(2).
+    b[1] = kInv ? cplx{(b[1].r - b[1].i) * h, (b[1].r + b[1].i) * h}
+                : cplx{(b[1].r + b[1].i) * h, (b[1].i - b[1].r) * h};
+    b[2] = rot90<kInv>(b[2]);
+    b[3] = kInv ? cplx{-(b[3].r + b[3].i) * h, (b[3].r - b[3].i) * h}
+                : cplx{(b[3].i - b[3].r) * h, -(b[3].r + b[3].i) * h};
+    dft_small<4, kInv>(a);
+    dft_small<4, kInv>(b);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      x[2 * k] = a[k];
+      x[2 * k + 1] = b[k];
+    }
   }
 }
 
-// Inverse transform (conjugate twiddles, no 1/P), bit-reversed order in,
-// natural order out.
-__device__ void fft_dit_inv(double* x, int64_t P, const double* ctab) {
-  for (int64_t h = 1; h < P; h <<= 1) {
-    const int64_t ts = kCapMaxP / (2 * h);
-    for (int64_t b = threadIdx.x; b < P / 2; b += kCapThreads) {
-      const int64_t pos = b & (h - 1);
-      const int64_t i0 = 2 * (b - pos) + pos, i1 = i0 + h;
-      const double wc = ctab[2 * pos * ts], ws = -ctab[2 * pos * ts + 1];
-      const double br = x[2 * i1], bi = x[2 * i1 + 1];
-      const double tr = fma(br, wc, -(bi * ws)), ti = fma(br, ws, bi * wc);
-      const double ar = x[2 * i0], ai = x[2 * i0 + 1];
-      x[2 * i0] = ar + tr;
-      x[2 * i0 + 1] = ai + ti;
-      x[2 * i1] = ar - tr;
-      x[2 * i1 + 1] = ai - ti;
+// One decimation-in-frequency pass of radix R over spans of S points (in
+// place in LDS, P points): for every span and position p < h = S/R,
+// y_q' = e^{-2 pi i p q'/S} sum_q x_{p + q h} e^{-2 pi i q q'/R}, written at
+// p + q' h.  The inverse pass undoes it up to a factor R: twiddles
+// conjugated and applied first, then the inverse R-point DFT.
+template <int R, bool kInv>
+__device__ __forceinline__ void fft_pass(double* x, int P, int S, const double* ctab) {
+  const int h = S / R;
+  const int tw = (int)kCapMaxP / S;   // table step of e^{-2 pi i/S}
+  for (int b = threadIdx.x; b < P / R; b += kCapThreads) {
+    const int pos = b % h;
+    const int base = (b - pos) * R + pos;
+    cplx v[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[q] = {x[2 * (base + q * h)], x[2 * (base + q * h) + 1]};
+    if constexpr (!kInv) dft_small<R, false>(v);
+#pragma unroll
+    for (int q = 1; q < R; ++q) {
+      const int k = (pos * q * tw) & ((int)kCapMaxP - 1);
+      const cplx w = {ctab[2 * k], kInv ? -ctab[2 * k + 1] : ctab[2 * k + 1]};
+      v[q] = cmul(v[q], w);
     }
-    __syncthreads();
+    if constexpr (kInv) dft_small<R, true>(v);
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      x[2 * (base + q * h)] = v[q].r;
+      x[2 * (base + q * h) + 1] = v[q].i;
+    }
+  }
+  __syncthreads();
+}
+
+// Forward transform of P (a power of two <= kCapMaxP) values in LDS,
+// natural order in, digit-reversed order out: radix-8 passes from the
+// widest span down, then one radix-4 or radix-2 pass if log2 P mod 3 is 2
+// or 1.
+__device__ void fft_dif(double* x, int P, const double* ctab) {
+  int S = P;
+  while (S >= 8) {
+    fft_pass<8, false>(x, P, S, ctab);
+    S >>= 3;
+  }
+  if (S == 4) fft_pass<4, false>(x, P, 4, ctab);
+  if (S == 2) fft_pass<2, false>(x, P, 2, ctab);
+}
+
+// Inverse of fft_dif times P: digit-reversed order in, natural order out,
+// the passes in reverse order.
+__device__ void fft_dit_inv(double* x, int P, const double* ctab) {
+  int e = 0;
+  while ((1 << e) < P) ++e;
+  int S = 1 << (e % 3);
+  if (S == 4) fft_pass<4, true>(x, P, 4, ctab);
+  if (S == 2) fft_pass<2, true>(x, P, 2, ctab);
+  while (S < P) {
+    S <<= 3;
+    fft_pass<8, true>(x, P, S, ctab);
   }
 }
 
-__global__ void __launch_bounds__(kCapThreads) k_cap_bluestein(int64_t nside, int64_t mmax,
+__global__ void __launch_bounds__(kCapThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
+k_cap_bluestein(int64_t nside, int64_t mmax,
                                                                const double* map,
                                                                const double* ctab, double* zslot,
                                                                double* F) {
   extern __shared__ double xs[];   // P complex values, (re, im) interleaved
   const int t = threadIdx.x;
   const int64_t N = nside, i = 1 + blockIdx.x, L = 4 * i;
-  const int64_t P = pow2_at_least(2 * i - 1);
+  const int P = (int)pow2_at_least(2 * i - 1);
   const double inv_p = 1.0 / (double)P;   // exact: P is a power of two
   const double* xn = map + 2 * i * (i - 1);
   const double* xsth = map + 12 * N * N - 2 * i * (i + 1);
   // Chirp filter b_m = conj(w_m) at m mod P for |m| < i, then its transform.
-  for (int64_t p = t; p < P; p += kCapThreads) {
+  for (int p = t; p < P; p += kCapThreads) {
     const int64_t n = p < i ? p : (p > P - i ? P - p : -1);
     double br = 0.0, bi = 0.0;
     if (n >= 0) {
@@ -340,32 +419,53 @@ __global__ void __launch_bounds__(kCapThreads) k_cap_bluestein(int64_t nside, in
   double Br[kCapPer], Bi[kCapPer];
 #pragma unroll
   for (int j = 0; j < kCapPer; ++j) {
-    const int64_t p = t + (int64_t)j * kCapThreads;
+    const int p = t + j * kCapThreads;
     Br[j] = p < P ? xs[2 * p] : 0.0;
     Bi[j] = p < P ? xs[2 * p + 1] : 0.0;
   }
   __syncthreads();
-  // E_r(kappa) = e^{-2 pi i r kappa / L} D_r(kappa).
-  double Er[4][kCapKappa], Ei[4][kCapKappa];
+  // The chirp w_n and the twist e^{-2 pi i n/L} at this thread's positions
+  // n = t + j * kCapThreads < i, shared by the four quarter-length DFTs:
+  // the inputs y_n w_n, the outputs w_kappa (...) and the twist powers
+  // e^{-2 pi i r kappa/L} = (e^{-2 pi i kappa/L})^r.
+  double wc[kCapKappa], ws[kCapKappa], tc[kCapKappa], ts[kCapKappa];
+#pragma unroll
+  for (int j = 0; j < kCapKappa; ++j) {
+    const int64_t n = t + (int64_t)j * kCapThreads;
+    wc[j] = ws[j] = tc[j] = ts[j] = 0.0;
+    if (n < i) {
+      chirp(n, i, wc[j], ws[j]);
+      double sp, cp;
+      sincospi((double)(2 * n) / (double)L, &sp, &cp);
+      tc[j] = cp;
+      ts[j] = -sp;
+    }
+  }
+  // E_r(kappa) = e^{-2 pi i r kappa / L} D_r(kappa), staged in the ring's Z
+  // slot at r i + kappa: the radix-4 step below reads back, from the same
+  // thread, exactly the four positions kappa + s i that it then writes.
+  double* Z = zslot + 2 * (2 * i * (i - 1));
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    for (int64_t p = t; p < P; p += kCapThreads) {
-      double ar = 0.0, ai = 0.0;
-      if (p < i) {
-        const double yr = xn[4 * p + r], yi = xsth[4 * p + r];
-        double c, s;
-        chirp(p, i, c, s);
-        ar = fma(yr, c, -(yi * s));
-        ai = fma(yr, s, yi * c);
+#pragma unroll
+    for (int j = 0; j < kCapPer; ++j) {
+      const int p = t + j * kCapThreads;
+      if (p < P) {
+        double ar = 0.0, ai = 0.0;
+        if (j < kCapKappa && p < i) {
+          const double yr = xn[4 * p + r], yi = xsth[4 * p + r];
+          ar = fma(yr, wc[j], -(yi * ws[j]));
+          ai = fma(yr, ws[j], yi * wc[j]);
+        }
+        xs[2 * p] = ar;
+        xs[2 * p + 1] = ai;
       }
-      xs[2 * p] = ar;
-      xs[2 * p + 1] = ai;
     }
     __syncthreads();
     fft_dif(xs, P, ctab);
 #pragma unroll
     for (int j = 0; j < kCapPer; ++j) {
-      const int64_t p = t + (int64_t)j * kCapThreads;
+      const int p = t + j * kCapThreads;
       if (p < P) {
         const double ar = xs[2 * p], ai = xs[2 * p + 1];
         xs[2 * p] = fma(ar, Br[j], -(ai * Bi[j]));
@@ -377,31 +477,37 @@ __global__ void __launch_bounds__(kCapThreads) k_cap_bluestein(int64_t nside, in
 #pragma unroll
     for (int j = 0; j < kCapKappa; ++j) {
       const int64_t kap = t + (int64_t)j * kCapThreads;
-      Er[r][j] = 0.0;
-      Ei[r][j] = 0.0;
       if (kap < i) {
-        double c, s;
-        chirp(kap, i, c, s);
         const double cr = xs[2 * kap] * inv_p, ci = xs[2 * kap + 1] * inv_p;
-        const double dr = fma(cr, c, -(ci * s)), di = fma(cr, s, ci * c);
-        double sp, cp;
-        sincospi((double)(2 * r * kap) / (double)L, &sp, &cp);
-        Er[r][j] = fma(dr, cp, di * sp);      // times e^{-i pi 2 r kappa / L}
-        Ei[r][j] = fma(di, cp, -(dr * sp));
+        double dr = fma(cr, wc[j], -(ci * ws[j])), di = fma(cr, ws[j], ci * wc[j]);
+        // times e^{-2 pi i r kappa / L}, r multiplications by the twist
+#pragma unroll
+        for (int q = 0; q < r; ++q) {
+          const double er = fma(dr, tc[j], -(di * ts[j]));
+          di = fma(dr, ts[j], di * tc[j]);
+          dr = er;
+        }
+        Z[2 * (r * i + kap)] = dr;
+        Z[2 * (r * i + kap) + 1] = di;
       }
     }
     __syncthreads();
   }
   // Radix-4 step: Z_{kappa + s i} = sum_r (-i)^{rs} E_r(kappa).
-  double* Z = zslot + 2 * (2 * i * (i - 1));
 #pragma unroll
   for (int j = 0; j < kCapKappa; ++j) {
     const int64_t kap = t + (int64_t)j * kCapThreads;
     if (kap < i) {
-      const double s0r = Er[0][j] + Er[2][j], s0i = Ei[0][j] + Ei[2][j];
-      const double d0r = Er[0][j] - Er[2][j], d0i = Ei[0][j] - Ei[2][j];
-      const double s1r = Er[1][j] + Er[3][j], s1i = Ei[1][j] + Ei[3][j];
-      const double d1r = Er[1][j] - Er[3][j], d1i = Ei[1][j] - Ei[3][j];
+      double Er[4], Ei[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        Er[r] = Z[2 * (r * i + kap)];
+        Ei[r] = Z[2 * (r * i + kap) + 1];
+      }
+      const double s0r = Er[0] + Er[2], s0i = Ei[0] + Ei[2];
+      const double d0r = Er[0] - Er[2], d0i = Ei[0] - Ei[2];
+      const double s1r = Er[1] + Er[3], s1i = Ei[1] + Ei[3];
+      const double d1r = Er[1] - Er[3], d1i = Ei[1] - Ei[3];
       Z[2 * kap] = s0r + s1r;                 // s = 0
       Z[2 * kap + 1] = s0i + s1i;
       Z[2 * (kap + i)] = d0r + d1i;           // s = 1: E0 - i E1 - E2 + i E3
@@ -429,41 +535,70 @@ __global__ void __launch_bounds__(kCapThreads) k_cap_bluestein(int64_t nside, in
   }
 }
 
-// Step 2a: lambda_mm of the north ring of every ring pair q = 1 .. 2N (its
-// z >= 0), for m = 0 .. mmax, as v * 2^(600 e); one thread per ring.
-// fac[m] = -sqrt((2m+1)/(2m)), m = 1 .. mmax: the ring-independent factor of
-// the lambda_mm recursion, formed once rather than in every ring's thread.
-__global__ void k_mm_factor(int64_t mmax, double* fac) {
-  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m < 1 || m > mmax) return;
-  fac[m] = -sqrt((2.0 * m + 1.0) / (2.0 * m));
+// Step 2a: the pieces of lambda_mm(z) = g[m] sin^m(theta) for the north
+// ring of every ring pair (its z >= 0): the factor g[m] and each ring's
+// cos and sin of the colatitude.  The Legendre kernel forms sin^m itself.
+// g[m] = (-1)^m sqrt(prod_{k=1}^m (2k+1)/(2k)) / sqrt(4 pi), the
+// ring-independent factor of lambda_mm = g[m] sin^m(theta), for
+// m = 0 .. mmax: one workgroup of 256 threads, each taking a run of
+// consecutive m, then a scan of the runs' products in LDS.  Its magnitude
+// grows like m^(1/4), so plain doubles hold it.
+__global__ void __launch_bounds__(256) k_mm_gain(int64_t mmax, double* g) {
+  __shared__ double part[256];
+  const int t = threadIdx.x;
+  const int M = (int)mmax + 1;
+  const int run = (M + 255) / 256;
+  const int lo = t * run, hi = min(lo + run, M);
+  double p = 1.0;
+  for (int m = max(lo, 1); m < hi; ++m) p *= -sqrt((2.0 * m + 1.0) / (2.0 * m));
+  part[t] = p;
+  __syncthreads();
+  for (int d = 1; d < 256; d <<= 1) {   // inclusive product scan
+    const double o = t >= d ? part[t - d] : 1.0;
+    __syncthreads();
+    part[t] *= o;
+    __syncthreads();
+  }
+  double v = (t > 0 ? part[t - 1] : 1.0) * (1.0 / sqrt(4.0 * 3.14159265358979323846));
+  for (int m = lo; m < hi; ++m) {
+    if (m > 0) v *= -sqrt((2.0 * m + 1.0) / (2.0 * m));
+    g[m] = v;
+  }
 }
 
-__global__ void k_lambda_mm(int64_t nside, int64_t mmax, const double* mm_fac, double* lam_v,
-                            int32_t* lam_e, double* ring_z) {
+// cos and sin of the colatitude of ring pair q (north ring q + 1), from the
+// ring's first pixel direction (sin from x and y, exact near the poles).
+__global__ void k_ring_zs(int64_t nside, double* ring_z, double* ring_s) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t npair = 2 * nside;
-  if (q >= npair) return;
+  if (q >= 2 * nside) return;
   const Ring r = ring_of(nside, q + 1);
   double x, y, z;
   pix2vec_ring(nside, r.first, &x, &y, &z);
-  const double s = sqrt(x * x + y * y);
   ring_z[q] = z;
-  double v = 1.0 / sqrt(4.0 * 3.14159265358979323846);
-  int32_t e = 0;
-  const double tiny = ldexp(1.0, -kLegScale);
-  cdp fac = (cdp)mm_fac;
-  for (int64_t m = 0; m <= mmax; ++m) {
-    if (m > 0) {
-      v = fac[m] * s * v;
-      if (fabs(v) < tiny) {
-        v = ldexp(v, kLegScale);
-        e -= 1;
-      }
+  ring_s[q] = sqrt(x * x + y * y);
+}
+
+// s^m as mant * 2^ex (s > 0), by binary powering with the operands
+// renormalised after every product, so that no intermediate leaves the
+// double range: at most 2 log2(m) roundings.
+__device__ __forceinline__ void pow_scaled(double s, int m, double& mant, int& ex) {
+  int eb;
+  double b = frexp(s, &eb);
+  double r = 1.0;
+  int er = 0;
+  for (int k = m; k > 0; k >>= 1) {
+    int t;
+    if (k & 1) {
+      r = frexp(r * b, &t);
+      er += t + eb;
     }
-    lam_v[m * npair + q] = v;
-    lam_e[m * npair + q] = e;
+    if (k > 1) {
+      b = frexp(b * b, &t);
+      eb = 2 * eb + t;
+    }
   }
+  mant = r;
+  ex = er;
 }
 
 // Step 2a': the coefficients of the rescaled recursion.  With
@@ -626,9 +761,9 @@ __device__ __forceinline__ double wave_sum16(const double v[16]) {
 // recursion and two multiply-adds.
 __global__ void __launch_bounds__(256) k_legendre(int64_t nside, int64_t lmax, int64_t mmax,
                                                  const double* __restrict__ F,
-                                                 const double* __restrict__ lam_v,
-                                                 const int32_t* __restrict__ lam_e,
+                                                 const double* __restrict__ gain,
                                                  const double* __restrict__ ring_z,
+                                                 const double* __restrict__ ring_s,
                                                  const double* __restrict__ coef, int64_t nblk,
                                                  double* __restrict__ part) {
   const int lane = threadIdx.x & 63;
@@ -670,6 +805,10 @@ __global__ void __launch_bounds__(256) k_legendre(int64_t nside, int64_t lmax, i
       oi[k] = ldexp(fn[1] - si, e);
     }
   };
+  // lambda_mm = g[m] sin^m(theta) as v * 2^(600 sc), 2^-602 < |v| < 8:
+  // sin^m by binary powering, its binary exponent split into sc and the
+  // rest.  The step at l = m moves it from prev to cur.
+  const double gm = gain[m];
 #pragma unroll
   for (int k = 0; k < kRingsPerLane; ++k) {
     const int64_t q = (blk * kRingsPerLane + k) * 64 + lane;   // pair index, 0-based
@@ -679,8 +818,11 @@ __global__ void __launch_bounds__(256) k_legendre(int64_t nside, int64_t lmax, i
     sc[k] = 0;
     if (q < npair) {
       z[k] = ring_z[q];
-      prev[k] = lam_v[m * npair + q];   // the step at l = m moves it to cur
-      sc[k] = lam_e[m * npair + q];
+      double mant;
+      int ex;
+      pow_scaled(ring_s[q], (int)m, mant, ex);
+      if (ex < -599) sc[k] = -((-ex) / kLegScale);   // -ceil((-599 - ex) / 600)
+      prev[k] = ldexp(gm * mant, ex - kLegScale * sc[k]);
     }
     factors(k);
   }
@@ -801,8 +943,6 @@ __global__ void __launch_bounds__(256) k_alm2cl(int64_t lmax, const double* alm,
 
 }  // namespace
 
-// Scratch needs of map2alm at (nside, lmax): bytes of the Fourier table,
-// the lambda_mm tables and the block partials.
 // Doubles of the region that holds the Legendre partial sums; the cap
 // rings' Z slots (2 N (N - 1) complex values) use it first.
 static int64_t part_doubles(int64_t nside, int64_t lmax) {
@@ -813,15 +953,17 @@ static int64_t part_doubles(int64_t nside, int64_t lmax) {
   return 2 * nblk * size > zs ? 2 * nblk * size : zs;
 }
 
+// Scratch needs of map2alm at (nside, lmax): bytes of the Fourier table,
+// the ring geometry, the recursion coefficients, the block partials and the
+// small tables.
 size_t map2alm_scratch_bytes(int64_t nside, int64_t lmax) {
   const int64_t M = lmax + 1;
   const int64_t nring = 4 * nside - 1, npair = 2 * nside;
   const int64_t size = (lmax + 1) * (lmax + 2) / 2;
-  return sizeof(double) * (size_t)(2 * nring * M) + sizeof(double) * (size_t)(M * npair) +
-         sizeof(int32_t) * (size_t)(M * npair) + sizeof(double) * (size_t)npair +
+  return sizeof(double) * (size_t)(2 * nring * M) + sizeof(double) * (size_t)(2 * npair) +
          sizeof(double) * (size_t)(2 * size) + sizeof(double) * (size_t)part_doubles(nside, lmax) +
-         sizeof(double) * (size_t)(2 * (4 * nside + 1)) + sizeof(double) * (size_t)kCapMaxP +
-         sizeof(double) * (size_t)M + 9 * 256;
+         sizeof(double) * (size_t)(2 * (4 * nside + 1)) + sizeof(double) * (size_t)(2 * kCapMaxP) +
+         sizeof(double) * (size_t)M + 8 * 256;
 }
 
 // All of map2alm on `st`; `scratch` holds map2alm_scratch_bytes(nside, lmax).
@@ -835,12 +977,9 @@ hipError_t launch_map2alm(int64_t nside, int64_t lmax, const double* map, double
   char* p = (char*)scratch;
   double* F = (double*)p;
   p += align(sizeof(double) * (size_t)(2 * nring * M));
-  double* lam_v = (double*)p;
-  p += align(sizeof(double) * (size_t)(M * npair));
-  int32_t* lam_e = (int32_t*)p;
-  p += align(sizeof(int32_t) * (size_t)(M * npair));
   double* ring_z = (double*)p;
-  p += align(sizeof(double) * (size_t)npair);
+  double* ring_s = ring_z + npair;
+  p += align(sizeof(double) * (size_t)(2 * npair));
   double* coef = (double*)p;
   p += align(sizeof(double) * (size_t)(2 * size));
   double* part = (double*)p;
@@ -848,8 +987,8 @@ hipError_t launch_map2alm(int64_t nside, int64_t lmax, const double* map, double
   double* tab = (double*)p;
   p += align(sizeof(double) * (size_t)(2 * (4 * nside + 1)));
   double* ctab = (double*)p;
-  p += align(sizeof(double) * (size_t)kCapMaxP);
-  double* mm_fac = (double*)p;
+  p += align(sizeof(double) * (size_t)(2 * kCapMaxP));
+  double* gain = (double*)p;
   const int64_t mblocks = (lmax + 64) / 64;
   // Belt rings by FFT when their length 4N is a power of two whose half
   // fits the LDS buffer; cap rings by the chirp transform when their
@@ -865,7 +1004,7 @@ hipError_t launch_map2alm(int64_t nside, int64_t lmax, const double* map, double
   if (caps) {
     int64_t P = 1;
     while (P < 2 * (nside - 1) - 1) P <<= 1;
-    k_cap_table<<<dim3((unsigned)((kCapMaxP / 2 + 255) / 256)), dim3(256), 0, st>>>(ctab);
+    k_cap_table<<<dim3((unsigned)((kCapMaxP + 255) / 256)), dim3(256), 0, st>>>(ctab);
     k_cap_bluestein<<<dim3((unsigned)(nside - 1)), dim3(kCapThreads),
                       sizeof(double) * 2 * (size_t)P, st>>>(nside, lmax, map, ctab, part, F);
   }
@@ -879,14 +1018,13 @@ hipError_t launch_map2alm(int64_t nside, int64_t lmax, const double* map, double
     k_ring_dft<<<dim3((unsigned)((dft_waves + 3) / 4)), dim3(256), 0, st>>>(nside, lmax, map, F,
                                                                            lo, hi);
   }
-  k_mm_factor<<<dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st>>>(lmax, mm_fac);
-  k_lambda_mm<<<dim3((unsigned)((npair + 255) / 256)), dim3(256), 0, st>>>(nside, lmax, mm_fac,
-                                                                          lam_v, lam_e, ring_z);
+  k_mm_gain<<<dim3(1), dim3(256), 0, st>>>(lmax, gain);
+  k_ring_zs<<<dim3((unsigned)((npair + 255) / 256)), dim3(256), 0, st>>>(nside, ring_z, ring_s);
   k_leg_coef<<<dim3((unsigned)((M + 255) / 256), (unsigned)M), dim3(256), 0, st>>>(lmax, coef);
   k_leg_scan<<<dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st>>>(lmax, coef);
   const int64_t leg_waves = M * nblk;
   k_legendre<<<dim3((unsigned)((leg_waves + 3) / 4)), dim3(256), 0, st>>>(
-      nside, lmax, lmax, F, lam_v, lam_e, ring_z, coef, nblk, part);
+      nside, lmax, lmax, F, gain, ring_z, ring_s, coef, nblk, part);
   const double w = 4.0 * 3.14159265358979323846 / (double)(12 * nside * nside);
   k_alm_sum<<<dim3((unsigned)((size + 255) / 256)), dim3(256), 0, st>>>(size, nblk, w, part,
                                                                         coef, alm);

@@ -74,3 +74,44 @@ def grad_segment_errors(got, ref, absref):
         nd = np.linalg.norm(got[:, sl] - ref[:, sl], axis=1)
         out[name] = float(np.max(nd / np.maximum(nref + k * nabs, 1e-300))) if nd.size else 0.0
     return out
+
+
+def ring_sparse_alm(nside, lmax, hmap, rings):
+    """a_lm of a map that is zero outside `rings` (1-based RING ring
+    indices): (4 pi / Npix) sum_r lambda_lm(z_r) F_m(r), with the ring's
+    Fourier sums F_m(r) = sum_j x_j e^{-i m phi_j} taken from numpy's FFT of
+    the ring (phi_j = phi_0 + 2 pi j / L, phi_0 and z_r from the oracle's
+    pixel direction of the ring's first pixel) and lambda from the oracle."""
+    import oracle
+    N = nside
+    npix = 12 * N * N
+    size = oracle.alm_size(lmax)
+    mm = np.arange(lmax + 1)
+
+    def one_ring(r):
+        alm = np.zeros(size, dtype=np.complex128)
+        if r < N:
+            L, first = 4 * r, 2 * r * (r - 1)
+        elif r <= 3 * N:
+            L, first = 4 * N, 2 * N * (N - 1) + (r - N) * 4 * N
+        else:
+            k = 4 * N - r
+            L, first = 4 * k, npix - 2 * k * (k + 1)
+        x = hmap[first:first + L]
+        v = oracle.pix2vec(nside, np.array([first]))[0]
+        z, s, phi0 = v[2], float(np.hypot(v[0], v[1])), float(np.arctan2(v[1], v[0]))
+        X = np.fft.fft(x)
+        F = X[mm % L] * np.exp(-1j * mm * phi0)
+        for m in range(lmax + 1):
+            lam = oracle.lambda_lm(lmax, m, z, s)
+            i0 = oracle.alm_index(lmax, m, m)
+            alm[i0:i0 + lmax + 1 - m] = lam * F[m]
+        return alm
+
+    from concurrent.futures import ThreadPoolExecutor
+    total = np.zeros(size, dtype=np.complex128)
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        for part in ex.map(one_ring, rings):
+            total += part
+    return total * (4 * np.pi / npix)
+

@@ -67,7 +67,7 @@ def test_invalid_arguments_rejected_on_host():
     assert L.csmap_map2alm_noalloc(0, 0, fake, fake, None) == B.CSMAP_E_INVALID
     assert L.csmap_map2alm_noalloc(64, 257, fake, fake, None) == B.CSMAP_E_INVALID
     assert L.csmap_map2alm_noalloc(64, 8, None, fake, None) == B.CSMAP_E_INVALID
-    assert L.csmap_map2alm_noalloc(512, 1024, fake, fake, None) == B.CSMAP_E_INVALID
+    assert L.csmap_map2alm_noalloc(1024, 1024, fake, fake, None) == B.CSMAP_E_INVALID
     assert "scratch" in B.csmap_last_error()
     assert L.csmap_map2alm_noalloc(2048, 4096, fake, fake, None) == B.CSMAP_E_INVALID
 

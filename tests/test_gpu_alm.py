@@ -130,3 +130,36 @@ def test_full_size_grid_symmetries(B):
     # A white-noise map of unit variance has C_l close to 4 pi / Npix.
     cl = B.alm2cl(torch.from_numpy(a).cuda(), lmax).cpu().numpy()
     assert abs(np.mean(cl[2:]) / (4 * np.pi / npix) - 1) < 0.01
+
+
+def test_full_size_ring_sparse_map(B):
+    """Nside 2048, lmax 4096 on a map that is non-zero only on a few rings:
+    cap rings whose quarter-length transforms take every chirp-transform
+    size from 1 to 4096 points (i = 1, 2, 3, 5, 64, 65, 513, 1024, 1025,
+    2047 in the north cap, 1, 700, 2047 in the south) and two belt rings."""
+    nside, lmax = 2048, 4096
+    N = nside
+    npix = 12 * N * N
+    rings = [1, 2, 3, 5, 64, 65, 513, 1024, 1025, 2047, N, 2 * N + 1,
+             4 * N - 1, 4 * N - 700, 4 * N - 2047]
+    rng = np.random.default_rng(29)
+    hmap = np.zeros(npix)
+    ref_rings = []
+    for r in rings:
+        if r < N:
+            L, first = 4 * r, 2 * r * (r - 1)
+        elif r <= 3 * N:
+            L, first = 4 * N, 2 * N * (N - 1) + (r - N) * 4 * N
+        else:
+            k = 4 * N - r
+            L, first = 4 * k, npix - 2 * k * (k + 1)
+        hmap[first:first + L] = rng.standard_normal(L) + 0.2
+        ref_rings.append(r)
+    say("map2alm nside=2048 lmax=4096, ring-sparse map")
+    got = gpu_alm(B, hmap, lmax)
+    from helpers import ring_sparse_alm
+    ref = ring_sparse_alm(nside, lmax, hmap, ref_rings)
+    scale = np.max(np.abs(ref))
+    err = np.max(np.abs(got - ref)) / scale
+    say(f"  max |da| / max |a| = {err:.3e}")
+    assert err <= 1e-11

@@ -151,3 +151,15 @@ def test_alm2cl_definition():
         s = sum((1 if m == 0 else 2) * abs(a[oracle.alm_index(lmax, l, m)]) ** 2
                 for m in range(l + 1))
         assert abs(cl[l] - s / (2 * l + 1)) <= 1e-14 * s
+
+
+def test_ring_sparse_reference_matches_direct_sum():
+    """The ring-by-ring reference that the full-size GPU test uses (numpy FFT
+    of each ring times the oracle's lambda_lm) equals the oracle's direct
+    sum over pixels on a whole map, at every (l, m)."""
+    from helpers import ring_sparse_alm
+    nside, lmax = 8, 24
+    hmap = np.random.default_rng(31).standard_normal(12 * nside * nside)
+    ref = oracle.map2alm(nside, lmax, hmap)
+    got = ring_sparse_alm(nside, lmax, hmap, list(range(1, 4 * nside)))
+    assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))

@@ -34,7 +34,7 @@ def _map(nside, seed):
 def test_noalloc_map2alm_equals_map2alm_on_two_calls(B):
     # The larger case first, so the second call runs on scratch that still
     # holds the first call's values.
-    for nside, lmax, seed in ((512, 512, 1), (64, 100, 2)):
+    for nside, lmax, seed in ((512, 1024, 1), (64, 100, 2)):
         say(f"map2alm_noalloc nside={nside} lmax={lmax}")
         m = _map(nside, seed)
         ref = torch.view_as_real(B.map2alm(m, lmax)).contiguous().view(-1)
@@ -48,7 +48,7 @@ def test_noalloc_map2alm_equals_map2alm_on_two_calls(B):
 
 
 def test_noalloc_map2alm_refuses_oversized_scratch(B):
-    m = _map(512, 3)
+    m = _map(1024, 3)
     out = torch.empty(2 * B.alm_size(1024), dtype=torch.float64, device="cuda")
     with pytest.raises(B.CsmapError):
         B.map2alm_noalloc(m, 1024, out)
