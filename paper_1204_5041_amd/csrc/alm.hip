@@ -771,10 +771,41 @@ __global__ void __launch_bounds__(256) k_legendre(int64_t nside, int64_t lmax, i
                        __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (wave >= (mmax + 1) * nblk) return;
   const int64_t m = wave / nblk;
-  const int64_t blk = wave % nblk;
+  // Blocks rotate with m: workgroups go to the XCDs in turn, and with a
+  // fixed block per wave slot every XCD would always get the same blocks
+  // (polar or equatorial), whose work differs once negligible terms are
+  // skipped.
+  const int64_t blk = (wave % nblk + m) % nblk;
   const int64_t npair = 2 * nside;
   const int64_t nring = 4 * nside - 1;
   const int64_t M = mmax + 1;
+  double* out = part + 2 * blk * ((lmax + 1) * (lmax + 2) / 2);
+  // Degree and table indices in 32 bits (2 (lmax + 1)(lmax + 2) / 2 < 2^31
+  // for lmax <= 32768), so that the loop's bounds and clamps stay on the
+  // scalar unit, which has no 64-bit ordered compare.
+  const int row = (int)(alm_idx(lmax, m, m) - m);   // idx(l, m) = row + l
+  const int L = (int)lmax;
+  const int v = lane >> 2;   // value a lane holds after the group reduction
+  // A block whose every term stays below 2^-403 up to lmax writes zeros.
+  // |lambda_lm(cos theta)| <= sqrt((2l+1)/(4 pi)) sin^m(theta)
+  //     sqrt((l+m)!/(l-m)!) / (2^m m!),
+  // from |P_l^(m)(x)| <= P_l^(m)(1) = (l+m)! / (2^m m! (l-m)!) on [-1, 1]
+  // (the m-th derivative of P_l is a Gegenbauer polynomial of positive
+  // index, largest at 1).  The bound grows with l and with sin(theta), so
+  // its value at lmax on the block's most equatorial ring bounds the block.
+  {
+    const int64_t qe = min((blk + 1) * 64 * kRingsPerLane, npair) - 1;
+    const double md = (double)m, Ld = (double)lmax;
+    const double lg = 0.5 * log2((2.0 * Ld + 1.0) / (4.0 * 3.14159265358979323846)) +
+                      md * log2(ring_s[qe]) +
+                      (0.5 * (lgamma(Ld + md + 1.0) - lgamma(Ld - md + 1.0)) - lgamma(md + 1.0)) *
+                          1.44269504088896340736 - md;
+    if (__builtin_amdgcn_readfirstlane((int)(lg < -403.0))) {
+      for (int l0 = (int)m; l0 <= L; l0 += 8)
+        if ((lane & 3) == 0 && l0 + (v >> 1) <= L) out[2 * (row + l0) + v] = 0.0;
+      return;
+    }
+  }
   double z[kRingsPerLane], cur[kRingsPerLane], prev[kRingsPerLane];
   double er[kRingsPerLane], ei[kRingsPerLane], orr[kRingsPerLane], oi[kRingsPerLane];
   int32_t sc[kRingsPerLane];
@@ -827,16 +858,10 @@ __global__ void __launch_bounds__(256) k_legendre(int64_t nside, int64_t lmax, i
     factors(k);
   }
   const double big = ldexp(1.0, kLegScale);
-  double* out = part + 2 * blk * ((lmax + 1) * (lmax + 2) / 2);
   cdp cf = (cdp)coef;
   // Recursion coefficients a_l of degrees l0 .. l0 + 7, the next group's
   // requested one group ahead.  Degrees past lmax take lmax's: their steps
   // run (every group is eight steps) but their sums are not written.
-  // Degree and table indices in 32 bits (2 (lmax + 1)(lmax + 2) / 2 < 2^31
-  // for lmax <= 32768), so that the loop's bounds and clamps stay on the
-  // scalar unit, which has no 64-bit ordered compare.
-  const int row = (int)(alm_idx(lmax, m, m) - m);   // idx(l, m) = row + l
-  const int L = (int)lmax;
   double cA[8];
 #pragma unroll
   for (int g = 0; g < 8; ++g) cA[g] = cf[2 * (row + min((int)m + g, L))];
@@ -844,37 +869,38 @@ __global__ void __launch_bounds__(256) k_legendre(int64_t nside, int64_t lmax, i
   // first use of it waits on every vector memory operation in flight, the
   // previous group's store included, in every iteration.
   __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+  // Bring scaled values back once they have grown, every 32 degrees: with
+  // |z| <= 1, max(|mu_l|, |mu_{l-1}|) grows by at most |a_l| + 1 per step,
+  // which over any 32 consecutive degrees is below 2^200 for every
+  // m <= l <= 32768, far inside the 2^424 between the 2^600 threshold and
+  // the double range.  One wavefront-wide test skips the whole block when
+  // no lane needs it.
+  auto rescale = [&]() {
+    bool need[kRingsPerLane];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < kRingsPerLane; ++k) {
+      need[k] = sc[k] < 0 && fmax(fabs(cur[k]), fabs(prev[k])) > big;
+      any |= need[k];
+    }
+    if (__builtin_amdgcn_ballot_w64(any)) {
+#pragma unroll
+      for (int k = 0; k < kRingsPerLane; ++k) {
+        if (need[k]) {
+          cur[k] = ldexp(cur[k], -kLegScale);
+          prev[k] = ldexp(prev[k], -kLegScale);
+          sc[k] += 1;
+          factors(k);
+        }
+      }
+    }
+  };
   for (int l0 = (int)m; l0 <= L; l0 += 8) {
     double nA[8];
 #pragma unroll
     for (int g = 0; g < 8; ++g) nA[g] = cf[2 * (row + min(l0 + 8 + g, L))];
     __builtin_amdgcn_sched_barrier(0);    // issue the requests before the arithmetic
-    // Bring scaled values back once they have grown, every 32 degrees: with
-    // |z| <= 1, max(|mu_l|, |mu_{l-1}|) grows by at most |a_l| + 1 per step,
-    // which over any 32 consecutive degrees is below 2^200 for every
-    // m <= l <= 32768, far inside the 2^424 between the 2^600 threshold and
-    // the double range.  One wavefront-wide test skips the whole block when
-    // no lane needs it.
-    if (((l0 - (int)m) & 31) == 0) {
-      bool need[kRingsPerLane];
-      bool any = false;
-#pragma unroll
-      for (int k = 0; k < kRingsPerLane; ++k) {
-        need[k] = sc[k] < 0 && fmax(fabs(cur[k]), fabs(prev[k])) > big;
-        any |= need[k];
-      }
-      if (__builtin_amdgcn_ballot_w64(any)) {
-#pragma unroll
-        for (int k = 0; k < kRingsPerLane; ++k) {
-          if (need[k]) {
-            cur[k] = ldexp(cur[k], -kLegScale);
-            prev[k] = ldexp(prev[k], -kLegScale);
-            sc[k] += 1;
-            factors(k);
-          }
-        }
-      }
-    }
+    if (((l0 - (int)m) & 31) == 0) rescale();
     double acc[16];
 #pragma unroll
     for (int g = 0; g < 16; ++g) acc[g] = 0.0;
@@ -901,7 +927,7 @@ __global__ void __launch_bounds__(256) k_legendre(int64_t nside, int64_t lmax, i
       }
     }
     const double tot = wave_sum16(acc);
-    const int v = lane >> 2;   // value held: real (even) or imaginary (odd) part of degree l0 + v/2
+    // v: the real (even) or imaginary (odd) part of degree l0 + v/2
     if ((lane & 3) == 0 && l0 + (v >> 1) <= L) out[2 * (row + l0) + v] = tot;
 #pragma unroll
     for (int g = 0; g < 8; ++g) cA[g] = nA[g];

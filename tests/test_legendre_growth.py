@@ -1,7 +1,8 @@
-"""Overflow margin of the Legendre kernel's scaled recursion (k_legendre in
-csrc/alm.hip).
+"""Bounds the Legendre kernel (k_legendre in csrc/alm.hip) relies on: the
+overflow margin of its scaled recursion and the bound with which it drops
+whole blocks of negligible terms.
 
-The kernel runs mu_l = (a_l z) mu_{l-1} + mu_{l-2}, a_l = A_l c_{l-1} / c_l,
+Overflow margin.  The kernel runs mu_l = (a_l z) mu_{l-1} + mu_{l-2}, a_l = A_l c_{l-1} / c_l,
 c_m = c_{m+1} = 1, c_l = -A_l B_l c_{l-2}, with A_l and B_l the coefficients
 of the normalised associated Legendre recursion (lambda_l = c_l mu_l).  A
 ring whose lambda_mm lies below 2^-600 carries its values as v * 2^(600 e)
@@ -65,3 +66,25 @@ def test_growth_bound_is_attained_by_the_first_steps():
     lo = _worst(4096, range(0, 2049))
     hi = _worst(4096, range(4000, 4097))
     assert lo < hi
+
+
+
+def test_gegenbauer_bound_on_oracle_lambda():
+    """|lambda_lm(cos theta)| <= sqrt((2l+1)/4pi) sin^m sqrt((l+m)!/(l-m)!) /
+    (2^m m!), the bound with which the Legendre kernel drops whole blocks,
+    holds on the oracle's lambda_lm (log2, 1e-9 slack) over a grid of m and
+    theta, at every degree up to lmax = 1024."""
+    import math
+    import oracle
+    L = 1024
+    for m in (0, 1, 5, 50, 300, 700, 1000):
+        for th in (1e-3, 0.05, 0.3, 0.7, 1.2, 1.5707963267948966):
+            s, z = math.sin(th), math.cos(th)
+            lam = oracle.lambda_lm(L, m, z, s)
+            l = np.arange(m, L + 1, dtype=np.float64)
+            lg = (0.5 * np.log2((2 * l + 1) / (4 * math.pi)) + m * math.log2(s) +
+                  (0.5 * (np.array([math.lgamma(x + m + 1) - math.lgamma(x - m + 1) for x in l]))
+                   - math.lgamma(m + 1)) / math.log(2) - m)
+            nz = lam != 0
+            assert np.all(np.log2(np.abs(lam[nz])) <= lg[nz] + 1e-9), (m, th)
+
