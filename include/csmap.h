@@ -140,7 +140,7 @@ typedef enum {
      * (p/q + m/d = (p d + m q)/(q d)) and divided once. */
     CSMAP_OPT_ACCUM = 7,
     /* How pixels are grouped into the tiles that wavefronts own:
-     *   0 = automatic (1 when every box sees every pixel, else 2);
+     *   0 = automatic (ring blocks, 2);
      *   1 = strips of 64 x (pixels per lane) consecutive RING pixels;
      *   2 = ring blocks: G consecutive rings (CSMAP_OPT_BLOCK_RINGS) x up to
      *       64 x (pixels per lane) / G consecutive pixels per ring,
