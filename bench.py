@@ -881,8 +881,11 @@ def measured_valu(kernel, kernel_ms):
 
 # Sources each counted kernel is built from (its record holds their SHA-256).
 VALU_SOURCES = {
+    # The kernel sources, and the host code that chooses its launch (tiling,
+    # tile plan), which changes what the counters see.
     "k_fwd32": ["paper_1204_5041_amd/csrc/kernels.hip", "paper_1204_5041_amd/csrc/segment_dev.h",
-                "paper_1204_5041_amd/csrc/internal.h", "paper_1204_5041_amd/csrc/healpix_dev.h"],
+                "paper_1204_5041_amd/csrc/internal.h", "paper_1204_5041_amd/csrc/healpix_dev.h",
+                "paper_1204_5041_amd/csrc/api.cpp", "paper_1204_5041_amd/csrc/sched.cpp"],
     "k_legendre": ["paper_1204_5041_amd/csrc/alm.hip", "paper_1204_5041_amd/csrc/healpix_dev.h"],
     "k_valu_probe": ["paper_1204_5041_amd/csrc/probe.hip"],
 }
