@@ -105,7 +105,7 @@ def main():
     ap.add_argument("--cpu-pixels", type=int, default=40000)
     ap.add_argument("--workload", default="config2",
                     choices=["config2", "config3", "config4", "events", "alm", "stack", "flat",
-                             "counters"],
+                             "counters", "hbm"],
                     help="config2: the headline Nside=2048 line (default); config3: the "
                          "batched uneven 256-box Nside=4096 sky; config4: forward + adjoint at "
                          "Nside=1024; events: light-cone event recording from slab-start "
@@ -116,7 +116,8 @@ def main():
                          "flat-sky small-angle map of a 7.2 degree 1024^2 patch from 2M "
                          "segments; counters: one launch each of a known-FMA probe (FP32, "
                          "FP64), the bench step's k_fwd32 and k_fwd64, the config4 adjoint "
-                         "and map2alm, for hardware counter runs")
+                         "and map2alm, for hardware counter runs; hbm: the streaming rate of "
+                         "a plain device copy, the yardstick for the HBM-bound kernels")
     ap.add_argument("--stack-seg", type=int, default=200_000,
                     help="stack: segments per simulation run")
     ap.add_argument("--count-scale", type=float, default=1.0,
@@ -165,6 +166,8 @@ def main():
         return bench_flat(args, B, torch)
     if args.workload == "counters":
         return bench_counters(args, B, torch)
+    if args.workload == "hbm":
+        return bench_hbm(args, torch)
 
     W, K = args.warmup, args.steps
     _log(f"bench: generating {W + K} boxes of {args.nseg:,} segments")
@@ -984,6 +987,29 @@ def summarize_counters(trace_dir, pmc_a, pmc_b, launches_json):
             k["hw_flop_per_pair"] = (f32 + f64) / p
         rec["kernels"][key] = k
     return rec
+
+
+def bench_hbm(args, torch):
+    """The rate a plain device copy streams at (1 GiB read and 1 GiB written
+    per copy, 20 back-to-back copies between HIP events): what an HBM-bound
+    kernel can reach in practice, against the 8 TB/s of the specification."""
+    n = 1 << 28
+    x = torch.empty(n, dtype=torch.float32, device="cuda").normal_()
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 20 / 1e3
+    gbs = 2 * 4 * n / s / 1e9
+    print(json.dumps({"metric": "device copy rate (read + write)", "value": gbs, "unit": "GB/s",
+                      "bytes_per_copy": 2 * 4 * n, "ms_per_copy": s * 1e3,
+                      "frac_of_8000": gbs / 8000.0}), flush=True)
 
 
 def bench_counters(args, B, torch):
