@@ -371,8 +371,9 @@ csmap_status csmap_get_stats(csmap_sky *sky, csmap_stats *out);
  * tiles spread evenly over the sky (about 25M pixels, each tile limited to
  * the first 2,048 segments of every box it sees).  First the launch shape
  * (pixels per lane, wavefronts per workgroup, accumulation mode; persistent
- * schedule); then, from the best shape, one setting at a time: the tiling
- * and rings per ring-block tile (skies with visibility rules), the FP32
+ * schedule), the shapes within 3% of the best measured again on 8,192
+ * segments per box and tile; then, from the best shape, one setting at a
+ * time: the tiling and rings per ring-block tile, the FP32
  * partial-sum length before each compensated update (16, 32 or 64; FP32C),
  * and the pair-form thresholds among those at least as accurate as the
  * defaults (CSMAP_OPT_FAR_W >= 5e-3, CSMAP_OPT_NEAR_W >= 5e-5), so tuning
