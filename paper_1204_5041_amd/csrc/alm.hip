@@ -146,136 +146,54 @@ __global__ void __launch_bounds__(256) k_ring_dft(int64_t nside, int64_t mmax, c
   }
 }
 
-// Step 1 for the 2N + 1 belt rings when Nside is a power of two: every belt
-// ring has L = 4N pixels, so its Fourier sums are one length-L DFT of real
-// data.  It is taken as a complex FFT of half length H = L/2 on
-// z_n = x_{2n} + i x_{2n+1} (radix 2, decimation in time from a bit-reversed
-// load, in LDS), then unpacked: with E_k = (Z_k + conj Z_{H-k})/2 and
-// O_k = (Z_k - conj Z_{H-k})/(2i), X_k = E_k + e^{-2 pi i k/L} O_k for
-// 0 <= k <= H and X_k = conj X_{L-k} above.  F_m = X_{m mod L}, times
-// e^{-i pi m/L} on rings with the half-pixel offset.  tab[k] = e^{-i pi k/L},
-// k = 0 .. L, holds every twiddle (e^{-2 pi i j/H} is entry 4j).  One
-// workgroup per ring.
-constexpr int kFftThreads = 512;
-constexpr int64_t kFftMaxH = 4096;   // 64 KB of LDS: H <= 4096, Nside <= 2048
-
-__global__ void k_fft_table(int64_t L, double* tab) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k > L) return;
-  double sp, cp;
-  sincospi((double)k / (double)L, &sp, &cp);
-  tab[2 * k] = cp;
-  tab[2 * k + 1] = -sp;
-}
-
-__global__ void __launch_bounds__(kFftThreads) k_ring_fft(int64_t nside, int64_t mmax,
-                                                          const double* map, const double* tab,
-                                                          double* F) {
-  extern __shared__ double zs[];   // H complex values, (re, im) interleaved
-  const int64_t i = nside + blockIdx.x;
-  const Ring r = ring_of(nside, i);
-  const int64_t L = r.len, H = L / 2;
-  const int bits = __builtin_ctzll((unsigned long long)H);
-  const double* x = map + r.first;
-  for (int64_t n = threadIdx.x; n < H; n += blockDim.x) {
-    const int64_t d = bits ? (int64_t)(__brev((unsigned)n) >> (32 - bits)) : 0;
-    zs[2 * d] = x[2 * n];
-    zs[2 * d + 1] = x[2 * n + 1];
-  }
-  __syncthreads();
-  for (int64_t half = 1; half < H; half <<= 1) {
-    const int64_t tstride = 4 * (H / (2 * half));
-    for (int64_t b = threadIdx.x; b < H / 2; b += blockDim.x) {
-      const int64_t pos = b & (half - 1);
-      const int64_t i0 = 2 * (b - pos) + pos, i1 = i0 + half;
-      const double wc = tab[2 * pos * tstride], ws = tab[2 * pos * tstride + 1];
-      const double br = zs[2 * i1], bi = zs[2 * i1 + 1];
-      const double tr = fma(br, wc, -(bi * ws)), ti = fma(br, ws, bi * wc);
-      const double ar = zs[2 * i0], ai = zs[2 * i0 + 1];
-      zs[2 * i0] = ar + tr;
-      zs[2 * i0 + 1] = ai + ti;
-      zs[2 * i1] = ar - tr;
-      zs[2 * i1 + 1] = ai - ti;
-    }
-    __syncthreads();
-  }
-  double* out = F + 2 * (i - 1) * (mmax + 1);
-  for (int64_t m = threadIdx.x; m <= mmax; m += blockDim.x) {
-    int64_t k = m % L;
-    const bool upper = k > H;
-    if (upper) k = L - k;
-    const int64_t ka = (k == H) ? 0 : k, kb = (H - k) % H;
-    const double zr = zs[2 * ka], zi = zs[2 * ka + 1];
-    const double cr = zs[2 * kb], ci = -zs[2 * kb + 1];        // conj Z_{H-k}
-    const double er = 0.5 * (zr + cr), ei = 0.5 * (zi + ci);
-    const double orr = 0.5 * (zi - ci), oi = -0.5 * (zr - cr);  // (Z - conj)/(2i)
-    const double wc = tab[4 * k], ws = tab[4 * k + 1];          // e^{-2 pi i k/L}
-    double xr = er + fma(wc, orr, -(ws * oi));
-    double xi = ei + fma(wc, oi, ws * orr);
-    if (upper) xi = -xi;
-    if (r.half) {
-      const double hc = tab[2 * m], hs = tab[2 * m + 1];        // e^{-i pi m/L}
-      const double yr = fma(xr, hc, -(xi * hs)), yi = fma(xr, hs, xi * hc);
-      xr = yr;
-      xi = yi;
-    }
-    out[2 * m] = xr;
-    out[2 * m + 1] = xi;
-  }
-}
-
-// Step 1 for the polar-cap rings (Nside <= 2048).  North ring i and south
-// ring 4N - i both have L = 4i pixels at azimuths 2 pi (j + 1/2)/L; they are
-// taken together as z_j = x^N_j + i x^S_j, whose DFT Z gives both:
-// X^N_k = (Z_k + conj Z_{L-k})/2, X^S_k = (Z_k - conj Z_{L-k})/(2i), and
-// F_m = e^{-i pi m/L} X_{m mod L}.  L = 4i is split by four (j = 4n + r):
-// Z_{kappa + s i} = sum_r (-i)^{rs} e^{-2 pi i r kappa/L} D_r(kappa), D_r the
-// length-i DFT of z_{4n+r}.  i is arbitrary, so each D_r is taken by
-// Bluestein's chirp transform: with w_n = e^{-i pi n^2/i} (from n^2 mod 2i,
-// exact), D(kappa) = w_kappa sum_n (y_n w_n) conj(w_{kappa-n}), a linear
-// convolution computed as a cyclic one of power-of-two length P >= 2i - 1.
-// The convolution's transforms run in LDS in radix-8 passes (one radix-2
-// or radix-4 pass when log2 P is not a multiple of 3), each thread taking
-// one 8-point butterfly in registers per pass: forward by decimation in
-// frequency (natural order in, digit-reversed out), the product with the
-// chirp filter's transform in that order, inverse by decimation in time
-// with the passes reversed (digit-reversed in, natural out), so no
-// reordering pass is needed.  The filter's transform stays in registers
-// over the four D_r, and D_r stays in registers until the radix-4 step; Z
-// goes through a global slot of 4i values before the unpacking, which pairs
-// k with L - k.  One workgroup per ring pair; ctab[k] = e^{-2 pi i k/kCapMaxP},
-// k < kCapMaxP.
-constexpr int kCapThreads = 512;
-constexpr int64_t kCapMaxP = 4096;                     // 64 KB of LDS: i <= 2048, Nside <= 2049
-constexpr int kCapPer = (int)(kCapMaxP / kCapThreads);  // transform positions per thread
-constexpr int kCapKappa = kCapPer / 2;                  // D_r values per thread (i <= kCapMaxP / 2)
-
-__global__ void k_cap_table(double* ctab) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= kCapMaxP) return;
-  double sp, cp;
-  sincospi((double)(2 * k) / (double)kCapMaxP, &sp, &cp);
-  ctab[2 * k] = cp;
-  ctab[2 * k + 1] = -sp;
-}
-
-__device__ __forceinline__ int64_t pow2_at_least(int64_t v) {
-  int64_t p = 1;
-  while (p < v) p <<= 1;
-  return p;
-}
-
-// w_n = e^{-i pi n^2 / len}.
-__device__ __forceinline__ void chirp(int64_t n, int64_t len, double& c, double& s) {
-  double sp, cp;
-  sincospi((double)((n * n) % (2 * len)) / (double)len, &sp, &cp);
-  c = cp;
-  s = -sp;
-}
-
 struct cplx {
   double r, i;
 };
+
+// The ring transforms of step 1 share one FFT over P = 2^e <= kFftMaxP
+// complex points in LDS, taken by a workgroup of kFftThreads threads in
+// radix-8 passes (one radix-2 or radix-4 pass when e is not a multiple of
+// 3), each thread taking one butterfly in registers per pass: forward by
+// decimation in frequency (natural order in, digit-reversed order out),
+// inverse by decimation in time with the passes reversed (digit-reversed
+// order in, natural order out), so no reordering pass is needed.  With
+// kSwz, point j lives at complex slot j ^ ((j >> 3) & 15): bits 3-6 of the
+// index are folded into bits 0-3, so that in every radix-8 pass the lanes
+// of an aligned group of 8 or 16 read and write 16-byte slots in distinct
+// LDS banks (stored in order, the lanes of the passes whose butterflies
+// take points 1, 2, 4 or 8 apart meet in the same banks: lane b reads
+// point 8b + q in the last forward pass, 128 bytes from its neighbours).
+// Only a final radix-2 or radix-4 pass keeps a two-way conflict within 16
+// lanes.  The fold leaves bits 4 and above alone, so a slot stays below P.
+// It costs an address computation per access, which pays where LDS bounds
+// the kernel (the belt rings) and not where latency does (the cap rings,
+// whose nine transforms per workgroup run at the same speed either way).
+// ftab[k] = e^{-2 pi i k/kFftMaxP}, k < kFftMaxP, holds every twiddle.
+constexpr int kFftThreads = 512;
+constexpr int64_t kFftMaxP = 4096;   // 64 KB of LDS
+
+template <bool kSwz>
+__device__ __forceinline__ int fft_slot(int j) { return kSwz ? j ^ ((j >> 3) & 15) : j; }
+
+// Point j of the transform in LDS, read and written as one 16-byte access.
+template <bool kSwz>
+__device__ __forceinline__ cplx fft_get(const double* x, int j) {
+  const double2 u = reinterpret_cast<const double2*>(x)[fft_slot<kSwz>(j)];
+  return {u.x, u.y};
+}
+template <bool kSwz>
+__device__ __forceinline__ void fft_put(double* x, int j, cplx v) {
+  reinterpret_cast<double2*>(x)[fft_slot<kSwz>(j)] = make_double2(v.r, v.i);
+}
+
+__global__ void k_fft_twiddles(double* ftab) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= kFftMaxP) return;
+  double sp, cp;
+  sincospi((double)(2 * k) / (double)kFftMaxP, &sp, &cp);
+  ftab[2 * k] = cp;
+  ftab[2 * k + 1] = -sp;
+}
 
 __device__ __forceinline__ cplx cadd(cplx a, cplx b) { return {a.r + b.r, a.i + b.i}; }
 __device__ __forceinline__ cplx csub(cplx a, cplx b) { return {a.r - b.r, a.i - b.i}; }
@@ -334,67 +252,167 @@ __device__ __forceinline__ void dft_small(cplx* x) {
 // y_q' = e^{-2 pi i p q'/S} sum_q x_{p + q h} e^{-2 pi i q q'/R}, written at
 // p + q' h.  The inverse pass undoes it up to a factor R: twiddles
 // conjugated and applied first, then the inverse R-point DFT.
-template <int R, bool kInv>
-__device__ __forceinline__ void fft_pass(double* x, int P, int S, const double* ctab) {
+template <int R, bool kInv, bool kSwz>
+__device__ __forceinline__ void fft_pass(double* x, int P, int S, const double* ftab) {
   const int h = S / R;
-  const int tw = (int)kCapMaxP / S;   // table step of e^{-2 pi i/S}
-  for (int b = threadIdx.x; b < P / R; b += kCapThreads) {
-    const int pos = b % h;
+  const int tw = (int)kFftMaxP / S;   // table step of e^{-2 pi i/S}
+  for (int b = threadIdx.x; b < P / R; b += kFftThreads) {
+    const int pos = b & (h - 1);
     const int base = (b - pos) * R + pos;
     cplx v[R];
 #pragma unroll
-    for (int q = 0; q < R; ++q) v[q] = {x[2 * (base + q * h)], x[2 * (base + q * h) + 1]};
+    for (int q = 0; q < R; ++q) v[q] = fft_get<kSwz>(x, base + q * h);
     if constexpr (!kInv) dft_small<R, false>(v);
 #pragma unroll
     for (int q = 1; q < R; ++q) {
-      const int k = (pos * q * tw) & ((int)kCapMaxP - 1);
-      const cplx w = {ctab[2 * k], kInv ? -ctab[2 * k + 1] : ctab[2 * k + 1]};
+      const int k = (pos * q * tw) & ((int)kFftMaxP - 1);
+      const cplx w = {ftab[2 * k], kInv ? -ftab[2 * k + 1] : ftab[2 * k + 1]};
       v[q] = cmul(v[q], w);
     }
     if constexpr (kInv) dft_small<R, true>(v);
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      x[2 * (base + q * h)] = v[q].r;
-      x[2 * (base + q * h) + 1] = v[q].i;
-    }
+    for (int q = 0; q < R; ++q) fft_put<kSwz>(x, base + q * h, v[q]);
   }
   __syncthreads();
 }
 
-// Forward transform of P (a power of two <= kCapMaxP) values in LDS,
+// Forward transform of P (a power of two <= kFftMaxP) values in LDS,
 // natural order in, digit-reversed order out: radix-8 passes from the
 // widest span down, then one radix-4 or radix-2 pass if log2 P mod 3 is 2
 // or 1.
-__device__ void fft_dif(double* x, int P, const double* ctab) {
+template <bool kSwz>
+__device__ void fft_dif(double* x, int P, const double* ftab) {
   int S = P;
   while (S >= 8) {
-    fft_pass<8, false>(x, P, S, ctab);
+    fft_pass<8, false, kSwz>(x, P, S, ftab);
     S >>= 3;
   }
-  if (S == 4) fft_pass<4, false>(x, P, 4, ctab);
-  if (S == 2) fft_pass<2, false>(x, P, 2, ctab);
+  if (S == 4) fft_pass<4, false, kSwz>(x, P, 4, ftab);
+  if (S == 2) fft_pass<2, false, kSwz>(x, P, 2, ftab);
 }
 
 // Inverse of fft_dif times P: digit-reversed order in, natural order out,
 // the passes in reverse order.
-__device__ void fft_dit_inv(double* x, int P, const double* ctab) {
+template <bool kSwz>
+__device__ void fft_dit_inv(double* x, int P, const double* ftab) {
   int e = 0;
   while ((1 << e) < P) ++e;
   int S = 1 << (e % 3);
-  if (S == 4) fft_pass<4, true>(x, P, 4, ctab);
-  if (S == 2) fft_pass<2, true>(x, P, 2, ctab);
+  if (S == 4) fft_pass<4, true, kSwz>(x, P, 4, ftab);
+  if (S == 2) fft_pass<2, true, kSwz>(x, P, 2, ftab);
   while (S < P) {
     S <<= 3;
-    fft_pass<8, true>(x, P, S, ctab);
+    fft_pass<8, true, kSwz>(x, P, S, ftab);
   }
 }
 
-__global__ void __launch_bounds__(kCapThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
-k_cap_bluestein(int64_t nside, int64_t mmax,
-                                                               const double* map,
-                                                               const double* ctab, double* zslot,
-                                                               double* F) {
-  extern __shared__ double xs[];   // P complex values, (re, im) interleaved
+// Position of frequency k in fft_dif's output over 2^e points.  The pass of
+// span S and radix R sends the points whose frequencies are q' mod R to the
+// block at q' S/R, so the base-8 digits of k, least significant first,
+// become the digits of the position from the most significant down, and
+// the digit of a final radix-2 or radix-4 pass (k's top e mod 3 bits) ends
+// up lowest.
+__device__ __forceinline__ int dif_pos(int k, int e) {
+  int p = 0;
+  for (; e >= 3; e -= 3, k >>= 3) p |= (k & 7) << (e - 3);
+  return p | k;
+}
+
+// Step 1 for the 2N + 1 belt rings when Nside is a power of two: every belt
+// ring has L = 4N pixels, so its Fourier sums are one length-L DFT of real
+// data.  It is taken as a complex FFT of half length H = L/2 on
+// z_n = x_{2n} + i x_{2n+1} (natural order in, digit-reversed out), then
+// unpacked: with E_k = (Z_k + conj Z_{H-k})/2 and O_k = (Z_k - conj
+// Z_{H-k})/(2i), X_k = E_k + e^{-2 pi i k/L} O_k for 0 <= k <= H and
+// X_k = conj X_{L-k} above.  F_m = X_{m mod L}, times e^{-i pi m/L} on
+// rings with the half-pixel offset.  tab[k] = e^{-i pi k/L}, k = 0 .. L.
+// One workgroup per ring.
+constexpr int64_t kBeltMaxH = kFftMaxP;   // H <= 4096: Nside <= 2048
+
+__global__ void k_fft_table(int64_t L, double* tab) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > L) return;
+  double sp, cp;
+  sincospi((double)k / (double)L, &sp, &cp);
+  tab[2 * k] = cp;
+  tab[2 * k + 1] = -sp;
+}
+
+__global__ void __launch_bounds__(kFftThreads) k_ring_fft(int64_t nside, int64_t mmax,
+                                                          const double* map, const double* tab,
+                                                          const double* ftab, double* F) {
+  extern __shared__ double zs[];   // H complex values at fft_slot<true> positions
+  const int64_t i = nside + blockIdx.x;
+  const Ring r = ring_of(nside, i);
+  const int L = (int)r.len, H = L / 2;
+  const int e = __builtin_ctz((unsigned)H);
+  const double* x = map + r.first;
+  for (int n = threadIdx.x; n < H; n += kFftThreads) fft_put<true>(zs, n, {x[2 * n], x[2 * n + 1]});
+  __syncthreads();
+  fft_dif<true>(zs, H, ftab);
+  double* out = F + 2 * (i - 1) * (mmax + 1);
+  for (int m = threadIdx.x; m <= (int)mmax; m += kFftThreads) {
+    int k = (int)((unsigned)m % (unsigned)L);
+    const bool upper = k > H;
+    if (upper) k = L - k;
+    const int ka = (k == H) ? 0 : k, kb = (k == 0) ? 0 : H - k;
+    const cplx za = fft_get<true>(zs, dif_pos(ka, e)), zb = fft_get<true>(zs, dif_pos(kb, e));
+    const double zr = za.r, zi = za.i;
+    const double cr = zb.r, ci = -zb.i;                         // conj Z_{H-k}
+    const double er = 0.5 * (zr + cr), ei = 0.5 * (zi + ci);
+    const double orr = 0.5 * (zi - ci), oi = -0.5 * (zr - cr);  // (Z - conj)/(2i)
+    const double wc = tab[4 * k], ws = tab[4 * k + 1];          // e^{-2 pi i k/L}
+    double xr = er + fma(wc, orr, -(ws * oi));
+    double xi = ei + fma(wc, oi, ws * orr);
+    if (upper) xi = -xi;
+    if (r.half) {
+      const double hc = tab[2 * m], hs = tab[2 * m + 1];        // e^{-i pi m/L}
+      const double yr = fma(xr, hc, -(xi * hs)), yi = fma(xr, hs, xi * hc);
+      xr = yr;
+      xi = yi;
+    }
+    out[2 * m] = xr;
+    out[2 * m + 1] = xi;
+  }
+}
+
+// Step 1 for the polar-cap rings (Nside <= 2048).  North ring i and south
+// ring 4N - i both have L = 4i pixels at azimuths 2 pi (j + 1/2)/L; they are
+// taken together as z_j = x^N_j + i x^S_j, whose DFT Z gives both:
+// X^N_k = (Z_k + conj Z_{L-k})/2, X^S_k = (Z_k - conj Z_{L-k})/(2i), and
+// F_m = e^{-i pi m/L} X_{m mod L}.  L = 4i is split by four (j = 4n + r):
+// Z_{kappa + s i} = sum_r (-i)^{rs} e^{-2 pi i r kappa/L} D_r(kappa), D_r the
+// length-i DFT of z_{4n+r}.  i is arbitrary, so each D_r is taken by
+// Bluestein's chirp transform: with w_n = e^{-i pi n^2/i} (from n^2 mod 2i,
+// exact), D(kappa) = w_kappa sum_n (y_n w_n) conj(w_{kappa-n}), a linear
+// convolution computed as a cyclic one of power-of-two length P >= 2i - 1
+// by the shared FFT: the product with the chirp filter's transform is taken
+// in the forward transform's digit-reversed order, which the inverse reads.
+// The filter's transform stays in registers over the four D_r, and D_r
+// stays in registers until the radix-4 step; Z goes through a global slot
+// of 4i values before the unpacking, which pairs k with L - k.  One
+// workgroup per ring pair.
+constexpr int kCapPer = (int)(kFftMaxP / kFftThreads);  // transform positions per thread
+constexpr int kCapKappa = kCapPer / 2;                  // D_r values per thread (i <= kFftMaxP / 2)
+
+__device__ __forceinline__ int64_t pow2_at_least(int64_t v) {
+  int64_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// w_n = e^{-i pi n^2 / len}.
+__device__ __forceinline__ void chirp(int64_t n, int64_t len, double& c, double& s) {
+  double sp, cp;
+  sincospi((double)((n * n) % (2 * len)) / (double)len, &sp, &cp);
+  c = cp;
+  s = -sp;
+}
+
+__global__ void __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
+k_cap_bluestein(int64_t nside, int64_t mmax, const double* map, const double* ftab,
+                double* zslot, double* F) {
+  extern __shared__ double xs[];   // P complex values, in order
   const int t = threadIdx.x;
   const int64_t N = nside, i = 1 + blockIdx.x, L = 4 * i;
   const int P = (int)pow2_at_least(2 * i - 1);
@@ -402,7 +420,7 @@ k_cap_bluestein(int64_t nside, int64_t mmax,
   const double* xn = map + 2 * i * (i - 1);
   const double* xsth = map + 12 * N * N - 2 * i * (i + 1);
   // Chirp filter b_m = conj(w_m) at m mod P for |m| < i, then its transform.
-  for (int p = t; p < P; p += kCapThreads) {
+  for (int p = t; p < P; p += kFftThreads) {
     const int64_t n = p < i ? p : (p > P - i ? P - p : -1);
     double br = 0.0, bi = 0.0;
     if (n >= 0) {
@@ -411,27 +429,27 @@ k_cap_bluestein(int64_t nside, int64_t mmax,
       br = c;
       bi = -s;
     }
-    xs[2 * p] = br;
-    xs[2 * p + 1] = bi;
+    fft_put<false>(xs, p, {br, bi});
   }
   __syncthreads();
-  fft_dif(xs, P, ctab);
+  fft_dif<false>(xs, P, ftab);
   double Br[kCapPer], Bi[kCapPer];
 #pragma unroll
   for (int j = 0; j < kCapPer; ++j) {
-    const int p = t + j * kCapThreads;
-    Br[j] = p < P ? xs[2 * p] : 0.0;
-    Bi[j] = p < P ? xs[2 * p + 1] : 0.0;
+    const int p = t + j * kFftThreads;
+    const cplx b = p < P ? fft_get<false>(xs, p) : cplx{0.0, 0.0};
+    Br[j] = b.r;
+    Bi[j] = b.i;
   }
   __syncthreads();
   // The chirp w_n and the twist e^{-2 pi i n/L} at this thread's positions
-  // n = t + j * kCapThreads < i, shared by the four quarter-length DFTs:
+  // n = t + j * kFftThreads < i, shared by the four quarter-length DFTs:
   // the inputs y_n w_n, the outputs w_kappa (...) and the twist powers
   // e^{-2 pi i r kappa/L} = (e^{-2 pi i kappa/L})^r.
   double wc[kCapKappa], ws[kCapKappa], tc[kCapKappa], ts[kCapKappa];
 #pragma unroll
   for (int j = 0; j < kCapKappa; ++j) {
-    const int64_t n = t + (int64_t)j * kCapThreads;
+    const int64_t n = t + (int64_t)j * kFftThreads;
     wc[j] = ws[j] = tc[j] = ts[j] = 0.0;
     if (n < i) {
       chirp(n, i, wc[j], ws[j]);
@@ -449,7 +467,7 @@ k_cap_bluestein(int64_t nside, int64_t mmax,
   for (int r = 0; r < 4; ++r) {
 #pragma unroll
     for (int j = 0; j < kCapPer; ++j) {
-      const int p = t + j * kCapThreads;
+      const int p = t + j * kFftThreads;
       if (p < P) {
         double ar = 0.0, ai = 0.0;
         if (j < kCapKappa && p < i) {
@@ -457,28 +475,27 @@ k_cap_bluestein(int64_t nside, int64_t mmax,
           ar = fma(yr, wc[j], -(yi * ws[j]));
           ai = fma(yr, ws[j], yi * wc[j]);
         }
-        xs[2 * p] = ar;
-        xs[2 * p + 1] = ai;
+        fft_put<false>(xs, p, {ar, ai});
       }
     }
     __syncthreads();
-    fft_dif(xs, P, ctab);
+    fft_dif<false>(xs, P, ftab);
 #pragma unroll
     for (int j = 0; j < kCapPer; ++j) {
-      const int p = t + j * kCapThreads;
+      const int p = t + j * kFftThreads;
       if (p < P) {
-        const double ar = xs[2 * p], ai = xs[2 * p + 1];
-        xs[2 * p] = fma(ar, Br[j], -(ai * Bi[j]));
-        xs[2 * p + 1] = fma(ar, Bi[j], ai * Br[j]);
+        const cplx a = fft_get<false>(xs, p);
+        fft_put<false>(xs, p, {fma(a.r, Br[j], -(a.i * Bi[j])), fma(a.r, Bi[j], a.i * Br[j])});
       }
     }
     __syncthreads();
-    fft_dit_inv(xs, P, ctab);
+    fft_dit_inv<false>(xs, P, ftab);
 #pragma unroll
     for (int j = 0; j < kCapKappa; ++j) {
-      const int64_t kap = t + (int64_t)j * kCapThreads;
+      const int64_t kap = t + (int64_t)j * kFftThreads;
       if (kap < i) {
-        const double cr = xs[2 * kap] * inv_p, ci = xs[2 * kap + 1] * inv_p;
+        const cplx c = fft_get<false>(xs, (int)kap);
+        const double cr = c.r * inv_p, ci = c.i * inv_p;
         double dr = fma(cr, wc[j], -(ci * ws[j])), di = fma(cr, ws[j], ci * wc[j]);
         // times e^{-2 pi i r kappa / L}, r multiplications by the twist
 #pragma unroll
@@ -496,7 +513,7 @@ k_cap_bluestein(int64_t nside, int64_t mmax,
   // Radix-4 step: Z_{kappa + s i} = sum_r (-i)^{rs} E_r(kappa).
 #pragma unroll
   for (int j = 0; j < kCapKappa; ++j) {
-    const int64_t kap = t + (int64_t)j * kCapThreads;
+    const int64_t kap = t + (int64_t)j * kFftThreads;
     if (kap < i) {
       double Er[4], Ei[4];
 #pragma unroll
@@ -521,13 +538,14 @@ k_cap_bluestein(int64_t nside, int64_t mmax,
   __syncthreads();
   double* fn = F + 2 * (i - 1) * (mmax + 1);
   double* fs = F + 2 * (4 * N - i - 1) * (mmax + 1);
-  for (int64_t m = t; m <= mmax; m += kCapThreads) {
-    const int64_t k = m % L, k2 = (L - k) % L;
+  const int Li = (int)L;
+  for (int m = t; m <= (int)mmax; m += kFftThreads) {
+    const int k = (int)((unsigned)m % (unsigned)Li), k2 = k == 0 ? 0 : Li - k;
     const double zr = Z[2 * k], zi = Z[2 * k + 1], yr = Z[2 * k2], yi = Z[2 * k2 + 1];
     const double nr = 0.5 * (zr + yr), ni = 0.5 * (zi - yi);    // (Z_k + conj Z_{L-k}) / 2
     const double sr = 0.5 * (zi + yi), si = -0.5 * (zr - yr);   // (Z_k - conj Z_{L-k}) / (2i)
     double sp, cp;
-    sincospi((double)(m % (2 * L)) / (double)L, &sp, &cp);      // e^{-i pi m / L} = cp - i sp
+    sincospi((double)((unsigned)m % (unsigned)(2 * Li)) / (double)L, &sp, &cp);   // e^{-i pi m/L}
     fn[2 * m] = fma(nr, cp, ni * sp);
     fn[2 * m + 1] = fma(ni, cp, -(nr * sp));
     fs[2 * m] = fma(sr, cp, si * sp);
@@ -610,48 +628,38 @@ __device__ __forceinline__ void pow_scaled(double s, int m, double& mant, int& e
 // once per (l, m).  At l = m + 1 (B = 0) the step is mu_{m+1} =
 // sqrt(2m+3) z mu_m; at l = m, a_m = 0 takes (mu_{m-1}, mu_{m-2}) =
 // (0, lambda_mm) to mu_m = lambda_mm.
-// First pass, one thread per (l, m) (blockIdx.y is m): coef[2 i] = A_l and
-// coef[2 i + 1] = -A_l B_l at a_lm's position i (A = 0 and 1 at l = m,
-// A = sqrt(2m+3) and 1 at l = m + 1, so that c_m = c_{m+1} = 1).
-__global__ void k_leg_coef(int64_t lmax, double* coef) {
-  const int64_t m = blockIdx.y;
-  const int64_t l = m + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (l > lmax) return;
-  const int64_t i = alm_idx(lmax, l, m);
-  const double mmd = (double)m, ll = (double)l;
-  double A, g;
-  if (l == m) {
-    A = 0.0;
-    g = 1.0;
-  } else if (l == m + 1) {
-    A = sqrt(2.0 * mmd + 3.0);
-    g = 1.0;
-  } else {
-    A = sqrt((4.0 * ll * ll - 1.0) / (ll * ll - mmd * mmd));
-    const double B =
-        sqrt(((ll - 1.0) * (ll - 1.0) - mmd * mmd) / (4.0 * (ll - 1.0) * (ll - 1.0) - 1.0));
-    g = -(A * B);
-  }
-  coef[2 * i] = A;
-  coef[2 * i + 1] = g;
-}
-
-// Second pass, one wavefront per m: c_l as the product of g over l, l - 2,
-// ..., and a_l = A_l c_{l-1} / c_l, in place (coef[2 i] = a_l,
-// coef[2 i + 1] = c_l).  64 consecutive degrees at a time: a product scan
-// over the lanes of equal parity (strides 2 .. 32), times the last c of
-// that parity from the previous 64.
+// One wavefront per m: A_l and g_l = -A_l B_l for 64 consecutive degrees at
+// a time, one per lane (A = 0, g = 1 at l = m; A = sqrt(2m+3), g = 1 at
+// l = m + 1, so that c_m = c_{m+1} = 1), then c_l as the product of g over
+// l, l - 2, ... by a product scan over the lanes of equal parity (strides
+// 2 .. 32), times the last c of that parity from the previous 64, and
+// a_l = A_l c_{l-1} / c_l.  coef[2 i] = a_l, coef[2 i + 1] = c_l at a_lm's
+// position i.
 __global__ void __launch_bounds__(256) k_leg_scan(int64_t lmax, double* coef) {
   const int lane = threadIdx.x & 63;
   const int64_t m = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (m > lmax) return;
   const int64_t row = alm_idx(lmax, m, m) - m;   // idx(l, m) = row + l
+  const double mm = (double)m;
   double carry0 = 1.0, carry1 = 1.0;             // c_{base-2}, c_{base-1}
   for (int64_t base = m; base <= lmax; base += 64) {
     const int64_t l = base + lane;
     const bool in = l <= lmax;
-    const double A = in ? coef[2 * (row + l)] : 0.0;
-    double p = in ? coef[2 * (row + l) + 1] : 1.0;
+    const double ll = (double)l;
+    double A, p;
+    if (l == m) {
+      A = 0.0;
+      p = 1.0;
+    } else if (l == m + 1) {
+      A = sqrt(2.0 * mm + 3.0);
+      p = 1.0;
+    } else {
+      A = sqrt((4.0 * ll * ll - 1.0) / (ll * ll - mm * mm));
+      const double B =
+          sqrt(((ll - 1.0) * (ll - 1.0) - mm * mm) / (4.0 * (ll - 1.0) * (ll - 1.0) - 1.0));
+      p = -(A * B);
+    }
+    if (!in) p = 1.0;
 #pragma unroll
     for (int s = 2; s < 64; s <<= 1) {
       const double o = __shfl_up(p, s);
@@ -988,7 +996,7 @@ size_t map2alm_scratch_bytes(int64_t nside, int64_t lmax) {
   const int64_t size = (lmax + 1) * (lmax + 2) / 2;
   return sizeof(double) * (size_t)(2 * nring * M) + sizeof(double) * (size_t)(2 * npair) +
          sizeof(double) * (size_t)(2 * size) + sizeof(double) * (size_t)part_doubles(nside, lmax) +
-         sizeof(double) * (size_t)(2 * (4 * nside + 1)) + sizeof(double) * (size_t)(2 * kCapMaxP) +
+         sizeof(double) * (size_t)(2 * (4 * nside + 1)) + sizeof(double) * (size_t)(2 * kFftMaxP) +
          sizeof(double) * (size_t)M + 8 * 256;
 }
 
@@ -1012,27 +1020,28 @@ hipError_t launch_map2alm(int64_t nside, int64_t lmax, const double* map, double
   p += align(sizeof(double) * (size_t)part_doubles(nside, lmax));
   double* tab = (double*)p;
   p += align(sizeof(double) * (size_t)(2 * (4 * nside + 1)));
-  double* ctab = (double*)p;
-  p += align(sizeof(double) * (size_t)(2 * kCapMaxP));
+  double* ftab = (double*)p;
+  p += align(sizeof(double) * (size_t)(2 * kFftMaxP));
   double* gain = (double*)p;
   const int64_t mblocks = (lmax + 64) / 64;
   // Belt rings by FFT when their length 4N is a power of two whose half
   // fits the LDS buffer; cap rings by the chirp transform when their
   // convolutions fit it; every other ring by direct sums.
-  const bool fft = (nside & (nside - 1)) == 0 && 2 * nside <= kFftMaxH;
-  const bool caps = nside >= 2 && nside - 1 <= kCapMaxP / 2;
+  const bool fft = (nside & (nside - 1)) == 0 && 2 * nside <= kBeltMaxH;
+  const bool caps = nside >= 2 && nside - 1 <= kFftMaxP / 2;
+  if (fft || caps)
+    k_fft_twiddles<<<dim3((unsigned)((kFftMaxP + 255) / 256)), dim3(256), 0, st>>>(ftab);
   if (fft) {
     const int64_t L = 4 * nside;
     k_fft_table<<<dim3((unsigned)((L + 256) / 256)), dim3(256), 0, st>>>(L, tab);
     k_ring_fft<<<dim3((unsigned)(2 * nside + 1)), dim3(kFftThreads),
-                 sizeof(double) * 2 * (size_t)(2 * nside), st>>>(nside, lmax, map, tab, F);
+                 sizeof(double) * 2 * (size_t)(2 * nside), st>>>(nside, lmax, map, tab, ftab, F);
   }
   if (caps) {
     int64_t P = 1;
     while (P < 2 * (nside - 1) - 1) P <<= 1;
-    k_cap_table<<<dim3((unsigned)((kCapMaxP + 255) / 256)), dim3(256), 0, st>>>(ctab);
-    k_cap_bluestein<<<dim3((unsigned)(nside - 1)), dim3(kCapThreads),
-                      sizeof(double) * 2 * (size_t)P, st>>>(nside, lmax, map, ctab, part, F);
+    k_cap_bluestein<<<dim3((unsigned)(nside - 1)), dim3(kFftThreads),
+                      sizeof(double) * 2 * (size_t)P, st>>>(nside, lmax, map, ftab, part, F);
   }
   // Rings left for the direct sums: none, the belt, or all (Nside 1 has no
   // cap rings; a belt done by FFT implies Nside <= 2048, where the caps
@@ -1046,7 +1055,6 @@ hipError_t launch_map2alm(int64_t nside, int64_t lmax, const double* map, double
   }
   k_mm_gain<<<dim3(1), dim3(256), 0, st>>>(lmax, gain);
   k_ring_zs<<<dim3((unsigned)((npair + 255) / 256)), dim3(256), 0, st>>>(nside, ring_z, ring_s);
-  k_leg_coef<<<dim3((unsigned)((M + 255) / 256), (unsigned)M), dim3(256), 0, st>>>(lmax, coef);
   k_leg_scan<<<dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st>>>(lmax, coef);
   const int64_t leg_waves = M * nblk;
   k_legendre<<<dim3((unsigned)((leg_waves + 3) / 4)), dim3(256), 0, st>>>(
