@@ -168,9 +168,38 @@ struct cplx {
 // It costs an address computation per access, which pays where LDS bounds
 // the kernel (the belt rings) and not where latency does (the cap rings,
 // whose nine transforms per workgroup run at the same speed either way).
-// ftab[k] = e^{-2 pi i k/kFftMaxP}, k < kFftMaxP, holds every twiddle.
+// ftab[k] = e^{-2 pi i k/kFftMaxP}, k < kFftMaxP/4, a quarter of the
+// period: a workgroup copies it into LDS and forms every twiddle from it,
+// e^{-2 pi i (q kFftMaxP/4 + r)/kFftMaxP} = (-i)^q e^{-2 pi i r/kFftMaxP}
+// (a swap and sign changes, exact).  Read from global memory, the seven
+// twiddles of each butterfly waited on the L2 in every pass: the two ring
+// kernels took 30% and 20% longer than with constant twiddles.
 constexpr int kFftThreads = 512;
-constexpr int64_t kFftMaxP = 4096;   // 64 KB of LDS
+constexpr int64_t kFftMaxP = 4096;   // 64 KB of LDS, and 16 KB for the twiddles
+constexpr int kTwQ = (int)(kFftMaxP / 4);
+
+// LDS bytes of a workgroup transforming P points: the quarter twiddle
+// table, then the points (gfx950 gives a workgroup up to 160 KB, so two of
+// the largest share a CU).
+constexpr size_t fft_lds_bytes(int64_t P) { return 16 * (size_t)(kTwQ + P); }
+
+// Copies the quarter table into LDS (tl); the caller synchronises.
+__device__ __forceinline__ void fft_load_twiddles(double* tl, const double* ftab) {
+  for (int k = threadIdx.x; k < kTwQ; k += kFftThreads)
+    reinterpret_cast<double2*>(tl)[k] = reinterpret_cast<const double2*>(ftab)[k];
+}
+
+// e^{-2 pi i k/kFftMaxP}, 0 <= k < kFftMaxP, from the quarter table.
+__device__ __forceinline__ cplx fft_twiddle(const double* tl, int k) {
+  const int q = k >> 10, r = k & (kTwQ - 1);
+  static_assert(kTwQ == 1024, "quarter index");
+  const double2 u = reinterpret_cast<const double2*>(tl)[r];
+  // (-i)^q (x + i y): q = 1 gives (y, -x), q = 2 (-x, -y), q = 3 (-y, x).
+  double x = (q & 1) ? u.y : u.x, y = (q & 1) ? u.x : u.y;
+  if (q & 2) x = -x;
+  if ((q ^ (q >> 1)) & 1) y = -y;
+  return {x, y};
+}
 
 template <bool kSwz>
 __device__ __forceinline__ int fft_slot(int j) { return kSwz ? j ^ ((j >> 3) & 15) : j; }
@@ -188,7 +217,7 @@ __device__ __forceinline__ void fft_put(double* x, int j, cplx v) {
 
 __global__ void k_fft_twiddles(double* ftab) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= kFftMaxP) return;
+  if (k >= kTwQ) return;
   double sp, cp;
   sincospi((double)(2 * k) / (double)kFftMaxP, &sp, &cp);
   ftab[2 * k] = cp;
@@ -253,7 +282,7 @@ __device__ __forceinline__ void dft_small(cplx* x) {
 // p + q' h.  The inverse pass undoes it up to a factor R: twiddles
 // conjugated and applied first, then the inverse R-point DFT.
 template <int R, bool kInv, bool kSwz>
-__device__ __forceinline__ void fft_pass(double* x, int P, int S, const double* ftab) {
+__device__ __forceinline__ void fft_pass(double* x, int P, int S, const double* tl) {
   const int h = S / R;
   const int tw = (int)kFftMaxP / S;   // table step of e^{-2 pi i/S}
   for (int b = threadIdx.x; b < P / R; b += kFftThreads) {
@@ -265,8 +294,8 @@ __device__ __forceinline__ void fft_pass(double* x, int P, int S, const double* 
     if constexpr (!kInv) dft_small<R, false>(v);
 #pragma unroll
     for (int q = 1; q < R; ++q) {
-      const int k = (pos * q * tw) & ((int)kFftMaxP - 1);
-      const cplx w = {ftab[2 * k], kInv ? -ftab[2 * k + 1] : ftab[2 * k + 1]};
+      const cplx t = fft_twiddle(tl, (pos * q * tw) & ((int)kFftMaxP - 1));
+      const cplx w = {t.r, kInv ? -t.i : t.i};
       v[q] = cmul(v[q], w);
     }
     if constexpr (kInv) dft_small<R, true>(v);
@@ -281,28 +310,28 @@ __device__ __forceinline__ void fft_pass(double* x, int P, int S, const double* 
 // widest span down, then one radix-4 or radix-2 pass if log2 P mod 3 is 2
 // or 1.
 template <bool kSwz>
-__device__ void fft_dif(double* x, int P, const double* ftab) {
+__device__ void fft_dif(double* x, int P, const double* tl) {
   int S = P;
   while (S >= 8) {
-    fft_pass<8, false, kSwz>(x, P, S, ftab);
+    fft_pass<8, false, kSwz>(x, P, S, tl);
     S >>= 3;
   }
-  if (S == 4) fft_pass<4, false, kSwz>(x, P, 4, ftab);
-  if (S == 2) fft_pass<2, false, kSwz>(x, P, 2, ftab);
+  if (S == 4) fft_pass<4, false, kSwz>(x, P, 4, tl);
+  if (S == 2) fft_pass<2, false, kSwz>(x, P, 2, tl);
 }
 
 // Inverse of fft_dif times P: digit-reversed order in, natural order out,
 // the passes in reverse order.
 template <bool kSwz>
-__device__ void fft_dit_inv(double* x, int P, const double* ftab) {
+__device__ void fft_dit_inv(double* x, int P, const double* tl) {
   int e = 0;
   while ((1 << e) < P) ++e;
   int S = 1 << (e % 3);
-  if (S == 4) fft_pass<4, true, kSwz>(x, P, 4, ftab);
-  if (S == 2) fft_pass<2, true, kSwz>(x, P, 2, ftab);
+  if (S == 4) fft_pass<4, true, kSwz>(x, P, 4, tl);
+  if (S == 2) fft_pass<2, true, kSwz>(x, P, 2, tl);
   while (S < P) {
     S <<= 3;
-    fft_pass<8, true, kSwz>(x, P, S, ftab);
+    fft_pass<8, true, kSwz>(x, P, S, tl);
   }
 }
 
@@ -341,7 +370,10 @@ __global__ void k_fft_table(int64_t L, double* tab) {
 __global__ void __launch_bounds__(kFftThreads) k_ring_fft(int64_t nside, int64_t mmax,
                                                           const double* map, const double* tab,
                                                           const double* ftab, double* F) {
-  extern __shared__ double zs[];   // H complex values at fft_slot<true> positions
+  extern __shared__ double sm[];   // quarter twiddle table, then H points
+  double* tl = sm;
+  double* zs = sm + 2 * kTwQ;      // H complex values at fft_slot<true> positions
+  fft_load_twiddles(tl, ftab);
   const int64_t i = nside + blockIdx.x;
   const Ring r = ring_of(nside, i);
   const int L = (int)r.len, H = L / 2;
@@ -349,7 +381,7 @@ __global__ void __launch_bounds__(kFftThreads) k_ring_fft(int64_t nside, int64_t
   const double* x = map + r.first;
   for (int n = threadIdx.x; n < H; n += kFftThreads) fft_put<true>(zs, n, {x[2 * n], x[2 * n + 1]});
   __syncthreads();
-  fft_dif<true>(zs, H, ftab);
+  fft_dif<true>(zs, H, tl);
   double* out = F + 2 * (i - 1) * (mmax + 1);
   for (int m = threadIdx.x; m <= (int)mmax; m += kFftThreads) {
     int k = (int)((unsigned)m % (unsigned)L);
@@ -412,7 +444,10 @@ __device__ __forceinline__ void chirp(int64_t n, int64_t len, double& c, double&
 __global__ void __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
 k_cap_bluestein(int64_t nside, int64_t mmax, const double* map, const double* ftab,
                 double* zslot, double* F) {
-  extern __shared__ double xs[];   // P complex values, in order
+  extern __shared__ double sm[];   // quarter twiddle table, then P points
+  double* tl = sm;
+  double* xs = sm + 2 * kTwQ;      // P complex values, in order
+  fft_load_twiddles(tl, ftab);
   const int t = threadIdx.x;
   const int64_t N = nside, i = 1 + blockIdx.x, L = 4 * i;
   const int P = (int)pow2_at_least(2 * i - 1);
@@ -432,7 +467,7 @@ k_cap_bluestein(int64_t nside, int64_t mmax, const double* map, const double* ft
     fft_put<false>(xs, p, {br, bi});
   }
   __syncthreads();
-  fft_dif<false>(xs, P, ftab);
+  fft_dif<false>(xs, P, tl);
   double Br[kCapPer], Bi[kCapPer];
 #pragma unroll
   for (int j = 0; j < kCapPer; ++j) {
@@ -479,7 +514,7 @@ k_cap_bluestein(int64_t nside, int64_t mmax, const double* map, const double* ft
       }
     }
     __syncthreads();
-    fft_dif<false>(xs, P, ftab);
+    fft_dif<false>(xs, P, tl);
 #pragma unroll
     for (int j = 0; j < kCapPer; ++j) {
       const int p = t + j * kFftThreads;
@@ -489,7 +524,7 @@ k_cap_bluestein(int64_t nside, int64_t mmax, const double* map, const double* ft
       }
     }
     __syncthreads();
-    fft_dit_inv<false>(xs, P, ftab);
+    fft_dit_inv<false>(xs, P, tl);
 #pragma unroll
     for (int j = 0; j < kCapKappa; ++j) {
       const int64_t kap = t + (int64_t)j * kFftThreads;
@@ -1030,18 +1065,18 @@ hipError_t launch_map2alm(int64_t nside, int64_t lmax, const double* map, double
   const bool fft = (nside & (nside - 1)) == 0 && 2 * nside <= kBeltMaxH;
   const bool caps = nside >= 2 && nside - 1 <= kFftMaxP / 2;
   if (fft || caps)
-    k_fft_twiddles<<<dim3((unsigned)((kFftMaxP + 255) / 256)), dim3(256), 0, st>>>(ftab);
+    k_fft_twiddles<<<dim3((unsigned)((kTwQ + 255) / 256)), dim3(256), 0, st>>>(ftab);
   if (fft) {
     const int64_t L = 4 * nside;
     k_fft_table<<<dim3((unsigned)((L + 256) / 256)), dim3(256), 0, st>>>(L, tab);
     k_ring_fft<<<dim3((unsigned)(2 * nside + 1)), dim3(kFftThreads),
-                 sizeof(double) * 2 * (size_t)(2 * nside), st>>>(nside, lmax, map, tab, ftab, F);
+                 fft_lds_bytes(2 * nside), st>>>(nside, lmax, map, tab, ftab, F);
   }
   if (caps) {
     int64_t P = 1;
     while (P < 2 * (nside - 1) - 1) P <<= 1;
     k_cap_bluestein<<<dim3((unsigned)(nside - 1)), dim3(kFftThreads),
-                      sizeof(double) * 2 * (size_t)P, st>>>(nside, lmax, map, ftab, part, F);
+                      fft_lds_bytes(P), st>>>(nside, lmax, map, ftab, part, F);
   }
   // Rings left for the direct sums: none, the belt, or all (Nside 1 has no
   // cap rings; a belt done by FFT implies Nside <= 2048, where the caps
