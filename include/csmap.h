@@ -118,9 +118,9 @@ typedef enum {
     /* 1 = capture render's launches in a hipGraph and replay it while the sky
      * and the output pointer are unchanged; 0 = plain launches. */
     CSMAP_OPT_GRAPH = 1,
-    /* Pixels per lane of the forward kernels: 1, 2, 4 or 8.  A tile of
-     * 64 x this many pixels (see CSMAP_OPT_TILING) is owned by one
-     * wavefront. */
+    /* Pixels per lane of the forward kernels: 1, 2, 4 or 8 (default 8 for
+     * the FP32C form, 4 for FP64).  A tile of 64 x this many pixels (see
+     * CSMAP_OPT_TILING) is owned by one wavefront. */
     CSMAP_OPT_PIX_PER_LANE = 2,
     /* Wavefronts per workgroup: 1, 2 or 4. */
     CSMAP_OPT_WAVES = 3,

@@ -552,7 +552,9 @@ csmap_status csmap_create_sky(int64_t nside, double eta0, csmap_form form, void*
   s->form = form;
   s->stream = (hipStream_t)hip_stream;
   s->chunk = (form == CSMAP_FORM_FP64) ? 64 : 32;
-  if (form == CSMAP_FORM_FP64) s->K = 2;
+  // FP64: four pixels per lane, which the per-ring sharing of the z terms
+  // makes pay (K = 2 without it was as fast as K = 4).
+  if (form == CSMAP_FORM_FP64) s->K = 4;
   for (auto& e : s->ev) {
     hipError_t r = hipEventCreate(&e);
     if (r != hipSuccess) {

@@ -964,13 +964,74 @@ __global__ void __launch_bounds__(256) k_fwd32(FwdArgs A) {
 }
 
 __device__ __forceinline__ double rcp_f64(double x) {
-  // Hardware estimate refined by two Newton steps (quadratic convergence).
+  // The hardware estimate r (relative error e = 1 - x r below 2^-24)
+  // refined by one third-order step: 1/x = r / (1 - e) = r (1 + e + e^2 +
+  // ...), truncated after e^2, leaves e^3 < 2^-72.  Three FMAs where two
+  // Newton steps take four; both measure within 1 ulp of 1/x over 2^22
+  // random operands spanning 2^-40 to 2^10.
   double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
+  const double e = fma(-x, r, 1.0);
+  r = fma(r, fma(e, e, e), r);
   return r;
+}
+
+// The FP64 pair steps over nk consecutive records (16 doubles each) into
+// part[j].  kRing: every lane's K pixels share one z (ring-block tiles keep
+// a lane on one ring), so the z parts of n - Ph, |n - Ph|^2, n.X', 1 + n.Xdot,
+// Xdot.(n - Ph) and X'.(n - Ph) are formed once per record for the lane
+// (3.5 fewer FP64 instructions per pair at K = 2; the sums are associated
+// differently, within an ulp).
+template <int K, bool kRing>
+__device__ __forceinline__ void fwd64_steps(cd2p rp, int32_t nk, const double (&nd)[K][3],
+                                            double (&part)[K]) {
+  for (int32_t k = 0; k < nk; ++k, rp += 8) {
+    const v2d q0 = rp[0];
+    const v2d q1 = rp[1];
+    const v2d q2 = rp[2];
+    const v2d q3 = rp[3];
+    const v2d q4 = rp[4];
+    const v2d q6 = rp[6];
+    const v2d q7 = rp[7];
+    const double px = q0.x, py = q0.y, pz = q1.x;
+    const double lx = q6.x, ly = q6.y, lz = q7.x;
+    const double tx = q1.y, ty = q2.x, tz = q2.y;
+    const double vx = q3.x, vy = q3.y, vz = q4.x;
+    const double kap = q4.y;
+    // (n - hi) is exact for nearby directions; the lo part then enters with
+    // a single rounding.
+    double dz0 = 0.0, qz = 0.0, az = 0.0, bz = 1.0, vdz = 0.0, tdz = 0.0;
+    if constexpr (kRing) {
+      dz0 = (nd[0][2] - pz) - lz;
+      qz = dz0 * dz0;
+      az = nd[0][2] * tz;
+      bz = fma(nd[0][2], vz, 1.0);
+      vdz = vz * dz0;
+      tdz = tz * dz0;
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const double dx = (nd[j][0] - px) - lx;
+      const double dy = (nd[j][1] - py) - ly;
+      double q, a, b, vd, td;
+      if constexpr (kRing) {
+        q = fma(dy, dy, fma(dx, dx, qz));
+        a = fma(nd[j][1], ty, fma(nd[j][0], tx, az));
+        b = fma(nd[j][1], vy, fma(nd[j][0], vx, bz));
+        vd = fma(vy, dy, fma(vx, dx, vdz));
+        td = fma(ty, dy, fma(tx, dx, tdz));
+      } else {
+        const double dz = (nd[j][2] - pz) - lz;
+        q = fma(dz, dz, fma(dy, dy, dx * dx));
+        a = fma(nd[j][2], tz, fma(nd[j][1], ty, nd[j][0] * tx));
+        b = fma(nd[j][2], vz, fma(nd[j][1], vy, fma(nd[j][0], vx, 1.0)));
+        vd = fma(vz, dz, fma(vy, dy, vx * dx));
+        td = fma(tz, dz, fma(ty, dy, tx * dx));
+      }
+      const double m = fma(vd, b, -(a * td));
+      const double r = (q > 0.0) ? rcp_f64(b * q) : 0.0;
+      part[j] = fma(kap * m, r, part[j]);
+    }
+  }
 }
 
 template <int K, bool PERSISTENT>
@@ -987,6 +1048,7 @@ __global__ void __launch_bounds__(256) k_fwd64(FwdArgs A) {
     const int64_t tile = tile_of(A, item);
     double nd[K][3];
     bool inmap[K];
+    bool same_ring = true;   // this lane's K pixels share one ring (one z)
     const LaneRow lr = lane_row<K>(A, tile, lane);
 #pragma unroll
     for (int j = 0; j < K; ++j) {
@@ -995,7 +1057,10 @@ __global__ void __launch_bounds__(256) k_fwd64(FwdArgs A) {
       nd[j][0] = A.dirx[pc];
       nd[j][1] = A.diry[pc];
       nd[j][2] = A.dirz[pc];
+      same_ring = same_ring && nd[j][2] == nd[0][2];
     }
+    // Ring z is computed from integers, so equal z means one ring.
+    const bool ring = __all(same_ring);
     double S[K], C[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) { S[j] = 0.0; C[j] = 0.0; }
@@ -1028,37 +1093,11 @@ __global__ void __launch_bounds__(256) k_fwd64(FwdArgs A) {
 #pragma unroll
         for (int j = 0; j < K; ++j) part[j] = 0.0;
         const int32_t nk = (int32_t)(c1 - c0);
-        cd2p rp = recs + 8 * c0;
-        for (int32_t k = 0; k < nk; ++k, rp += 8) {
-          const v2d q0 = rp[0];
-          const v2d q1 = rp[1];
-          const v2d q2 = rp[2];
-          const v2d q3 = rp[3];
-          const v2d q4 = rp[4];
-          const v2d q6 = rp[6];
-          const v2d q7 = rp[7];
-          const double px = q0.x, py = q0.y, pz = q1.x;
-          const double lx = q6.x, ly = q6.y, lz = q7.x;
-          const double tx = q1.y, ty = q2.x, tz = q2.y;
-          const double vx = q3.x, vy = q3.y, vz = q4.x;
-          const double kap = q4.y;
-#pragma unroll
-          for (int j = 0; j < K; ++j) {
-            // (n - hi) is exact for nearby directions; the lo part then
-            // enters with a single rounding.
-            const double dx = (nd[j][0] - px) - lx;
-            const double dy = (nd[j][1] - py) - ly;
-            const double dz = (nd[j][2] - pz) - lz;
-            const double q = fma(dz, dz, fma(dy, dy, dx * dx));
-            const double a = fma(nd[j][2], tz, fma(nd[j][1], ty, nd[j][0] * tx));
-            const double b = fma(nd[j][2], vz, fma(nd[j][1], vy, fma(nd[j][0], vx, 1.0)));
-            const double vd = fma(vz, dz, fma(vy, dy, vx * dx));
-            const double td = fma(tz, dz, fma(ty, dy, tx * dx));
-            const double m = fma(vd, b, -(a * td));
-            const double r = (q > 0.0) ? rcp_f64(b * q) : 0.0;
-            part[j] = fma(kap * m, r, part[j]);
-          }
-        }
+        const cd2p rp = recs + 8 * c0;
+        if (ring)
+          fwd64_steps<K, true>(rp, nk, nd, part);
+        else
+          fwd64_steps<K, false>(rp, nk, nd, part);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
           const double y = part[j] - C[j];
