@@ -183,17 +183,24 @@ constexpr int kTwQ = (int)(kFftMaxP / 4);
 // the largest share a CU).
 constexpr size_t fft_lds_bytes(int64_t P) { return 16 * (size_t)(kTwQ + P); }
 
+// Slot of quarter-table entry r (< 1024) in LDS: bits 4-9 folded into bits
+// 0-3.  A pass of span S reads entries pos q (4096/S) apart across its
+// lanes; stored in order, those of spans 512 and 64 meet in one or two
+// banks (8- to 16-way conflicts), folded they spread over most of them
+// (1.5-way on average over all passes in a CPU model of the accesses).
+__device__ __forceinline__ int tw_slot(int r) { return r ^ ((r >> 4) & 15) ^ (r >> 8); }
+
 // Copies the quarter table into LDS (tl); the caller synchronises.
 __device__ __forceinline__ void fft_load_twiddles(double* tl, const double* ftab) {
   for (int k = threadIdx.x; k < kTwQ; k += kFftThreads)
-    reinterpret_cast<double2*>(tl)[k] = reinterpret_cast<const double2*>(ftab)[k];
+    reinterpret_cast<double2*>(tl)[tw_slot(k)] = reinterpret_cast<const double2*>(ftab)[k];
 }
 
 // e^{-2 pi i k/kFftMaxP}, 0 <= k < kFftMaxP, from the quarter table.
 __device__ __forceinline__ cplx fft_twiddle(const double* tl, int k) {
   const int q = k >> 10, r = k & (kTwQ - 1);
   static_assert(kTwQ == 1024, "quarter index");
-  const double2 u = reinterpret_cast<const double2*>(tl)[r];
+  const double2 u = reinterpret_cast<const double2*>(tl)[tw_slot(r)];
   // (-i)^q (x + i y): q = 1 gives (y, -x), q = 2 (-x, -y), q = 3 (-y, x).
   double x = (q & 1) ? u.y : u.x, y = (q & 1) ? u.x : u.y;
   if (q & 2) x = -x;
@@ -215,8 +222,8 @@ __device__ __forceinline__ void fft_put(double* x, int j, cplx v) {
   reinterpret_cast<double2*>(x)[fft_slot<kSwz>(j)] = make_double2(v.r, v.i);
 }
 
-__global__ void k_fft_twiddles(double* ftab) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ void fft_twiddles_block(double* ftab, int64_t blk) {
+  const int64_t k = blk * 256 + threadIdx.x;
   if (k >= kTwQ) return;
   double sp, cp;
   sincospi((double)(2 * k) / (double)kFftMaxP, &sp, &cp);
@@ -358,8 +365,8 @@ __device__ __forceinline__ int dif_pos(int k, int e) {
 // One workgroup per ring.
 constexpr int64_t kBeltMaxH = kFftMaxP;   // H <= 4096: Nside <= 2048
 
-__global__ void k_fft_table(int64_t L, double* tab) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ void fft_table_block(int64_t L, double* tab, int64_t blk) {
+  const int64_t k = blk * 256 + threadIdx.x;
   if (k > L) return;
   double sp, cp;
   sincospi((double)k / (double)L, &sp, &cp);
@@ -596,8 +603,7 @@ k_cap_bluestein(int64_t nside, int64_t mmax, const double* map, const double* ft
 // m = 0 .. mmax: one workgroup of 256 threads, each taking a run of
 // consecutive m, then a scan of the runs' products in LDS.  Its magnitude
 // grows like m^(1/4), so plain doubles hold it.
-__global__ void __launch_bounds__(256) k_mm_gain(int64_t mmax, double* g) {
-  __shared__ double part[256];
+__device__ void mm_gain_block(int64_t mmax, double* g, double* part) {
   const int t = threadIdx.x;
   const int M = (int)mmax + 1;
   const int run = (M + 255) / 256;
@@ -621,8 +627,8 @@ __global__ void __launch_bounds__(256) k_mm_gain(int64_t mmax, double* g) {
 
 // cos and sin of the colatitude of ring pair q (north ring q + 1), from the
 // ring's first pixel direction (sin from x and y, exact near the poles).
-__global__ void k_ring_zs(int64_t nside, double* ring_z, double* ring_s) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ void ring_zs_block(int64_t nside, double* ring_z, double* ring_s, int64_t blk) {
+  const int64_t q = blk * 256 + threadIdx.x;
   if (q >= 2 * nside) return;
   const Ring r = ring_of(nside, q + 1);
   double x, y, z;
@@ -670,9 +676,9 @@ __device__ __forceinline__ void pow_scaled(double s, int m, double& mant, int& e
 // 2 .. 32), times the last c of that parity from the previous 64, and
 // a_l = A_l c_{l-1} / c_l.  coef[2 i] = a_l, coef[2 i + 1] = c_l at a_lm's
 // position i.
-__global__ void __launch_bounds__(256) k_leg_scan(int64_t lmax, double* coef) {
+__device__ void leg_scan_block(int64_t lmax, double* coef, int64_t blk) {
   const int lane = threadIdx.x & 63;
-  const int64_t m = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t m = blk * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (m > lmax) return;
   const int64_t row = alm_idx(lmax, m, m) - m;   // idx(l, m) = row + l
   const double mm = (double)m;
@@ -710,6 +716,31 @@ __global__ void __launch_bounds__(256) k_leg_scan(int64_t lmax, double* coef) {
     carry0 = __shfl(c, 62);
     carry1 = __shfl(c, 63);
   }
+}
+
+// The set-up of one call in a single launch of 256-thread workgroups, each
+// taking one role by its index: the recursion coefficients (four m per
+// workgroup), the lambda_mm gains (one workgroup), the ring geometry, the
+// half-pixel phase table and the twiddle quarter.  The roles share nothing;
+// every later kernel reads their tables.
+struct SetupArgs {
+  int64_t nside, lmax, L;
+  double *coef, *gain, *ring_z, *ring_s, *tab, *ftab;
+  int64_t n_scan, n_zs, n_tab, n_tw;   // workgroups per role, in this order after the gain's
+};
+
+__global__ void __launch_bounds__(256) k_setup(SetupArgs a) {
+  __shared__ double part[256];
+  int64_t b = blockIdx.x;
+  if (b < a.n_scan) return leg_scan_block(a.lmax, a.coef, b);
+  b -= a.n_scan;
+  if (b == 0) return mm_gain_block(a.lmax, a.gain, part);
+  b -= 1;
+  if (b < a.n_zs) return ring_zs_block(a.nside, a.ring_z, a.ring_s, b);
+  b -= a.n_zs;
+  if (b < a.n_tab) return fft_table_block(a.L, a.tab, b);
+  b -= a.n_tab;
+  if (b < a.n_tw) fft_twiddles_block(a.ftab, b);
 }
 
 __device__ __forceinline__ double wave_sum(double x) {
@@ -1064,11 +1095,25 @@ hipError_t launch_map2alm(int64_t nside, int64_t lmax, const double* map, double
   // convolutions fit it; every other ring by direct sums.
   const bool fft = (nside & (nside - 1)) == 0 && 2 * nside <= kBeltMaxH;
   const bool caps = nside >= 2 && nside - 1 <= kFftMaxP / 2;
-  if (fft || caps)
-    k_fft_twiddles<<<dim3((unsigned)((kTwQ + 255) / 256)), dim3(256), 0, st>>>(ftab);
+  {
+    SetupArgs a;
+    a.nside = nside;
+    a.lmax = lmax;
+    a.L = 4 * nside;
+    a.coef = coef;
+    a.gain = gain;
+    a.ring_z = ring_z;
+    a.ring_s = ring_s;
+    a.tab = tab;
+    a.ftab = ftab;
+    a.n_scan = (M + 3) / 4;
+    a.n_zs = (npair + 255) / 256;
+    a.n_tab = fft ? (a.L + 256) / 256 : 0;
+    a.n_tw = (fft || caps) ? (kTwQ + 255) / 256 : 0;
+    const int64_t nb = a.n_scan + 1 + a.n_zs + a.n_tab + a.n_tw;
+    k_setup<<<dim3((unsigned)nb), dim3(256), 0, st>>>(a);
+  }
   if (fft) {
-    const int64_t L = 4 * nside;
-    k_fft_table<<<dim3((unsigned)((L + 256) / 256)), dim3(256), 0, st>>>(L, tab);
     k_ring_fft<<<dim3((unsigned)(2 * nside + 1)), dim3(kFftThreads),
                  fft_lds_bytes(2 * nside), st>>>(nside, lmax, map, tab, ftab, F);
   }
@@ -1088,9 +1133,6 @@ hipError_t launch_map2alm(int64_t nside, int64_t lmax, const double* map, double
     k_ring_dft<<<dim3((unsigned)((dft_waves + 3) / 4)), dim3(256), 0, st>>>(nside, lmax, map, F,
                                                                            lo, hi);
   }
-  k_mm_gain<<<dim3(1), dim3(256), 0, st>>>(lmax, gain);
-  k_ring_zs<<<dim3((unsigned)((npair + 255) / 256)), dim3(256), 0, st>>>(nside, ring_z, ring_s);
-  k_leg_scan<<<dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st>>>(lmax, coef);
   const int64_t leg_waves = M * nblk;
   k_legendre<<<dim3((unsigned)((leg_waves + 3) / 4)), dim3(256), 0, st>>>(
       nside, lmax, lmax, F, gain, ring_z, ring_s, coef, nblk, part);
