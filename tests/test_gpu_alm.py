@@ -34,8 +34,12 @@ def gpu_alm(B, hmap, lmax):
 
 
 # Powers of two take the FFT of the belt rings, other Nside the direct sums.
+# Nside 2 and 3 take the smallest transforms (a one-point chirp transform for
+# the first cap ring, a radix-4 belt FFT at Nside 2), lmax 0 the shortest
+# recursion.
 @pytest.mark.parametrize("nside,lmax", [(1, 4), (4, 12), (8, 16), (16, 64), (32, 64), (64, 128),
-                                        (12, 48), (48, 96), (64, 256)])
+                                        (12, 48), (48, 96), (64, 256), (2, 8), (3, 11), (2, 0),
+                                        (8, 0)])
 def test_map2alm_matches_oracle(B, nside, lmax):
     rng = np.random.default_rng(100 + nside)
     hmap = rng.standard_normal(12 * nside * nside) + 0.3
